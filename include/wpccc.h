@@ -1,0 +1,177 @@
+/*
+ * wpccc.h -- C ABI of the MI355X (gfx950) WP-CCC propagation library.
+ *
+ * The library integrates the close-coupling equations of the wave-packet
+ * convergent-close-coupling method (arXiv:2403.04252, Eq. 1 and Eq. DIFFEQ)
+ *
+ *     dX/dz = M(z) X,   M = -(i/v) S(z)^{-1} H(z)
+ *
+ * along straight-line paths R = (b, 0, z) with the fourth-order Runge-Kutta
+ * scheme of the paper's Algorithm 1, for a batch of impact parameters b at
+ * once.  In the one-centre (1C) form S = I and H = D_T (Eq. NOINV, with the
+ * -i/v of Eq. INV kept).  D_T is Eq. D1 with the radial integrals of Eq. D2
+ * evaluated by the r-grid quadrature at the exact R = sqrt(b^2 + z^2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: WPCCC_OK (0) or a negative code.
+ *    wpccc_last_error() returns a thread-local message for the last failure.
+ *    No function aborts the process.
+ *  - Handles (wpccc_basis_t, wpccc_plan_t) are owned by the library and are
+ *    released with the matching *_destroy call.
+ *  - Pointers named *_host are caller-owned host memory.  Pointers named
+ *    *_dev are caller-owned device memory on the plan's device (for example
+ *    a PyTorch tensor's data_ptr()).  The library never frees them.
+ *  - Complex numbers are (re, im) pairs of doubles (HIP double2 layout).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Device work is enqueued asynchronously on it.  Errors found on the
+ *    device (non-finite amplitudes) are latched and returned by
+ *    wpccc_plan_status(), which synchronises the stream.
+ *  - There is no CPU path: without a usable gfx950 device, plan creation
+ *    returns WPCCC_EHIP.
+ *
+ * State order (canonical, shared with every array below)
+ * -------------------------------------------------------
+ *  Radial functions are ordered by l, then bound states n = l+1..n_max, then
+ *  wave-packet bins by increasing k.  States are ordered by l, then
+ *  m = -l..l, then radial index: state (l, m, i) has index
+ *  off_l + (m + l) * N_l + i with N_l = n_max - l + n_bins and
+ *  off_l = sum_{l' < l} (2l'+1) N_l'.  State 0 is the ground state (1s),
+ *  the paper's X[1] = 1 initial condition.
+ */
+#ifndef WPCCC_H
+#define WPCCC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define WPCCC_OK         0
+#define WPCCC_EINVAL    -1   /* bad argument or specification */
+#define WPCCC_ENOMEM    -2   /* host or device allocation failed */
+#define WPCCC_EHIP      -3   /* a HIP runtime call failed (no device, launch error) */
+#define WPCCC_ESINGULAR -4   /* exact zero pivot in an LU factorisation */
+#define WPCCC_ENUMERIC  -5   /* non-finite amplitude detected on the device */
+#define WPCCC_ENOTSUP   -6   /* requested form not available in this build */
+
+typedef struct wpccc_basis_s* wpccc_basis_t;
+typedef struct wpccc_plan_s* wpccc_plan_t;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* wpccc_last_error(void);
+
+/* Library version as "major.minor.patch". */
+const char* wpccc_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Basis (Sec. II: bound eigenstates plus wave-packet pseudostates; the      */
+/* r-grid of the paper's Sec. II, 0..r_max, denser near the origin).         */
+/* ------------------------------------------------------------------------ */
+
+/* Recipe of one centre's basis.
+ *  n_max   bound hydrogen-like states n = 1..n_max with l <= min(n-1, l_max)
+ *  l_max   largest orbital angular momentum (0..10)
+ *  n_bins  wave-packet bins per l, uniform in k on [0, k_max] (0 = none)
+ *  k_max   upper edge of the last bin (a.u.)
+ *  n_r     number of grid intervals (even, 2..20000); r_i = r_max (i/n_r)^2
+ *  r_max   grid extent (a.u.)
+ *  Z       nuclear charge of the centre the states belong to (> 0)
+ * Bound radial functions are the closed-form R_nl; a bin is
+ * Delta_k^{-1/2} int_bin sqrt(2/pi) F_l(-Z/k, kr)/r dk (16-point
+ * Gauss-Legendre per bin); per l the set is orthonormalised on the grid by
+ * modified Gram-Schmidt (bound states first).  Energies: -Z^2/(2n^2) and
+ * (k_lo^2 + k_lo k_hi + k_hi^2)/6. */
+typedef struct {
+    int n_max;
+    int l_max;
+    int n_bins;
+    double k_max;
+    int n_r;
+    double r_max;
+    double Z;
+} wpccc_basis_spec;
+
+/* Build a basis on the host (setup; not part of the propagation).
+ * Errors: WPCCC_EINVAL for an invalid recipe, WPCCC_ENOMEM. */
+int wpccc_basis(const wpccc_basis_spec* spec, wpccc_basis_t* out);
+
+/* Sizes: number of states N, radial functions N_f and grid intervals n_r.
+ * Any output pointer may be NULL. */
+int wpccc_basis_info(wpccc_basis_t basis, int* n_states, int* n_radial, int* n_r);
+
+/* Copy the basis out (host arrays, any may be NULL):
+ *  r_host[n_r+1], w_host[n_r+1]      grid and Simpson weights
+ *  phi_host[N_f*(n_r+1)]             radial functions, row-major [a][i]
+ *  eps_host[N]                       state energies (a.u.)
+ *  lmi_host[3*N]                     (l, m, radial index) per state */
+int wpccc_basis_export(wpccc_basis_t basis, double* r_host, double* w_host,
+                       double* phi_host, double* eps_host, int* lmi_host);
+
+int wpccc_basis_destroy(wpccc_basis_t basis);
+
+/* ------------------------------------------------------------------------ */
+/* Plan: a batch of straight-line paths sharing one basis (1C).              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double Zp;      /* projectile charge: the target electron sees -Zp/|r-R|
+                       (Eq. D1 is written for Zp = 1; Zp = -1 is the negatively
+                       charged projectile of Eq. NOINV).  0 means 1. */
+    int batched;    /* 1: all paths in each launch (default); 0: one path per
+                       launch sequence, paths one after another */
+    int two_centre; /* must be 0 in this build (WPCCC_ENOTSUP otherwise) */
+} wpccc_plan_opts;
+
+/* Create a plan for n_traj paths with impact parameters b_host[j] > 0 and
+ * speeds v_host[j] > 0 (a.u.), all expanded in `target`.  The basis must
+ * outlive the plan.  Uploads the basis, builds the radial moment tables on
+ * the device (synchronously on `stream`) and allocates the per-path
+ * workspace.  opts may be NULL (defaults).
+ * Errors: WPCCC_EINVAL, WPCCC_ENOMEM, WPCCC_EHIP, WPCCC_ENOTSUP. */
+int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host,
+                      const double* v_host, const wpccc_plan_opts* opts,
+                      void* stream, wpccc_plan_t* out);
+
+/* n_states: N of the basis; n_pad: row stride (in complex elements) of the
+ * [n_traj][n_pad] amplitude arrays; device_bytes: device memory held. */
+int wpccc_plan_info(wpccc_plan_t plan, int* n_traj, int* n_states, int* n_pad,
+                    long long* device_bytes);
+
+int wpccc_plan_destroy(wpccc_plan_t plan);
+
+/* Returns the first device-side error latched since the last call (after
+ * synchronising `stream`), then clears it: WPCCC_OK or WPCCC_ENUMERIC. */
+int wpccc_plan_status(wpccc_plan_t plan, void* stream);
+
+/* Couplings of path j at one z (Eq. D1/D2, with the interaction-picture
+ * phases exp(i(eps_row - eps_col) z / v)):
+ *   H_dev  complex [N][N] row-major, H[row*N + col] = D_T(b_j, z)
+ *   S_dev  must be NULL in 1C.
+ * Errors: WPCCC_EINVAL (j out of range, R = 0). */
+int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev,
+                    void* stream);
+
+/* One RK4 step of Algorithm 1 from z to z + h for every path of the plan:
+ * M is evaluated at z, z + h/2 and z + h.  X_dev: complex [n_traj][n_pad],
+ * updated in place (entries beyond N are left untouched).
+ * Errors: WPCCC_EINVAL (h == 0 or a path with R = 0 on the step). */
+int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream);
+
+/* Algorithm 1 over the whole z-grid zgrid_host[0..n_points-1] (strictly
+ * increasing), starting from the amplitudes already in X_dev (set X = e_0
+ * for the paper's initial condition).  M at each grid point is evaluated
+ * once and carried to the next step, as in the paper.  On return (enqueued
+ * on `stream`):
+ *   X_dev     complex [n_traj][n_pad], amplitudes at zgrid[n_points-1]
+ *   P_dev     double  [n_traj][n_pad], P_i = |X_i|^2 (may be NULL)
+ *   norm_dev  double  [n_traj], sum_i |X_i|^2 (X^dagger S X with S = I;
+ *             may be NULL)
+ * Errors: WPCCC_EINVAL (fewer than 2 points, non-increasing grid). */
+int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
+                    void* X_dev, void* P_dev, void* norm_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WPCCC_H */

@@ -1,0 +1,246 @@
+"""Python binding of the MI355X WP-CCC propagation library (``libwpccc.so``).
+
+A thin ctypes layer over the C ABI in ``include/wpccc.h``: the functions keep
+the C names and only marshal arguments (PyTorch tensors supply device memory
+and streams).  Every computation runs in the HIP library; if the library is
+not built or no GPU is usable the calls raise, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "WpcccError", "BasisSpec", "load_library", "library_path",
+    "wpccc_version", "wpccc_basis", "wpccc_basis_info", "wpccc_basis_export",
+    "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_info", "wpccc_plan_destroy",
+    "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libwpccc.so")
+_lib = None
+
+WPCCC_OK = 0
+_STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
+
+
+class WpcccError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"WPCCC_{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int), ("l_max", ctypes.c_int), ("n_bins", ctypes.c_int),
+                ("k_max", ctypes.c_double), ("n_r", ctypes.c_int), ("r_max", ctypes.c_double),
+                ("Z", ctypes.c_double)]
+
+
+class _PlanOpts(ctypes.Structure):
+    _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int)]
+
+
+@dataclass
+class BasisSpec:
+    """One centre's basis recipe (see ``wpccc_basis_spec`` in include/wpccc.h)."""
+    n_max: int
+    l_max: int
+    n_bins: int
+    k_max: float
+    n_r: int
+    r_max: float = 100.0
+    Z: float = 1.0
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libwpccc.so (built in-tree by ``paper_2403_04252_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_2403_04252_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    pi, pd = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "wpccc_last_error": ([], ctypes.c_char_p),
+        "wpccc_version": ([], ctypes.c_char_p),
+        "wpccc_basis": ([ctypes.POINTER(_Spec), ctypes.POINTER(vp)], i),
+        "wpccc_basis_info": ([vp, pi, pi, pi], i),
+        "wpccc_basis_export": ([vp, pd, pd, pd, pd, pi], i),
+        "wpccc_basis_destroy": ([vp], i),
+        "wpccc_plan_create": ([vp, i, pd, pd, ctypes.POINTER(_PlanOpts), vp, ctypes.POINTER(vp)], i),
+        "wpccc_plan_info": ([vp, pi, pi, pi, ctypes.POINTER(ctypes.c_longlong)], i),
+        "wpccc_plan_destroy": ([vp], i),
+        "wpccc_plan_status": ([vp, vp], i),
+        "wpccc_couplings": ([vp, i, d, vp, vp, vp], i),
+        "wpccc_step": ([vp, vp, d, d, vp], i),
+        "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != WPCCC_OK:
+        msg = load_library().wpccc_last_error().decode()
+        raise WpcccError(rc, msg)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name, shape=None, name="tensor"):
+    if t is None:
+        return None
+    import torch
+    want = {"complex128": torch.complex128, "float64": torch.float64}[dtype_name]
+    if t.dtype != want or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype_name} CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Basis:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wpccc_basis_destroy(self.handle)
+            self.handle = None
+
+
+class Plan:
+    def __init__(self, handle, basis, n_traj, n_states, n_pad):
+        self.handle = handle
+        self.basis = basis          # keeps the basis alive as long as the plan
+        self.n_traj = n_traj
+        self.n_states = n_states
+        self.n_pad = n_pad
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wpccc_plan_destroy(self.handle)
+            self.handle = None
+
+
+def wpccc_version() -> str:
+    return load_library().wpccc_version().decode()
+
+
+def wpccc_basis(spec) -> Basis:
+    """Build one centre's basis on the host (see BasisSpec)."""
+    lib = load_library()
+    s = _Spec(int(spec.n_max), int(spec.l_max), int(spec.n_bins), float(spec.k_max),
+              int(spec.n_r), float(spec.r_max), float(spec.Z))
+    h = ctypes.c_void_p()
+    _check(lib.wpccc_basis(ctypes.byref(s), ctypes.byref(h)))
+    return Basis(h)
+
+
+def wpccc_basis_info(basis: Basis):
+    """(n_states, n_radial, n_r)."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().wpccc_basis_info(basis.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def wpccc_basis_export(basis: Basis) -> dict:
+    """Grid, weights, radial functions, energies and (l, m, radial index) per state."""
+    n, nf, nr = wpccc_basis_info(basis)
+    r = np.zeros(nr + 1)
+    w = np.zeros(nr + 1)
+    phi = np.zeros((nf, nr + 1))
+    eps = np.zeros(n)
+    lmi = np.zeros((n, 3), dtype=np.int32)
+    dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(load_library().wpccc_basis_export(basis.handle, dp(r), dp(w), dp(phi), dp(eps),
+                                             lmi.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return {"r": r, "w": w, "phi": phi, "eps": eps, "l": lmi[:, 0], "m": lmi[:, 1], "a": lmi[:, 2]}
+
+
+def wpccc_basis_destroy(basis: Basis):
+    if basis.handle:
+        _check(load_library().wpccc_basis_destroy(basis.handle))
+        basis.handle = None
+
+
+def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
+                      two_centre: bool = False, stream=None) -> Plan:
+    """Plan for len(b) straight-line paths in one basis; b, v in a.u."""
+    lib = load_library()
+    b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
+    v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
+    opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0)
+    h = ctypes.c_void_p()
+    dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
+                                 _stream_ptr(stream), ctypes.byref(h)))
+    nt, ns, npad, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+    _check(lib.wpccc_plan_info(h, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(npad), ctypes.byref(nb)))
+    p = Plan(h, basis, nt.value, ns.value, npad.value)
+    p.device_bytes = nb.value
+    return p
+
+
+def wpccc_plan_info(plan: Plan):
+    """(n_traj, n_states, n_pad, device_bytes)."""
+    nt, ns, npad, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+    _check(load_library().wpccc_plan_info(plan.handle, ctypes.byref(nt), ctypes.byref(ns),
+                                          ctypes.byref(npad), ctypes.byref(nb)))
+    return nt.value, ns.value, npad.value, nb.value
+
+
+def wpccc_plan_destroy(plan: Plan):
+    if plan.handle:
+        _check(load_library().wpccc_plan_destroy(plan.handle))
+        plan.handle = None
+
+
+def wpccc_plan_status(plan: Plan, stream=None):
+    _check(load_library().wpccc_plan_status(plan.handle, _stream_ptr(stream)))
+
+
+def wpccc_couplings(plan: Plan, j: int, z: float, H, S=None, stream=None):
+    """H (complex128 CUDA [N, N]) <- D_T(b_j, z) with phases; S must be None (1C)."""
+    N = plan.n_states
+    _check(load_library().wpccc_couplings(plan.handle, int(j), float(z),
+                                          _dev_ptr(H, "complex128", (N, N), "H"),
+                                          _dev_ptr(S, "complex128", (N, N), "S"), _stream_ptr(stream)))
+
+
+def wpccc_step(plan: Plan, X, z: float, h: float, stream=None):
+    """One RK4 step z -> z + h for all paths; X complex128 CUDA [n_traj, n_pad], in place."""
+    _check(load_library().wpccc_step(plan.handle, _dev_ptr(X, "complex128", (plan.n_traj, plan.n_pad), "X"),
+                                     float(z), float(h), _stream_ptr(stream)))
+
+
+def wpccc_propagate(plan: Plan, zgrid, X, P=None, norm=None, stream=None):
+    """Algorithm 1 over zgrid (host array) starting from X (in place)."""
+    z = np.ascontiguousarray(zgrid, dtype=np.float64)
+    shp = (plan.n_traj, plan.n_pad)
+    _check(load_library().wpccc_propagate(
+        plan.handle, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(z.size),
+        _dev_ptr(X, "complex128", shp, "X"), _dev_ptr(P, "float64", shp, "P"),
+        _dev_ptr(norm, "float64", (plan.n_traj,), "norm"), _stream_ptr(stream)))

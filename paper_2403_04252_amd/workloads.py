@@ -1,0 +1,98 @@
+"""Seeded synthetic workloads (inputs only: basis recipes, impact parameters,
+speeds and z-grids).  No coupling, solver or propagation arithmetic lives here;
+both the HIP library and the oracle receive these plain values.
+
+The shapes follow the paper's proton + hydrogen workload: bound hydrogen
+states plus Coulomb wave-packet bins per l (all m), an r-grid to 100 a.u.,
+straight-line paths at fixed v, batched over impact parameters b.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Recipe:
+    n_max: int
+    l_max: int
+    n_bins: int
+    k_max: float
+    n_r: int
+    r_max: float = 100.0
+    Z: float = 1.0
+
+
+@dataclass
+class Workload:
+    name: str
+    description: str
+    basis: Recipe
+    b: np.ndarray
+    v: np.ndarray
+    zgrid: np.ndarray
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.zgrid.size - 1)
+
+
+def z_uniform(z0: float, z1: float, dz: float) -> np.ndarray:
+    n = int(round((z1 - z0) / dz))
+    return np.linspace(z0, z1, n + 1)
+
+
+def z_geometric(z_min: float, z_max: float, n_z: int) -> np.ndarray:
+    """zgrid[i] = z_min (z_max/z_min)^(i/n_z), zgrid[0] = 0, zgrid[-i] = -zgrid[i]."""
+    pos = z_min * (z_max / z_min) ** (np.arange(1, n_z + 1) / n_z)
+    return np.concatenate([-pos[::-1], [0.0], pos])
+
+
+def single_centre_small() -> Workload:
+    """n <= 3 bound + 8 bins/l, l <= 2 (N = 86), 1500-point grid; one path b = 1,
+    v = 1, z from -40 to 40 with dz = 0.1 (800 RK4 steps)."""
+    return Workload("p+H 1C N=86 b=1 v=1", "single-centre, FP64, one path",
+                    Recipe(3, 2, 8, 3.0, 1500), np.array([1.0]), np.array([1.0]),
+                    z_uniform(-40.0, 40.0, 0.1))
+
+
+def single_centre_batched() -> Workload:
+    """n <= 6 bound + 20 bins/l, l <= 4 (N = 580), 4000-point grid; 32 paths with
+    b log-spaced 0.05..20, v = 1, z from -40 to 40 with dz = 0.1."""
+    j = np.arange(32)
+    b = 0.05 * 400.0 ** (j / 31.0)
+    return Workload("p+H 1C N=580 x32 b", "single-centre, FP64, 32 paths in one batch",
+                    Recipe(6, 4, 20, 3.0, 4000), b, np.ones(32), z_uniform(-40.0, 40.0, 0.1))
+
+
+def single_centre_seeded(n_paths: int = 64, seed: int = 4) -> Workload:
+    """The N = 580 basis with b drawn log-uniform in [0.05, 20] (numpy default_rng(seed)), sorted."""
+    rng = np.random.default_rng(seed)
+    b = np.sort(np.exp(rng.uniform(np.log(0.05), np.log(20.0), n_paths)))
+    return Workload(f"p+H 1C N=580 x{n_paths} seeded b", "single-centre, seeded impact parameters",
+                    Recipe(6, 4, 20, 3.0, 4000), b, np.ones(n_paths), z_uniform(-40.0, 40.0, 0.1))
+
+
+def reduced(w: Workload, n_paths: int | None = None, n_steps: int | None = None,
+            n_r: int | None = None) -> Workload:
+    """A cheaper cut of a workload for oracle comparisons: the first n_steps steps
+    of the z-grid, a spread subset of the paths, or a coarser grid."""
+    b, v, z = w.b, w.v, w.zgrid
+    if n_paths is not None and n_paths < b.size:
+        idx = np.unique(np.linspace(0, b.size - 1, n_paths).round().astype(int))
+        b, v = b[idx], v[idx]
+    if n_steps is not None:
+        z = z[: n_steps + 1]
+    rec = w.basis
+    if n_r is not None:
+        rec = Recipe(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, n_r, rec.r_max, rec.Z)
+    return Workload(w.name + " (reduced)", w.description, rec, b.copy(), v.copy(), z.copy())
+
+
+def random_state(n_paths: int, n_states: int, seed: int) -> np.ndarray:
+    """A normalised random complex amplitude vector per path (for single-step checks)."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n_paths, n_states)) + 1j * rng.standard_normal((n_paths, n_states))
+    return X / np.linalg.norm(X, axis=1, keepdims=True)

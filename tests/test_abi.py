@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+* every function declared in include/wpccc.h is exported by libwpccc.so;
+* the library's host basis builder (independent code) reproduces the oracle's
+  basis: grid, weights, radial functions, energies and state order;
+* invalid specifications are rejected with WPCCC_EINVAL.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2403_04252_amd as W
+from oracle.radial import BasisSpec, build_basis
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "wpccc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wpccc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(W.library_path()):
+        from paper_2403_04252_amd.build import build_library
+        build_library()
+    return W.load_library()
+
+
+def test_header_symbols_exported(lib):
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version(lib):
+    assert re.match(r"^\d+\.\d+\.\d+$", W.wpccc_version())
+
+
+@pytest.mark.parametrize("spec", [BasisSpec(3, 2, 8, 3.0, 1500), BasisSpec(2, 3, 5, 2.0, 800, 60.0)])
+def test_library_basis_matches_oracle(lib, spec):
+    hb = W.wpccc_basis(W.BasisSpec(spec.n_max, spec.l_max, spec.n_bins, spec.k_max, spec.n_r,
+                                   spec.r_max, spec.Z))
+    ex = W.wpccc_basis_export(hb)
+    ob = build_basis(spec)
+    assert W.wpccc_basis_info(hb) == (ob.n_states, ob.n_radial, spec.n_r)
+    assert np.array_equal(ex["r"], ob.r)
+    assert np.abs(ex["w"] - ob.w).max() <= 1e-15 * np.abs(ob.w).max()
+    assert np.abs(ex["phi"] - ob.phi).max() <= 1e-13 * np.abs(ob.phi).max()
+    assert np.abs(ex["eps"] - ob.eps).max() <= 1e-15
+    assert np.array_equal(ex["l"], ob.st_l)
+    assert np.array_equal(ex["m"], ob.st_m)
+    assert np.array_equal(ex["a"], ob.st_a)
+
+
+@pytest.mark.parametrize("bad", [dict(n_r=1501), dict(l_max=11), dict(n_max=0), dict(Z=0.0),
+                                 dict(k_max=0.0), dict(r_max=-1.0)])
+def test_invalid_spec_rejected(lib, bad):
+    kw = dict(n_max=2, l_max=1, n_bins=2, k_max=1.0, n_r=100, r_max=50.0, Z=1.0)
+    kw.update(bad)
+    with pytest.raises(W.WpcccError) as ei:
+        W.wpccc_basis(W.BasisSpec(**kw))
+    assert ei.value.code == -1
+
+
+def test_plan_without_gpu_fails_loudly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: plan creation is exercised by the GPU tests")
+    hb = W.wpccc_basis(W.BasisSpec(2, 1, 2, 1.0, 100, 50.0))
+    with pytest.raises(W.WpcccError) as ei:
+        W.wpccc_plan_create(hb, [1.0], [1.0], stream=0)
+    assert ei.value.code == -3

@@ -1,0 +1,210 @@
+"""GPU parity of the one-centre path against the FP64 oracle (through the C ABI).
+
+Tolerances
+----------
+* couplings: element-wise |H_gpu - H_oracle| <= 1e-12 max|H|.  The two sides
+  sum the same n_r quadrature terms in different orders (prefix moments vs a
+  direct sum), which moves each element by a few units of n_r^(1/2) eps of
+  the largest term.
+* amplitudes after one step: |dX| <= 1e-13 (unit-norm X).
+* probabilities after a whole path: |P_gpu - P_oracle| <= 1e-10 max(P, 1e-6),
+  the 1e-10 relative target with a floor at P = 1e-6 (below it the
+  amplitude rounding of ~1e-14 dominates any relative measure).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2403_04252_amd as W
+from paper_2403_04252_amd import workloads as WL
+from oracle.direct import direct_matrix
+from oracle.propagate import (initial_state, m_one_centre, probabilities, propagate_one_centre,
+                              rk4_propagate)
+from oracle.radial import BasisSpec as OSpec, build_basis
+
+pytestmark = pytest.mark.gpu
+
+P_FLOOR = 1e-6
+
+
+def lib_basis(rec):
+    return W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+
+
+def oracle_basis(rec):
+    return build_basis(OSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+
+
+def prob_ok(P, Pref):
+    return np.abs(P - Pref) <= 1e-10 * np.maximum(Pref, P_FLOOR)
+
+
+@pytest.fixture(scope="module")
+def small():
+    rec = WL.single_centre_small().basis
+    return rec, lib_basis(rec), oracle_basis(rec)
+
+
+@pytest.fixture(scope="module")
+def large():
+    rec = WL.single_centre_batched().basis
+    return rec, lib_basis(rec), oracle_basis(rec)
+
+
+def test_device_present():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    print("device:", torch.cuda.get_device_name(0), flush=True)
+
+
+@pytest.mark.parametrize("which", ["small", "large"])
+def test_couplings_parity(which, request):
+    rec, lb, ob = request.getfixturevalue(which)
+    bs = [0.3, 1.0, 7.5] if which == "small" else [0.05, 2.4]
+    zs = [-40.0, -3.3, -0.05, 0.0, 1.234, 40.0] if which == "small" else [-17.0, 0.0, 0.61]
+    v = 1.0
+    plan = W.wpccc_plan_create(lb, bs, v)
+    N = plan.n_states
+    H = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    worst = 0.0
+    for j, b in enumerate(bs):
+        for z in zs:
+            print(f"couplings {which} b={b} z={z}", flush=True)
+            W.wpccc_couplings(plan, j, z, H)
+            torch.cuda.synchronize()
+            Hg = H.cpu().numpy()
+            Ho = direct_matrix(ob, b, z, v)
+            err = np.abs(Hg - Ho).max() / np.abs(Ho).max()
+            worst = max(worst, err)
+            assert err <= 1e-12, (b, z, err)
+    print("worst relative coupling error", worst)
+
+
+def test_couplings_outside_grid(small):
+    rec, lb, ob = small
+    plan = W.wpccc_plan_create(lb, [150.0], [1.3])
+    N = plan.n_states
+    H = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    for z in (0.0, 90.0):
+        W.wpccc_couplings(plan, 0, z, H)
+        torch.cuda.synchronize()
+        Ho = direct_matrix(ob, 150.0, z, 1.3)
+        assert np.abs(H.cpu().numpy() - Ho).max() <= 1e-12 * np.abs(Ho).max()
+
+
+def test_couplings_hermitian(large):
+    rec, lb, ob = large
+    plan = W.wpccc_plan_create(lb, [0.7], [1.0])
+    N = plan.n_states
+    H = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    W.wpccc_couplings(plan, 0, -2.2, H)
+    torch.cuda.synchronize()
+    Hg = H.cpu().numpy()
+    assert np.abs(Hg - Hg.conj().T).max() <= 1e-14 * np.abs(Hg).max()
+
+
+def test_step_parity(small):
+    rec, lb, ob = small
+    bs, vs = [0.4, 1.0, 3.0], [1.0, 0.5, 2.0]
+    plan = W.wpccc_plan_create(lb, bs, vs)
+    N, npad = plan.n_states, plan.n_pad
+    X0 = WL.random_state(3, N, seed=11)
+    X = torch.zeros((3, npad), dtype=torch.complex128, device="cuda")
+    X[:, :N] = torch.from_numpy(X0).cuda()
+    z, h = -0.37, 0.1
+    W.wpccc_step(plan, X, z, h)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy()[:, :N]
+    for j in range(3):
+        Xo = rk4_propagate(m_one_centre(ob, bs[j], vs[j]), X0[j], np.array([z, z + h]))
+        assert np.abs(Xg[j] - Xo).max() <= 1e-13, (j, np.abs(Xg[j] - Xo).max())
+
+
+def _propagate_gpu(lb, b, v, zgrid, Zp=1.0, batched=True):
+    plan = W.wpccc_plan_create(lb, b, v, Zp=Zp, batched=batched)
+    X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    P = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
+    nrm = torch.zeros(plan.n_traj, dtype=torch.float64, device="cuda")
+    W.wpccc_propagate(plan, zgrid, X, P, nrm)
+    W.wpccc_plan_status(plan)
+    torch.cuda.synchronize()
+    N = plan.n_states
+    return X.cpu().numpy()[:, :N], P.cpu().numpy()[:, :N], nrm.cpu().numpy()
+
+
+def test_propagate_single_path_full(small):
+    """The N = 86 single-path workload, all 800 steps, against the oracle."""
+    rec, lb, ob = small
+    w = WL.single_centre_small()
+    print("propagate N=86 full path on GPU", flush=True)
+    X, P, nrm = _propagate_gpu(lb, w.b, w.v, w.zgrid)
+    print("oracle", flush=True)
+    Xo = propagate_one_centre(ob, w.b[0], w.v[0], w.zgrid)
+    Po = probabilities(Xo)
+    ok = prob_ok(P[0], Po)
+    print("max |dP|", np.abs(P[0] - Po).max(), "max |dX|", np.abs(X[0] - Xo).max())
+    assert ok.all(), np.abs(P[0] - Po).max()
+    assert abs(nrm[0] - P[0].sum()) < 1e-13
+    assert abs(nrm[0] - 1.0) < 1e-4
+
+
+def test_propagate_large_basis_reduced(large):
+    """N = 580 basis, two paths, the first 40 steps."""
+    rec, lb, ob = large
+    w = WL.reduced(WL.single_centre_batched(), n_paths=2, n_steps=40)
+    X, P, _ = _propagate_gpu(lb, w.b, w.v, w.zgrid)
+    for j in range(2):
+        Xo = propagate_one_centre(ob, w.b[j], w.v[j], w.zgrid)
+        assert np.abs(X[j] - Xo).max() <= 1e-12
+        assert prob_ok(P[j], probabilities(Xo)).all()
+
+
+def test_batched_equals_sequential(small):
+    rec, lb, ob = small
+    b = [0.2, 0.9, 2.5, 6.0]
+    zg = WL.z_uniform(-10.0, 5.0, 0.1)
+    Xb, Pb, _ = _propagate_gpu(lb, b, 1.0, zg, batched=True)
+    Xs, Ps, _ = _propagate_gpu(lb, b, 1.0, zg, batched=False)
+    assert np.array_equal(Xb, Xs)
+
+
+def test_negative_projectile(small):
+    rec, lb, ob = small
+    zg = WL.z_uniform(-15.0, 15.0, 0.1)
+    X, P, _ = _propagate_gpu(lb, [1.2], 1.0, zg, Zp=-1.0)
+    Xo = propagate_one_centre(ob, 1.2, 1.0, zg, Zp=-1.0)
+    assert prob_ok(P[0], probabilities(Xo)).all()
+
+
+def test_geometric_grid(small):
+    """The paper's geometric z-grid (z_min = 1e-3, z_max = 20, n_z = 60)."""
+    rec, lb, ob = small
+    zg = WL.z_geometric(1e-3, 20.0, 60)
+    X, P, _ = _propagate_gpu(lb, [0.8], 1.5, zg)
+    Xo = propagate_one_centre(ob, 0.8, 1.5, zg)
+    assert prob_ok(P[0], probabilities(Xo)).all()
+
+
+def test_single_step_grid_and_errors(small):
+    rec, lb, ob = small
+    zg = np.array([-1.0, -0.9])
+    X, P, _ = _propagate_gpu(lb, [1.0], 1.0, zg)
+    Xo = propagate_one_centre(ob, 1.0, 1.0, zg)
+    assert np.abs(X[0] - Xo).max() <= 1e-14
+    plan = W.wpccc_plan_create(lb, [1.0], [1.0])
+    Xd = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+    with pytest.raises(W.WpcccError) as e1:
+        W.wpccc_propagate(plan, np.array([0.0, 0.0]), Xd)
+    assert e1.value.code == -1
+    with pytest.raises(W.WpcccError) as e2:
+        W.wpccc_step(plan, Xd, 0.0, 0.0)
+    assert e2.value.code == -1
+    H = torch.empty((plan.n_states, plan.n_states), dtype=torch.complex128, device="cuda")
+    with pytest.raises(W.WpcccError) as e3:
+        W.wpccc_couplings(plan, 1, 0.0, H)
+    assert e3.value.code == -1
+    with pytest.raises(W.WpcccError) as e4:
+        W.wpccc_plan_create(lb, [0.0], [1.0])
+    assert e4.value.code == -1
