@@ -18,6 +18,7 @@ __all__ = [
     "wpccc_version", "wpccc_basis", "wpccc_basis_info", "wpccc_basis_export",
     "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_info", "wpccc_plan_destroy",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
+    "wpccc_plan_timing", "wpccc_plan_kernel_time",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,6 +86,8 @@ def load_library():
         "wpccc_couplings": ([vp, i, d, vp, vp, vp], i),
         "wpccc_step": ([vp, vp, d, d, vp], i),
         "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
+        "wpccc_plan_timing": ([vp, i], i),
+        "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -244,3 +247,16 @@ def wpccc_propagate(plan: Plan, zgrid, X, P=None, norm=None, stream=None):
         plan.handle, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(z.size),
         _dev_ptr(X, "complex128", shp, "X"), _dev_ptr(P, "float64", shp, "P"),
         _dev_ptr(norm, "float64", (plan.n_traj,), "norm"), _stream_ptr(stream)))
+
+
+def wpccc_plan_timing(plan: Plan, enable: bool):
+    """Start (True) or stop (False) per-kernel HIP-event timing on the plan."""
+    _check(load_library().wpccc_plan_timing(plan.handle, 1 if enable else 0))
+
+
+def wpccc_plan_kernel_time(plan: Plan, kernel: str):
+    """(total_ms, launches) of `kernel` since timing was enabled or last read."""
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    _check(load_library().wpccc_plan_kernel_time(plan.handle, kernel.encode(), ctypes.byref(ms),
+                                                 ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,500 @@
+// HIP kernels of the one-centre path on gfx950 (64-wide waves, FP64 VALU).
+//
+// One RK4 stage of Algorithm 1 for every path of the batch is one launch of
+// k_stage: from (b, z, v) and the basis tables it forms, per workgroup, the
+// part of M(z) = -(i/v) Zp D_T(b, z) it needs and applies it to the stage
+// input, then writes the RK4 combination of that stage.  D_T (Eq. D1) is
+// never formed: its (l'm', lm) block is sum_lambda c Pbar_lambda^|m'-m| F_lambda
+// with F_lambda the N_l' x N_l matrix of Eq. D2 radial integrals, so
+//   y_{l'm'}[n'] = sum_{l, lambda, q} G_l'[m'][(l,lambda), q] sum_n F_l'[n'][(l,lambda), n] x'_{l q n}
+// with x' = conj(phase) u (interaction picture).
+//
+// Radial integrals at the exact R.  For the grid quadrature of Eq. D2
+//   F(R) = sum_i w_i r_i^2 f_a f_b min(r_i,R)^lam / max(r_i,R)^(lam+1)
+//        = R^-(lam+1) A_k + R^lam B_(k+1),
+//   A_k = sum_{i<=k} w_i r_i^(2+lam) f_a f_b,   B_k = sum_{i>=k} w_i r_i^(1-lam) f_a f_b,
+// with k the last node r_k <= R: the multipole kernel factorises into a power
+// of r times a power of R on either side of R.  k_moments tabulates A and B
+// once per basis; per R each integral costs one 16-byte load and two
+// multiplies instead of an n_r-term sum.  It is the same quadrature, summed
+// in a different association order.
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace wpccc {
+
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Partial moments, one thread per Frow entry d = (a, b, lambda); phiT is [n_r+1][n_f].
+//   tab[k][d].x = A_k     = sum_{i=1..k}      w_i r_i^(2+lam) f_a(r_i) f_b(r_i)
+//   tab[k][d].y = B_(k+1) = sum_{i=k+1..n_r}  w_i r_i^(1-lam) f_a(r_i) f_b(r_i)
+__global__ void k_moments(const double* __restrict__ r, const double* __restrict__ w,
+                          const double* __restrict__ phiT, const int* __restrict__ da,
+                          const int* __restrict__ db, const int* __restrict__ dl, int n_r, int n_f,
+                          int n_frow, double2* __restrict__ tab) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n_frow) return;
+    const int a = da[d], b = db[d], lam = dl[d];
+    double A = 0.0;
+    tab[d].x = 0.0;
+    for (int i = 1; i <= n_r; ++i) {
+        const double ri = r[i];
+        double p = ri * ri;
+        for (int q = 0; q < lam; ++q) p *= ri;
+        A += w[i] * p * phiT[(size_t)i * n_f + a] * phiT[(size_t)i * n_f + b];
+        tab[(size_t)i * n_frow + d].x = A;
+    }
+    double B = 0.0;
+    tab[(size_t)n_r * n_frow + d].y = 0.0;
+    for (int i = n_r; i >= 1; --i) {
+        const double ri = r[i];
+        double p;  // r^(1 - lam)
+        if (lam == 0) {
+            p = ri;
+        } else {
+            double q = 1.0;
+            for (int s = 1; s < lam; ++s) q *= ri;
+            p = 1.0 / q;
+        }
+        B += w[i] * p * phiT[(size_t)i * n_f + a] * phiT[(size_t)i * n_f + b];
+        tab[(size_t)(i - 1) * n_frow + d].y = B;
+    }
+}
+
+// Column mu of Pbar_l^mu = sqrt((l-mu)!/(l+mu)!) P_l^mu(x) (Condon-Shortley
+// phase) for l = mu..lam_max, written to pb[pb_index(l, mu)].
+__device__ void legendre_column(int lam_max, int mu, double x, double* pb) {
+    const double s = sqrt(fmax(0.0, 1.0 - x * x));
+    double pmm = 1.0;
+    for (int i = 1; i <= mu; ++i) pmm *= -sqrt((2.0 * i - 1.0) / (2.0 * i)) * s;
+    pb[pb_index(mu, mu)] = pmm;
+    if (mu + 1 > lam_max) return;
+    double p0 = pmm;
+    double p1 = sqrt(2.0 * mu + 1.0) * x * pmm;
+    pb[pb_index(mu + 1, mu)] = p1;
+    for (int l = mu + 1; l < lam_max; ++l) {
+        const double p2 = ((2.0 * l + 1.0) * x * p1 - sqrt((double)(l + mu) * (l - mu)) * p0) /
+                          sqrt((double)(l + 1 + mu) * (l + 1 - mu));
+        pb[pb_index(l + 1, mu)] = p2;
+        p0 = p1;
+        p1 = p2;
+    }
+}
+
+// Last grid node with r_k <= R; the nodes r_k = r_max (k/n_r)^2 are recomputed
+// in registers with the same arithmetic as the host grid.
+__device__ inline int grid_index(double R, double r_max, int n_r) {
+    int k = (int)floor(n_r * sqrt(fmin(R / r_max, 1.0)));
+    k = max(0, min(k, n_r));
+    auto rk = [&](int q) {
+        const double x = (double)q / n_r;
+        return r_max * x * x;
+    };
+    while (k < n_r && rk(k + 1) <= R) ++k;
+    while (k > 0 && rk(k) > R) --k;
+    return k;
+}
+
+// F at R from the table entry (A_k, B_(k+1)).
+__device__ inline double radial_at(double2 ab, double R, int lam) {
+    double Rl = 1.0;
+    for (int q = 0; q < lam; ++q) Rl *= R;
+    return ab.x / (Rl * R) + ab.y * Rl;
+}
+
+__device__ inline double2 phase(double eps, double z, double v) {
+    double sn, cs;
+    sincos(eps * z / v, &sn, &cs);
+    return make_double2(cs, sn);
+}
+
+// Per (path, z-point): grid node of R, powers of R, Pbar table and phases per
+// radial function.  grid: x = point, y = path; one wave per block.
+__global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
+    const Meta& m = a.meta;
+    const int j = a.traj0 + blockIdx.y;
+    const int p = blockIdx.x;
+    const double z = a.z[p];
+    const double b = a.tb.bvec[j], v = a.tb.vvec[j];
+    const double R = sqrt(b * b + z * z);
+    const size_t jp = (size_t)j * a.pt.n_pts + p;
+    const int t = threadIdx.x;
+    if (t == 0) a.pt.kidx[jp] = grid_index(R, m.r_max, m.n_r);
+    if (t <= m.lam_max) {
+        double Rl = 1.0;
+        for (int q = 0; q < t; ++q) Rl *= R;
+        a.pt.rpow[jp * kRpow + 2 * t] = 1.0 / (Rl * R);
+        a.pt.rpow[jp * kRpow + 2 * t + 1] = Rl;
+        legendre_column(m.lam_max, t, z / R, a.pt.pbar + jp * kMaxPb);
+    }
+    for (int f = t; f < m.n_f; f += blockDim.x) a.pt.ph[jp * m.n_f + f] = phase(a.tb.rad_eps[f], z, v);
+}
+
+constexpr int kFBatch = 12;  // table entries per thread held in registers
+constexpr int kXBatch = 4;   // amplitudes per thread held in registers
+constexpr int kGBatch = 4;   // angular coefficients per thread held in registers
+
+// One stage for rows [row0, row0 + nrows) of the l' block, all nmp = 2l'+1 values of m'.
+//   phase 0: every independent global load of the stage is issued at once
+//            (table entries, stage input, coefficients) and the per-point
+//            tables (R powers, Pbar, phases) go to LDS;
+//   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
+//   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
+//   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
+__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
+    const Meta& m = a.meta;
+    const Tables& T = a.tb;
+    const int N = m.n_states;
+    const int nmp = 2 * lp + 1;
+    const int nlp = m.n_l[lp];
+    const int nV = m.nV[lp];
+    const int gcols = m.gcols[lp];
+    const int B = blockDim.x;
+    const int tid = threadIdx.x;
+    const size_t jp = (size_t)j * a.pt.n_pts + a.p;
+
+    double2* xs = reinterpret_cast<double2*>(smem);                       // [N]
+    double2* Ws = xs + N;                                                  // [rows][gcols]
+    double2* phs = Ws + kRowsPerBlock * gcols;                             // [n_f]
+    double* Fs = reinterpret_cast<double*>(phs + m.n_f);                  // [rows][nV]
+    double* Gs = Fs + kRowsPerBlock * nV;                                  // [nmp][gcols]
+    double* rps = Gs + nmp * gcols;                                        // [kRpow]
+    double* pbs = rps + kRpow;                                             // [kMaxPb]
+    int2* gis = reinterpret_cast<int2*>(pbs + kMaxPb);                     // [gcols]
+
+    // phase 0
+    const int k = a.pt.kidx[jp];
+    const double2* row = T.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
+    const int* cl = T.col_lam + m.col_off[lp];
+    const int totF = nrows * nV;
+    double2 tv[kFBatch];
+    int lv[kFBatch];
+#pragma unroll
+    for (int i = 0; i < kFBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < totF) {
+            tv[i] = row[idx];
+            lv[i] = cl[idx % nV];
+        }
+    }
+    const double2* u = a.u_in + (size_t)j * a.n_pad;
+    double2 uv[kXBatch];
+    int sv[kXBatch];
+#pragma unroll
+    for (int i = 0; i < kXBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < N) {
+            uv[i] = u[idx];
+            sv[i] = T.st_rad[idx];
+        }
+    }
+    const double* gc = T.gcoef + m.g_off[lp];
+    const int* gp = T.gpb + m.g_off[lp];
+    const int totG = nmp * gcols;
+    double gcv[kGBatch];
+    int gpv[kGBatch];
+#pragma unroll
+    for (int i = 0; i < kGBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < totG) {
+            gcv[i] = gc[idx];
+            gpv[i] = gp[idx];
+        }
+    }
+    // output-side values, prefetched by the thread that writes output o
+    const int n_out = nrows * nmp;
+    int S = 1;
+    while (S < 64 && n_out * S * 2 <= B) S *= 2;
+    const int o = tid / S, s = tid - o * S;
+    const bool writer = (o < n_out) && (s == 0);
+    const double v = T.vvec[j];
+    size_t oi = 0;
+    int rad_o = 0;
+    double2 x0 = make_double2(0.0, 0.0), xa = make_double2(0.0, 0.0);
+    if (writer) {
+        const int r = o / nmp, qp = o - r * nmp;
+        oi = (size_t)j * a.n_pad + m.state_off[lp] + qp * nlp + row0 + r;
+        rad_o = m.rad_off[lp] + row0 + r;
+        if (a.stage < 4) x0 = a.X[oi];
+        if (a.stage > 1) xa = a.Xacc[oi];
+    }
+    for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
+    if (tid < 2 * (m.lam_max + 1)) rps[tid] = a.pt.rpow[jp * kRpow + tid];
+    for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
+    for (int i = tid; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
+    __syncthreads();
+
+    // phase 1
+#pragma unroll
+    for (int i = 0; i < kXBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < N) {
+            const double2 ph = phs[sv[i]], x = uv[i];
+            xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+        }
+    }
+    for (int idx = tid + kXBatch * B; idx < N; idx += B) {
+        const double2 ph = phs[T.st_rad[idx]], x = u[idx];
+        xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+    }
+#pragma unroll
+    for (int i = 0; i < kFBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < totF) Fs[idx] = tv[i].x * rps[2 * lv[i]] + tv[i].y * rps[2 * lv[i] + 1];
+    }
+    for (int idx = tid + kFBatch * B; idx < totF; idx += B) {
+        const double2 t0 = row[idx];
+        const int l0 = cl[idx % nV];
+        Fs[idx] = t0.x * rps[2 * l0] + t0.y * rps[2 * l0 + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < kGBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < totG) Gs[idx] = gpv[i] >= 0 ? gcv[i] * pbs[gpv[i]] : 0.0;
+    }
+    for (int idx = tid + kGBatch * B; idx < totG; idx += B) {
+        const int p = gp[idx];
+        Gs[idx] = p >= 0 ? gc[idx] * pbs[p] : 0.0;
+    }
+    __syncthreads();
+
+    // phase 2
+    {
+        for (int idx = tid; idx < nrows * gcols; idx += B) {
+            const int r = idx / gcols, g = idx - r * gcols;
+            const int2 info = gis[g];
+            const int e0 = info.x & 0xffff, nl = info.x >> 16;
+            const double* f = Fs + r * nV + e0;
+            const double2* x = xs + info.y;
+            double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+            int n = 0;
+            for (; n + 7 < nl; n += 8) {
+                const double f0 = f[n], f1 = f[n + 1], f2 = f[n + 2], f3 = f[n + 3];
+                const double f4 = f[n + 4], f5 = f[n + 5], f6 = f[n + 6], f7 = f[n + 7];
+                const double2 y0 = x[n], y1 = x[n + 1], y2 = x[n + 2], y3 = x[n + 3];
+                const double2 y4 = x[n + 4], y5 = x[n + 5], y6 = x[n + 6], y7 = x[n + 7];
+                re0 += f0 * y0.x + f1 * y1.x + f2 * y2.x + f3 * y3.x;
+                im0 += f0 * y0.y + f1 * y1.y + f2 * y2.y + f3 * y3.y;
+                re1 += f4 * y4.x + f5 * y5.x + f6 * y6.x + f7 * y7.x;
+                im1 += f4 * y4.y + f5 * y5.y + f6 * y6.y + f7 * y7.y;
+            }
+            for (; n < nl; ++n) {
+                re0 += f[n] * x[n].x;
+                im0 += f[n] * x[n].y;
+            }
+            Ws[idx] = make_double2(re0 + re1, im0 + im1);
+        }
+    }
+    __syncthreads();
+
+    // phase 3: outputs o = (r, q'), S lanes per output (S a power of two dividing 64)
+    double re = 0.0, im = 0.0;
+    if (o < n_out) {
+        const int r = o / nmp, qp = o - r * nmp;
+        const double* g = Gs + qp * gcols;
+        const double2* w = Ws + r * gcols;
+        double re1 = 0.0, im1 = 0.0;
+        int c = s;
+        for (; c + S < gcols; c += 2 * S) {
+            const double g0 = g[c], g1 = g[c + S];
+            const double2 w0 = w[c], w1 = w[c + S];
+            re += g0 * w0.x;
+            im += g0 * w0.y;
+            re1 += g1 * w1.x;
+            im1 += g1 * w1.y;
+        }
+        if (c < gcols) {
+            re += g[c] * w[c].x;
+            im += g[c] * w[c].y;
+        }
+        re += re1;
+        im += im1;
+    }
+    for (int off = S >> 1; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+    }
+    if (writer) {
+        const double2 py = cmul(phs[rad_o], make_double2(re, im));
+        const double sc = a.Zp / v;
+        const double2 K = make_double2(sc * py.y, -sc * py.x);  // -(i/v) Zp ph y
+        const double h = a.h;
+        if (a.stage == 1) {
+            a.u_out[oi] = make_double2(x0.x + 0.5 * h * K.x, x0.y + 0.5 * h * K.y);
+            a.Xacc[oi] = make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
+        } else if (a.stage == 2 || a.stage == 3) {
+            const double c = (a.stage == 2) ? 0.5 * h : h;
+            a.u_out[oi] = make_double2(x0.x + c * K.x, x0.y + c * K.y);
+            a.Xacc[oi] = make_double2(xa.x + h / 3.0 * K.x, xa.y + h / 3.0 * K.y);
+        } else {
+            const double2 xn = make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
+            if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
+            a.X[oi] = xn;
+        }
+    }
+}
+
+// grid: x = (l', row chunk) pairs in l' order, y = path.
+__global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
+    extern __shared__ double2 smem2[];
+    const Meta& m = a.meta;
+    const int j = a.traj0 + blockIdx.y;
+    int c = blockIdx.x, lp = 0;
+    for (; lp < m.l_max; ++lp) {
+        const int nc = (m.n_l[lp] + kRowsPerBlock - 1) / kRowsPerBlock;
+        if (c < nc) break;
+        c -= nc;
+    }
+    const int row0 = c * kRowsPerBlock;
+    const int nrows = min(kRowsPerBlock, m.n_l[lp] - row0);
+    if (nrows <= 0) return;
+    stage_body(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+}
+
+// Diagnostic path: Frow, G and phases of one (path, z) into scratch arrays.
+// grid: x = [nbF Frow blocks | nbP phase blocks | G blocks].
+__global__ __launch_bounds__(256) void k_slot_setup(SetupArgs a) {
+    const Meta& m = a.meta;
+    const Tables& T = a.tb;
+    const double z = a.z;
+    const double b = T.bvec[a.j], v = T.vvec[a.j];
+    const double R = sqrt(b * b + z * z);
+    const int bx = blockIdx.x;
+    if (bx < a.nbF) {
+        const int d = bx * blockDim.x + threadIdx.x;
+        if (d >= m.n_frow) return;
+        int lp = 0;
+        while (lp < m.l_max && d >= m.frow_off[lp + 1]) ++lp;
+        const int e = (d - m.frow_off[lp]) % m.nV[lp];
+        const int k = grid_index(R, m.r_max, m.n_r);
+        a.Frow[d] = radial_at(T.tab[(size_t)k * m.n_frow + d], R, T.col_lam[m.col_off[lp] + e]);
+        return;
+    }
+    if (bx < a.nbF + a.nbP) {
+        const int i = (bx - a.nbF) * blockDim.x + threadIdx.x;
+        if (i < m.n_states) a.PH[i] = phase(T.eps[i], z, v);
+        return;
+    }
+    __shared__ double pb[kMaxPb];
+    if ((int)threadIdx.x <= m.lam_max) legendre_column(m.lam_max, threadIdx.x, z / R, pb);
+    __syncthreads();
+    const int i = (bx - a.nbF - a.nbP) * blockDim.x + threadIdx.x;
+    if (i < m.n_g) {
+        const int p = T.gpb[i];
+        a.G[i] = p >= 0 ? T.gcoef[i] * pb[p] : 0.0;
+    }
+}
+
+// Dense D_T (Eq. D1) with phases: H[row][col] = Zp ph_row conj(ph_col) sum_lambda G F.
+__global__ void k_couplings_dense(Meta m, const double* __restrict__ Frow, const double* __restrict__ G,
+                                  const double2* __restrict__ PH, double Zp, double2* __restrict__ H) {
+    const int N = m.n_states;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (col >= N) return;
+    int lp = 0, l = 0;
+    while (lp < m.l_max && row >= m.state_off[lp + 1]) ++lp;
+    while (l < m.l_max && col >= m.state_off[l + 1]) ++l;
+    const int rp = row - m.state_off[lp], rc = col - m.state_off[l];
+    const int qp = rp / m.n_l[lp], np = rp - qp * m.n_l[lp];
+    const int q = rc / m.n_l[l], n = rc - q * m.n_l[l];
+    int e0 = 0, g0 = 0;
+    for (int ll = 0; ll < l; ++ll) {
+        const int nlam = min(ll, lp) + 1;
+        e0 += nlam * m.n_l[ll];
+        g0 += nlam * (2 * ll + 1);
+    }
+    const double* Fr = Frow + m.frow_off[lp] + (size_t)np * m.nV[lp];
+    const double* Gr = G + m.g_off[lp] + (size_t)qp * m.gcols[lp];
+    double acc = 0.0;
+    for (int lam = abs(l - lp); lam <= l + lp; lam += 2) {
+        acc += Gr[g0 + q] * Fr[e0 + n];
+        e0 += m.n_l[l];
+        g0 += 2 * l + 1;
+    }
+    const double2 pr = PH[row], pc = PH[col];
+    const double2 w = make_double2(pr.x * pc.x + pr.y * pc.y, pr.y * pc.x - pr.x * pc.y);  // pr conj(pc)
+    H[(size_t)row * N + col] = make_double2(Zp * acc * w.x, Zp * acc * w.y);
+}
+
+__global__ void k_probabilities(const double2* __restrict__ X, int n_states, int n_pad,
+                                double* __restrict__ P, double* __restrict__ norm) {
+    const int j = blockIdx.x;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_states; i += blockDim.x) {
+        const double2 x = X[(size_t)j * n_pad + i];
+        const double p = x.x * x.x + x.y * x.y;
+        if (P) P[(size_t)j * n_pad + i] = p;
+        s += p;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && norm) norm[j] = red[0];
+}
+
+}  // namespace
+
+int stage_smem_bytes(const Meta& m) {
+    int best = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) {
+        const size_t nmp = 2 * lp + 1;
+        const size_t bytes = m.n_states * sizeof(double2) + (size_t)kRowsPerBlock * m.gcols[lp] * sizeof(double2) +
+                             (size_t)m.n_f * sizeof(double2) + (size_t)kRowsPerBlock * m.nV[lp] * sizeof(double) +
+                             nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
+                             (size_t)m.gcols[lp] * sizeof(int2);
+        if ((int)bytes > best) best = (int)bytes;
+    }
+    return best;
+}
+
+hipError_t stage_set_smem_limit(int, int bytes) {
+    return hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da, const int* db,
+                          const int* dl, int n_r, int n_f, int n_frow, double2* tab, hipStream_t st) {
+    const int nb = (n_frow + 127) / 128;
+    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(128), 0, st, r, w, phiT, da, db, dl, n_r, n_f, n_frow, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st) {
+    hipLaunchKernelGGL(k_prologue, dim3(a.n, n_traj_launch), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_setup(const SetupArgs& a, hipStream_t st) {
+    const int nbG = (a.meta.n_g + 255) / 256;
+    hipLaunchKernelGGL(k_slot_setup, dim3(a.nbF + a.nbP + nbG), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& a, int n_traj_launch, int smem, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage, dim3(a.meta.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_couplings_dense(const Meta& m, const double* Frow, const double* G, const double2* PH,
+                                  double Zp, double2* H, hipStream_t st) {
+    hipLaunchKernelGGL(k_couplings_dense, dim3((m.n_states + 127) / 128, m.n_states), dim3(128), 0, st, m, Frow,
+                       G, PH, Zp, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P, double* norm,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_probabilities, dim3(n_traj), dim3(256), 0, st, X, n_states, n_pad, P, norm);
+    return hipGetLastError();
+}
+
+}  // namespace wpccc

@@ -1,0 +1,134 @@
+// Plan layout and kernel launchers of the one-centre path (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "wpccc_impl.h"
+
+namespace wpccc {
+
+constexpr int kMaxL = 10;            // largest l of a basis
+constexpr int kMaxLam = 2 * kMaxL;   // largest multipole order
+constexpr int kMaxPb = (kMaxLam + 1) * (kMaxLam + 2) / 2;
+constexpr int kSlots = 3;            // couplings kept for the diagnostic entry point
+constexpr int kStageThreads = 256;
+constexpr int kRowsPerBlock = 8;     // output rows n' per stage workgroup
+
+// Per-basis sizes passed to kernels by value.
+//
+// Row layout ("Frow") of the radial integrals of one output l': the matrix
+// F_l'[n'][e], n' < N_l', e < nV[l'], whose columns run over the blocks
+// (l, lambda) in the order l = 0..l_max, lambda = |l-l'|..l+l' step 2, each
+// block holding N_l columns (the radial index n of the input state):
+//   F_l'[n'][e0(l, lambda) + n] = F_{(l' n'), (l n), lambda}(R)     (Eq. D2)
+// The moment tables use the same layout per grid node k.
+// Angular factors ("G") of one output l': the matrix G_l'[q'][g], q' = m'+l',
+// g < gcols[l'], over the same blocks with 2l+1 columns (q = m+l) each:
+//   G_l'[q'][g0(l, lambda) + q] = c(l'm', lm, lambda) Pbar_lambda^|m'-m|(cos Theta).
+struct Meta {
+    int l_max, lam_max, n_r, n_f, n_states, n_frow, n_g, n_chunks, n_cols, n_gcols;
+    double r_max;
+    int n_l[kMaxL + 1];
+    int state_off[kMaxL + 1];
+    int rad_off[kMaxL + 1];   // first radial index of each l
+    int nV[kMaxL + 1];        // columns of F_l'
+    int frow_off[kMaxL + 1];  // offset of F_l' in a Frow array / table row
+    int col_off[kMaxL + 1];   // offset of l' in col_lam
+    int gcols[kMaxL + 1];     // columns of G_l'
+    int g_off[kMaxL + 1];     // offset of G_l' in a G array
+    int gcol_off[kMaxL + 1];  // offset of l' in gcol_info
+};
+
+__host__ __device__ inline int pb_index(int lam, int mu) { return lam * (lam + 1) / 2 + mu; }
+
+// G column info: x = e0 | (N_l << 16) (F column block start, block width),
+// y = state offset of x'_{l, q, 0} (the input states the column contracts with)
+__host__ __device__ inline int2 gcol_pack(int e0, int nl, int xoff) { return make_int2(e0 | (nl << 16), xoff); }
+
+// Basis tables shared by every launch of a plan.
+struct Tables {
+    const double2* tab;     // [n_r+1][n_frow]: (A_k, B_(k+1)) per Frow entry
+    const int* col_lam;     // [n_cols] lambda of each Frow column, per l'
+    const int2* gcol_info;  // [n_gcols] gcol_pack of each G column, per l'
+    const double* gcoef;    // [n_g] c(l'm', lm, lambda), (-1)^mu folded in for mu < 0
+    const int* gpb;         // [n_g] pb_index(lambda, |mu|) or -1
+    const double* eps;      // [N] state energies
+    const int* st_rad;      // [N] radial index of each state
+    const double* rad_eps;  // [n_f] energy of each radial function
+    const double* bvec;     // [n_traj]
+    const double* vvec;     // [n_traj]
+};
+
+// Per (path, z-point) quantities shared by every workgroup of a stage,
+// computed once by k_prologue for all points of a propagation chunk:
+//   kidx[j][p]                grid node of R (last r_k <= R)
+//   rpow[j][p][2 lam]         R^-(lam+1) at 2 lam, R^lam at 2 lam + 1
+//   pbar[j][p][n_pb]          Pbar_lam^mu(cos Theta)
+//   ph[j][p][n_f]             exp(i eps_f z / v) per radial function
+struct PointArrays {
+    int* kidx;
+    double* rpow;
+    double* pbar;
+    double2* ph;
+    int n_pts;      // capacity in points per path
+};
+
+constexpr int kRpow = 2 * (kMaxLam + 1);
+
+struct StageArgs {
+    Meta meta;
+    Tables tb;
+    PointArrays pt;
+    double Zp;
+    int p;                // z-point of this stage's couplings in pt
+    double h;
+    int n_pad;
+    int stage;            // 1..4
+    int traj0;
+    const double2* u_in;  // stage input   [n_traj][n_pad]
+    double2* X;           // amplitudes    [n_traj][n_pad]
+    double2* Xacc;        // accumulator   [n_traj][n_pad]
+    double2* u_out;       // next input    [n_traj][n_pad]
+    int* flag;            // non-finite latch
+};
+
+struct SetupArgs {
+    Meta meta;
+    Tables tb;
+    double z;
+    int j;                // path
+    double* Frow;         // [n_frow]
+    double* G;            // [n_g]
+    double2* PH;          // [N]
+    int nbF, nbP;         // block ranges: Frow entries, phases, then G
+};
+
+constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
+constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
+
+struct PrologueArgs {
+    Meta meta;
+    Tables tb;
+    PointArrays pt;
+    double z[kChunkPoints];  // z of each point of the chunk
+    int n;                   // points in this launch
+    int traj0;
+};
+
+// launchers (kernels_1c.hip)
+hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st);
+hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da,
+                          const int* db, const int* dl, int n_r, int n_f, int n_frow, double2* tab,
+                          hipStream_t st);
+hipError_t launch_slot_setup(const SetupArgs& a, hipStream_t st);
+hipError_t launch_stage(const StageArgs& a, int n_traj_launch, int smem, hipStream_t st);
+hipError_t launch_couplings_dense(const Meta& m, const double* Frow, const double* G, const double2* PH,
+                                  double Zp, double2* H, hipStream_t st);
+hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
+                                double* norm, hipStream_t st);
+hipError_t stage_set_smem_limit(int l_max, int bytes);
+int stage_smem_bytes(const Meta& m);
+
+}  // namespace wpccc
