@@ -171,6 +171,23 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
 int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
                     void* X_dev, void* P_dev, void* norm_dev, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: per-kernel device time with HIP events.                      */
+/* ------------------------------------------------------------------------ */
+
+/* enable != 0: from now on every kernel launch of this plan is bracketed by a
+ * pair of HIP events recorded on the launch stream (adds a small gap between
+ * launches); enable == 0 stops recording and drops collected records. */
+int wpccc_plan_timing(wpccc_plan_t plan, int enable);
+
+/* Synchronises the recorded events and returns the summed device time (ms)
+ * and the number of launches of `kernel` ("k_stage", "k_slot_setup",
+ * "k_couplings_dense", "k_probabilities", "k_moments") recorded since timing
+ * was enabled or last read; the records are then cleared.
+ * Errors: WPCCC_EINVAL (unknown kernel name). */
+int wpccc_plan_kernel_time(wpccc_plan_t plan, const char* kernel, double* total_ms,
+                           long long* launches);
+
 #ifdef __cplusplus
 }
 #endif
