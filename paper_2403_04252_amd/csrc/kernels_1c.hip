@@ -116,7 +116,7 @@ __device__ inline double2 phase(double eps, double z, double v) {
 // Per (path, z-point): grid node of R, powers of R, Pbar table and phases per
 // radial function.  grid: x = point, y = path; one wave per block.
 __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
-    const Meta& m = a.meta;
+    const Meta& m = *a.meta;
     const int j = a.traj0 + blockIdx.y;
     const int p = blockIdx.x;
     const double z = a.z[p];
@@ -147,7 +147,7 @@ constexpr int kGBatch = 4;   // angular coefficients per thread held in register
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
 __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
-    const Meta& m = a.meta;
+    const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
     const int nmp = 2 * lp + 1;
@@ -342,7 +342,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
 // grid: x = (l', row chunk) pairs in l' order, y = path.
 __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
-    const Meta& m = a.meta;
+    const Meta& m = *a.meta;
     const int j = a.traj0 + blockIdx.y;
     int c = blockIdx.x, lp = 0;
     for (; lp < m.l_max; ++lp) {
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
 // Diagnostic path: Frow, G and phases of one (path, z) into scratch arrays.
 // grid: x = [nbF Frow blocks | nbP phase blocks | G blocks].
 __global__ __launch_bounds__(256) void k_slot_setup(SetupArgs a) {
-    const Meta& m = a.meta;
+    const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const double z = a.z;
     const double b = T.bvec[a.j], v = T.vvec[a.j];
@@ -391,8 +391,10 @@ __global__ __launch_bounds__(256) void k_slot_setup(SetupArgs a) {
 }
 
 // Dense D_T (Eq. D1) with phases: H[row][col] = Zp ph_row conj(ph_col) sum_lambda G F.
-__global__ void k_couplings_dense(Meta m, const double* __restrict__ Frow, const double* __restrict__ G,
-                                  const double2* __restrict__ PH, double Zp, double2* __restrict__ H) {
+__global__ void k_couplings_dense(const Meta* __restrict__ mp_, const double* __restrict__ Frow,
+                                  const double* __restrict__ G, const double2* __restrict__ PH, double Zp,
+                                  double2* __restrict__ H) {
+    const Meta& m = *mp_;
     const int N = m.n_states;
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
@@ -473,20 +475,20 @@ hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_slot_setup(const SetupArgs& a, hipStream_t st) {
-    const int nbG = (a.meta.n_g + 255) / 256;
+hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st) {
+    const int nbG = (hm.n_g + 255) / 256;
     hipLaunchKernelGGL(k_slot_setup, dim3(a.nbF + a.nbP + nbG), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_stage(const StageArgs& a, int n_traj_launch, int smem, hipStream_t st) {
-    hipLaunchKernelGGL(k_stage, dim3(a.meta.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_couplings_dense(const Meta& m, const double* Frow, const double* G, const double2* PH,
-                                  double Zp, double2* H, hipStream_t st) {
-    hipLaunchKernelGGL(k_couplings_dense, dim3((m.n_states + 127) / 128, m.n_states), dim3(128), 0, st, m, Frow,
+hipError_t launch_couplings_dense(const Meta* m, const Meta& hm, const double* Frow, const double* G,
+                                  const double2* PH, double Zp, double2* H, hipStream_t st) {
+    hipLaunchKernelGGL(k_couplings_dense, dim3((hm.n_states + 127) / 128, hm.n_states), dim3(128), 0, st, m, Frow,
                        G, PH, Zp, H);
     return hipGetLastError();
 }

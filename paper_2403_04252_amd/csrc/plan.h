@@ -78,7 +78,7 @@ struct PointArrays {
 constexpr int kRpow = 2 * (kMaxLam + 1);
 
 struct StageArgs {
-    Meta meta;
+    const Meta* meta;     // device copy (indexed per lane: kept out of kernel arguments)
     Tables tb;
     PointArrays pt;
     double Zp;
@@ -95,7 +95,7 @@ struct StageArgs {
 };
 
 struct SetupArgs {
-    Meta meta;
+    const Meta* meta;
     Tables tb;
     double z;
     int j;                // path
@@ -109,7 +109,7 @@ constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
 constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
 
 struct PrologueArgs {
-    Meta meta;
+    const Meta* meta;
     Tables tb;
     PointArrays pt;
     double z[kChunkPoints];  // z of each point of the chunk
@@ -122,10 +122,10 @@ hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t
 hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da,
                           const int* db, const int* dl, int n_r, int n_f, int n_frow, double2* tab,
                           hipStream_t st);
-hipError_t launch_slot_setup(const SetupArgs& a, hipStream_t st);
-hipError_t launch_stage(const StageArgs& a, int n_traj_launch, int smem, hipStream_t st);
-hipError_t launch_couplings_dense(const Meta& m, const double* Frow, const double* G, const double2* PH,
-                                  double Zp, double2* H, hipStream_t st);
+hipError_t launch_slot_setup(const SetupArgs& a, const Meta& host_meta, hipStream_t st);
+hipError_t launch_stage(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st);
+hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const double* Frow, const double* G,
+                                  const double2* PH, double Zp, double2* H, hipStream_t st);
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
                                 double* norm, hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);

@@ -34,6 +34,7 @@ using namespace wpccc;
 
 struct wpccc_plan_s {
     Meta meta{};
+    Meta* d_meta = nullptr;  // device copy of meta
     int n_traj = 0, n_pad = 0, batched = 1;
     double Zp = 1.0;
     std::vector<double> b, v;
@@ -102,6 +103,7 @@ int dev_alloc(T** p, size_t count, long long& total) {
 
 void free_plan(wpccc_plan_s* p) {
     if (!p) return;
+    if (p->d_meta) (void)hipFree(p->d_meta);
     void* bufs[] = {p->d_eps, p->d_b,    p->d_v,   p->d_gcoef, p->d_col_lam, p->d_gcol, p->d_gpb,
                     p->d_flag, p->d_tab, p->d_Frow1, p->d_G1,  p->d_PH1,     p->d_Ua,   p->d_Ub,
                     p->d_Xacc, p->d_st_rad, p->d_kidx, p->d_rad_eps, p->d_rpow, p->d_pbar, p->d_ph};
@@ -170,7 +172,7 @@ void block_columns(const Meta& m, int lp, int l, int lam, int& e0, int& g0) {
 // Per-point quantities for z[0..n) of paths [j0, j0+nj) into point slots 0..n-1.
 int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hipStream_t st) {
     PrologueArgs a;
-    a.meta = p->meta;
+    a.meta = p->d_meta;
     a.tb = p->tables();
     a.pt = p->points();
     for (int i = 0; i < n; ++i) a.z[i] = z[i];
@@ -185,7 +187,7 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
 int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double h, const double2* u_in,
                   double2* X, double2* u_out, hipStream_t st) {
     StageArgs a;
-    a.meta = p->meta;
+    a.meta = p->d_meta;
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -200,7 +202,7 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.u_out = u_out;
     a.flag = p->d_flag;
     time_mark(p, kStage, st, true);
-    hipError_t e = launch_stage(a, nj, p->stage_smem, st);
+    hipError_t e = launch_stage(a, p->meta, nj, p->stage_smem, st);
     time_mark(p, kStage, st, false);
     return launched(e, "k_stage");
 }
@@ -446,6 +448,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     }
 
     long long& tot = plan->bytes;
+    TRY(dev_alloc(&plan->d_meta, 1, tot));
     TRY(dev_alloc(&plan->d_eps, (size_t)N, tot));
     TRY(dev_alloc(&plan->d_b, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_v, (size_t)n_traj, tot));
@@ -501,6 +504,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     up(plan->d_gcol, gcol.data(), gcol.size() * sizeof(int2));
     up(plan->d_gcoef, gcoef.data(), gcoef.size() * sizeof(double));
     up(plan->d_gpb, gpb.data(), gpb.size() * sizeof(int));
+    up(plan->d_meta, &plan->meta, sizeof(Meta));
     up(plan->d_eps, hb.eps.data(), (size_t)N * sizeof(double));
     up(plan->d_st_rad, hb.st_i.data(), (size_t)N * sizeof(int));
     up(plan->d_rad_eps, hb.rad_eps.data(), (size_t)m.n_f * sizeof(double));
@@ -573,7 +577,7 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
     hipStream_t st = (hipStream_t)stream;
     const Meta& m = plan->meta;
     SetupArgs a;
-    a.meta = m;
+    a.meta = plan->d_meta;
     a.tb = plan->tables();
     a.z = z;
     a.j = j;
@@ -583,12 +587,12 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
     a.nbF = (m.n_frow + 255) / 256;
     a.nbP = (m.n_states + 255) / 256;
     time_mark(plan, kSetup, st, true);
-    hipError_t e = launch_slot_setup(a, st);
+    hipError_t e = launch_slot_setup(a, m, st);
     time_mark(plan, kSetup, st, false);
     int rc = launched(e, "k_slot_setup");
     if (rc) return rc;
     time_mark(plan, kDense, st, true);
-    e = launch_couplings_dense(m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp, (double2*)H_dev, st);
+    e = launch_couplings_dense(plan->d_meta, m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp, (double2*)H_dev, st);
     time_mark(plan, kDense, st, false);
     return launched(e, "k_couplings_dense");
 }

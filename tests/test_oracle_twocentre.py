@@ -1,0 +1,167 @@
+"""Pins of the oracle's two-centre couplings (no GPU).
+
+* closed forms at v = 0: the 1s-1s overlap e^{-R}(1 + R + R^2/3) and the
+  transfer integral <1s_T| -1/r_T |1s_P> = -(1 + R) e^{-R};
+* a lab-frame quadrature of phi_T^* exp(i v.r_c) phi_P (and with -Z_T/r_T)
+  over the same spheroidal nodes but with an explicit trapezoidal rule in the
+  azimuth, lab-frame spherical harmonics from scipy and the lab geometry of
+  each point: it uses none of the Wigner rotation, the Bessel-function phi
+  integral, the i^(q-q') factor or the Eq. K2 prefactor, so it pins all the
+  frame conventions of Eq. K1/K2;
+* Gauss-Laguerre weights against their defining moments.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import roots_laguerre, sph_harm_y
+
+from oracle.propagate import initial_state, rk4_propagate
+from oracle.radial import BasisSpec, build_basis
+from oracle.twocentre import (Q_DAGGER, Q_PRIOR, interpolate_radial, lab_matrix,
+                              laguerre_scaled_weights, m_two_centre, spheroidal_quadrature,
+                              two_centre_matrices)
+
+
+@pytest.fixture(scope="module")
+def bound2():
+    """Bound hydrogen states n <= 2 (1s, 2s, 2p) on a fine grid, both centres."""
+    return build_basis(BasisSpec(n_max=2, l_max=1, n_bins=0, k_max=1.0, n_r=3000, r_max=60.0))
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    """n <= 3 bound + 1 bin per l, l <= 2: covers l up to 2 and every m."""
+    return build_basis(BasisSpec(n_max=3, l_max=2, n_bins=1, k_max=1.0, n_r=1200, r_max=60.0))
+
+
+def test_laguerre_scaled_weights_moments():
+    x, W = laguerre_scaled_weights(40)
+    for k in range(0, 12):
+        # int_0^inf x^k e^{-x} dx = k!
+        val = np.sum(W * np.exp(-x) * x ** k)
+        assert abs(val - math.factorial(k)) < 1e-11 * math.factorial(k)
+    xr, wr = roots_laguerre(40)
+    assert np.allclose(W * np.exp(-x), wr, rtol=1e-11, atol=0)
+
+
+def test_laguerre_scaled_weights_large_n_finite():
+    x, W = laguerre_scaled_weights(256)
+    assert np.all(np.isfinite(W)) and np.all(W > 0)
+    # the integral of e^{-x} (weight function times 1) with the scaled weights
+    assert abs(np.sum(W * np.exp(-x)) - 1.0) < 1e-11
+
+
+def test_interpolation_reproduces_grid_and_smooth_function(bound2):
+    b = bound2
+    # at grid nodes the interpolant returns the node values
+    idx = np.array([3, 100, 1500, 2990])
+    assert np.allclose(interpolate_radial(b, b.r[idx]), b.phi[:, idx], rtol=0, atol=1e-14)
+    # off-grid: close to the closed form 1s function 2 exp(-r)
+    r = np.array([0.0123, 0.77, 3.3, 10.1])
+    f = interpolate_radial(b, r)[0]
+    assert np.abs(f - 2 * np.exp(-r)).max() < 1e-9
+    assert np.all(interpolate_radial(b, np.array([60.5, 100.0])) == 0.0)
+
+
+@pytest.mark.parametrize("R", [0.8, 2.0, 5.0])
+def test_overlap_and_transfer_closed_forms(bound2, R):
+    b = bound2
+    K = lab_matrix(b, b, R, 0.0, 0.0, 128, 128, "overlap")
+    Q = lab_matrix(b, b, R, 0.0, 0.0, 128, 128, "target", 1.0)
+    assert abs(K[0, 0] - math.exp(-R) * (1 + R + R * R / 3)) < 1e-8
+    assert abs(Q[0, 0] + (1 + R) * math.exp(-R)) < 1e-8
+    # arbitrary orientation (z != 0) at v = 0: the s-s overlap depends on R only
+    K2 = lab_matrix(b, b, R * 0.6, R * 0.8, 0.0, 128, 128, "overlap")
+    assert abs(K2[0, 0] - K[0, 0]) < 1e-9
+
+
+def _lab_quadrature(tb, pb, bb, z, v, n_eta, n_tau, n_phi, weight):
+    """phi_T^* exp(i v.r_c) [W] phi_P by direct summation on spheroidal nodes x phi."""
+    R = math.hypot(bb, z)
+    th = math.acos(z / R)
+    eta, tau, om = spheroidal_quadrature(n_eta, n_tau, R)
+    rA = R * (eta + tau) / 2
+    rB = R * (eta - tau) / 2
+    keep = np.maximum(rA, rB) <= 60.0 + 1e-9
+    eta, tau, om, rA, rB = eta[keep], tau[keep], om[keep], rA[keep], rB[keep]
+    cA = (1 + eta * tau) / (eta + tau)
+    rho = rA * np.sqrt(np.maximum(0.0, 1 - cA * cA))
+    zp = rA * cA
+    phi = np.arange(n_phi) * (2 * np.pi / n_phi)
+    # molecular-frame point (origin at the target) -> lab by a rotation of th about y
+    X = rho[:, None] * np.cos(phi)[None, :]
+    Y = rho[:, None] * np.sin(phi)[None, :]
+    Z = np.broadcast_to(zp[:, None], X.shape)
+    xl = math.cos(th) * X + math.sin(th) * Z
+    yl = Y
+    zl = -math.sin(th) * X + math.cos(th) * Z
+    Rv = np.array([bb, 0.0, z])
+    rT = np.sqrt(xl ** 2 + yl ** 2 + zl ** 2)
+    xp, yp, zpp = xl - Rv[0], yl - Rv[1], zl - Rv[2]
+    rP = np.sqrt(xp ** 2 + yp ** 2 + zpp ** 2)
+    assert np.allclose(rT, rA[:, None], atol=1e-9) and np.allclose(rP, rB[:, None], atol=1e-9)
+    thT, phT = np.arccos(np.clip(zl / rT, -1, 1)), np.arctan2(yl, xl)
+    thP, phP = np.arccos(np.clip(zpp / rP, -1, 1)), np.arctan2(yp, xp)
+    trans = np.exp(1j * v * (zl - z / 2))
+    jac = (R / 2) ** 3 * (eta * eta - tau * tau) * om * (2 * np.pi / n_phi)
+    if weight == "target":
+        wgt = -1.0 / rT
+    else:
+        wgt = 1.0
+    fA = interpolate_radial(tb, rA)
+    fB = interpolate_radial(pb, rB)
+    out = np.zeros((tb.n_states, pb.n_states), dtype=np.complex128)
+    ylm_T = {}
+    ylm_P = {}
+    for i in range(tb.n_states):
+        l, m, a = tb.st_l[i], tb.st_m[i], tb.st_a[i]
+        if (l, m) not in ylm_T:
+            ylm_T[(l, m)] = np.conj(sph_harm_y(l, m, thT, phT))
+        left = fA[a][:, None] * ylm_T[(l, m)] * trans * wgt * jac[:, None]
+        for j in range(pb.n_states):
+            lb, mb, bidx = pb.st_l[j], pb.st_m[j], pb.st_a[j]
+            if (lb, mb) not in ylm_P:
+                ylm_P[(lb, mb)] = sph_harm_y(lb, mb, thP, phP)
+            out[i, j] = np.sum(left * (fB[bidx][:, None] * ylm_P[(lb, mb)]))
+    return out
+
+
+@pytest.mark.parametrize("bb,z,v", [(1.3, 0.7, 1.0), (0.6, -1.9, 2.0), (2.5, 0.0, 0.5)])
+def test_k1_k2_conventions_against_lab_frame(mixed, bb, z, v):
+    nE, nT = 40, 48
+    for weight in ("overlap", "target"):
+        ref = _lab_quadrature(mixed, mixed, bb, z, v, nE, nT, 96, weight)
+        got = lab_matrix(mixed, mixed, bb, z, v, nE, nT, weight, 1.0)
+        # the lab quadrature drops nodes beyond r_max where both vanish; the
+        # azimuthal rule is spectrally accurate for these smooth integrands
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-9 * scale, (weight, np.abs(got - ref).max(), scale)
+
+
+def test_overlap_block_structure(bound2):
+    b = bound2
+    S, H = two_centre_matrices(b, b, 1.1, 0.4, 1.0, 48, 64)
+    n = b.n_states
+    assert np.abs(S - S.conj().T).max() < 1e-15
+    assert np.linalg.eigvalsh(S).min() > 0
+    # D_T, D_P blocks Hermitian; with Q^dagger the whole H is Hermitian
+    assert np.abs(H - H.conj().T).max() < 1e-14 * np.abs(H).max()
+    S2, H2 = two_centre_matrices(b, b, 1.1, 0.4, 1.0, 48, 64, q_lower=Q_PRIOR)
+    assert np.array_equal(S, S2) and np.array_equal(H[:n, :], H2[:n, :])
+    assert np.abs(H2[n:, :n] - H[n:, :n]).max() > 1e-6
+
+
+def test_two_centre_rk4_conserves_norm_approximately(bound2):
+    """With the prior form the 2C equations conserve X^dag S X for exact
+    eigenstates; on a bound-only basis the drift is small and falls with h."""
+    b = bound2
+    M = m_two_centre(b, b, 1.5, 1.0, 24, 32, q_lower=Q_PRIOR)
+    S0, _ = two_centre_matrices(b, b, 1.5, -6.0, 1.0, 24, 32, q_lower=Q_PRIOR)
+    zg = np.linspace(-6.0, 6.0, 61)
+    X0 = initial_state(2 * b.n_states)
+    X0 = X0 / np.sqrt((X0.conj() @ S0 @ X0).real)
+    X = rk4_propagate(M, X0, zg)
+    S1, _ = two_centre_matrices(b, b, 1.5, 6.0, 1.0, 24, 32, q_lower=Q_PRIOR)
+    nrm = (X.conj() @ S1 @ X).real
+    assert abs(nrm - 1.0) < 2e-2
