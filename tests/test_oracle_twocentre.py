@@ -18,7 +18,7 @@ from scipy.special import roots_laguerre, sph_harm_y
 
 from oracle.propagate import initial_state, rk4_propagate
 from oracle.radial import BasisSpec, build_basis
-from oracle.twocentre import (Q_DAGGER, Q_PRIOR, interpolate_radial, lab_matrix,
+from oracle.twocentre import (Q_DAGGER, Q_PRIOR, gauss_legendre, interpolate_radial, lab_matrix,
                               laguerre_scaled_weights, m_two_centre, spheroidal_quadrature,
                               two_centre_matrices)
 
@@ -50,6 +50,33 @@ def test_laguerre_scaled_weights_large_n_finite():
     assert np.all(np.isfinite(W)) and np.all(W > 0)
     # the integral of e^{-x} (weight function times 1) with the scaled weights
     assert abs(np.sum(W * np.exp(-x)) - 1.0) < 1e-11
+
+
+@pytest.mark.parametrize("n", [32, 512])
+def test_gauss_legendre_moments_and_extended_precision(n):
+    """tau rule of the spheroidal quadrature: exact for x^k, k <= 2n - 1
+    (int_-1^1 x^k = 2/(k+1) for even k, 0 for odd), and equal to the rule
+    recomputed by Newton's method in extended precision."""
+    x, w = gauss_legendre(n)
+    assert np.all(np.diff(x) > 0) and np.all(w > 0)
+    for k in [0, 1, 2, 7, 10, 100, 500, 1000]:
+        if k > 2 * n - 1:
+            continue
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** k) - exact) <= 1e-13 * max(exact, 1e-3), k
+    L = np.longdouble
+    t = np.cos(np.pi * (np.arange(n, dtype=L) + L(0.75)) / (L(n) + L(0.5)))
+    for _ in range(8):
+        p0, p1 = np.ones_like(t), t.copy()
+        for k in range(1, n):
+            p0, p1 = p1, ((2 * k + 1) * t * p1 - k * p0) / (k + 1)
+        t = t - p1 / (n * (t * p1 - p0) / (t * t - 1))
+    p0, p1 = np.ones_like(t), t.copy()
+    for k in range(1, n):
+        p0, p1 = p1, ((2 * k + 1) * t * p1 - k * p0) / (k + 1)
+    wl = (2 * (1 - t * t) / (n * n * p0 * p0))[::-1]
+    assert np.abs(x - t[::-1].astype(np.float64)).max() <= 2e-16
+    assert np.abs(w / wl.astype(np.float64) - 1.0).max() <= 1e-11
 
 
 def test_interpolation_reproduces_grid_and_smooth_function(bound2):
