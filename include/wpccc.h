@@ -114,13 +114,21 @@ int wpccc_basis_destroy(wpccc_basis_t basis);
 /* Plan: a batch of straight-line paths sharing one basis (1C).              */
 /* ------------------------------------------------------------------------ */
 
+/* lower-left block of H in the two-centre form */
+#define WPCCC_Q_DAGGER 0   /* Q^dagger, as printed in Eq. 1 */
+#define WPCCC_Q_PRIOR  1   /* <phi_P | -Z_P/r_P | phi_T>, the other side's potential */
+
 typedef struct {
-    double Zp;      /* projectile charge: the target electron sees -Zp/|r-R|
+    double Zp;      /* 1C: projectile charge, the target electron sees -Zp/|r-R|
                        (Eq. D1 is written for Zp = 1; Zp = -1 is the negatively
-                       charged projectile of Eq. NOINV).  0 means 1. */
+                       charged projectile of Eq. NOINV).  0 means 1.  In 2C the
+                       charges are the Z of the two bases. */
     int batched;    /* 1: all paths in each launch (default); 0: one path per
                        launch sequence, paths one after another */
-    int two_centre; /* must be 0 in this build (WPCCC_ENOTSUP otherwise) */
+    int two_centre; /* set by wpccc_plan_create_2c; must be 0 for wpccc_plan_create */
+    int q_lower;    /* 2C: WPCCC_Q_DAGGER (default) or WPCCC_Q_PRIOR */
+    int n_eta;      /* 2C: Gauss-Laguerre nodes in eta (0 means 256) */
+    int n_tau;      /* 2C: Gauss-Legendre nodes in tau (0 means 512) */
 } wpccc_plan_opts;
 
 /* Create a plan for n_traj paths with impact parameters b_host[j] > 0 and
@@ -133,22 +141,44 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host,
                       const double* v_host, const wpccc_plan_opts* opts,
                       void* stream, wpccc_plan_t* out);
 
-/* n_states: N of the basis; n_pad: row stride (in complex elements) of the
- * [n_traj][n_pad] amplitude arrays; device_bytes: device memory held. */
+/* Two-centre plan (Eq. 1 with capture): n_sets pairs (targets[s],
+ * projectiles[s]) of bases, path j expanded in pair set_of_traj[j] (bases of
+ * uneven size may share one batch).  Each path has N_j = N_T + N_P states,
+ * target states first, then projectile states, each in the canonical order.
+ * Couplings: D_T (Eq. D1, charge Z of the projectile basis), D_P (Eq. D1
+ * about the projectile, charge Z of the target basis), overlaps K and
+ * transfer couplings Q by the spheroidal quadrature of Eq. K2 on n_eta x
+ * n_tau nodes with the rotation of Eq. K1; M = -(i/v) S^{-1} H with S LU
+ * factorised (partial pivoting) on the device.  The bases must outlive the
+ * plan.  Errors: WPCCC_EINVAL, WPCCC_ENOMEM, WPCCC_EHIP. */
+int wpccc_plan_create_2c(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles,
+                         int n_sets, int n_traj, const int* set_of_traj, const double* b_host,
+                         const double* v_host, const wpccc_plan_opts* opts, void* stream,
+                         wpccc_plan_t* out);
+
+/* Size of path j's system: n_states = N_j, n_target = N_T of its set (equal
+ * to N_j in 1C). */
+int wpccc_plan_path_info(wpccc_plan_t plan, int j, int* n_states, int* n_target);
+
+/* n_states: largest N_j of the plan; n_pad: row stride (in complex elements)
+ * of the [n_traj][n_pad] amplitude arrays; device_bytes: device memory held. */
 int wpccc_plan_info(wpccc_plan_t plan, int* n_traj, int* n_states, int* n_pad,
                     long long* device_bytes);
 
 int wpccc_plan_destroy(wpccc_plan_t plan);
 
 /* Returns the first device-side error latched since the last call (after
- * synchronising `stream`), then clears it: WPCCC_OK or WPCCC_ENUMERIC. */
+ * synchronising `stream`), then clears it: WPCCC_OK, WPCCC_ENUMERIC or (2C)
+ * WPCCC_ESINGULAR with the path and pivot row in the message. */
 int wpccc_plan_status(wpccc_plan_t plan, void* stream);
 
-/* Couplings of path j at one z (Eq. D1/D2, with the interaction-picture
- * phases exp(i(eps_row - eps_col) z / v)):
- *   H_dev  complex [N][N] row-major, H[row*N + col] = D_T(b_j, z)
- *   S_dev  must be NULL in 1C.
- * Errors: WPCCC_EINVAL (j out of range, R = 0). */
+/* Couplings of path j at one z, with the interaction-picture phases
+ * exp(i(eps_row - eps_col) z / v):
+ *   H_dev  complex [N_j][N_j] row-major: 1C D_T(b_j, z) (Eq. D1/D2);
+ *          2C [[D_T, Q], [Q^dagger or prior, D_P]] (Eq. 1)
+ *   S_dev  2C: complex [N_j][N_j] row-major [[I, K], [K^dagger, I]];
+ *          must be NULL in 1C.
+ * Errors: WPCCC_EINVAL (j out of range, R = 0, S_dev NULL in 2C). */
 int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev,
                     void* stream);
 
@@ -165,9 +195,10 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
  * on `stream`):
  *   X_dev     complex [n_traj][n_pad], amplitudes at zgrid[n_points-1]
  *   P_dev     double  [n_traj][n_pad], P_i = |X_i|^2 (may be NULL)
- *   norm_dev  double  [n_traj], sum_i |X_i|^2 (X^dagger S X with S = I;
+ *   norm_dev  double  [n_traj], X^dagger S X at the last point (1C: S = I;
  *             may be NULL)
- * Errors: WPCCC_EINVAL (fewer than 2 points, non-increasing grid). */
+ * Errors: WPCCC_EINVAL (fewer than 2 points, non-increasing grid);
+ * WPCCC_ESINGULAR is latched (wpccc_plan_status) for an exact zero pivot. */
 int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
                     void* X_dev, void* P_dev, void* norm_dev, void* stream);
 

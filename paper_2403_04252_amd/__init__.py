@@ -16,7 +16,8 @@ import numpy as np
 __all__ = [
     "WpcccError", "BasisSpec", "load_library", "library_path",
     "wpccc_version", "wpccc_basis", "wpccc_basis_info", "wpccc_basis_export",
-    "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_info", "wpccc_plan_destroy",
+    "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_create_2c", "wpccc_plan_info",
+    "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time",
 ]
@@ -26,6 +27,8 @@ _LIB_PATH = os.path.join(_HERE, "libwpccc.so")
 _lib = None
 
 WPCCC_OK = 0
+WPCCC_Q_DAGGER = 0
+WPCCC_Q_PRIOR = 1
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
 
 
@@ -42,7 +45,8 @@ class _Spec(ctypes.Structure):
 
 
 class _PlanOpts(ctypes.Structure):
-    _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int)]
+    _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int),
+                ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int)]
 
 
 @dataclass
@@ -80,7 +84,10 @@ def load_library():
         "wpccc_basis_export": ([vp, pd, pd, pd, pd, pi], i),
         "wpccc_basis_destroy": ([vp], i),
         "wpccc_plan_create": ([vp, i, pd, pd, ctypes.POINTER(_PlanOpts), vp, ctypes.POINTER(vp)], i),
+        "wpccc_plan_create_2c": ([ctypes.POINTER(vp), ctypes.POINTER(vp), i, i, pi, pd, pd,
+                                  ctypes.POINTER(_PlanOpts), vp, ctypes.POINTER(vp)], i),
         "wpccc_plan_info": ([vp, pi, pi, pi, ctypes.POINTER(ctypes.c_longlong)], i),
+        "wpccc_plan_path_info": ([vp, i, pi, pi], i),
         "wpccc_plan_destroy": ([vp], i),
         "wpccc_plan_status": ([vp, vp], i),
         "wpccc_couplings": ([vp, i, d, vp, vp, vp], i),
@@ -195,7 +202,7 @@ def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
-    opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0)
+    opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -205,6 +212,38 @@ def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
     p = Plan(h, basis, nt.value, ns.value, npad.value)
     p.device_bytes = nb.value
     return p
+
+
+def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
+                         n_eta: int = 0, n_tau: int = 0, batched: bool = True, stream=None) -> Plan:
+    """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j]."""
+    lib = load_library()
+    b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
+    v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
+    sets = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(set_of_traj), b.shape), dtype=np.int32)
+    ns = len(targets)
+    if len(projectiles) != ns:
+        raise ValueError("targets and projectiles must pair up")
+    T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
+    P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
+    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau))
+    h = ctypes.c_void_p()
+    dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    dp(b), dp(v), ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+    nt, nst, npad, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+    _check(lib.wpccc_plan_info(h, ctypes.byref(nt), ctypes.byref(nst), ctypes.byref(npad), ctypes.byref(nb)))
+    p = Plan(h, (list(targets), list(projectiles)), nt.value, nst.value, npad.value)
+    p.device_bytes = nb.value
+    p.two_centre = True
+    return p
+
+
+def wpccc_plan_path_info(plan: Plan, j: int):
+    """(n_states, n_target) of path j."""
+    a, t = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().wpccc_plan_path_info(plan.handle, int(j), ctypes.byref(a), ctypes.byref(t)))
+    return a.value, t.value
 
 
 def wpccc_plan_info(plan: Plan):
@@ -226,8 +265,9 @@ def wpccc_plan_status(plan: Plan, stream=None):
 
 
 def wpccc_couplings(plan: Plan, j: int, z: float, H, S=None, stream=None):
-    """H (complex128 CUDA [N, N]) <- D_T(b_j, z) with phases; S must be None (1C)."""
-    N = plan.n_states
+    """H (complex128 CUDA [N_j, N_j]) <- couplings of path j at z with phases;
+    S: None for a one-centre plan, the [N_j, N_j] overlap matrix for a two-centre plan."""
+    N = wpccc_plan_path_info(plan, j)[0]
     _check(load_library().wpccc_couplings(plan.handle, int(j), float(z),
                                           _dev_ptr(H, "complex128", (N, N), "H"),
                                           _dev_ptr(S, "complex128", (N, N), "S"), _stream_ptr(stream)))

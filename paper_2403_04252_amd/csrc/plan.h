@@ -117,6 +117,57 @@ struct PrologueArgs {
     int traj0;
 };
 
+// Device tables of one centre's basis (moment tables, column maps, angular
+// coefficients, energies), built once per basis by centre_build().
+struct Centre {
+    Meta meta{};
+    Meta* d_meta = nullptr;
+    double *d_eps = nullptr, *d_gcoef = nullptr, *d_rad_eps = nullptr;
+    int *d_col_lam = nullptr, *d_gpb = nullptr, *d_st_rad = nullptr;
+    int2* d_gcol = nullptr;
+    double2* d_tab = nullptr;
+    long long bytes = 0;
+    Tables tables(const double* bvec, const double* vvec) const {
+        Tables t;
+        t.tab = d_tab;
+        t.col_lam = d_col_lam;
+        t.gcol_info = d_gcol;
+        t.gcoef = d_gcoef;
+        t.gpb = d_gpb;
+        t.eps = d_eps;
+        t.st_rad = d_st_rad;
+        t.rad_eps = d_rad_eps;
+        t.bvec = bvec;
+        t.vvec = vvec;
+        return t;
+    }
+};
+
+// centre.hip
+int centre_build(const HostBasis& hb, hipStream_t st, Centre& c);
+void centre_free(Centre& c);
+
+// device allocation with error text; adds to `total`
+int dev_alloc_bytes(void** p, size_t bytes, long long& total);
+template <typename T>
+inline int dev_alloc(T** p, size_t count, long long& total) {
+    return dev_alloc_bytes(reinterpret_cast<void**>(p), (count ? count : 1) * sizeof(T), total);
+}
+int launched(hipError_t e, const char* what);
+
+// two-centre plan (plan2c.hip)
+struct Plan2C;
+int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,
+                  const int* set_of_traj, const double* b, const double* v, const wpccc_plan_opts& o,
+                  hipStream_t st, Plan2C** out);
+void plan2c_destroy(Plan2C* p);
+int plan2c_info(Plan2C* p, int* n_traj, int* n_states, int* n_pad, long long* bytes);
+int plan2c_path_info(Plan2C* p, int j, int* n_states, int* n_target);
+int plan2c_status(Plan2C* p, hipStream_t st);
+int plan2c_couplings(Plan2C* p, int j, double z, void* H, void* S, hipStream_t st);
+int plan2c_step(Plan2C* p, void* X, double z, double h, hipStream_t st);
+int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* X, void* P, void* norm, hipStream_t st);
+
 // launchers (kernels_1c.hip)
 hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st);
 hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da,

@@ -1,5 +1,5 @@
-// C ABI of the one-centre path: basis handles, plan creation (device tables),
-// and the entry points that enqueue the kernels of kernels_1c.hip.
+// C ABI: basis handles, the one-centre plan and the entry points; the
+// two-centre plan lives in plan2c.hip and is reached through the same calls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,21 +33,18 @@ void clear_error() { g_err.clear(); }
 using namespace wpccc;
 
 struct wpccc_plan_s {
-    Meta meta{};
-    Meta* d_meta = nullptr;  // device copy of meta
+    Plan2C* p2c = nullptr;   // set for a two-centre plan (everything below unused)
+    Centre c;                // one-centre basis tables
     int n_traj = 0, n_pad = 0, batched = 1;
     double Zp = 1.0;
     std::vector<double> b, v;
-    // device buffers owned by the plan
-    double *d_eps = nullptr, *d_b = nullptr, *d_v = nullptr, *d_gcoef = nullptr;
-    int *d_col_lam = nullptr, *d_gpb = nullptr, *d_flag = nullptr;
-    int2* d_gcol = nullptr;
-    double2* d_tab = nullptr;
+    double *d_b = nullptr, *d_v = nullptr;
+    int* d_flag = nullptr;
     double *d_Frow1 = nullptr, *d_G1 = nullptr;  // diagnostic couplings scratch
     double2* d_PH1 = nullptr;
     double2 *d_Ua = nullptr, *d_Ub = nullptr, *d_Xacc = nullptr;
-    int *d_st_rad = nullptr, *d_kidx = nullptr;
-    double *d_rad_eps = nullptr, *d_rpow = nullptr, *d_pbar = nullptr;
+    int* d_kidx = nullptr;
+    double *d_rpow = nullptr, *d_pbar = nullptr;
     double2* d_ph = nullptr;
     long long bytes = 0;
     int stage_smem = 0;
@@ -60,20 +57,7 @@ struct wpccc_plan_s {
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
 
-    Tables tables() const {
-        Tables t;
-        t.tab = d_tab;
-        t.col_lam = d_col_lam;
-        t.gcol_info = d_gcol;
-        t.gcoef = d_gcoef;
-        t.gpb = d_gpb;
-        t.eps = d_eps;
-        t.st_rad = d_st_rad;
-        t.rad_eps = d_rad_eps;
-        t.bvec = d_b;
-        t.vvec = d_v;
-        return t;
-    }
+    Tables tables() const { return c.tables(d_b, d_v); }
     PointArrays points() const {
         PointArrays q;
         q.kidx = d_kidx;
@@ -87,26 +71,12 @@ struct wpccc_plan_s {
 
 namespace {
 
-template <typename T>
-int dev_alloc(T** p, size_t count, long long& total) {
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
-        *p = nullptr;
-        return e == hipErrorOutOfMemory ? WPCCC_ENOMEM : WPCCC_EHIP;
-    }
-    total += (long long)(count * sizeof(T));
-    return WPCCC_OK;
-}
-
 void free_plan(wpccc_plan_s* p) {
     if (!p) return;
-    if (p->d_meta) (void)hipFree(p->d_meta);
-    void* bufs[] = {p->d_eps, p->d_b,    p->d_v,   p->d_gcoef, p->d_col_lam, p->d_gcol, p->d_gpb,
-                    p->d_flag, p->d_tab, p->d_Frow1, p->d_G1,  p->d_PH1,     p->d_Ua,   p->d_Ub,
-                    p->d_Xacc, p->d_st_rad, p->d_kidx, p->d_rad_eps, p->d_rpow, p->d_pbar, p->d_ph};
+    if (p->p2c) plan2c_destroy(p->p2c);
+    centre_free(p->c);
+    void* bufs[] = {p->d_b,  p->d_v,  p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1, p->d_Ua,
+                    p->d_Ub, p->d_Xacc, p->d_kidx, p->d_rpow, p->d_pbar, p->d_ph};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     for (auto& r : p->recs) {
@@ -145,34 +115,10 @@ void time_mark(wpccc_plan_s* p, int kernel, hipStream_t st, bool open) {
     }
 }
 
-int launched(hipError_t e, const char* what) {
-    if (e != hipSuccess) {
-        set_error("launch of %s failed: %s", what, hipGetErrorString(e));
-        return WPCCC_EHIP;
-    }
-    return WPCCC_OK;
-}
-
-// number of multipoles lambda coupling l and l' (|l-l'|..l+l' step 2)
-inline int n_lambda(int l, int lp) { return std::min(l, lp) + 1; }
-
-// first column of block (l, lambda) in the l' row layouts (Frow / G)
-void block_columns(const Meta& m, int lp, int l, int lam, int& e0, int& g0) {
-    e0 = 0;
-    g0 = 0;
-    for (int ll = 0; ll < l; ++ll) {
-        e0 += n_lambda(ll, lp) * m.n_l[ll];
-        g0 += n_lambda(ll, lp) * (2 * ll + 1);
-    }
-    const int k = (lam - std::abs(l - lp)) / 2;
-    e0 += k * m.n_l[l];
-    g0 += k * (2 * l + 1);
-}
-
 // Per-point quantities for z[0..n) of paths [j0, j0+nj) into point slots 0..n-1.
 int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hipStream_t st) {
     PrologueArgs a;
-    a.meta = p->d_meta;
+    a.meta = p->c.d_meta;
     a.tb = p->tables();
     a.pt = p->points();
     for (int i = 0; i < n; ++i) a.z[i] = z[i];
@@ -187,7 +133,7 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
 int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double h, const double2* u_in,
                   double2* X, double2* u_out, hipStream_t st) {
     StageArgs a;
-    a.meta = p->d_meta;
+    a.meta = p->c.d_meta;
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -202,7 +148,7 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.u_out = u_out;
     a.flag = p->d_flag;
     time_mark(p, kStage, st, true);
-    hipError_t e = launch_stage(a, p->meta, nj, p->stage_smem, st);
+    hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem, st);
     time_mark(p, kStage, st, false);
     return launched(e, "k_stage");
 }
@@ -225,6 +171,19 @@ bool path_hits_origin(const wpccc_plan_s* p, double z) {
     return false;
 }
 
+int check_grid(const double* zgrid, int n_points) {
+    if (!zgrid || n_points < 2) {
+        set_error("wpccc_propagate: need a z-grid of at least 2 points");
+        return WPCCC_EINVAL;
+    }
+    for (int i = 0; i < n_points; ++i)
+        if (!std::isfinite(zgrid[i]) || (i > 0 && !(zgrid[i] > zgrid[i - 1]))) {
+            set_error("wpccc_propagate: z-grid must be finite and strictly increasing");
+            return WPCCC_EINVAL;
+        }
+    return WPCCC_OK;
+}
+
 }  // namespace
 
 #define TRY(x)                 \
@@ -240,7 +199,7 @@ extern "C" {
 
 const char* wpccc_last_error(void) { return g_err.c_str(); }
 
-const char* wpccc_version(void) { return "0.2.0"; }
+const char* wpccc_version(void) { return "0.3.0"; }
 
 int wpccc_basis(const wpccc_basis_spec* spec, wpccc_basis_t* out) {
     clear_error();
@@ -319,8 +278,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     if (opts) o = *opts;
     if (o.Zp == 0.0) o.Zp = 1.0;
     if (o.two_centre) {
-        set_error("wpccc_plan_create: the two-centre form is not available in this build");
-        return WPCCC_ENOTSUP;
+        set_error("wpccc_plan_create: use wpccc_plan_create_2c for the two-centre form");
+        return WPCCC_EINVAL;
     }
     for (int j = 0; j < n_traj; ++j)
         if (!(b_host[j] > 0.0) || !(v_host[j] > 0.0) || !std::isfinite(b_host[j]) || !std::isfinite(v_host[j])) {
@@ -334,10 +293,6 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_EHIP;
     }
     const HostBasis& hb = target->hb;
-    if (hb.spec.l_max > kMaxL) {
-        set_error("wpccc_plan_create: l_max %d exceeds %d", hb.spec.l_max, kMaxL);
-        return WPCCC_EINVAL;
-    }
     wpccc_plan_s* plan = new (std::nothrow) wpccc_plan_s;
     if (!plan) {
         set_error("wpccc_plan_create: out of host memory");
@@ -351,170 +306,34 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->v.assign(v_host, v_host + n_traj);
     const int N = hb.n_states;
     plan->n_pad = (N + 7) & ~7;
-
-    Meta& m = plan->meta;
-    m.l_max = hb.spec.l_max;
-    m.lam_max = 2 * m.l_max;
-    m.n_r = hb.n_r;
-    m.n_f = hb.n_f;
-    m.n_states = N;
-    m.r_max = hb.spec.r_max;
-    for (int l = 0; l <= kMaxL; ++l) {
-        m.n_l[l] = l <= m.l_max ? hb.n_l[l] : 0;
-        m.state_off[l] = l <= m.l_max ? hb.state_off[l] : N;
-        m.rad_off[l] = l <= m.l_max ? hb.rad_off[l] : hb.n_f;
-    }
-    m.n_frow = m.n_g = m.n_chunks = m.n_cols = m.n_gcols = 0;
-    for (int lp = 0; lp <= kMaxL; ++lp) {
-        m.nV[lp] = m.gcols[lp] = 0;
-        m.frow_off[lp] = m.n_frow;
-        m.g_off[lp] = m.n_g;
-        m.col_off[lp] = m.n_cols;
-        m.gcol_off[lp] = m.n_gcols;
-        if (lp > m.l_max) continue;
-        for (int l = 0; l <= m.l_max; ++l) {
-            m.nV[lp] += n_lambda(l, lp) * m.n_l[l];
-            m.gcols[lp] += n_lambda(l, lp) * (2 * l + 1);
-        }
-        m.n_frow += m.n_l[lp] * m.nV[lp];
-        m.n_g += (2 * lp + 1) * m.gcols[lp];
-        m.n_cols += m.nV[lp];
-        m.n_gcols += m.gcols[lp];
-        m.n_chunks += (m.n_l[lp] + kRowsPerBlock - 1) / kRowsPerBlock;
-    }
-    // Frow entries (a, b, lambda) in row layout; column lambda and G column maps
-    std::vector<int> da, db, dl, col_lam;
-    std::vector<int2> gcol;
-    for (int lp = 0; lp <= m.l_max; ++lp) {
-        std::vector<int> lam_of_col, a_off_of_col;
-        for (int l = 0; l <= m.l_max; ++l)
-            for (int lam = std::abs(l - lp); lam <= l + lp; lam += 2) {
-                int e0, g0;
-                block_columns(m, lp, l, lam, e0, g0);
-                for (int n = 0; n < m.n_l[l]; ++n) {
-                    lam_of_col.push_back(lam);
-                    a_off_of_col.push_back(hb.rad_off[l] + n);
-                }
-                for (int q = 0; q <= 2 * l; ++q) gcol.push_back(gcol_pack(e0, m.n_l[l], m.state_off[l] + q * m.n_l[l]));
-            }
-        col_lam.insert(col_lam.end(), lam_of_col.begin(), lam_of_col.end());
-        for (int np = 0; np < m.n_l[lp]; ++np)
-            for (int e = 0; e < m.nV[lp]; ++e) {
-                da.push_back(hb.rad_off[lp] + np);
-                db.push_back(a_off_of_col[e]);
-                dl.push_back(lam_of_col[e]);
-            }
-    }
-    if ((int)da.size() != m.n_frow || (int)col_lam.size() != m.n_cols || (int)gcol.size() != m.n_gcols) {
-        set_error("wpccc_plan_create: internal layout mismatch");
-        free_plan(plan);
-        return WPCCC_EINVAL;
-    }
-    // angular factors: c(l'm', lm, lambda) = -sqrt((2l+1)/(2l'+1)) C^{l'0}_{lam 0 l 0}
-    // C^{l'm'}_{lam mu l m}, mu = m'-m, times (-1)^mu for mu < 0, so that
-    // c * Pbar_lam^|mu| = -sqrt((2l+1)(lam-mu)!/((2l'+1)(lam+mu)!)) C C P_lam^mu (Eq. D1).
-    std::vector<double> gcoef((size_t)m.n_g, 0.0);
-    std::vector<int> gpb((size_t)m.n_g, -1);
-    for (int lp = 0; lp <= m.l_max; ++lp)
-        for (int qp = 0; qp <= 2 * lp; ++qp) {
-            const int mp = qp - lp;
-            for (int l = 0; l <= m.l_max; ++l)
-                for (int lam = std::abs(l - lp); lam <= l + lp; lam += 2) {
-                    int e0, g0;
-                    block_columns(m, lp, l, lam, e0, g0);
-                    for (int q = 0; q <= 2 * l; ++q) {
-                        const int mm = q - l, mu = mp - mm;
-                        const size_t idx = (size_t)m.g_off[lp] + (size_t)qp * m.gcols[lp] + g0 + q;
-                        if (std::abs(mu) > lam) continue;
-                        double c = -std::sqrt((2.0 * l + 1.0) / (2.0 * lp + 1.0)) *
-                                   clebsch_gordan(lam, 0, l, 0, lp, 0) * clebsch_gordan(lam, mu, l, mm, lp, mp);
-                        if (c == 0.0) continue;
-                        if (mu < 0 && (mu % 2)) c = -c;
-                        gcoef[idx] = c;
-                        gpb[idx] = pb_index(lam, std::abs(mu));
-                    }
-                }
-        }
-    // phi transposed [n_r+1][n_f]
-    std::vector<double> phiT((size_t)(hb.n_r + 1) * hb.n_f);
-    for (int a = 0; a < hb.n_f; ++a)
-        for (int i = 0; i <= hb.n_r; ++i) phiT[(size_t)i * hb.n_f + a] = hb.phi[(size_t)a * (hb.n_r + 1) + i];
-
+    TRY(centre_build(hb, st, plan->c));
+    const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
     if (plan->stage_smem > 160 * 1024) {
         set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes)", plan->stage_smem);
         free_plan(plan);
         return WPCCC_ENOTSUP;
     }
-
     long long& tot = plan->bytes;
-    TRY(dev_alloc(&plan->d_meta, 1, tot));
-    TRY(dev_alloc(&plan->d_eps, (size_t)N, tot));
+    tot = plan->c.bytes;
     TRY(dev_alloc(&plan->d_b, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_v, (size_t)n_traj, tot));
-    TRY(dev_alloc(&plan->d_gcoef, (size_t)m.n_g, tot));
-    TRY(dev_alloc(&plan->d_gpb, (size_t)m.n_g, tot));
-    TRY(dev_alloc(&plan->d_col_lam, (size_t)m.n_cols, tot));
-    TRY(dev_alloc(&plan->d_gcol, (size_t)m.n_gcols, tot));
     TRY(dev_alloc(&plan->d_flag, 1, tot));
-    TRY(dev_alloc(&plan->d_tab, (size_t)(m.n_r + 1) * m.n_frow, tot));
     TRY(dev_alloc(&plan->d_Frow1, (size_t)m.n_frow, tot));
     TRY(dev_alloc(&plan->d_G1, (size_t)m.n_g, tot));
     TRY(dev_alloc(&plan->d_PH1, (size_t)N, tot));
     TRY(dev_alloc(&plan->d_Ua, (size_t)n_traj * plan->n_pad, tot));
     TRY(dev_alloc(&plan->d_Ub, (size_t)n_traj * plan->n_pad, tot));
     TRY(dev_alloc(&plan->d_Xacc, (size_t)n_traj * plan->n_pad, tot));
-    TRY(dev_alloc(&plan->d_st_rad, (size_t)N, tot));
-    TRY(dev_alloc(&plan->d_rad_eps, (size_t)m.n_f, tot));
     TRY(dev_alloc(&plan->d_kidx, (size_t)n_traj * kChunkPoints, tot));
     TRY(dev_alloc(&plan->d_rpow, (size_t)n_traj * kChunkPoints * kRpow, tot));
     TRY(dev_alloc(&plan->d_pbar, (size_t)n_traj * kChunkPoints * kMaxPb, tot));
     TRY(dev_alloc(&plan->d_ph, (size_t)n_traj * kChunkPoints * m.n_f, tot));
-    // temporaries for the moment tables
-    double *d_r = nullptr, *d_w = nullptr, *d_phiT = nullptr;
-    int *d_da = nullptr, *d_db = nullptr, *d_dl = nullptr;
-    long long tmp = 0;
-    auto free_tmp = [&]() {
-        void* q[] = {d_r, d_w, d_phiT, d_da, d_db, d_dl};
-        for (void* x : q)
-            if (x) (void)hipFree(x);
-    };
-    int rc = dev_alloc(&d_r, hb.r.size(), tmp);
-    if (rc == WPCCC_OK) rc = dev_alloc(&d_w, hb.w.size(), tmp);
-    if (rc == WPCCC_OK) rc = dev_alloc(&d_phiT, phiT.size(), tmp);
-    if (rc == WPCCC_OK) rc = dev_alloc(&d_da, da.size(), tmp);
-    if (rc == WPCCC_OK) rc = dev_alloc(&d_db, db.size(), tmp);
-    if (rc == WPCCC_OK) rc = dev_alloc(&d_dl, dl.size(), tmp);
-    if (rc != WPCCC_OK) {
-        free_tmp();
-        free_plan(plan);
-        return rc;
-    }
-    hipError_t e = hipSuccess;
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
-    };
-    up(d_r, hb.r.data(), hb.r.size() * sizeof(double));
-    up(d_w, hb.w.data(), hb.w.size() * sizeof(double));
-    up(d_phiT, phiT.data(), phiT.size() * sizeof(double));
-    up(d_da, da.data(), da.size() * sizeof(int));
-    up(d_db, db.data(), db.size() * sizeof(int));
-    up(d_dl, dl.data(), dl.size() * sizeof(int));
-    up(plan->d_col_lam, col_lam.data(), col_lam.size() * sizeof(int));
-    up(plan->d_gcol, gcol.data(), gcol.size() * sizeof(int2));
-    up(plan->d_gcoef, gcoef.data(), gcoef.size() * sizeof(double));
-    up(plan->d_gpb, gpb.data(), gpb.size() * sizeof(int));
-    up(plan->d_meta, &plan->meta, sizeof(Meta));
-    up(plan->d_eps, hb.eps.data(), (size_t)N * sizeof(double));
-    up(plan->d_st_rad, hb.st_i.data(), (size_t)N * sizeof(int));
-    up(plan->d_rad_eps, hb.rad_eps.data(), (size_t)m.n_f * sizeof(double));
-    up(plan->d_b, b_host, (size_t)n_traj * sizeof(double));
-    up(plan->d_v, v_host, (size_t)n_traj * sizeof(double));
-    if (e == hipSuccess) e = hipMemsetAsync(plan->d_flag, 0, sizeof(int), st);
+    hipError_t e = hipMemcpyAsync(plan->d_b, b_host, (size_t)n_traj * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = launch_moments(d_r, d_w, d_phiT, d_da, d_db, d_dl, m.n_r, m.n_f, m.n_frow, plan->d_tab, st);
+        e = hipMemcpyAsync(plan->d_v, v_host, (size_t)n_traj * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(plan->d_flag, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    free_tmp();
     if (e == hipSuccess && plan->stage_smem > 64 * 1024) e = stage_set_smem_limit(m.l_max, plan->stage_smem);
     if (e != hipSuccess) {
         set_error("wpccc_plan_create: device setup failed: %s", hipGetErrorString(e));
@@ -525,15 +344,62 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     return WPCCC_OK;
 }
 
+int wpccc_plan_create_2c(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,
+                         const int* set_of_traj, const double* b_host, const double* v_host,
+                         const wpccc_plan_opts* opts, void* stream, wpccc_plan_t* out) {
+    clear_error();
+    if (!targets || !projectiles || n_sets < 1 || n_traj < 1 || !set_of_traj || !b_host || !v_host || !out) {
+        set_error("wpccc_plan_create_2c: NULL argument or empty plan");
+        return WPCCC_EINVAL;
+    }
+    *out = nullptr;
+    wpccc_plan_opts o{};
+    o.batched = 1;
+    if (opts) o = *opts;
+    o.two_centre = 1;
+    if (o.n_eta == 0) o.n_eta = 256;
+    if (o.n_tau == 0) o.n_tau = 512;
+    wpccc_plan_s* plan = new (std::nothrow) wpccc_plan_s;
+    if (!plan) {
+        set_error("wpccc_plan_create_2c: out of host memory");
+        return WPCCC_ENOMEM;
+    }
+    const int rc = plan2c_create(targets, projectiles, n_sets, n_traj, set_of_traj, b_host, v_host, o,
+                                 (hipStream_t)stream, &plan->p2c);
+    if (rc != WPCCC_OK) {
+        plan->p2c = nullptr;
+        free_plan(plan);
+        return rc;
+    }
+    *out = plan;
+    return WPCCC_OK;
+}
+
 int wpccc_plan_info(wpccc_plan_t plan, int* n_traj, int* n_states, int* n_pad, long long* device_bytes) {
     if (!plan) {
         set_error("wpccc_plan_info: NULL plan");
         return WPCCC_EINVAL;
     }
+    if (plan->p2c) return plan2c_info(plan->p2c, n_traj, n_states, n_pad, device_bytes);
     if (n_traj) *n_traj = plan->n_traj;
-    if (n_states) *n_states = plan->meta.n_states;
+    if (n_states) *n_states = plan->c.meta.n_states;
     if (n_pad) *n_pad = plan->n_pad;
     if (device_bytes) *device_bytes = plan->bytes;
+    return WPCCC_OK;
+}
+
+int wpccc_plan_path_info(wpccc_plan_t plan, int j, int* n_states, int* n_target) {
+    if (!plan) {
+        set_error("wpccc_plan_path_info: NULL plan");
+        return WPCCC_EINVAL;
+    }
+    if (plan->p2c) return plan2c_path_info(plan->p2c, j, n_states, n_target);
+    if (j < 0 || j >= plan->n_traj) {
+        set_error("wpccc_plan_path_info: path index out of range");
+        return WPCCC_EINVAL;
+    }
+    if (n_states) *n_states = plan->c.meta.n_states;
+    if (n_target) *n_target = plan->c.meta.n_states;
     return WPCCC_OK;
 }
 
@@ -549,6 +415,7 @@ int wpccc_plan_status(wpccc_plan_t plan, void* stream) {
         return WPCCC_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (plan->p2c) return plan2c_status(plan->p2c, st);
     int flag = 0;
     WPCCC_HIP_CHECK(hipMemcpyAsync(&flag, plan->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     WPCCC_HIP_CHECK(hipStreamSynchronize(st));
@@ -562,8 +429,14 @@ int wpccc_plan_status(wpccc_plan_t plan, void* stream) {
 
 int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev, void* stream) {
     clear_error();
-    if (!plan || !H_dev || j < 0 || j >= plan->n_traj || !std::isfinite(z)) {
-        set_error("wpccc_couplings: bad plan, path index or z");
+    if (!plan || !H_dev || !std::isfinite(z)) {
+        set_error("wpccc_couplings: bad plan, H_dev or z");
+        return WPCCC_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (plan->p2c) return plan2c_couplings(plan->p2c, j, z, H_dev, S_dev, st);
+    if (j < 0 || j >= plan->n_traj) {
+        set_error("wpccc_couplings: path index out of range");
         return WPCCC_EINVAL;
     }
     if (S_dev) {
@@ -574,10 +447,9 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
         set_error("wpccc_couplings: R = 0");
         return WPCCC_EINVAL;
     }
-    hipStream_t st = (hipStream_t)stream;
-    const Meta& m = plan->meta;
+    const Meta& m = plan->c.meta;
     SetupArgs a;
-    a.meta = plan->d_meta;
+    a.meta = plan->c.d_meta;
     a.tb = plan->tables();
     a.z = z;
     a.j = j;
@@ -592,7 +464,8 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
     int rc = launched(e, "k_slot_setup");
     if (rc) return rc;
     time_mark(plan, kDense, st, true);
-    e = launch_couplings_dense(plan->d_meta, m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp, (double2*)H_dev, st);
+    e = launch_couplings_dense(plan->c.d_meta, m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp,
+                               (double2*)H_dev, st);
     time_mark(plan, kDense, st, false);
     return launched(e, "k_couplings_dense");
 }
@@ -603,11 +476,12 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
         set_error("wpccc_step: bad plan, X_dev, z or h");
         return WPCCC_EINVAL;
     }
+    hipStream_t st = (hipStream_t)stream;
+    if (plan->p2c) return plan2c_step(plan->p2c, X_dev, z, h, st);
     if (path_hits_origin(plan, z) || path_hits_origin(plan, z + 0.5 * h) || path_hits_origin(plan, z + h)) {
         set_error("wpccc_step: R = 0 on the step");
         return WPCCC_EINVAL;
     }
-    hipStream_t st = (hipStream_t)stream;
     double2* X = (double2*)X_dev;
     const int chunk = plan->batched ? plan->n_traj : 1;
     for (int j0 = 0; j0 < plan->n_traj; j0 += chunk) {
@@ -623,22 +497,20 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
 int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, void* X_dev, void* P_dev,
                     void* norm_dev, void* stream) {
     clear_error();
-    if (!plan || !zgrid_host || !X_dev || n_points < 2) {
-        set_error("wpccc_propagate: bad plan, grid or X_dev (need >= 2 points)");
+    if (!plan || !X_dev) {
+        set_error("wpccc_propagate: bad plan or X_dev");
         return WPCCC_EINVAL;
     }
-    for (int i = 0; i < n_points; ++i) {
-        if (!std::isfinite(zgrid_host[i]) || (i > 0 && !(zgrid_host[i] > zgrid_host[i - 1]))) {
-            set_error("wpccc_propagate: z-grid must be finite and strictly increasing");
-            return WPCCC_EINVAL;
-        }
+    int rc = check_grid(zgrid_host, n_points);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (plan->p2c) return plan2c_propagate(plan->p2c, zgrid_host, n_points, X_dev, P_dev, norm_dev, st);
+    for (int i = 0; i < n_points; ++i)
         if (path_hits_origin(plan, zgrid_host[i]) ||
             (i + 1 < n_points && path_hits_origin(plan, 0.5 * (zgrid_host[i] + zgrid_host[i + 1])))) {
             set_error("wpccc_propagate: R = 0 on the grid");
             return WPCCC_EINVAL;
         }
-    }
-    hipStream_t st = (hipStream_t)stream;
     double2* X = (double2*)X_dev;
     const int chunk = plan->batched ? plan->n_traj : 1;
     for (int j0 = 0; j0 < plan->n_traj; j0 += chunk) {
@@ -652,8 +524,7 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
                 pts[2 * i] = zgrid_host[c0 + i];
                 if (i < ns) pts[2 * i + 1] = 0.5 * (zgrid_host[c0 + i] + zgrid_host[c0 + i + 1]);
             }
-            int rc = enqueue_prologue(plan, pts, 2 * ns + 1, j0, nj, st);
-            if (rc) return rc;
+            if ((rc = enqueue_prologue(plan, pts, 2 * ns + 1, j0, nj, st))) return rc;
             for (int i = 0; i < ns; ++i) {
                 const double h = zgrid_host[c0 + i + 1] - zgrid_host[c0 + i];
                 if ((rc = enqueue_step(plan, X, j0, nj, 2 * i, h, st))) return rc;
@@ -662,11 +533,10 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
     }
     if (P_dev || norm_dev) {
         time_mark(plan, kProb, st, true);
-        hipError_t e = launch_probabilities((const double2*)X, plan->n_traj, plan->meta.n_states, plan->n_pad,
+        hipError_t e = launch_probabilities((const double2*)X, plan->n_traj, plan->c.meta.n_states, plan->n_pad,
                                             (double*)P_dev, (double*)norm_dev, st);
         time_mark(plan, kProb, st, false);
-        int rc = launched(e, "k_probabilities");
-        if (rc) return rc;
+        if ((rc = launched(e, "k_probabilities"))) return rc;
     }
     return WPCCC_OK;
 }

@@ -1,0 +1,167 @@
+// Two-centre path (Eq. 1 with capture): data layout and launchers (internal).
+//
+// A two-centre plan holds one group per (target, projectile) basis pair; the
+// paths of a group share sizes, so every launch covers one group.  Each path
+// keeps three coupling slots (z, z_mid, z_new of Algorithm 1) holding
+//   S  = [[I, K], [K^dag, I]]   column-major [N][N]
+//   LU = S factorised with partial pivoting (LAPACK layout, pivots in piv)
+//   H  = [[D_T, Q], [L, D_P]]   row-major [N][N]
+// Couplings are computed for up to two slots per path in one pass ("jobs":
+// job y -> path y / n_sub, slot slot[y % n_sub], position z[y % n_sub]).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace wpccc {
+
+constexpr int kMaxW = 3;          // weights: overlap, target potential, projectile potential
+constexpr int kNodeChunk = 16;    // spheroidal nodes per MFMA chunk (4 k-steps of 4)
+constexpr int kTile = 32;         // rows (target) and columns (projectile) per contraction workgroup
+constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
+constexpr int kNodeFixed = 19;    // node fields before the Bessel values
+constexpr int kSlots2C = 3;
+
+// Per-group constants of the two-centre kernels (device copy passed by pointer).
+struct Meta2C {
+    int LT, LP, L;           // l_max of target, projectile; max of both
+    int NT, NP, N;           // states; N = NT + NP
+    int nfT, nfP;            // radial functions
+    int nrT, nrP;            // grid intervals
+    double rmaxT, rmaxP;
+    double ZT, ZP;
+    int n_eta, n_tau, n_nodes;
+    int n_fields;            // kNodeFixed + 2L + 1
+    int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
+    int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
+    // contraction blocks: rows of block s are the radial functions a >= radT_off[s]
+    int radT_off[kMaxL + 2], radP_off[kMaxL + 2];
+    int nA[kMaxL + 1], nB[kMaxL + 1];
+    int st_off[kMaxL + 1][kMaxL + 1];   // offset of the (s, t) block in tmol
+    int n_tmol;                         // doubles of tmol per job
+    int stT_off[kMaxL + 2], stP_off[kMaxL + 2];  // state offsets per l
+    int n_lT[kMaxL + 1], n_lP[kMaxL + 1];
+    int n_tiles;
+};
+
+// weights of the (s, t) block: Bessel orders |s-t| and s+t (one if s t = 0),
+// each with cos and sin of (v z / 2) eta tau, each with the n_w weights;
+// index ((order * 2 + trig) * n_w + w)
+__host__ __device__ inline int st_nk(int s, int t, int n_w) { return ((s > 0 && t > 0) ? 2 : 1) * 2 * n_w; }
+
+struct Jobs {
+    int path0;       // first local path of the launch
+    int n_sub;       // 1 or 2 coupling positions per path
+    int slot[2];
+    double z[2];
+};
+
+struct NodeArgs {
+    const Meta2C* m;
+    Jobs jobs;
+    const double* xlag;   // [n_eta] Gauss-Laguerre nodes
+    const double* wlag;   // [n_eta] w e^x
+    const double* tleg;   // [n_tau]
+    const double* wleg;   // [n_tau]
+    const int* paths;     // [n_paths] global index of each local path
+    const double* bvec;
+    const double* vvec;
+    double* nodes;        // [job][n_fields][n_nodes]
+    int* jst;             // [job][2][n_nodes] first stencil node at rA, rB (-1 beyond r_max)
+    int* n_act;           // [job] nodes in the active eta prefix
+};
+
+struct ContractArgs {
+    const Meta2C* m;
+    const int2* tiles;      // [n_tiles] (s | t << 8, a0 | b0 << 16)
+    const double* phiT_T;   // [nrT+1][nfT] target radial functions, transposed
+    const double* phiT_P;   // [nrP+1][nfP]
+    const int* radl_T;      // [nfT] l of each radial function
+    const int* radl_P;
+    const double* nodes;
+    const int* jst;
+    const int* n_act;
+    double* tmol;           // [job][n_tmol]
+};
+
+struct AssembleArgs {
+    const Meta2C* m;
+    Jobs jobs;
+    const int* paths;
+    const double* bvec;
+    const double* vvec;
+    const double* epsT;     // [NT]
+    const double* epsP;     // [NP]
+    const double* tmol;     // [job][n_tmol]
+    double2* S;             // [path][slot][N*N] column-major
+    double2* LU;            // copy of S for the factorisation
+    double2* H;             // [path][slot][N*N] row-major
+};
+
+struct SetupBatchArgs {     // Frow, G, phases of one centre for the jobs of a launch
+    const Meta* meta;
+    Tables tb;
+    Jobs jobs;
+    const int* paths;
+    int parity;             // -1: the other nucleus sits at -R (projectile centre)
+    double* Frow;           // [job][n_frow]
+    double* G;              // [job][n_g]
+    double2* PH;            // [job][N_centre]
+    int nbF, nbP;
+};
+
+struct DirectArgs {         // D_T and D_P blocks of H from the per-job Frow / G / phases
+    const Meta* mT;
+    const Meta* mP;
+    const Meta2C* m;
+    Jobs jobs;
+    const double* FrowT;
+    const double* GT;
+    const double2* PHT;
+    const double* FrowP;
+    const double* GP;
+    const double2* PHP;
+    int n_frowT, n_gT, n_frowP, n_gP;
+    double2* H;
+};
+
+struct LUArgs {
+    int N;
+    Jobs jobs;
+    double2* LU;            // [path][slot][N*N] column-major, factorised in place
+    int* piv;               // [path][slot][N]
+    const int* paths;
+    int* flag;              // [1] first singular path + 1, [2] its pivot row
+};
+
+struct Stage2CArgs {
+    int N, n_pad, stage;
+    double h;
+    int slot;               // coupling slot used by this stage
+    const int* paths;       // global index of each local path
+    const double* vvec;
+    const double2* H;
+    const double2* LU;
+    const int* piv;
+    const double2* u_in;
+    double2* X;
+    double2* Xacc;
+    double2* u_out;
+    int* flag;
+};
+
+hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
+hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
+hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
+hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st);
+hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
+hipError_t launch_lu(const LUArgs& a, int n_jobs, hipStream_t st);
+hipError_t launch_2c_stage(const Stage2CArgs& a, int n_paths, hipStream_t st);
+hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,
+                            int slot, double* P, double* norm, hipStream_t st);
+hipError_t launch_transpose_copy(const double2* src_colmajor, double2* dst_rowmajor, int N, hipStream_t st);
+int contract_smem_bytes(int n_w);
+hipError_t contract_set_smem(int bytes);
+
+}  // namespace wpccc

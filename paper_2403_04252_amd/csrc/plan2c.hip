@@ -1,0 +1,707 @@
+// Two-centre plan (Eq. 1 with electron capture): host side.
+//
+// Paths are grouped by their (target, projectile) basis pair; each group
+// holds both centres' Eq. D1 tables, its Meta2C and, per path, three coupling
+// slots (z, z_mid, z_new of Algorithm 1) with S, its LU factors and H.  A
+// step computes the couplings of the positions not yet held (normally z_mid
+// and z_new, z being the previous step's z_new), factorises S at each and
+// runs the four RK4 stages.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "plan2c.h"
+
+namespace wpccc {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Quadrature nodes (host, once per plan)
+// ---------------------------------------------------------------------------
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal d and off-diagonal e (e[0] unused), by the Sturm sequence of its
+// leading minors.
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t k = 0; k < d.size(); ++k) {
+        const double off = k ? e[k] * e[k] / q : 0.0;
+        q = d[k] - x - off;
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Gauss-Laguerre nodes x_i of L_n (ascending) and the scaled weights
+// w_i e^{x_i}.  The nodes are the eigenvalues of the Jacobi matrix of the
+// Laguerre polynomials (diagonal 2k+1, off-diagonal k), isolated by
+// bisection on Sturm counts and polished by Newton steps on L_n; the weights
+// follow from w_i = x_i / ((n+1)^2 L_{n+1}(x_i)^2), evaluated with the
+// recurrence for e^{-x/2} L_k(x), which stays bounded for large x.
+void gauss_laguerre_scaled(int n, std::vector<double>& x, std::vector<double>& ws) {
+    std::vector<double> d(n), e(n, 0.0);
+    for (int k = 0; k < n; ++k) d[k] = 2.0 * k + 1.0;
+    for (int k = 1; k < n; ++k) e[k] = k;
+    x.assign(n, 0.0);
+    ws.assign(n, 0.0);
+    const double hi = 4.0 * n + 2.0;
+    for (int i = 0; i < n; ++i) {
+        double lo = 0.0, up = hi;
+        for (int it = 0; it < 200 && up - lo > 1e-15 * std::max(1.0, up); ++it) {
+            const double mid = 0.5 * (lo + up);
+            if (sturm_count(d, e, mid) > i) up = mid;
+            else lo = mid;
+        }
+        double xi = 0.5 * (lo + up);
+        for (int it = 0; it < 3; ++it) {
+            double p0 = std::exp(-xi / 2.0), p1 = (1.0 - xi) * p0;  // scaled L_0, L_1
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0 - xi) * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            // L_n' = n (L_n - L_{n-1}) / x; the scale factor cancels in the ratio
+            const double den = n * (p1 - p0);
+            if (den != 0.0) xi -= xi * p1 / den;
+        }
+        double p0 = std::exp(-xi / 2.0), p1 = (1.0 - xi) * p0;
+        for (int k = 1; k <= n; ++k) {
+            const double p2 = ((2.0 * k + 1.0 - xi) * p1 - k * p0) / (k + 1.0);
+            p0 = p1;
+            p1 = p2;
+        }
+        x[i] = xi;
+        ws[i] = xi / ((n + 1.0) * (n + 1.0) * p1 * p1);
+    }
+}
+
+// Gauss-Legendre nodes (ascending) and weights: Newton on P_n from the
+// cosine estimates of its zeros, w = 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = t;
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+        }
+        x[n - 1 - i] = t;
+        w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+
+struct Group2C {
+    const HostBasis* tb = nullptr;
+    const HostBasis* pb = nullptr;
+    Centre cT, cP;
+    Meta2C m{};
+    Meta2C* d_m = nullptr;
+    std::vector<int> paths;  // global path of each local path
+    int* d_paths = nullptr;
+    std::vector<int2> tiles;
+    int2* d_tiles = nullptr;
+    double *d_phiT_T = nullptr, *d_phiT_P = nullptr;
+    int *d_radl_T = nullptr, *d_radl_P = nullptr;
+    double2 *d_S = nullptr, *d_LU = nullptr, *d_H = nullptr;  // [path][slot][N*N]
+    int* d_piv = nullptr;                                      // [path][slot][N]
+    int max_jobs = 0;
+    double* d_nodes = nullptr;
+    int* d_jst = nullptr;
+    int* d_nact = nullptr;
+    double* d_tmol = nullptr;
+    double *d_FrowT = nullptr, *d_GT = nullptr, *d_FrowP = nullptr, *d_GP = nullptr;
+    double2 *d_PHT = nullptr, *d_PHP = nullptr;
+};
+
+struct Plan2C {
+    std::vector<Group2C> groups;
+    std::vector<int> group_of, local_of;
+    int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0;
+    std::vector<double> b, v;
+    double *d_b = nullptr, *d_v = nullptr;
+    int* d_flag = nullptr;  // [0] non-finite amplitude, [1] singular path + 1, [2] its pivot row
+    double2 *d_Ua = nullptr, *d_Ub = nullptr, *d_Xacc = nullptr;
+    double *d_xlag = nullptr, *d_wlag = nullptr, *d_tleg = nullptr, *d_wleg = nullptr;
+    long long bytes = 0;
+    double slot_z[kSlots2C];
+    bool slot_ok[kSlots2C] = {false, false, false};
+};
+
+namespace {
+
+void free_group(Group2C& g) {
+    centre_free(g.cT);
+    centre_free(g.cP);
+    void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
+                    g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_nodes,  g.d_jst,    g.d_nact,
+                    g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP};
+    for (void* q : bufs)
+        if (q) (void)hipFree(q);
+}
+
+int check_basis(const HostBasis& hb, const char* who) {
+    if (hb.spec.l_max > kMaxL) {
+        set_error("wpccc_plan_create_2c: %s basis l_max %d exceeds %d", who, hb.spec.l_max, kMaxL);
+        return WPCCC_EINVAL;
+    }
+    if (hb.n_r < 4) {
+        set_error("wpccc_plan_create_2c: %s basis needs at least 4 grid intervals", who);
+        return WPCCC_EINVAL;
+    }
+    return WPCCC_OK;
+}
+
+// Meta2C of one basis pair.
+void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, Meta2C& m,
+               std::vector<int2>& tiles) {
+    std::memset(&m, 0, sizeof m);
+    m.LT = tb.spec.l_max;
+    m.LP = pb.spec.l_max;
+    m.L = std::max(m.LT, m.LP);
+    m.NT = tb.n_states;
+    m.NP = pb.n_states;
+    m.N = m.NT + m.NP;
+    m.nfT = tb.n_f;
+    m.nfP = pb.n_f;
+    m.nrT = tb.n_r;
+    m.nrP = pb.n_r;
+    m.rmaxT = tb.spec.r_max;
+    m.rmaxP = pb.spec.r_max;
+    m.ZT = tb.spec.Z;
+    m.ZP = pb.spec.Z;
+    m.n_eta = n_eta;
+    m.n_tau = n_tau;
+    m.n_nodes = n_eta * n_tau;
+    m.n_fields = kNodeFixed + 2 * m.L + 1;
+    m.n_w = q_prior ? 3 : 2;
+    m.q_prior = q_prior;
+    for (int l = 0; l <= kMaxL + 1; ++l) {
+        m.radT_off[l] = l <= m.LT ? tb.rad_off[l] : tb.n_f;
+        m.radP_off[l] = l <= m.LP ? pb.rad_off[l] : pb.n_f;
+        m.stT_off[l] = l <= m.LT ? tb.state_off[l] : tb.n_states;
+        m.stP_off[l] = l <= m.LP ? pb.state_off[l] : pb.n_states;
+    }
+    for (int l = 0; l <= kMaxL; ++l) {
+        m.nA[l] = l <= m.LT ? tb.n_f - tb.rad_off[l] : 0;
+        m.nB[l] = l <= m.LP ? pb.n_f - pb.rad_off[l] : 0;
+        m.n_lT[l] = l <= m.LT ? tb.n_l[l] : 0;
+        m.n_lP[l] = l <= m.LP ? pb.n_l[l] : 0;
+    }
+    tiles.clear();
+    int off = 0;
+    for (int s = 0; s <= m.LT; ++s)
+        for (int t = 0; t <= m.LP; ++t) {
+            m.st_off[s][t] = off;
+            off += st_nk(s, t, m.n_w) * m.nA[s] * m.nB[t];
+            for (int a0 = 0; a0 < m.nA[s]; a0 += kTile)
+                for (int b0 = 0; b0 < m.nB[t]; b0 += kTile) tiles.push_back(make_int2(s | (t << 8), a0 | (b0 << 16)));
+        }
+    m.n_tmol = off;
+    m.n_tiles = (int)tiles.size();
+}
+
+std::vector<double> transposed_phi(const HostBasis& hb) {
+    std::vector<double> t((size_t)(hb.n_r + 1) * hb.n_f);
+    for (int a = 0; a < hb.n_f; ++a)
+        for (int i = 0; i <= hb.n_r; ++i) t[(size_t)i * hb.n_f + a] = hb.phi[(size_t)a * (hb.n_r + 1) + i];
+    return t;
+}
+
+std::vector<int> radial_l(const HostBasis& hb) {
+    std::vector<int> r(hb.n_f, 0);
+    for (int l = 0; l <= hb.spec.l_max; ++l)
+        for (int n = 0; n < hb.n_l[l]; ++n) r[hb.rad_off[l] + n] = l;
+    return r;
+}
+
+int upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (!bytes) return WPCCC_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        set_error("host to device copy failed: %s", hipGetErrorString(e));
+        return WPCCC_EHIP;
+    }
+    return WPCCC_OK;
+}
+
+int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
+    int rc;
+    if ((rc = centre_build(*g.tb, st, g.cT))) return rc;
+    if ((rc = centre_build(*g.pb, st, g.cP))) return rc;
+    fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, g.m, g.tiles);
+    long long& tot = p->bytes;
+    tot += g.cT.bytes + g.cP.bytes;
+    const Meta2C& m = g.m;
+    const size_t np = g.paths.size();
+    const size_t NN = (size_t)m.N * m.N;
+    g.max_jobs = 2 * (p->batched ? (int)np : 1);
+    const size_t J = (size_t)g.max_jobs;
+    const std::vector<double> phT = transposed_phi(*g.tb), phP = transposed_phi(*g.pb);
+    const std::vector<int> rlT = radial_l(*g.tb), rlP = radial_l(*g.pb);
+    if ((rc = dev_alloc(&g.d_m, 1, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_paths, np, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_tiles, g.tiles.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_phiT_T, phT.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_phiT_P, phP.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_radl_T, rlT.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_radl_P, rlP.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_S, np * kSlots2C * NN, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_LU, np * kSlots2C * NN, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_H, np * kSlots2C * NN, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_piv, np * kSlots2C * m.N, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_nodes, J * m.n_fields * m.n_nodes, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_jst, J * 2 * m.n_nodes, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_nact, J, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_tmol, J * m.n_tmol, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_FrowT, J * g.cT.meta.n_frow, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_GT, J * g.cT.meta.n_g, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_PHT, J * m.NT, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_FrowP, J * g.cP.meta.n_frow, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_GP, J * g.cP.meta.n_g, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_PHP, J * m.NP, tot))) return rc;
+    if ((rc = upload(g.d_m, &g.m, sizeof(Meta2C), st))) return rc;
+    if ((rc = upload(g.d_paths, g.paths.data(), np * sizeof(int), st))) return rc;
+    if ((rc = upload(g.d_tiles, g.tiles.data(), g.tiles.size() * sizeof(int2), st))) return rc;
+    if ((rc = upload(g.d_phiT_T, phT.data(), phT.size() * sizeof(double), st))) return rc;
+    if ((rc = upload(g.d_phiT_P, phP.data(), phP.size() * sizeof(double), st))) return rc;
+    if ((rc = upload(g.d_radl_T, rlT.data(), rlT.size() * sizeof(int), st))) return rc;
+    if ((rc = upload(g.d_radl_P, rlP.data(), rlP.size() * sizeof(int), st))) return rc;
+    // the host vectors above are released on return: wait for the copies
+    WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+    return WPCCC_OK;
+}
+
+// Couplings of local paths [l0, l0 + np) of group g at n_sub positions
+// (slot[k], z[k]): D_T and D_P, K and Q (and the prior block), then LU of S.
+int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const int* slot, const double* z,
+                      hipStream_t st) {
+    Jobs J{};
+    J.path0 = l0;
+    J.n_sub = n_sub;
+    for (int k = 0; k < n_sub; ++k) {
+        J.slot[k] = slot[k];
+        J.z[k] = z[k];
+    }
+    const int nj = np * n_sub;
+    int rc;
+    for (int side = 0; side < 2; ++side) {
+        const Centre& c = side ? g.cP : g.cT;
+        SetupBatchArgs a;
+        a.meta = c.d_meta;
+        a.tb = c.tables(p->d_b, p->d_v);
+        a.jobs = J;
+        a.paths = g.d_paths;
+        a.parity = side ? -1 : 1;
+        a.Frow = side ? g.d_FrowP : g.d_FrowT;
+        a.G = side ? g.d_GP : g.d_GT;
+        a.PH = side ? g.d_PHP : g.d_PHT;
+        a.nbF = (c.meta.n_frow + 255) / 256;
+        a.nbP = (c.meta.n_states + 255) / 256;
+        if ((rc = launched(launch_setup_batch(a, c.meta, nj, st), "k_setup_batch"))) return rc;
+    }
+    {
+        DirectArgs a;
+        a.mT = g.cT.d_meta;
+        a.mP = g.cP.d_meta;
+        a.m = g.d_m;
+        a.jobs = J;
+        a.FrowT = g.d_FrowT;
+        a.GT = g.d_GT;
+        a.PHT = g.d_PHT;
+        a.FrowP = g.d_FrowP;
+        a.GP = g.d_GP;
+        a.PHP = g.d_PHP;
+        a.n_frowT = g.cT.meta.n_frow;
+        a.n_gT = g.cT.meta.n_g;
+        a.n_frowP = g.cP.meta.n_frow;
+        a.n_gP = g.cP.meta.n_g;
+        a.H = g.d_H;
+        if ((rc = launched(launch_2c_direct(a, g.m, nj, st), "k_2c_direct"))) return rc;
+    }
+    {
+        NodeArgs a;
+        a.m = g.d_m;
+        a.jobs = J;
+        a.xlag = p->d_xlag;
+        a.wlag = p->d_wlag;
+        a.tleg = p->d_tleg;
+        a.wleg = p->d_wleg;
+        a.paths = g.d_paths;
+        a.bvec = p->d_b;
+        a.vvec = p->d_v;
+        a.nodes = g.d_nodes;
+        a.jst = g.d_jst;
+        a.n_act = g.d_nact;
+        if ((rc = launched(launch_2c_nodes(a, g.m, nj, st), "k_2c_nodes"))) return rc;
+    }
+    {
+        ContractArgs a;
+        a.m = g.d_m;
+        a.tiles = g.d_tiles;
+        a.phiT_T = g.d_phiT_T;
+        a.phiT_P = g.d_phiT_P;
+        a.radl_T = g.d_radl_T;
+        a.radl_P = g.d_radl_P;
+        a.nodes = g.d_nodes;
+        a.jst = g.d_jst;
+        a.n_act = g.d_nact;
+        a.tmol = g.d_tmol;
+        if ((rc = launched(launch_2c_contract(a, g.m, nj, st), "k_2c_contract"))) return rc;
+    }
+    {
+        AssembleArgs a;
+        a.m = g.d_m;
+        a.jobs = J;
+        a.paths = g.d_paths;
+        a.bvec = p->d_b;
+        a.vvec = p->d_v;
+        a.epsT = g.cT.d_eps;
+        a.epsP = g.cP.d_eps;
+        a.tmol = g.d_tmol;
+        a.S = g.d_S;
+        a.LU = g.d_LU;
+        a.H = g.d_H;
+        if ((rc = launched(launch_2c_assemble(a, g.m, nj, st), "k_2c_assemble"))) return rc;
+    }
+    {
+        LUArgs a;
+        a.N = g.m.N;
+        a.jobs = J;
+        a.LU = g.d_LU;
+        a.piv = g.d_piv;
+        a.paths = g.d_paths;
+        a.flag = p->d_flag;
+        if ((rc = launched(launch_lu(a, nj, st), "k_lu"))) return rc;
+    }
+    return WPCCC_OK;
+}
+
+int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,
+                  double2* X, double2* u_out, hipStream_t st) {
+    const size_t NN = (size_t)g.m.N * g.m.N;
+    Stage2CArgs a;
+    a.N = g.m.N;
+    a.n_pad = p->n_pad;
+    a.stage = stage;
+    a.h = h;
+    a.slot = slot;
+    a.paths = g.d_paths + l0;
+    a.vvec = p->d_v;
+    a.H = g.d_H + (size_t)l0 * kSlots2C * NN;
+    a.LU = g.d_LU + (size_t)l0 * kSlots2C * NN;
+    a.piv = g.d_piv + (size_t)l0 * kSlots2C * g.m.N;
+    a.u_in = u_in;
+    a.X = X;
+    a.Xacc = p->d_Xacc;
+    a.u_out = u_out;
+    a.flag = p->d_flag;
+    return launched(launch_2c_stage(a, np, st), "k_2c_stage");
+}
+
+int find_slot(const Plan2C* p, double z) {
+    for (int s = 0; s < kSlots2C; ++s)
+        if (p->slot_ok[s] && p->slot_z[s] == z) return s;
+    return -1;
+}
+
+bool hits_origin(const Plan2C* p, double z) {
+    for (double b : p->b)
+        if (!(std::sqrt(b * b + z * z) > 0.0)) return true;
+    return false;
+}
+
+// One RK4 step z -> z + h of every path.
+int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
+    const double zm = z + 0.5 * h, zn = z + h;
+    int s0 = find_slot(p, z);
+    const bool have0 = s0 >= 0;
+    if (!have0) s0 = 0;
+    int sm = -1, sn = -1;
+    for (int s = 0; s < kSlots2C; ++s) {
+        if (s == s0) continue;
+        if (sm < 0) sm = s;
+        else sn = s;
+    }
+    for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+    int rc;
+    for (Group2C& g : p->groups) {
+        const int npath = (int)g.paths.size();
+        const int chunk = p->batched ? npath : 1;
+        for (int l0 = 0; l0 < npath; l0 += chunk) {
+            const int np = std::min(chunk, npath - l0);
+            if (!have0) {
+                const int sl[1] = {s0};
+                const double zz[1] = {z};
+                if ((rc = enqueue_couplings(p, g, l0, np, 1, sl, zz, st))) return rc;
+            }
+            const int sl[2] = {sm, sn};
+            const double zz[2] = {zm, zn};
+            if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, st))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 1, s0, h, X, X, p->d_Ua, st))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 2, sm, h, p->d_Ua, X, p->d_Ub, st))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 3, sm, h, p->d_Ub, X, p->d_Ua, st))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 4, sn, h, p->d_Ua, X, nullptr, st))) return rc;
+        }
+    }
+    // every path keeps its own slots, so they hold these positions for all paths
+    p->slot_ok[s0] = p->slot_ok[sm] = p->slot_ok[sn] = true;
+    p->slot_z[s0] = z;
+    p->slot_z[sm] = zm;
+    p->slot_z[sn] = zn;
+    return WPCCC_OK;
+}
+
+}  // namespace
+
+int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,
+                  const int* set_of_traj, const double* b, const double* v, const wpccc_plan_opts& o,
+                  hipStream_t st, Plan2C** out) {
+    *out = nullptr;
+    if (o.q_lower != WPCCC_Q_DAGGER && o.q_lower != WPCCC_Q_PRIOR) {
+        set_error("wpccc_plan_create_2c: q_lower must be WPCCC_Q_DAGGER or WPCCC_Q_PRIOR");
+        return WPCCC_EINVAL;
+    }
+    if (o.n_eta < 4 || o.n_eta > 1024 || o.n_tau < 4 || o.n_tau > 4096) {
+        set_error("wpccc_plan_create_2c: n_eta must be in [4, 1024] and n_tau in [4, 4096]");
+        return WPCCC_EINVAL;
+    }
+    for (int s = 0; s < n_sets; ++s)
+        if (!targets[s] || !projectiles[s]) {
+            set_error("wpccc_plan_create_2c: NULL basis in set %d", s);
+            return WPCCC_EINVAL;
+        }
+    for (int j = 0; j < n_traj; ++j) {
+        if (set_of_traj[j] < 0 || set_of_traj[j] >= n_sets) {
+            set_error("wpccc_plan_create_2c: path %d names set %d of %d", j, set_of_traj[j], n_sets);
+            return WPCCC_EINVAL;
+        }
+        if (!(b[j] > 0.0) || !(v[j] > 0.0) || !std::isfinite(b[j]) || !std::isfinite(v[j])) {
+            set_error("wpccc_plan_create_2c: path %d needs finite b > 0 and v > 0", j);
+            return WPCCC_EINVAL;
+        }
+    }
+    int rc;
+    for (int s = 0; s < n_sets; ++s) {
+        if ((rc = check_basis(targets[s]->hb, "target"))) return rc;
+        if ((rc = check_basis(projectiles[s]->hb, "projectile"))) return rc;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("wpccc_plan_create_2c: no HIP device available");
+        return WPCCC_EHIP;
+    }
+    Plan2C* p = new (std::nothrow) Plan2C;
+    if (!p) {
+        set_error("wpccc_plan_create_2c: out of host memory");
+        return WPCCC_ENOMEM;
+    }
+    p->n_traj = n_traj;
+    p->batched = o.batched ? 1 : 0;
+    p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
+    p->n_eta = o.n_eta;
+    p->n_tau = o.n_tau;
+    p->b.assign(b, b + n_traj);
+    p->v.assign(v, v + n_traj);
+    p->group_of.assign(n_traj, -1);
+    p->local_of.assign(n_traj, -1);
+    int maxN = 0;
+    for (int s = 0; s < n_sets; ++s) {
+        Group2C g;
+        g.tb = &targets[s]->hb;
+        g.pb = &projectiles[s]->hb;
+        for (int j = 0; j < n_traj; ++j)
+            if (set_of_traj[j] == s) {
+                p->group_of[j] = (int)p->groups.size();
+                p->local_of[j] = (int)g.paths.size();
+                g.paths.push_back(j);
+            }
+        if (g.paths.empty()) continue;
+        maxN = std::max(maxN, g.tb->n_states + g.pb->n_states);
+        p->groups.push_back(g);
+    }
+    p->n_pad = (maxN + 7) & ~7;
+    auto fail = [&](int code) {
+        plan2c_destroy(p);
+        return code;
+    };
+    for (Group2C& g : p->groups)
+        if ((rc = build_group(p, g, st))) return fail(rc);
+    std::vector<double> xl, wl, tl, wt;
+    gauss_laguerre_scaled(p->n_eta, xl, wl);
+    gauss_legendre(p->n_tau, tl, wt);
+    long long& tot = p->bytes;
+    if ((rc = dev_alloc(&p->d_b, (size_t)n_traj, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_v, (size_t)n_traj, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_flag, 4, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_Ua, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_Ub, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_Xacc, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_xlag, xl.size(), tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_wlag, wl.size(), tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_tleg, tl.size(), tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_wleg, wt.size(), tot))) return fail(rc);
+    if ((rc = upload(p->d_b, b, n_traj * sizeof(double), st))) return fail(rc);
+    if ((rc = upload(p->d_v, v, n_traj * sizeof(double), st))) return fail(rc);
+    if ((rc = upload(p->d_xlag, xl.data(), xl.size() * sizeof(double), st))) return fail(rc);
+    if ((rc = upload(p->d_wlag, wl.data(), wl.size() * sizeof(double), st))) return fail(rc);
+    if ((rc = upload(p->d_tleg, tl.data(), tl.size() * sizeof(double), st))) return fail(rc);
+    if ((rc = upload(p->d_wleg, wt.data(), wt.size() * sizeof(double), st))) return fail(rc);
+    hipError_t e = hipMemsetAsync(p->d_flag, 0, 4 * sizeof(int), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error("wpccc_plan_create_2c: device setup failed: %s", hipGetErrorString(e));
+        return fail(WPCCC_EHIP);
+    }
+    *out = p;
+    return WPCCC_OK;
+}
+
+void plan2c_destroy(Plan2C* p) {
+    if (!p) return;
+    for (Group2C& g : p->groups) free_group(g);
+    void* bufs[] = {p->d_b, p->d_v, p->d_flag, p->d_Ua, p->d_Ub, p->d_Xacc, p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg};
+    for (void* q : bufs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+int plan2c_info(Plan2C* p, int* n_traj, int* n_states, int* n_pad, long long* bytes) {
+    int maxN = 0;
+    for (const Group2C& g : p->groups) maxN = std::max(maxN, g.m.N);
+    if (n_traj) *n_traj = p->n_traj;
+    if (n_states) *n_states = maxN;
+    if (n_pad) *n_pad = p->n_pad;
+    if (bytes) *bytes = p->bytes;
+    return WPCCC_OK;
+}
+
+int plan2c_path_info(Plan2C* p, int j, int* n_states, int* n_target) {
+    if (j < 0 || j >= p->n_traj) {
+        set_error("wpccc_plan_path_info: path index out of range");
+        return WPCCC_EINVAL;
+    }
+    const Group2C& g = p->groups[p->group_of[j]];
+    if (n_states) *n_states = g.m.N;
+    if (n_target) *n_target = g.m.NT;
+    return WPCCC_OK;
+}
+
+int plan2c_status(Plan2C* p, hipStream_t st) {
+    int flag[4] = {0, 0, 0, 0};
+    WPCCC_HIP_CHECK(hipMemcpyAsync(flag, p->d_flag, sizeof flag, hipMemcpyDeviceToHost, st));
+    WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_flag, 0, sizeof flag, st));
+    WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+    if (flag[1]) {
+        set_error("overlap matrix S singular on path %d (zero pivot in column %d)", flag[1] - 1, flag[2]);
+        return WPCCC_ESINGULAR;
+    }
+    if (flag[0]) {
+        set_error("non-finite amplitude detected during propagation");
+        return WPCCC_ENUMERIC;
+    }
+    return WPCCC_OK;
+}
+
+int plan2c_couplings(Plan2C* p, int j, double z, void* H, void* S, hipStream_t st) {
+    if (j < 0 || j >= p->n_traj) {
+        set_error("wpccc_couplings: path index out of range");
+        return WPCCC_EINVAL;
+    }
+    if (!S) {
+        set_error("wpccc_couplings: S_dev is required for a two-centre plan");
+        return WPCCC_EINVAL;
+    }
+    if (!(std::sqrt(p->b[j] * p->b[j] + z * z) > 0.0)) {
+        set_error("wpccc_couplings: R = 0");
+        return WPCCC_EINVAL;
+    }
+    Group2C& g = p->groups[p->group_of[j]];
+    const int l = p->local_of[j];
+    for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+    const int sl[1] = {0};
+    const double zz[1] = {z};
+    int rc = enqueue_couplings(p, g, l, 1, 1, sl, zz, st);
+    if (rc) return rc;
+    const size_t NN = (size_t)g.m.N * g.m.N;
+    const size_t off = (size_t)l * kSlots2C * NN;
+    WPCCC_HIP_CHECK(hipMemcpyAsync(H, g.d_H + off, NN * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    return launched(launch_transpose_copy(g.d_S + off, (double2*)S, g.m.N, st), "k_transpose_copy");
+}
+
+int plan2c_step(Plan2C* p, void* X, double z, double h, hipStream_t st) {
+    if (hits_origin(p, z) || hits_origin(p, z + 0.5 * h) || hits_origin(p, z + h)) {
+        set_error("wpccc_step: R = 0 on the step");
+        return WPCCC_EINVAL;
+    }
+    return enqueue_step(p, (double2*)X, z, h, st);
+}
+
+int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* Xv, void* P, void* norm, hipStream_t st) {
+    for (int i = 0; i < n_points; ++i)
+        if (hits_origin(p, zgrid[i]) || (i + 1 < n_points && hits_origin(p, 0.5 * (zgrid[i] + zgrid[i + 1])))) {
+            set_error("wpccc_propagate: R = 0 on the grid");
+            return WPCCC_EINVAL;
+        }
+    double2* X = (double2*)Xv;
+    int rc;
+    for (int i = 0; i + 1 < n_points; ++i)
+        if ((rc = enqueue_step(p, X, zgrid[i], zgrid[i + 1] - zgrid[i], st))) return rc;
+    if (!P && !norm) return WPCCC_OK;
+    const double zl = zgrid[n_points - 1];
+    for (Group2C& g : p->groups) {
+        const int npath = (int)g.paths.size();
+        int slot = find_slot(p, zl);
+        if (slot < 0) {
+            // S at the last point for every path of the group
+            slot = 0;
+            for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+            const int sl[1] = {0};
+            const double zz[1] = {zl};
+            const int chunk = std::max(1, g.max_jobs);
+            for (int l0 = 0; l0 < npath; l0 += chunk)
+                if ((rc = enqueue_couplings(p, g, l0, std::min(chunk, npath - l0), 1, sl, zz, st))) return rc;
+        }
+        if ((rc = launched(launch_2c_finish(X, g.d_S, g.m.N, p->n_pad, g.d_paths, npath, slot, (double*)P,
+                                            (double*)norm, st),
+                           "k_2c_finish")))
+            return rc;
+    }
+    return WPCCC_OK;
+}
+
+}  // namespace wpccc

@@ -96,3 +96,53 @@ def random_state(n_paths: int, n_states: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n_paths, n_states)) + 1j * rng.standard_normal((n_paths, n_states))
     return X / np.linalg.norm(X, axis=1, keepdims=True)
+
+
+@dataclass
+class TwoCentreWorkload:
+    """Paths of a two-centre batch: path j expands in the basis pair
+    (targets[set_of[j]], projectiles[set_of[j]])."""
+    name: str
+    description: str
+    targets: list
+    projectiles: list
+    set_of: np.ndarray
+    b: np.ndarray
+    v: np.ndarray
+    zgrid: np.ndarray
+    n_eta: int = 256
+    n_tau: int = 512
+    q_lower: str = "prior"   # lower-left block of H: "prior" or "dagger" (Q^dagger as printed)
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.zgrid.size - 1)
+
+
+def two_centre_batched() -> TwoCentreWorkload:
+    """p + H with capture: three basis sizes per centre (bound n <= 6 plus 11, 13
+    or 15 Coulomb bins per l, l <= 4, 4000-point grid: 355, 405 or 455 states per
+    centre), 8 impact parameters b log-spaced 0.1..10 at each of v = 0.5, 1, 2
+    (v = 0.5 with the smallest basis, 2 with the largest), 24 paths in one batch,
+    256 x 512 spheroidal nodes, z from -40 to 40 with dz = 0.1."""
+    recs = [Recipe(6, 4, nb, 3.0, 4000) for nb in (11, 13, 15)]
+    k = np.arange(24) % 8
+    s = np.arange(24) // 8
+    b = 0.1 * 100.0 ** (k / 7.0)
+    v = np.array([0.5, 1.0, 2.0])[s]
+    return TwoCentreWorkload("p+H 2C N=710..910 x24 b", "two-centre with capture, FP64, uneven bases",
+                             recs, recs, s.astype(np.int32), b, v, z_uniform(-40.0, 40.0, 0.1))
+
+
+def two_centre_small() -> TwoCentreWorkload:
+    """A two-centre batch the oracle finishes in seconds: target bound n <= 2 plus
+    one bin (l <= 1) or n <= 3 plus one bin (l <= 2), projectile n <= 2 plus two
+    bins (l <= 1), 600-point grid to 40 a.u.; three paths (b = 0.8, 1.5, 3, v = 0.5,
+    1, 2), 24 x 32 nodes, z from -4 to 4 with dz = 0.5."""
+    t0 = Recipe(2, 1, 1, 1.5, 600, 40.0)
+    t1 = Recipe(3, 2, 1, 1.5, 600, 40.0)
+    p0 = Recipe(2, 1, 2, 1.5, 600, 40.0)
+    return TwoCentreWorkload("p+H 2C small", "two-centre, FP64, oracle-sized",
+                             [t0, t1], [p0, p0], np.array([0, 1, 0], dtype=np.int32),
+                             np.array([0.8, 1.5, 3.0]), np.array([0.5, 1.0, 2.0]),
+                             z_uniform(-4.0, 4.0, 0.5), n_eta=24, n_tau=32)

@@ -76,3 +76,26 @@ def test_plan_without_gpu_fails_loudly(lib):
     with pytest.raises(W.WpcccError) as ei:
         W.wpccc_plan_create(hb, [1.0], [1.0], stream=0)
     assert ei.value.code == -3
+
+
+@pytest.mark.parametrize("bad", [dict(q_lower=2), dict(n_eta=2), dict(n_tau=5000), dict(sets=[1]),
+                                 dict(b=[0.0]), dict(v=[-1.0])])
+def test_two_centre_plan_arguments_rejected(lib, bad):
+    """Argument checks of wpccc_plan_create_2c run on the host, before any device call."""
+    hb = W.wpccc_basis(W.BasisSpec(2, 1, 2, 1.0, 100, 50.0))
+    kw = dict(q_lower=0, n_eta=8, n_tau=8, sets=[0], b=[1.0], v=[1.0])
+    kw.update(bad)
+    with pytest.raises(W.WpcccError) as ei:
+        W.wpccc_plan_create_2c([hb], [hb], kw["sets"], kw["b"], kw["v"], q_lower=kw["q_lower"],
+                               n_eta=kw["n_eta"], n_tau=kw["n_tau"], stream=0)
+    assert ei.value.code == -1
+
+
+def test_two_centre_plan_without_gpu_fails_loudly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: plan creation is exercised by the GPU tests")
+    hb = W.wpccc_basis(W.BasisSpec(2, 1, 2, 1.0, 100, 50.0))
+    with pytest.raises(W.WpcccError) as ei:
+        W.wpccc_plan_create_2c([hb], [hb], [0], [1.0], [1.0], n_eta=8, n_tau=8, stream=0)
+    assert ei.value.code == -3
