@@ -63,6 +63,34 @@ def n_triples(n_l, l_max):
     return t
 
 
+def n_frow_entries(n_l, l_max):
+    """Radial-integral entries of the row layout: for every output l' and input
+    l, N_l' x N_l entries per multipole lambda = |l-l'|..l+l' step 2."""
+    return sum(n_l[lp] * n_l[l] * (min(l, lp) + 1) for lp in range(l_max + 1) for l in range(l_max + 1))
+
+
+def profiled_traffic(summary, source):
+    """HBM bytes per launch recorded in profiles/<summary> by the FETCH_SIZE and
+    WRITE_SIZE counter runs, or None when the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2403_04252_amd", "csrc", source)
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, _, v = line.strip().partition(":")
+            fields[k.strip()] = v.strip()
+    key = source.replace(".hip", "").replace("kernels_", "kernels_") + "_sha256"
+    if fields.get(key) != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def run_propagation(W, plan, X, zgrid, K):
     """Advance every path by K RK4 steps along the grid (wrapping to the start)."""
     done = 0
@@ -76,10 +104,19 @@ def run_propagation(W, plan, X, zgrid, K):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=800, help="timed RK4 steps (each over all paths)")
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed RK4 steps, each over all paths (default 800; 20 for c3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 40; 2 for c3)")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: batched one-centre N=580 (the headline); c3: batched two-centre")
+    ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the one-path-per-launch comparison (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, launch one elementwise copy kernel that reads and writes "
+                         "MIB MiB each (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -87,6 +124,12 @@ def main():
               f"(paths shard across GPUs without communication; see DESIGN.md). "
               f"--gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c3":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        return bench_two_centre(args)
+    args.steps = 800 if args.steps is None else args.steps
+    args.warmup = 40 if args.warmup is None else args.warmup
 
     import torch
     import paper_2403_04252_amd as W
@@ -132,31 +175,46 @@ def main():
 
     stage_flops = stage_work(n_l, rec.l_max) * n_traj
     stage_avg_s = st_ms / max(st_n, 1) * 1e-3
-    trip = n_triples(n_l, rec.l_max)
-    setup_avg_s = su_ms / max(su_n, 1) * 1e-3
-    dominant = "k_stage"
-    if dominant == "k_stage":
-        achieved = stage_flops / stage_avg_s / 1e12
-        roof = {"kernel": "k_stage", "bound": "alu", "achieved": achieved,
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "avg_launch_us": stage_avg_s * 1e6, "launches": st_n,
-                "algorithmic_flops_per_launch": stage_flops}
+    # algorithmic bytes of one k_stage launch: every path reads its rows of the
+    # moment table (one (A_k, B_k+1) pair of 16 B per radial-integral entry) and
+    # five amplitude vectors (u_in, X, Xacc in and out, u_out)
+    n_entries = n_frow_entries(n_l, rec.l_max)
+    stage_bytes = n_traj * (n_entries * 16 + 5 * n_states * 16)
+    achieved = stage_bytes / stage_avg_s / 1e9
+    roof = {"kernel": "k_stage", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic("k_stage_1c_N580x32.md", "kernels_1c.hip"),
+            "avg_launch_us": stage_avg_s * 1e6, "launches": st_n,
+            "algorithmic_bytes_per_launch": stage_bytes,
+            "flops_per_launch": stage_flops,
+            "fp64_alu_frac": stage_flops / stage_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     kernel_times = {"k_stage": {"total_ms": st_ms, "launches": st_n},
                     "k_prologue": {"total_ms": su_ms, "launches": su_n}}
 
     # plain FP64 form: the same paths one after another
-    seq_steps = min(args.steps, 100)
-    plan_seq = W.wpccc_plan_create(lb, w.b, w.v, batched=False)
-    X.zero_()
-    X[:, 0] = 1.0
-    run_propagation(W, plan_seq, X, w.zgrid, 5)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_propagation(W, plan_seq, X, w.zgrid, seq_steps)
-    torch.cuda.synchronize()
-    seq_value = n_traj * seq_steps / (time.perf_counter() - t0)
-    del plan_seq
+    seq = None
+    if not args.no_sequential:
+        seq_steps = min(args.steps, 100)
+        plan_seq = W.wpccc_plan_create(lb, w.b, w.v, batched=False)
+        X.zero_()
+        X[:, 0] = 1.0
+        run_propagation(W, plan_seq, X, w.zgrid, 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_propagation(W, plan_seq, X, w.zgrid, seq_steps)
+        torch.cuda.synchronize()
+        seq = {"value": n_traj * seq_steps / (time.perf_counter() - t0), "unit": "trajectory-steps/s",
+               "steps": seq_steps}
+        del plan_seq
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     prob_err = None
@@ -211,8 +269,127 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "prob_error": prob_err,
-        "plain_fp64_sequential": {"value": seq_value, "unit": "trajectory-steps/s", "steps": seq_steps},
+        "plain_fp64_sequential": seq,
         "kernel_times": kernel_times,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def n_per_l(rec):
+    """Radial functions per l of a basis recipe: bound n <= n_max (n > l) plus the bins."""
+    return [max(0, rec.n_max - l) + rec.n_bins for l in range(rec.l_max + 1)]
+
+
+def contract_flops(recT, recP, n_w, n_act):
+    """Algorithmic flops of the Eq. K2 contraction of one position: for molecular
+    |q'| = s, |q| = t, 2 * nk(s, t) * nA[s] * nB[t] per active node, nA[s] = radial
+    functions of the target with l >= s; nk = 2 n_w weights (cos, sin) per
+    Bessel order, one order when s t = 0 and two (|s-t|, s+t) otherwise."""
+    nlT, nlP = n_per_l(recT), n_per_l(recP)
+    nA = [sum(nlT[s:]) for s in range(len(nlT))]
+    nB = [sum(nlP[t:]) for t in range(len(nlP))]
+    tot = 0
+    for s in range(len(nA)):
+        for t in range(len(nB)):
+            nk = (2 if s > 0 and t > 0 else 1) * 2 * n_w
+            tot += 2 * nk * nA[s] * nB[t]
+    return tot * n_act
+
+
+def bench_two_centre(args):
+    """Batched two-centre propagation (Eq. 1 with capture) on one GPU."""
+    import torch
+    from scipy.special import roots_laguerre
+    import paper_2403_04252_amd as W
+    from paper_2403_04252_amd import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WL.two_centre_batched(args.v)
+    bases = [W.wpccc_basis(W.BasisSpec(r.n_max, r.l_max, r.n_bins, r.k_max, r.n_r, r.r_max, r.Z))
+             for r in w.targets]
+    ql = W.WPCCC_Q_PRIOR if w.q_lower == "prior" else W.WPCCC_Q_DAGGER
+    t0 = time.perf_counter()
+    plan = W.wpccc_plan_create_2c(bases, bases, w.set_of, w.b, w.v, q_lower=ql, n_eta=w.n_eta, n_tau=w.n_tau)
+    setup_s = time.perf_counter() - t0
+    n_traj = plan.n_traj
+    X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    run_propagation(W, plan, X, w.zgrid, args.warmup)
+    torch.cuda.synchronize()
+    X.zero_()
+    X[:, 0] = 1.0
+    zs = w.zgrid[: args.steps + 1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W.wpccc_propagate(plan, zs, X)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    W.wpccc_plan_status(plan)
+    value = n_traj * args.steps / wall
+
+    # per-kernel device time over the same steps (events on the library's stream)
+    X.zero_()
+    X[:, 0] = 1.0
+    W.wpccc_plan_timing(plan, True)
+    W.wpccc_propagate(plan, zs, X)
+    names = ["k_2c_contract", "k_2c_nodes", "k_2c_assemble", "k_setup_batch", "k_2c_direct", "k_lu_panel",
+             "k_lu_swap_trsm", "k_lu_update", "k_2c_stage"]
+    kt = {}
+    for nm in names:
+        ms, n = W.wpccc_plan_kernel_time(plan, nm)
+        kt[nm] = {"total_ms": ms, "launches": n}
+    W.wpccc_plan_timing(plan, False)
+    torch.cuda.synchronize()
+
+    # algorithmic flops of the contraction over the timed steps: the first step
+    # computes z, z_mid, z_new, later steps z_mid and z_new
+    n_w = 3 if w.q_lower == "prior" else 2
+    xl = roots_laguerre(w.n_eta)[0]
+    fl = 0
+    for i in range(args.steps):
+        pos = [zs[i], 0.5 * (zs[i] + zs[i + 1]), zs[i + 1]] if i == 0 else [0.5 * (zs[i] + zs[i + 1]), zs[i + 1]]
+        for j in range(n_traj):
+            rec = w.targets[w.set_of[j]]
+            for z in pos:
+                R = math.hypot(w.b[j], z)
+                lim = (2 * rec.r_max - R) * (1.0 + 1e-12) + 1e-12
+                n_act = int(np.sum(xl <= lim)) * w.n_tau
+                fl += contract_flops(rec, rec, n_w, n_act)
+    c_ms = kt["k_2c_contract"]["total_ms"]
+    achieved = fl / (c_ms * 1e-3) / 1e12
+    roof = {"kernel": "k_2c_contract", "bound": "mfma", "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None, "avg_launch_us": c_ms / max(kt["k_2c_contract"]["launches"], 1) * 1e3,
+            "launches": kt["k_2c_contract"]["launches"], "algorithmic_flops_total": fl}
+    lu_fl = 0
+    for j in range(n_traj):
+        N = 2 * sum((2 * l + 1) * n for l, n in enumerate(n_per_l(w.targets[w.set_of[j]])))
+        lu_fl += (args.steps * 2 + 1) * 8.0 / 3.0 * N ** 3
+    lu_ms = sum(kt[k]["total_ms"] for k in ("k_lu_panel", "k_lu_swap_trsm", "k_lu_update"))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + ": same recipe on both centres (n<=6 + 20 bins/l, l<=1/2/3), "
+                               "4000-pt grid, 8 b log-spaced 0.2-10 per size, 256x512 nodes, "
+                               f"z -40..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
+                   "form": "batched FP64", "n_paths": n_traj, "plan_setup_s": setup_s,
+                   "parallelism": "1 GPU, paths batched per basis size"},
+        "roofline": roof,
+        "lu": {"algorithmic_flops": lu_fl, "device_ms": lu_ms,
+               "achieved_tflops": lu_fl / max(lu_ms * 1e-3, 1e-12) / 1e12},
+        "kernel_times": kt,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
