@@ -129,6 +129,9 @@ typedef struct {
     int q_lower;    /* 2C: WPCCC_Q_DAGGER (default) or WPCCC_Q_PRIOR */
     int n_eta;      /* 2C: Gauss-Laguerre nodes in eta (0 means 256) */
     int n_tau;      /* 2C: Gauss-Legendre nodes in tau (0 means 512) */
+    double model_a; /* 1C: screened target potential V(r) = -(1 + a e^{-c r})/r on the */
+    double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
+    int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
 } wpccc_plan_opts;
 
 /* Create a plan for n_traj paths with impact parameters b_host[j] > 0 and
@@ -201,6 +204,23 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
  * WPCCC_ESINGULAR is latched (wpccc_plan_status) for an exact zero pivot. */
 int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
                     void* X_dev, void* P_dev, void* norm_dev, void* stream);
+
+/* Gradients of a real loss of the final amplitudes (1C; Algorithm 1 on the
+ * given grid differentiated exactly, reverse mode): the forward propagation
+ * from X0 stores the state every `checkpoint_every` steps, the reverse sweep
+ * recomputes each segment and runs the adjoint of every RK4 step,
+ *   lambda_n = A_n^H lambda_(n+1),
+ *   dL/dtheta += 2 Re(mu_k^H (dM/dtheta) u_k)  over the four stages,
+ * with M^H = -M (Hermitian D_T) and dM/dtheta for theta = a, c (model
+ * potential, plan options) and b (Eq. D1/D2 differentiated at fixed z).
+ *   X0_dev    complex [n_traj][n_pad], initial amplitudes (read)
+ *   X_dev     complex [n_traj][n_pad], final amplitudes (written; may be NULL)
+ *   gX_dev    complex [n_traj][n_pad], dL/d conj(X) at the last point (read)
+ *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
+ * Device memory for the checkpoints is allocated by the first call.  Errors:
+ * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan). */
+int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
+                  void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics: per-kernel device time with HIP events.                      */

@@ -19,7 +19,7 @@ __all__ = [
     "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_create_2c", "wpccc_plan_info",
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
-    "wpccc_plan_timing", "wpccc_plan_kernel_time",
+    "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,7 +46,9 @@ class _Spec(ctypes.Structure):
 
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int),
-                ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int)]
+                ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int),
+                ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
+                ("checkpoint_every", ctypes.c_int)]
 
 
 @dataclass
@@ -93,6 +95,7 @@ def load_library():
         "wpccc_couplings": ([vp, i, d, vp, vp, vp], i),
         "wpccc_step": ([vp, vp, d, d, vp], i),
         "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
+        "wpccc_adjoint": ([vp, pd, i, vp, vp, vp, vp, vp], i),
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
     }
@@ -197,12 +200,15 @@ def wpccc_basis_destroy(basis: Basis):
 
 
 def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
-                      two_centre: bool = False, stream=None) -> Plan:
-    """Plan for len(b) straight-line paths in one basis; b, v in a.u."""
+                      two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
+                      checkpoint_every: int = 0, stream=None) -> Plan:
+    """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
+    model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
-    opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0)
+    opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
+                     float(model_a), float(model_c), int(checkpoint_every))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -226,7 +232,7 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
         raise ValueError("targets and projectiles must pair up")
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
-    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau))
+    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
@@ -287,6 +293,18 @@ def wpccc_propagate(plan: Plan, zgrid, X, P=None, norm=None, stream=None):
         plan.handle, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(z.size),
         _dev_ptr(X, "complex128", shp, "X"), _dev_ptr(P, "float64", shp, "P"),
         _dev_ptr(norm, "float64", (plan.n_traj,), "norm"), _stream_ptr(stream)))
+
+
+def wpccc_adjoint(plan: Plan, zgrid, X0, gX, grad, X=None, stream=None):
+    """Reverse-mode gradients (see include/wpccc.h): grad (float64 CUDA [n_traj, 3])
+    <- dL/da, dL/dc, dL/db per path, given gX = dL/d conj(X) at the last point."""
+    z = np.ascontiguousarray(zgrid, dtype=np.float64)
+    shp = (plan.n_traj, plan.n_pad)
+    _check(load_library().wpccc_adjoint(
+        plan.handle, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(z.size),
+        _dev_ptr(X0, "complex128", shp, "X0"), _dev_ptr(X, "complex128", shp, "X"),
+        _dev_ptr(gX, "complex128", shp, "gX"), _dev_ptr(grad, "float64", (plan.n_traj, 3), "grad"),
+        _stream_ptr(stream)))
 
 
 def wpccc_plan_timing(plan: Plan, enable: bool):

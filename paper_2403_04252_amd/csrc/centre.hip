@@ -65,7 +65,28 @@ void centre_free(Centre& c) {
     c = Centre{};
 }
 
-int centre_build(const HostBasis& hb, hipStream_t st, Centre& c) {
+void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& va, std::vector<double>& vc) {
+    va.clear();
+    vc.clear();
+    for (int l = 0; l <= hb.spec.l_max; ++l) {
+        const int nl = hb.n_l[l];
+        for (int np = 0; np < nl; ++np)
+            for (int n = 0; n < nl; ++n) {
+                const double* fp = hb.phi.data() + (size_t)(hb.rad_off[l] + np) * (hb.n_r + 1);
+                const double* f = hb.phi.data() + (size_t)(hb.rad_off[l] + n) * (hb.n_r + 1);
+                double sa = 0.0, sc = 0.0;
+                for (int i = 1; i <= hb.n_r; ++i) {
+                    const double r = hb.r[i], e = std::exp(-c * r) * hb.w[i] * fp[i] * f[i];
+                    sa += r * e;
+                    sc += r * r * e;
+                }
+                va.push_back(-sa);
+                vc.push_back(a * sc);
+            }
+    }
+}
+
+int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a, double model_c, double Zp) {
     if (hb.spec.l_max > kMaxL) {
         set_error("basis l_max %d exceeds %d", hb.spec.l_max, kMaxL);
         return WPCCC_EINVAL;
@@ -202,8 +223,36 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c) {
     up(d_dl, dl.data(), dl.size() * sizeof(int));
     if (rc == WPCCC_OK && e == hipSuccess)
         e = launch_moments(d_r, d_w, d_phiT, d_da, d_db, d_dl, m.n_r, m.n_f, m.n_frow, c.d_tab, st);
+    // model potential: -DeltaV / Zp on the lambda = 0 moments B of the equal-l
+    // blocks (D = Zp sum G F with G = -1 for lambda = 0, l = l', m = m')
+    std::vector<int> sh_idx;
+    std::vector<double> sh_val;
+    int* d_sidx = nullptr;
+    double* d_sval = nullptr;
+    if (model_a != 0.0) {
+        std::vector<double> va, vc;
+        model_blocks(hb, model_a, model_c, va, vc);
+        size_t vo = 0;
+        for (int l = 0; l <= m.l_max; ++l) {
+            int e0, g0;
+            block_columns(m, l, l, 0, e0, g0);
+            const int nl = m.n_l[l];
+            for (int np = 0; np < nl; ++np)
+                for (int n = 0; n < nl; ++n) {
+                    sh_idx.push_back(m.frow_off[l] + np * m.nV[l] + e0 + n);
+                    sh_val.push_back(-model_a * va[vo + (size_t)np * nl + n] / Zp);
+                }
+            vo += (size_t)nl * nl;
+        }
+        A(dev_alloc(&d_sidx, sh_idx.size(), tmp));
+        A(dev_alloc(&d_sval, sh_val.size(), tmp));
+        up(d_sidx, sh_idx.data(), sh_idx.size() * sizeof(int));
+        up(d_sval, sh_val.data(), sh_val.size() * sizeof(double));
+        if (rc == WPCCC_OK && e == hipSuccess)
+            e = launch_table_shift(c.d_tab, m.n_frow, m.n_r, d_sidx, d_sval, (int)sh_idx.size(), st);
+    }
     if (rc == WPCCC_OK && e == hipSuccess) e = hipStreamSynchronize(st);
-    void* tq[] = {d_r, d_w, d_phiT, d_da, d_db, d_dl};
+    void* tq[] = {d_r, d_w, d_phiT, d_da, d_db, d_dl, d_sidx, d_sval};
     for (void* x : tq)
         if (x) (void)hipFree(x);
     if (rc == WPCCC_OK && e != hipSuccess) {

@@ -86,6 +86,27 @@ __device__ void legendre_column(int lam_max, int mu, double x, double* pb) {
     }
 }
 
+// dPbar_l^mu/dx for l = mu..lam_max into pb[pb_index(l, mu)], from
+// (x^2 - 1) dPbar_l^mu/dx = l x Pbar_l^mu - sqrt((l+mu)(l-mu)) Pbar_(l-1)^mu, |x| < 1.
+__device__ void legendre_column_dx(int lam_max, int mu, double x, double* pb) {
+    const double s = sqrt(fmax(0.0, 1.0 - x * x));
+    const double den = x * x - 1.0;
+    double pmm = 1.0;
+    for (int i = 1; i <= mu; ++i) pmm *= -sqrt((2.0 * i - 1.0) / (2.0 * i)) * s;
+    pb[pb_index(mu, mu)] = mu * x * pmm / den;
+    if (mu + 1 > lam_max) return;
+    double p0 = pmm;
+    double p1 = sqrt(2.0 * mu + 1.0) * x * pmm;
+    pb[pb_index(mu + 1, mu)] = ((mu + 1) * x * p1 - sqrt((double)(2 * mu + 1)) * p0) / den;
+    for (int l = mu + 1; l < lam_max; ++l) {
+        const double p2 = ((2.0 * l + 1.0) * x * p1 - sqrt((double)(l + mu) * (l - mu)) * p0) /
+                          sqrt((double)(l + 1 + mu) * (l + 1 - mu));
+        pb[pb_index(l + 1, mu)] = ((l + 1) * x * p2 - sqrt((double)(l + 1 + mu) * (l + 1 - mu)) * p1) / den;
+        p0 = p1;
+        p1 = p2;
+    }
+}
+
 // Last grid node with r_k <= R; the nodes r_k = r_max (k/n_r)^2 are recomputed
 // in registers with the same arithmetic as the host grid.
 __device__ inline int grid_index(double R, double r_max, int n_r) {
@@ -140,12 +161,15 @@ constexpr int kXBatch = 4;   // amplitudes per thread held in registers
 constexpr int kGBatch = 4;   // angular coefficients per thread held in registers
 
 // One stage for rows [row0, row0 + nrows) of the l' block, all nmp = 2l'+1 values of m'.
+// KIND 0: RK4 stage (k_stage); KIND 1: operator application (k_apply, see
+// StageArgs) with the same three phases.
 //   phase 0: every independent global load of the stage is issued at once
 //            (table entries, stage input, coefficients) and the per-point
 //            tables (R powers, Pbar, phases) go to LDS;
 //   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
+template <int KIND>
 __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
@@ -220,12 +244,34 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         const int r = o / nmp, qp = o - r * nmp;
         oi = (size_t)j * a.n_pad + m.state_off[lp] + qp * nlp + row0 + r;
         rad_o = m.rad_off[lp] + row0 + r;
-        if (a.stage < 4) x0 = a.X[oi];
-        if (a.stage > 1) xa = a.Xacc[oi];
+        if (KIND == 0) {
+            if (a.stage < 4) x0 = a.X[oi];
+            if (a.stage > 1) xa = a.Xacc[oi];
+        } else {
+            if (a.w) x0 = a.w[oi];
+            if (a.dv) xa = a.dv[oi];
+        }
     }
     for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
-    if (tid < 2 * (m.lam_max + 1)) rps[tid] = a.pt.rpow[jp * kRpow + tid];
-    for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
+    const int deriv = (KIND == 1) ? a.deriv : 0;
+    const double bj = T.bvec[j];
+    const double Rz = sqrt(bj * bj + a.z * a.z);
+    if (deriv == 1) {
+        // d/dR of R^-(lam+1) and R^lam
+        if (tid <= m.lam_max) {
+            double Rl = 1.0;
+            for (int q = 0; q < tid; ++q) Rl *= Rz;
+            rps[2 * tid] = -(tid + 1.0) / (Rl * Rz * Rz);
+            rps[2 * tid + 1] = tid > 0 ? tid * Rl / Rz : 0.0;
+        }
+    } else if (tid < 2 * (m.lam_max + 1)) {
+        rps[tid] = a.pt.rpow[jp * kRpow + tid];
+    }
+    if (deriv == 2) {
+        if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
+    } else {
+        for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
+    }
     for (int i = tid; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
     __syncthreads();
 
@@ -319,12 +365,20 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         re += __shfl_xor(re, off, 64);
         im += __shfl_xor(im, off, 64);
     }
+    double gval = 0.0;
     if (writer) {
         const double2 py = cmul(phs[rad_o], make_double2(re, im));
         const double sc = a.Zp / v;
-        const double2 K = make_double2(sc * py.y, -sc * py.x);  // -(i/v) Zp ph y
+        double2 K = make_double2(sc * py.y, -sc * py.x);  // -(i/v) Zp ph y
         const double h = a.h;
-        if (a.stage == 1) {
+        if (KIND == 1) {
+            if (deriv) {
+                const double f = deriv == 1 ? bj / Rz : -a.z * bj / (Rz * Rz * Rz);
+                K = make_double2(f * K.x, f * K.y);
+            }
+            if (a.out) a.out[oi] = make_double2(a.alpha * K.x + a.beta * x0.x, a.alpha * K.y + a.beta * x0.y);
+            gval = 2.0 * a.gamma * (xa.x * K.x + xa.y * K.y);  // 2 gamma Re(conj(dv) K)
+        } else if (a.stage == 1) {
             a.u_out[oi] = make_double2(x0.x + 0.5 * h * K.x, x0.y + 0.5 * h * K.y);
             a.Xacc[oi] = make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
         } else if (a.stage == 2 || a.stage == 3) {
@@ -335,6 +389,17 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             const double2 xn = make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
             if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
             a.X[oi] = xn;
+        }
+    }
+    if (KIND == 1 && a.grad) {
+        __shared__ double red[kStageThreads / 64];
+        for (int off = 32; off > 0; off >>= 1) gval += __shfl_xor(gval, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = gval;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < B / 64; ++w) sum += red[w];
+            atomicAdd(a.grad + (size_t)j * 3 + a.gslot, sum);
         }
     }
 }
@@ -353,7 +418,108 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
     const int row0 = c * kRowsPerBlock;
     const int nrows = min(kRowsPerBlock, m.n_l[lp] - row0);
     if (nrows <= 0) return;
-    stage_body(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+    stage_body<0>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+}
+
+// Operator application with the grid of k_stage (see StageArgs).
+__global__ __launch_bounds__(kStageThreads) void k_apply(StageArgs a) {
+    extern __shared__ double2 smem2[];
+    const Meta& m = *a.meta;
+    const int j = a.traj0 + blockIdx.y;
+    int c = blockIdx.x, lp = 0;
+    for (; lp < m.l_max; ++lp) {
+        const int nc = (m.n_l[lp] + kRowsPerBlock - 1) / kRowsPerBlock;
+        if (c < nc) break;
+        c -= nc;
+    }
+    const int row0 = c * kRowsPerBlock;
+    const int nrows = min(kRowsPerBlock, m.n_l[lp] - row0);
+    if (nrows <= 0) return;
+    stage_body<1>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+}
+
+// grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] += 2 gamma Re(dv^H dM/dc u),
+// dM/dtheta = -(i/v) ph (dDeltaV/dtheta) conj(ph); one workgroup per path.
+__global__ __launch_bounds__(256) void k_model_dot(ModelArgs a) {
+    const Meta& m = *a.meta;
+    const int j = a.traj0 + blockIdx.x;
+    const size_t jp = (size_t)j * a.pt.n_pts + a.p;
+    const double2* ph = a.pt.ph + jp * m.n_f;
+    const double2* u = a.u + (size_t)j * a.n_pad;
+    const double2* dv = a.dv + (size_t)j * a.n_pad;
+    const double v = a.tb.vvec[j];
+    double sa = 0.0, sc = 0.0;
+    for (int row = threadIdx.x; row < m.n_states; row += blockDim.x) {
+        int lp = 0;
+        while (lp < m.l_max && row >= m.state_off[lp + 1]) ++lp;
+        const int nl = m.n_l[lp];
+        const int rr = row - m.state_off[lp], q = rr / nl, np = rr - q * nl;
+        const int base = m.state_off[lp] + q * nl, rad0 = m.rad_off[lp];
+        int vo = 0;
+        for (int l = 0; l < lp; ++l) vo += m.n_l[l] * m.n_l[l];
+        double2 ca = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
+        for (int n = 0; n < nl; ++n) {
+            const double2 p = ph[rad0 + n], x = u[base + n];
+            const double2 ut = make_double2(p.x * x.x + p.y * x.y, p.x * x.y - p.y * x.x);  // conj(p) x
+            const double fa = a.va[vo + np * nl + n], fc = a.vc[vo + np * nl + n];
+            ca.x += fa * ut.x;
+            ca.y += fa * ut.y;
+            cc.x += fc * ut.x;
+            cc.y += fc * ut.y;
+        }
+        const double2 d = dv[row], p = ph[rad0 + np];
+        const double2 t = make_double2(d.x * p.x + d.y * p.y, d.x * p.y - d.y * p.x);  // conj(d) p
+        // Re(-(i/v) t c) = Im(t c) / v
+        sa += (t.x * ca.y + t.y * ca.x) / v;
+        sc += (t.x * cc.y + t.y * cc.x) / v;
+    }
+    __shared__ double ra[4], rc[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        sa += __shfl_xor(sa, off, 64);
+        sc += __shfl_xor(sc, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        ra[threadIdx.x >> 6] = sa;
+        rc[threadIdx.x >> 6] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tc = 0.0;
+        for (int w = 0; w < (int)blockDim.x / 64; ++w) {
+            ta += ra[w];
+            tc += rc[w];
+        }
+        atomicAdd(a.grad + (size_t)j * 3 + 0, 2.0 * a.gamma * ta);
+        atomicAdd(a.grad + (size_t)j * 3 + 1, 2.0 * a.gamma * tc);
+    }
+}
+
+struct Combine {
+    const double2* v[5];
+    double c[5];
+};
+
+// out = sum_k c_k v_k per path; grid (state blocks, path)
+__global__ __launch_bounds__(256) void k_combine(double2* __restrict__ out, Combine cb, int n_terms, int n,
+                                                 int n_pad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t oi = (size_t)blockIdx.y * n_pad + i;
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k < n_terms; ++k) {
+        const double2 x = cb.v[k][oi];
+        s.x += cb.c[k] * x.x;
+        s.y += cb.c[k] * x.y;
+    }
+    out[oi] = s;
+}
+
+// tab[k][idx[e]].y += val[e] for every grid node k; grid (entries, nodes)
+__global__ void k_table_shift(double2* __restrict__ tab, int n_frow, const int* __restrict__ idx,
+                              const double* __restrict__ val, int count) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    tab[(size_t)blockIdx.y * n_frow + idx[e]].y += val[e];
 }
 
 // Diagnostic path: Frow, G and phases of one (path, z) into scratch arrays.
@@ -460,7 +626,40 @@ int stage_smem_bytes(const Meta& m) {
 }
 
 hipError_t stage_set_smem_limit(int, int bytes) {
-    return hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+hipError_t launch_apply(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st,
+                        const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_apply, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st) {
+    hipLaunchKernelGGL(k_model_dot, dim3(n_traj_launch), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(double2* out, const double2* const* v, const double* c, int n_terms, int n_traj, int n,
+                          int n_pad, hipStream_t st) {
+    Combine cb{};
+    for (int k = 0; k < n_terms && k < 5; ++k) {
+        cb.v[k] = v[k];
+        cb.c[k] = c[k];
+    }
+    hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256, n_traj), dim3(256), 0, st, out, cb, n_terms, n, n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
+                              hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_table_shift, dim3((count + 255) / 256, n_r + 1), dim3(256), 0, st, tab, n_frow, idx, val,
+                       count);
+    return hipGetLastError();
 }
 
 hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da, const int* db,
@@ -470,32 +669,32 @@ hipError_t launch_moments(const double* r, const double* w, const double* phiT, 
     return hipGetLastError();
 }
 
-hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st) {
-    hipLaunchKernelGGL(k_prologue, dim3(a.n, n_traj_launch), dim3(64), 0, st, a);
+hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_prologue, dim3(a.n, n_traj_launch), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st) {
+hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st, const LaunchEv& ev) {
     const int nbG = (hm.n_g + 255) / 256;
-    hipLaunchKernelGGL(k_slot_setup, dim3(a.nbF + a.nbP + nbG), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_slot_setup, dim3(a.nbF + a.nbP + nbG), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st) {
-    hipLaunchKernelGGL(k_stage, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_stage, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_couplings_dense(const Meta* m, const Meta& hm, const double* Frow, const double* G,
-                                  const double2* PH, double Zp, double2* H, hipStream_t st) {
-    hipLaunchKernelGGL(k_couplings_dense, dim3((hm.n_states + 127) / 128, hm.n_states), dim3(128), 0, st, m, Frow,
+                                  const double2* PH, double Zp, double2* H, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_couplings_dense, dim3((hm.n_states + 127) / 128, hm.n_states), dim3(128), 0, st, m, Frow,
                        G, PH, Zp, H);
     return hipGetLastError();
 }
 
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P, double* norm,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_probabilities, dim3(n_traj), dim3(256), 0, st, X, n_states, n_pad, P, norm);
+                                hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_probabilities, dim3(n_traj), dim3(256), 0, st, X, n_states, n_pad, P, norm);
     return hipGetLastError();
 }
 

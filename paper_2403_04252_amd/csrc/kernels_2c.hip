@@ -1,10 +1,10 @@
 // HIP kernels of the two-centre path on gfx950.
 //
 // Per new coupling position (z_mid, z_new of Algorithm 1) and path:
-//   k_2c_nodes     spheroidal nodes (eta, tau) of Eq. K2 at this R: r_A, r_B,
-//                  angles, the phase (v z / 2) eta tau, Bessel J_m(X), the
-//                  quadrature weight times each potential weight, and the
-//                  five-point interpolation stencils at r_A and r_B
+//   k_2c_nodes     spheroidal nodes (eta, tau) of Eq. K2 at this R: the phase
+//                  (v z / 2) eta tau, Bessel J_m(X), the quadrature weight
+//                  times each potential weight, the five-point interpolation
+//                  stencils at r_A and r_B and Pbar_l^m at theta_A, theta_B
 //   k_2c_contract  the Eq. K2 integrals as dense real contractions on MFMA
 //                  (v_mfma_f64_16x16x4): for molecular |q'| = s, |q| = t,
 //                  T[k][a][b] = sum_p A_s[a](p) B_t[b](p) w_k(p) with
@@ -14,8 +14,9 @@
 //                  the Eq. K2 prefactor and the Wigner rotation to the lab
 //                  frame, interaction phases -> K, Q blocks of S and H
 //   k_setup_batch, k_2c_direct   D_T and D_P blocks (Eq. D1 on each centre)
-//   k_lu           LU with partial pivoting of S (LAPACK conventions)
-// Per RK4 stage: k_2c_stage  y = S^{-1} (H u), K = -(i/v) y and the RK4 update.
+// Per RK4 stage: k_2c_hu  y = P (H u) over many workgroups per path, then
+// k_2c_solve  y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update.
+// The LU factorisation of S is in kernels_lu.hip.
 #include <hip/hip_runtime.h>
 
 #include "plan2c.h"
@@ -100,146 +101,146 @@ __global__ __launch_bounds__(256) void k_2c_nodes(NodeArgs a) {
     const size_t nn = m.n_nodes;
     double* nd = a.nodes + (size_t)blockIdx.y * m.n_fields * nn;
     int* js = a.jst + (size_t)blockIdx.y * 2 * nn;
-    nd[0 * nn + p] = rA;
-    nd[1 * nn + p] = rB;
-    nd[2 * nn + p] = cA;
-    nd[3 * nn + p] = cB;
-    nd[4 * nn + p] = cs;
-    nd[5 * nn + p] = sn;
-    nd[6 * nn + p] = om * (eta * eta - tau * tau);
-    nd[7 * nn + p] = om * (-(2.0 * m.ZT / R) * (eta - tau));
-    nd[8 * nn + p] = om * (-(2.0 * m.ZP / R) * (eta + tau));
+    nd[kFCos * nn + p] = cs;
+    nd[kFSin * nn + p] = sn;
+    nd[(kFW + 0) * nn + p] = om * (eta * eta - tau * tau);
+    nd[(kFW + 1) * nn + p] = om * (-(2.0 * m.ZT / R) * (eta - tau));
+    nd[(kFW + 2) * nn + p] = om * (-(2.0 * m.ZP / R) * (eta + tau));
     double L[5];
     js[p] = lagrange5(rA, m.rmaxT, m.nrT, L);
-    for (int i = 0; i < 5; ++i) nd[(9 + i) * nn + p] = L[i];
+    for (int i = 0; i < 5; ++i) nd[(kFLA + i) * nn + p] = L[i];
     js[nn + p] = lagrange5(rB, m.rmaxP, m.nrP, L);
-    for (int i = 0; i < 5; ++i) nd[(14 + i) * nn + p] = L[i];
-    for (int q = 0; q <= 2 * m.L; ++q) nd[(kNodeFixed + q) * nn + p] = jn(q, X);
+    for (int i = 0; i < 5; ++i) nd[(kFLB + i) * nn + p] = L[i];
+    for (int q = 0; q <= 2 * m.L; ++q) nd[(kFJ + q) * nn + p] = jn(q, X);
+    for (int l = 0; l <= m.LT; ++l)
+        for (int mm = 0; mm <= l; ++mm) nd[(m.f_pa + l * (l + 1) / 2 + mm) * nn + p] = pbar(l, mm, cA);
+    for (int l = 0; l <= m.LP; ++l)
+        for (int mm = 0; mm <= l; ++mm) nd[(m.f_pb + l * (l + 1) / 2 + mm) * nn + p] = pbar(l, mm, cB);
 }
 
-constexpr int kMaxFields = kNodeFixed + 2 * kMaxL + 1;
-
-// grid: x = tile (s, t, a0, b0), y = job.  Four waves; each wave owns nk/2
-// column tiles of 16 (B' columns k*32 + b) for both 16-row halves of the tile.
+// One workgroup per (job, tile) with an XCD-aware order: consecutive
+// workgroup ids go to the eight XCDs in turn, and the work items of XCD x are
+// the x-th eighth of the job-major list, so the tiles of one job (which
+// stream the same node fields) share an L2.  Per chunk of kNodeChunk nodes:
+// stage the Lagrange weights, stencil starts, Legendre values and the nk
+// weights w_k of the chunk, then A (32 rows) and B (32 columns) in LDS; each
+// wave owns one 16 x 16 quarter of the tile for all nk weights and feeds the
+// MFMA with (A w_k) and B, so B is staged once for every weight.
 __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
-    extern __shared__ double Bs[];  // [kNodeChunk][32 * nk]
-    __shared__ double As[kNodeChunk][kTile];
-    __shared__ double nf[kNodeChunk][kMaxFields];
-    __shared__ int jA[kNodeChunk], jB[kNodeChunk];
-    __shared__ double PbA[kNodeChunk][kMaxL + 1], PbB[kNodeChunk][kMaxL + 1];
+    __shared__ double As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
     __shared__ double wk[kNodeChunk][kMaxK];
+    __shared__ double sLA[kNodeChunk][5], sLB[kNodeChunk][5];
+    __shared__ double sPA[kNodeChunk][kMaxL + 1], sPB[kNodeChunk][kMaxL + 1];
+    __shared__ int sjA[kNodeChunk], sjB[kNodeChunk];
     const Meta2C& m = *a.m;
-    const int y = blockIdx.y;
-    const int2 tl = a.tiles[blockIdx.x];
+    const int total = m.n_tiles * a.n_jobs;
+    const int per = (total + 7) / 8;
+    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (W >= total) return;
+    const int y = W / m.n_tiles;
+    const int2 tl = a.tiles[W - y * m.n_tiles];
     const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
     const int n_w = m.n_w;
     const int nk = st_nk(s, t, n_w);
     const int o1 = abs(s - t), o2 = s + t;
     const int nA = m.nA[s], nB = m.nB[t];
-    const int nF = m.n_fields;
     const size_t nn = m.n_nodes;
-    const double* nd = a.nodes + (size_t)y * nF * nn;
+    const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
     const int* js = a.jst + (size_t)y * 2 * nn;
     const int nact = a.n_act[y];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int n_nt = nk / 2;
-    const int nrow = kTile * nk;
+    // fixed row (column) of this thread in the A (B) staging
+    const int rr = tid % kTile, k_first = tid / kTile;
+    const int ia = a0 + rr, ib = b0 + rr;
+    const bool okA = ia < nA, okB = ib < nB;
+    const int arad = m.radT_off[s] + (okA ? ia : 0), brad = m.radP_off[t] + (okB ? ib : 0);
+    const int la = a.radl_T[arad], lb = a.radl_P[brad];
+    const double* fA = a.phiT_T + arad;
+    const double* fB = a.phiT_P + brad;
+    const int mt = wave & 1, nt = wave >> 1;
+    const int li = lane & 15, lk = lane >> 4;
 
     dbl4 acc[kMaxK];
 #pragma unroll
     for (int i = 0; i < kMaxK; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     for (int base = 0; base < nact; base += kNodeChunk) {
-        for (int e = tid; e < kNodeChunk * nF; e += blockDim.x) {
-            const int k = e % kNodeChunk, f = e / kNodeChunk;
-            const int p = base + k;
-            nf[k][f] = (p < nact) ? nd[(size_t)f * nn + p] : 0.0;
+        // per-node data of the chunk
+        for (int e = tid; e < kNodeChunk * 10; e += blockDim.x) {
+            const int k = e % kNodeChunk, q = e / kNodeChunk, p = base + k;
+            const double val = (p < nact) ? nd[(size_t)(kFLA + q) * nn + p] : 0.0;
+            if (q < 5) sLA[k][q] = val;
+            else sLB[k][q - 5] = val;
         }
         if (tid < 2 * kNodeChunk) {
-            const int k = tid % kNodeChunk, side = tid / kNodeChunk;
-            const int p = base + k;
+            const int k = tid % kNodeChunk, side = tid / kNodeChunk, p = base + k;
             const int jv = (p < nact) ? js[side * nn + p] : -1;
-            if (side == 0) jA[k] = jv;
-            else jB[k] = jv;
+            if (side == 0) sjA[k] = jv;
+            else sjB[k] = jv;
         }
-        __syncthreads();
         for (int e = tid; e < kNodeChunk * (kMaxL + 1) * 2; e += blockDim.x) {
-            const int side = e / (kNodeChunk * (kMaxL + 1));
-            const int rem = e - side * kNodeChunk * (kMaxL + 1);
-            const int k = rem / (kMaxL + 1), l = rem - k * (kMaxL + 1);
+            const int k = e % kNodeChunk, rest = e / kNodeChunk;
+            const int side = rest / (kMaxL + 1), l = rest - side * (kMaxL + 1), p = base + k;
             if (side == 0) {
-                if (l >= s && l <= m.LT) PbA[k][l] = pbar(l, s, nf[k][2]);
+                if (l >= s && l <= m.LT)
+                    sPA[k][l] = (p < nact) ? nd[(size_t)(m.f_pa + l * (l + 1) / 2 + s) * nn + p] : 0.0;
             } else {
-                if (l >= t && l <= m.LP) PbB[k][l] = pbar(l, t, nf[k][3]);
+                if (l >= t && l <= m.LP)
+                    sPB[k][l] = (p < nact) ? nd[(size_t)(m.f_pb + l * (l + 1) / 2 + t) * nn + p] : 0.0;
             }
         }
         for (int e = tid; e < kNodeChunk * nk; e += blockDim.x) {
-            const int k = e / nk, kk = e - k * nk;
+            const int k = e % kNodeChunk, kk = e / kNodeChunk, p = base + k;
             const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
-            const double J = nf[k][kNodeFixed + (order == 0 ? o1 : o2)];
-            wk[k][kk] = J * (trig ? nf[k][5] : nf[k][4]) * nf[k][6 + w];
+            double val = 0.0;
+            if (p < nact)
+                val = nd[(size_t)(kFJ + (order == 0 ? o1 : o2)) * nn + p] *
+                      nd[(size_t)(trig ? kFSin : kFCos) * nn + p] * nd[(size_t)(kFW + w) * nn + p];
+            wk[k][kk] = val;
         }
         __syncthreads();
-        for (int e = tid; e < kNodeChunk * kTile; e += blockDim.x) {
-            const int k = e / kTile, r = e - k * kTile;
-            const int i = a0 + r;
-            double val = 0.0;
-            if (i < nA && jA[k] >= 0) {
-                const int arad = m.radT_off[s] + i;
-                const double* f = a.phiT_T + (size_t)jA[k] * m.nfT + arad;
-                const double fv = nf[k][9] * f[0] + nf[k][10] * f[m.nfT] + nf[k][11] * f[2 * m.nfT] +
-                                  nf[k][12] * f[3 * m.nfT] + nf[k][13] * f[4 * m.nfT];
-                val = fv * PbA[k][a.radl_T[arad]];
+        // interpolated radial functions times Legendre values
+#pragma unroll
+        for (int q = 0; q < kNodeChunk / 8; ++q) {
+            const int k = k_first + 8 * q;
+            double va = 0.0, vb = 0.0;
+            const int ja = sjA[k], jb = sjB[k];
+            if (okA && ja >= 0) {
+                const double* f = fA + (size_t)ja * m.nfT;
+                va = (sLA[k][0] * f[0] + sLA[k][1] * f[m.nfT] + sLA[k][2] * f[2 * m.nfT] +
+                      sLA[k][3] * f[3 * m.nfT] + sLA[k][4] * f[4 * m.nfT]) * sPA[k][la];
             }
-            As[k][r] = val;
-        }
-        for (int e = tid; e < kNodeChunk * kTile; e += blockDim.x) {
-            const int k = e / kTile, c = e - k * kTile;
-            const int jj = b0 + c;
-            double val = 0.0;
-            if (jj < nB && jB[k] >= 0) {
-                const int brad = m.radP_off[t] + jj;
-                const double* f = a.phiT_P + (size_t)jB[k] * m.nfP + brad;
-                const double fv = nf[k][14] * f[0] + nf[k][15] * f[m.nfP] + nf[k][16] * f[2 * m.nfP] +
-                                  nf[k][17] * f[3 * m.nfP] + nf[k][18] * f[4 * m.nfP];
-                val = fv * PbB[k][a.radl_P[brad]];
+            if (okB && jb >= 0) {
+                const double* f = fB + (size_t)jb * m.nfP;
+                vb = (sLB[k][0] * f[0] + sLB[k][1] * f[m.nfP] + sLB[k][2] * f[2 * m.nfP] +
+                      sLB[k][3] * f[3 * m.nfP] + sLB[k][4] * f[4 * m.nfP]) * sPB[k][lb];
             }
-            double* row = Bs + k * nrow;
-            for (int kk = 0; kk < nk; ++kk) row[kk * kTile + c] = val * wk[k][kk];
+            As[k][rr] = va;
+            Bs[k][rr] = vb;
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4), li = lane & 15;
-            const double af0 = As[kr][li], af1 = As[kr][16 + li];
+            const int kr = ks * 4 + lk;
+            const double av = As[kr][mt * 16 + li], bv = Bs[kr][nt * 16 + li];
 #pragma unroll
-            for (int q = 0; q < kMaxK / 2; ++q) {
-                if (q < n_nt) {
-                    const int nt = wave + 4 * q;
-                    const double bf = Bs[kr * nrow + nt * 16 + li];
-                    acc[2 * q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af0, bf, acc[2 * q], 0, 0, 0);
-                    acc[2 * q + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af1, bf, acc[2 * q + 1], 0, 0, 0);
-                }
-            }
+            for (int kk = 0; kk < kMaxK; ++kk)
+                if (kk < nk) acc[kk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av * wk[kr][kk], bv, acc[kk], 0, 0, 0);
         }
         __syncthreads();
     }
     // D[row][col] of a 16x16 tile: lane l, register r -> row 4 r + l / 16, col l % 16
     // (A[i][k] in lane i + 16 k and B[k][j] in lane j + 16 k, as loaded above)
     double* out = a.tmol + (size_t)y * m.n_tmol + m.st_off[s][t];
+    const int jj = b0 + nt * 16 + li;
 #pragma unroll
-    for (int q = 0; q < kMaxK / 2; ++q) {
-        if (q < n_nt) {
-            const int nt = wave + 4 * q;
-            const int kk = nt / 2, half = nt % 2;
+    for (int kk = 0; kk < kMaxK; ++kk) {
+        if (kk < nk) {
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = a0 + mt * 16 + 4 * r + (lane >> 4);
-                    const int jj = b0 + half * 16 + (lane & 15);
-                    if (i < nA && jj < nB) out[((size_t)kk * nA + i) * nB + jj] = acc[2 * q + mt][r];
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int i = a0 + mt * 16 + 4 * r + lk;
+                if (i < nA && jj < nB) out[((size_t)kk * nA + i) * nB + jj] = acc[kk][r];
+            }
         }
     }
 }
@@ -491,140 +492,127 @@ __global__ __launch_bounds__(256) void k_2c_direct(DirectArgs a) {
     a.H[ps + (size_t)(off + row) * N + off + col] = make_double2(Zc * acc * wr, Zc * acc * wi);
 }
 
-// LU with partial pivoting (ties: lowest row), column-major, one workgroup per matrix.
-__global__ __launch_bounds__(256) void k_lu(LUArgs a) {
-    __shared__ double rv[256];
-    __shared__ int ri[256];
-    int pl, slot;
-    double z;
-    job_of(a.jobs, blockIdx.x, pl, slot, z);
-    const int N = a.N;
-    double2* A = a.LU + ((size_t)pl * kSlots2C + slot) * (size_t)N * N;
-    int* piv = a.piv + ((size_t)pl * kSlots2C + slot) * N;
-    const int tid = threadIdx.x;
-    for (int k = 0; k < N; ++k) {
-        double best = -1.0;
-        int bi = N;
-        for (int i = k + tid; i < N; i += blockDim.x) {
-            const double2 x = A[i + (size_t)k * N];
-            const double mag = x.x * x.x + x.y * x.y;
-            if (mag > best) {
-                best = mag;
-                bi = i;
-            }
+// y = P (H u) for every path of the launch: grid x = blocks of 16 rows,
+// y = path; each wave accumulates four rows at once (four 1 KB row segments
+// in flight per iteration).
+__global__ __launch_bounds__(256) void k_2c_hu(Stage2CArgs a) {
+    const int pl = blockIdx.y;
+    const int j = a.paths[pl];
+    const int N = a.N, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t ps = ((size_t)pl * kSlots2C + a.slot) * (size_t)N * N;
+    const double2* H = a.H + ps;
+    const int* perm = a.perm + ((size_t)pl * kSlots2C + a.slot) * N;
+    const double2* u = a.u_in + (size_t)j * a.n_pad;
+    const int r0 = blockIdx.x * 16 + wave * 4;
+    const double2* hr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hr[q] = H + (size_t)perm[min(r0 + q, N - 1)] * N;
+    double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = lane; c < N; c += 64) {
+        const double2 x = u[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 h = hr[q][c];
+            re[q] += h.x * x.x - h.y * x.y;
+            im[q] += h.x * x.y + h.y * x.x;
         }
-        rv[tid] = best;
-        ri[tid] = bi;
-        __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double v2 = rv[tid + o];
-                const int i2 = ri[tid + o];
-                if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
-                    rv[tid] = v2;
-                    ri[tid] = i2;
-                }
-            }
-            __syncthreads();
-        }
-        const int p = ri[0];
-        const double pmag = rv[0];
-        __syncthreads();
-        if (tid == 0) piv[k] = (pmag > 0.0) ? p : k;
-        if (!(pmag > 0.0)) {
-            if (tid == 0 && atomicCAS(&a.flag[1], 0, a.paths[pl] + 1) == 0) a.flag[2] = k;
-            continue;
-        }
-        if (p != k)
-            for (int c = tid; c < N; c += blockDim.x) {
-                const double2 t0 = A[k + (size_t)c * N];
-                A[k + (size_t)c * N] = A[p + (size_t)c * N];
-                A[p + (size_t)c * N] = t0;
-            }
-        __syncthreads();
-        const double2 d = A[k + (size_t)k * N];
-        const double dn = d.x * d.x + d.y * d.y;
-        const double2 inv = make_double2(d.x / dn, -d.y / dn);
-        for (int i = k + 1 + tid; i < N; i += blockDim.x) {
-            const double2 x = A[i + (size_t)k * N];
-            A[i + (size_t)k * N] = make_double2(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
-        }
-        __syncthreads();
-        for (int c = k + 1; c < N; ++c) {
-            const double2 u = A[k + (size_t)c * N];
-            for (int i = k + 1 + tid; i < N; i += blockDim.x) {
-                const double2 l = A[i + (size_t)k * N];
-                double2 x = A[i + (size_t)c * N];
-                x.x -= l.x * u.x - l.y * u.y;
-                x.y -= l.x * u.y + l.y * u.x;
-                A[i + (size_t)c * N] = x;
-            }
-        }
-        __syncthreads();
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int off = 32; off > 0; off >>= 1) {
+            re[q] += __shfl_xor(re[q], off, 64);
+            im[q] += __shfl_xor(im[q], off, 64);
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (r0 + q < N) a.Y[(size_t)j * a.n_pad + r0 + q] = make_double2(re[q], im[q]);
 }
 
-// One RK4 stage of one path: y = H u, y <- S^{-1} y (pivots, L, U), K = -(i/v) y.
-__global__ __launch_bounds__(256) void k_2c_stage(Stage2CArgs a) {
-    extern __shared__ double2 sm[];  // u [N], y [N]
+constexpr int kSolveBlock = 32;
+
+// y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update; one workgroup per
+// path.  The triangular solves go by blocks of 32 rows: the diagonal block is
+// staged in LDS and solved by one wave with lane shuffles, then all waves
+// update the rows below (above) it from the column-major factors.
+__global__ __launch_bounds__(256) void k_2c_solve(Stage2CArgs a) {
+    extern __shared__ double2 ys[];      // [N]
+    __shared__ double2 blk[kSolveBlock][kSolveBlock + 1];
     const int pl = blockIdx.x;
     const int j = a.paths[pl];
     const int N = a.N, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const size_t ps = ((size_t)pl * kSlots2C + a.slot) * (size_t)N * N;
-    const double2* H = a.H + ps;
     const double2* LU = a.LU + ps;
-    const int* piv = a.piv + ((size_t)pl * kSlots2C + a.slot) * N;
-    double2* us = sm;
-    double2* ys = sm + N;
-    const double2* u = a.u_in + (size_t)j * a.n_pad;
-    for (int i = tid; i < N; i += blockDim.x) us[i] = u[i];
+    for (int i = tid; i < N; i += blockDim.x) ys[i] = a.Y[(size_t)j * a.n_pad + i];
     __syncthreads();
-    for (int r = wave; r < N; r += blockDim.x >> 6) {
-        const double2* hr = H + (size_t)r * N;
-        double re = 0.0, im = 0.0;
-        for (int c = lane; c < N; c += 64) {
-            const double2 h = hr[c], x = us[c];
-            re += h.x * x.x - h.y * x.y;
-            im += h.x * x.y + h.y * x.x;
+    // L (unit diagonal): forward
+    for (int kb = 0; kb < N; kb += kSolveBlock) {
+        const int nbk = min(kSolveBlock, N - kb);
+        for (int e = tid; e < nbk * nbk; e += blockDim.x) {
+            const int r = e % nbk, c = e / nbk;
+            blk[r][c] = LU[(kb + r) + (size_t)(kb + c) * N];
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            re += __shfl_xor(re, off, 64);
-            im += __shfl_xor(im, off, 64);
-        }
-        if (lane == 0) ys[r] = make_double2(re, im);
-    }
-    __syncthreads();
-    if (tid == 0)
-        for (int k = 0; k < N; ++k) {
-            const int p = piv[k];
-            if (p != k) {
-                const double2 t0 = ys[k];
-                ys[k] = ys[p];
-                ys[p] = t0;
+        __syncthreads();
+        if (wave == 0) {
+            double2 y = (lane < nbk) ? ys[kb + lane] : make_double2(0.0, 0.0);
+            for (int c = 0; c + 1 < nbk; ++c) {
+                const double yr = __shfl(y.x, c, 64), yi = __shfl(y.y, c, 64);
+                if (lane > c && lane < nbk) {
+                    const double2 l = blk[lane][c];
+                    y.x -= l.x * yr - l.y * yi;
+                    y.y -= l.x * yi + l.y * yr;
+                }
             }
+            if (lane < nbk) ys[kb + lane] = y;
         }
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        const double2 yk = ys[k];
-        for (int i = k + 1 + tid; i < N; i += blockDim.x) {
-            const double2 l = LU[i + (size_t)k * N];
-            ys[i].x -= l.x * yk.x - l.y * yk.y;
-            ys[i].y -= l.x * yk.y + l.y * yk.x;
+        __syncthreads();
+        for (int i = kb + nbk + tid; i < N; i += blockDim.x) {
+            double re = 0.0, im = 0.0;
+            for (int c = 0; c < nbk; ++c) {
+                const double2 l = LU[i + (size_t)(kb + c) * N], x = ys[kb + c];
+                re += l.x * x.x - l.y * x.y;
+                im += l.x * x.y + l.y * x.x;
+            }
+            ys[i].x -= re;
+            ys[i].y -= im;
         }
         __syncthreads();
     }
-    for (int k = N - 1; k >= 0; --k) {
-        if (tid == 0) {
-            const double2 d = LU[k + (size_t)k * N], x = ys[k];
-            const double dn = d.x * d.x + d.y * d.y;
-            ys[k] = make_double2((x.x * d.x + x.y * d.y) / dn, (x.y * d.x - x.x * d.y) / dn);
+    // U: backward
+    for (int kb = ((N - 1) / kSolveBlock) * kSolveBlock; kb >= 0; kb -= kSolveBlock) {
+        const int nbk = min(kSolveBlock, N - kb);
+        for (int e = tid; e < nbk * nbk; e += blockDim.x) {
+            const int r = e % nbk, c = e / nbk;
+            blk[r][c] = LU[(kb + r) + (size_t)(kb + c) * N];
         }
         __syncthreads();
-        const double2 yk = ys[k];
-        for (int i = tid; i < k; i += blockDim.x) {
-            const double2 uu = LU[i + (size_t)k * N];
-            ys[i].x -= uu.x * yk.x - uu.y * yk.y;
-            ys[i].y -= uu.x * yk.y + uu.y * yk.x;
+        if (wave == 0) {
+            double2 y = (lane < nbk) ? ys[kb + lane] : make_double2(0.0, 0.0);
+            for (int c = nbk - 1; c >= 0; --c) {
+                if (lane == c) {
+                    const double2 d = blk[c][c];
+                    const double dn = d.x * d.x + d.y * d.y;
+                    y = make_double2((y.x * d.x + y.y * d.y) / dn, (y.y * d.x - y.x * d.y) / dn);
+                }
+                const double yr = __shfl(y.x, c, 64), yi = __shfl(y.y, c, 64);
+                if (lane < c) {
+                    const double2 uu = blk[lane][c];
+                    y.x -= uu.x * yr - uu.y * yi;
+                    y.y -= uu.x * yi + uu.y * yr;
+                }
+            }
+            if (lane < nbk) ys[kb + lane] = y;
+        }
+        __syncthreads();
+        for (int i = tid; i < kb; i += blockDim.x) {
+            double re = 0.0, im = 0.0;
+            for (int c = 0; c < nbk; ++c) {
+                const double2 uu = LU[i + (size_t)(kb + c) * N], x = ys[kb + c];
+                re += uu.x * x.x - uu.y * x.y;
+                im += uu.x * x.y + uu.y * x.x;
+            }
+            ys[i].x -= re;
+            ys[i].y -= im;
         }
         __syncthreads();
     }
@@ -692,53 +680,47 @@ __global__ void k_transpose_copy(const double2* __restrict__ src, double2* __res
 
 }  // namespace
 
-int contract_smem_bytes(int n_w) { return kNodeChunk * kTile * 4 * n_w * (int)sizeof(double); }
-
-hipError_t contract_set_smem(int bytes) {
-    return hipFuncSetAttribute((const void*)k_2c_contract, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st) {
-    hipLaunchKernelGGL(k_2c_nodes, dim3((hm.n_nodes + 255) / 256, n_jobs), dim3(256), 0, st, a);
+hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_nodes, dim3((hm.n_nodes + 255) / 256, n_jobs), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st) {
-    hipLaunchKernelGGL(k_2c_contract, dim3(hm.n_tiles, n_jobs), dim3(256), contract_smem_bytes(hm.n_w), st, a);
+hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_contract, dim3(8 * ((hm.n_tiles * n_jobs + 7) / 8)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st) {
+hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     const int nb = (hm.NT * hm.NP + 255) / 256 + (hm.NT * hm.NT + hm.NP * hm.NP + 255) / 256;
-    hipLaunchKernelGGL(k_2c_assemble, dim3(nb, n_jobs), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_2c_assemble, dim3(nb, n_jobs), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st) {
+hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     const int nbG = (hm.n_g + 255) / 256;
-    hipLaunchKernelGGL(k_setup_batch, dim3(a.nbF + a.nbP + nbG, n_jobs), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_setup_batch, dim3(a.nbF + a.nbP + nbG, n_jobs), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st) {
+hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     const int nb = (hm.NT * hm.NT + hm.NP * hm.NP + 255) / 256;
-    hipLaunchKernelGGL(k_2c_direct, dim3(nb, n_jobs), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_2c_direct, dim3(nb, n_jobs), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_lu(const LUArgs& a, int n_jobs, hipStream_t st) {
-    hipLaunchKernelGGL(k_lu, dim3(n_jobs), dim3(256), 0, st, a);
+hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_hu, dim3((a.N + 15) / 16, n_paths), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_2c_stage(const Stage2CArgs& a, int n_paths, hipStream_t st) {
-    hipLaunchKernelGGL(k_2c_stage, dim3(n_paths), dim3(256), 2 * a.N * sizeof(double2), st, a);
+hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_solve, dim3(n_paths), dim3(256), a.N * sizeof(double2), st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,
-                            int slot, double* P, double* norm, hipStream_t st) {
-    hipLaunchKernelGGL(k_2c_finish, dim3(n_paths), dim3(256), 0, st, X, S, N, n_pad, paths, slot, P, norm);
+                            int slot, double* P, double* norm, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_finish, dim3(n_paths), dim3(256), 0, st, X, S, N, n_pad, paths, slot, P, norm);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Plan layout and kernel launchers of the one-centre path (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -92,6 +93,37 @@ struct StageArgs {
     double2* Xacc;        // accumulator   [n_traj][n_pad]
     double2* u_out;       // next input    [n_traj][n_pad]
     int* flag;            // non-finite latch
+    // operator application (k_apply): y = O u with O = M(z_p) (deriv 0),
+    // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2), then
+    //   out = alpha y + beta w            (out may be NULL, w may be NULL)
+    //   grad[j][gslot] += 2 gamma Re(dv^H y)   (grad may be NULL)
+    int deriv;
+    double z;             // z of the point (deriv 1, 2)
+    double alpha, beta, gamma;
+    const double2* w;
+    double2* out;
+    const double2* dv;
+    double* grad;         // [n_traj][3]
+    int gslot;
+};
+
+// Radial blocks of the model potential on one basis (one-centre plans):
+//   va[vo(l) + n' N_l + n] = -sum_i w_i r_i f f e^{-c r_i}        (d DeltaV / da)
+//   vc[vo(l) + n' N_l + n] = +a sum_i w_i r_i^2 f f e^{-c r_i}    (d DeltaV / dc)
+// with vo(l) = sum_{l'' < l} N_l''^2.
+struct ModelArgs {
+    const Meta* meta;
+    Tables tb;
+    PointArrays pt;
+    int p;
+    int traj0;
+    int n_pad;
+    const double* va;
+    const double* vc;
+    const double2* u;
+    const double2* dv;
+    double gamma;
+    double* grad;         // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] likewise for c
 };
 
 struct SetupArgs {
@@ -143,8 +175,52 @@ struct Centre {
     }
 };
 
+// Events of one timed launch: recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so their interval is the kernel's execution.
+struct LaunchEv {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+#define WPCCC_LAUNCH(ev, kernel, grid, block, smem, st, ...)                                        \
+    do {                                                                                          \
+        if ((ev).a)                                                                               \
+            hipExtLaunchKernelGGL(kernel, grid, block, smem, st, (ev).a, (ev).b, 0, __VA_ARGS__); \
+        else                                                                                      \
+            hipLaunchKernelGGL(kernel, grid, block, smem, st, __VA_ARGS__);                       \
+    } while (0)
+
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// (wpccc_plan_timing / wpccc_plan_kernel_time).
+enum KernelId {
+    kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
+    k2cNodes, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
+    kNumKernels
+};
+extern const char* const kKernelNames[kNumKernels];
+
+struct KernelTimer {
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    // events for one launch of `kernel` (none when timing is off)
+    LaunchEv open(int kernel);
+    void recycle_all();
+    // total time and count of the finished launches of `kernel`, which are then forgotten
+    int take(int kernel, double* total_ms, long long* launches);
+    ~KernelTimer();
+};
+
 // centre.hip
-int centre_build(const HostBasis& hb, hipStream_t st, Centre& c);
+// model_a != 0 adds DeltaV = -a e^{-c r}/r (block diagonal in l, m) to the
+// lambda = 0 moments of the equal-l blocks, so that every use of the tables
+// sees D_T + DeltaV (projectile charge Zp)
+int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a = 0.0, double model_c = 0.0,
+                 double Zp = 1.0);
+// radial blocks va, vc of the model potential (layout of ModelArgs)
+void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& va, std::vector<double>& vc);
 void centre_free(Centre& c);
 
 // device allocation with error text; adds to `total`
@@ -159,7 +235,7 @@ int launched(hipError_t e, const char* what);
 struct Plan2C;
 int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,
                   const int* set_of_traj, const double* b, const double* v, const wpccc_plan_opts& o,
-                  hipStream_t st, Plan2C** out);
+                  KernelTimer* timer, hipStream_t st, Plan2C** out);
 void plan2c_destroy(Plan2C* p);
 int plan2c_info(Plan2C* p, int* n_traj, int* n_states, int* n_pad, long long* bytes);
 int plan2c_path_info(Plan2C* p, int j, int* n_states, int* n_target);
@@ -169,16 +245,26 @@ int plan2c_step(Plan2C* p, void* X, double z, double h, hipStream_t st);
 int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* X, void* P, void* norm, hipStream_t st);
 
 // launchers (kernels_1c.hip)
-hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st);
+hipError_t launch_prologue(const PrologueArgs& a, int n_traj_launch, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_moments(const double* r, const double* w, const double* phiT, const int* da,
                           const int* db, const int* dl, int n_r, int n_f, int n_frow, double2* tab,
                           hipStream_t st);
-hipError_t launch_slot_setup(const SetupArgs& a, const Meta& host_meta, hipStream_t st);
-hipError_t launch_stage(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st);
+hipError_t launch_slot_setup(const SetupArgs& a, const Meta& host_meta, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_stage(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
+                        const LaunchEv& ev = LaunchEv{});
 hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const double* Frow, const double* G,
-                                  const double2* PH, double Zp, double2* H, hipStream_t st);
+                                  const double2* PH, double Zp, double2* H, hipStream_t st,
+                                  const LaunchEv& ev = LaunchEv{});
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
-                                double* norm, hipStream_t st);
+                                double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_apply(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
+                        const LaunchEv& ev = LaunchEv{});
+hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st);
+// out[j] = sum_k c[k] v[k][j] over the first n states of every path (k < n_terms <= 5)
+hipError_t launch_combine(double2* out, const double2* const* v, const double* c, int n_terms, int n_traj,
+                          int n, int n_pad, hipStream_t st);
+hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
+                              hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);
 int stage_smem_bytes(const Meta& m);
 

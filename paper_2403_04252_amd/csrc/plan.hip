@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -46,16 +48,15 @@ struct wpccc_plan_s {
     int* d_kidx = nullptr;
     double *d_rpow = nullptr, *d_pbar = nullptr;
     double2* d_ph = nullptr;
+    // model potential blocks and adjoint workspace (allocated on first use)
+    double *d_va = nullptr, *d_vc = nullptr;
+    int ckpt_every = 0;
+    int adj_K = 0, adj_nck = 0;
+    double2 *d_lam = nullptr, *d_mu = nullptr, *d_nu = nullptr, *d_u2 = nullptr, *d_u3 = nullptr, *d_u4 = nullptr;
+    double2 *d_ckpt = nullptr, *d_seg = nullptr;
     long long bytes = 0;
     int stage_smem = 0;
-    // optional per-kernel event timing
-    struct TimingRec {
-        int kernel;
-        hipEvent_t a, b;
-    };
-    bool timing = false;
-    std::vector<TimingRec> recs;
-    std::vector<hipEvent_t> pool;
+    KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
     PointArrays points() const {
@@ -75,44 +76,13 @@ void free_plan(wpccc_plan_s* p) {
     if (!p) return;
     if (p->p2c) plan2c_destroy(p->p2c);
     centre_free(p->c);
-    void* bufs[] = {p->d_b,  p->d_v,  p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1, p->d_Ua,
-                    p->d_Ub, p->d_Xacc, p->d_kidx, p->d_rpow, p->d_pbar, p->d_ph};
+    void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
+                    p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
+                    p->d_vc,   p->d_lam,  p->d_mu,   p->d_nu,    p->d_u2,   p->d_u3,   p->d_u4,
+                    p->d_ckpt, p->d_seg};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
-    for (auto& r : p->recs) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
     delete p;
-}
-
-enum KernelId { kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue, kNumKernels };
-const char* const kKernelNames[kNumKernels] = {"k_stage", "k_slot_setup", "k_couplings_dense",
-                                               "k_probabilities", "k_moments", "k_prologue"};
-
-hipEvent_t take_event(wpccc_plan_s* p) {
-    if (!p->pool.empty()) {
-        hipEvent_t e = p->pool.back();
-        p->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Bracket one launch with events when timing is on (open before, close after).
-void time_mark(wpccc_plan_s* p, int kernel, hipStream_t st, bool open) {
-    if (!p->timing) return;
-    if (open) {
-        wpccc_plan_s::TimingRec r{kernel, take_event(p), take_event(p)};
-        if (!r.a || !r.b) return;
-        (void)hipEventRecord(r.a, st);
-        p->recs.push_back(r);
-    } else if (!p->recs.empty() && p->recs.back().kernel == kernel) {
-        (void)hipEventRecord(p->recs.back().b, st);
-    }
 }
 
 // Per-point quantities for z[0..n) of paths [j0, j0+nj) into point slots 0..n-1.
@@ -124,9 +94,7 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     for (int i = 0; i < n; ++i) a.z[i] = z[i];
     a.n = n;
     a.traj0 = j0;
-    time_mark(p, kPrologue, st, true);
-    hipError_t e = launch_prologue(a, nj, st);
-    time_mark(p, kPrologue, st, false);
+    hipError_t e = launch_prologue(a, nj, st, p->timer.open(kPrologue));
     return launched(e, "k_prologue");
 }
 
@@ -147,9 +115,7 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.Xacc = p->d_Xacc;
     a.u_out = u_out;
     a.flag = p->d_flag;
-    time_mark(p, kStage, st, true);
-    hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem, st);
-    time_mark(p, kStage, st, false);
+    hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem, st, p->timer.open(kStage));
     return launched(e, "k_stage");
 }
 
@@ -182,6 +148,76 @@ int check_grid(const double* zgrid, int n_points) {
             return WPCCC_EINVAL;
         }
     return WPCCC_OK;
+}
+
+// One RK4 step z -> z + h of every path (prologue for its three points).
+int forward_step(wpccc_plan_s* p, double2* X, double z, double h, hipStream_t st) {
+    const double pts[3] = {z, z + 0.5 * h, z + h};
+    int rc = enqueue_prologue(p, pts, 3, 0, p->n_traj, st);
+    if (rc) return rc;
+    return enqueue_step(p, X, 0, p->n_traj, 0, h, st);
+}
+
+// out = alpha O u + beta w and/or grad[.][gslot] += 2 gamma Re(dv^H O u), O at point slot pt.
+int enqueue_apply(wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha, const double2* w,
+                  double beta, double2* out, const double2* dv, double gamma, int gslot, double* grad,
+                  hipStream_t st) {
+    StageArgs a{};
+    a.meta = p->c.d_meta;
+    a.tb = p->tables();
+    a.pt = p->points();
+    a.Zp = p->Zp;
+    a.p = pt;
+    a.n_pad = p->n_pad;
+    a.traj0 = 0;
+    a.u_in = u;
+    a.flag = p->d_flag;
+    a.deriv = deriv;
+    a.z = z;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = gamma;
+    a.w = w;
+    a.out = out;
+    a.dv = dv;
+    a.grad = grad;
+    a.gslot = gslot;
+    return launched(launch_apply(a, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
+}
+
+// grad += 2 gamma Re(dv^H dM/dtheta u) for theta = a, c, b at point slot pt.
+int enqueue_grad_terms(wpccc_plan_s* p, int pt, double z, const double2* u, const double2* dv, double gamma,
+                       double* grad, hipStream_t st) {
+    int rc;
+    for (int d = 1; d <= 2; ++d)
+        if ((rc = enqueue_apply(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, dv, gamma, 2, grad, st))) return rc;
+    ModelArgs m{};
+    m.meta = p->c.d_meta;
+    m.tb = p->tables();
+    m.pt = p->points();
+    m.p = pt;
+    m.traj0 = 0;
+    m.n_pad = p->n_pad;
+    m.va = p->d_va;
+    m.vc = p->d_vc;
+    m.u = u;
+    m.dv = dv;
+    m.gamma = gamma;
+    m.grad = grad;
+    return launched(launch_model_dot(m, p->n_traj, st), "k_model_dot");
+}
+
+int enqueue_combine(wpccc_plan_s* p, double2* out, std::initializer_list<std::pair<double, const double2*>> terms,
+                    hipStream_t st) {
+    const double2* v[5];
+    double c[5];
+    int n = 0;
+    for (auto& t : terms) {
+        c[n] = t.first;
+        v[n] = t.second;
+        ++n;
+    }
+    return launched(launch_combine(out, v, c, n, p->n_traj, p->c.meta.n_states, p->n_pad, st), "k_combine");
 }
 
 }  // namespace
@@ -306,7 +342,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->v.assign(v_host, v_host + n_traj);
     const int N = hb.n_states;
     plan->n_pad = (N + 7) & ~7;
-    TRY(centre_build(hb, st, plan->c));
+    TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp));
+    plan->ckpt_every = o.checkpoint_every;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
     if (plan->stage_smem > 160 * 1024) {
@@ -329,10 +366,18 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     TRY(dev_alloc(&plan->d_rpow, (size_t)n_traj * kChunkPoints * kRpow, tot));
     TRY(dev_alloc(&plan->d_pbar, (size_t)n_traj * kChunkPoints * kMaxPb, tot));
     TRY(dev_alloc(&plan->d_ph, (size_t)n_traj * kChunkPoints * m.n_f, tot));
+    std::vector<double> va, vc;
+    model_blocks(hb, o.model_a, o.model_c, va, vc);
+    TRY(dev_alloc(&plan->d_va, va.size(), tot));
+    TRY(dev_alloc(&plan->d_vc, vc.size(), tot));
     hipError_t e = hipMemcpyAsync(plan->d_b, b_host, (size_t)n_traj * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->d_v, v_host, (size_t)n_traj * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(plan->d_flag, 0, sizeof(int), st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->d_va, va.data(), va.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->d_vc, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && plan->stage_smem > 64 * 1024) e = stage_set_smem_limit(m.l_max, plan->stage_smem);
     if (e != hipSuccess) {
@@ -365,7 +410,7 @@ int wpccc_plan_create_2c(const wpccc_basis_t* targets, const wpccc_basis_t* proj
         return WPCCC_ENOMEM;
     }
     const int rc = plan2c_create(targets, projectiles, n_sets, n_traj, set_of_traj, b_host, v_host, o,
-                                 (hipStream_t)stream, &plan->p2c);
+                                 &plan->timer, (hipStream_t)stream, &plan->p2c);
     if (rc != WPCCC_OK) {
         plan->p2c = nullptr;
         free_plan(plan);
@@ -458,15 +503,11 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
     a.PH = plan->d_PH1;
     a.nbF = (m.n_frow + 255) / 256;
     a.nbP = (m.n_states + 255) / 256;
-    time_mark(plan, kSetup, st, true);
-    hipError_t e = launch_slot_setup(a, m, st);
-    time_mark(plan, kSetup, st, false);
+    hipError_t e = launch_slot_setup(a, m, st, plan->timer.open(kSetup));
     int rc = launched(e, "k_slot_setup");
     if (rc) return rc;
-    time_mark(plan, kDense, st, true);
     e = launch_couplings_dense(plan->c.d_meta, m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp,
-                               (double2*)H_dev, st);
-    time_mark(plan, kDense, st, false);
+                               (double2*)H_dev, st, plan->timer.open(kDense));
     return launched(e, "k_couplings_dense");
 }
 
@@ -532,11 +573,120 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
         }
     }
     if (P_dev || norm_dev) {
-        time_mark(plan, kProb, st, true);
         hipError_t e = launch_probabilities((const double2*)X, plan->n_traj, plan->c.meta.n_states, plan->n_pad,
-                                            (double*)P_dev, (double*)norm_dev, st);
-        time_mark(plan, kProb, st, false);
+                                            (double*)P_dev, (double*)norm_dev, st, plan->timer.open(kProb));
         if ((rc = launched(e, "k_probabilities"))) return rc;
+    }
+    return WPCCC_OK;
+}
+
+int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev, void* X_dev,
+                  const void* gX_dev, void* grad_dev, void* stream) {
+    clear_error();
+    if (!plan || !X0_dev || !gX_dev || !grad_dev) {
+        set_error("wpccc_adjoint: NULL argument");
+        return WPCCC_EINVAL;
+    }
+    if (plan->p2c) {
+        set_error("wpccc_adjoint: one-centre plans only");
+        return WPCCC_ENOTSUP;
+    }
+    int rc = check_grid(zgrid_host, n_points);
+    if (rc) return rc;
+    for (int i = 0; i < n_points; ++i)
+        if (path_hits_origin(plan, zgrid_host[i]) ||
+            (i + 1 < n_points && path_hits_origin(plan, 0.5 * (zgrid_host[i] + zgrid_host[i + 1])))) {
+            set_error("wpccc_adjoint: R = 0 on the grid");
+            return WPCCC_EINVAL;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    const int n_steps = n_points - 1;
+    int K = plan->ckpt_every > 0 ? plan->ckpt_every : (int)std::ceil(std::sqrt((double)n_steps));
+    K = std::max(1, std::min(K, n_steps));
+    const int n_ck = (n_steps + K - 1) / K;
+    const size_t V = (size_t)plan->n_traj * plan->n_pad;
+    if (K > plan->adj_K || n_ck > plan->adj_nck || !plan->d_lam) {
+        void* old[] = {plan->d_lam, plan->d_mu, plan->d_nu, plan->d_u2, plan->d_u3, plan->d_u4, plan->d_ckpt,
+                       plan->d_seg};
+        (void)hipStreamSynchronize(st);
+        for (void* q : old)
+            if (q) (void)hipFree(q);
+        plan->d_lam = plan->d_mu = plan->d_nu = plan->d_u2 = plan->d_u3 = plan->d_u4 = nullptr;
+        plan->d_ckpt = plan->d_seg = nullptr;
+        plan->adj_K = std::max(K, plan->adj_K);
+        plan->adj_nck = std::max(n_ck, plan->adj_nck);
+        long long& tot = plan->bytes;
+        if ((rc = dev_alloc(&plan->d_lam, V, tot)) || (rc = dev_alloc(&plan->d_mu, V, tot)) ||
+            (rc = dev_alloc(&plan->d_nu, 4 * V, tot)) || (rc = dev_alloc(&plan->d_u2, V, tot)) ||
+            (rc = dev_alloc(&plan->d_u3, V, tot)) || (rc = dev_alloc(&plan->d_u4, V, tot)) ||
+            (rc = dev_alloc(&plan->d_ckpt, (size_t)plan->adj_nck * V, tot)) ||
+            (rc = dev_alloc(&plan->d_seg, (size_t)plan->adj_K * V, tot))) {
+            plan->adj_K = plan->adj_nck = 0;
+            return rc;
+        }
+    }
+    const size_t VB = V * sizeof(double2);
+    double2* lam = plan->d_lam;
+    double2* mu = plan->d_mu;
+    double2* nu[4] = {plan->d_nu, plan->d_nu + V, plan->d_nu + 2 * V, plan->d_nu + 3 * V};
+    double* grad = (double*)grad_dev;
+    // forward sweep with checkpoints (the working state lives in seg[0])
+    double2* xw = plan->d_seg;
+    WPCCC_HIP_CHECK(hipMemcpyAsync(xw, X0_dev, VB, hipMemcpyDeviceToDevice, st));
+    for (int n = 0; n < n_steps; ++n) {
+        if (n % K == 0)
+            WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_ckpt + (size_t)(n / K) * V, xw, VB, hipMemcpyDeviceToDevice, st));
+        if ((rc = forward_step(plan, xw, zgrid_host[n], zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+    }
+    if (X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xw, VB, hipMemcpyDeviceToDevice, st));
+    // reverse sweep
+    WPCCC_HIP_CHECK(hipMemcpyAsync(lam, gX_dev, VB, hipMemcpyDeviceToDevice, st));
+    WPCCC_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)plan->n_traj * 3 * sizeof(double), st));
+    for (int s = n_ck - 1; s >= 0; --s) {
+        const int n0 = s * K, n1 = std::min(n0 + K, n_steps);
+        WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_seg, plan->d_ckpt + (size_t)s * V, VB, hipMemcpyDeviceToDevice, st));
+        for (int n = n0; n + 1 < n1; ++n) {
+            double2* nxt = plan->d_seg + (size_t)(n - n0 + 1) * V;
+            WPCCC_HIP_CHECK(hipMemcpyAsync(nxt, nxt - V, VB, hipMemcpyDeviceToDevice, st));
+            if ((rc = forward_step(plan, nxt, zgrid_host[n], zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const double2* x = plan->d_seg + (size_t)(n - n0) * V;
+            const double z0 = zgrid_host[n], z1 = zgrid_host[n + 1], zm = 0.5 * (z0 + z1), h = z1 - z0;
+            const double pts[3] = {z0, zm, z1};
+            if ((rc = enqueue_prologue(plan, pts, 3, 0, plan->n_traj, st))) return rc;
+            // stage inputs of the forward step
+            if ((rc = enqueue_apply(plan, 0, z0, 0, x, 0.5 * h, x, 1.0, plan->d_u2, nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            if ((rc = enqueue_apply(plan, 1, zm, 0, plan->d_u2, 0.5 * h, x, 1.0, plan->d_u3, nullptr, 0.0, 0, nullptr,
+                                    st)))
+                return rc;
+            if ((rc = enqueue_apply(plan, 1, zm, 0, plan->d_u3, h, x, 1.0, plan->d_u4, nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            // stage 4: mu4 = h/6 lambda, nu4 = M3^H mu4 = -M3 mu4
+            if ((rc = enqueue_apply(plan, 2, z1, 0, lam, -h / 6.0, nullptr, 0.0, nu[3], nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            if ((rc = enqueue_grad_terms(plan, 2, z1, plan->d_u4, lam, h / 6.0, grad, st))) return rc;
+            // stage 3: mu3 = h/3 lambda + h nu4
+            if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {h, nu[3]}}, st))) return rc;
+            if ((rc = enqueue_apply(plan, 1, zm, 0, mu, -1.0, nullptr, 0.0, nu[2], nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            if ((rc = enqueue_grad_terms(plan, 1, zm, plan->d_u3, mu, 1.0, grad, st))) return rc;
+            // stage 2: mu2 = h/3 lambda + h/2 nu3
+            if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {0.5 * h, nu[2]}}, st))) return rc;
+            if ((rc = enqueue_apply(plan, 1, zm, 0, mu, -1.0, nullptr, 0.0, nu[1], nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            if ((rc = enqueue_grad_terms(plan, 1, zm, plan->d_u2, mu, 1.0, grad, st))) return rc;
+            // stage 1: mu1 = h/6 lambda + h/2 nu2
+            if ((rc = enqueue_combine(plan, mu, {{h / 6.0, lam}, {0.5 * h, nu[1]}}, st))) return rc;
+            if ((rc = enqueue_apply(plan, 0, z0, 0, mu, -1.0, nullptr, 0.0, nu[0], nullptr, 0.0, 0, nullptr, st)))
+                return rc;
+            if ((rc = enqueue_grad_terms(plan, 0, z0, x, mu, 1.0, grad, st))) return rc;
+            // lambda_n = lambda_(n+1) + nu1 + nu2 + nu3 + nu4
+            if ((rc = enqueue_combine(plan, lam, {{1.0, lam}, {1.0, nu[0]}, {1.0, nu[1]}, {1.0, nu[2]}, {1.0, nu[3]}},
+                                      st)))
+                return rc;
+        }
     }
     return WPCCC_OK;
 }
@@ -548,13 +698,9 @@ int wpccc_plan_timing(wpccc_plan_t plan, int enable) {
     }
     if (!enable) {
         WPCCC_HIP_CHECK(hipDeviceSynchronize());
-        for (auto& r : plan->recs) {
-            plan->pool.push_back(r.a);
-            plan->pool.push_back(r.b);
-        }
-        plan->recs.clear();
+        plan->timer.recycle_all();
     }
-    plan->timing = enable != 0;
+    plan->timer.on = enable != 0;
     return WPCCC_OK;
 }
 
@@ -570,26 +716,79 @@ int wpccc_plan_kernel_time(wpccc_plan_t plan, const char* kernel, double* total_
         set_error("wpccc_plan_kernel_time: unknown kernel '%s'", kernel);
         return WPCCC_EINVAL;
     }
+    return plan->timer.take(id, total_ms, launches);
+}
+
+}  // extern "C"
+
+namespace wpccc {
+
+const char* const kKernelNames[kNumKernels] = {
+    "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
+    "k_2c_nodes",     "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
+    "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish"};
+
+LaunchEv KernelTimer::open(int kernel) {
+    LaunchEv ev;
+    if (!on) return ev;
+    Rec r{kernel, nullptr, nullptr};
+    for (hipEvent_t* e : {&r.a, &r.b}) {
+        if (!pool.empty()) {
+            *e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            *e = nullptr;
+        }
+    }
+    if (!r.a || !r.b) {
+        if (r.a) pool.push_back(r.a);
+        if (r.b) pool.push_back(r.b);
+        return ev;
+    }
+    recs.push_back(r);
+    ev.a = r.a;
+    ev.b = r.b;
+    return ev;
+}
+
+void KernelTimer::recycle_all() {
+    for (auto& r : recs) {
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    recs.clear();
+}
+
+int KernelTimer::take(int kernel, double* total_ms, long long* launches) {
     double tot = 0.0;
     long long n = 0;
-    std::vector<wpccc_plan_s::TimingRec> keep;
-    for (auto& r : plan->recs) {
-        if (r.kernel != id) {
+    std::vector<Rec> keep;
+    for (auto& r : recs) {
+        if (r.kernel != kernel) {
             keep.push_back(r);
             continue;
         }
         WPCCC_HIP_CHECK(hipEventSynchronize(r.b));
         float ms = 0.f;
-        WPCCC_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
-        tot += ms;
-        ++n;
-        plan->pool.push_back(r.a);
-        plan->pool.push_back(r.b);
+        // a launcher that had nothing to do records neither event: not a launch
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            tot += ms;
+            ++n;
+        } else {
+            (void)hipGetLastError();
+        }
+        pool.push_back(r.a);
+        pool.push_back(r.b);
     }
-    plan->recs.swap(keep);
+    recs.swap(keep);
     if (total_ms) *total_ms = tot;
     if (launches) *launches = n;
     return WPCCC_OK;
 }
 
-}  // extern "C"
+KernelTimer::~KernelTimer() {
+    recycle_all();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace wpccc

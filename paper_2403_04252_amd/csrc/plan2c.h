@@ -17,11 +17,20 @@
 namespace wpccc {
 
 constexpr int kMaxW = 3;          // weights: overlap, target potential, projectile potential
-constexpr int kNodeChunk = 16;    // spheroidal nodes per MFMA chunk (4 k-steps of 4)
+constexpr int kNodeChunk = 32;    // spheroidal nodes per contraction chunk (8 MFMA k-steps of 4)
 constexpr int kTile = 32;         // rows (target) and columns (projectile) per contraction workgroup
 constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
-constexpr int kNodeFixed = 19;    // node fields before the Bessel values
 constexpr int kSlots2C = 3;
+
+// Per-node fields of one coupling position ([field][n_nodes], SoA):
+constexpr int kFCos = 0;          // cos((v z / 2) eta tau)
+constexpr int kFSin = 1;          // sin((v z / 2) eta tau)
+constexpr int kFW = 2;            // omega W_w, w < kMaxW
+constexpr int kFLA = kFW + kMaxW; // five Lagrange weights at r_A
+constexpr int kFLB = kFLA + 5;    // five Lagrange weights at r_B
+constexpr int kFJ = kFLB + 5;     // J_m(X), m = 0 .. 2L
+// then Pbar_l^m(cos theta_A) for l <= LT, m <= l (index l(l+1)/2 + m) from
+// field f_pa, and Pbar_l^m(cos theta_B), l <= LP, from field f_pb
 
 // Per-group constants of the two-centre kernels (device copy passed by pointer).
 struct Meta2C {
@@ -32,7 +41,8 @@ struct Meta2C {
     double rmaxT, rmaxP;
     double ZT, ZP;
     int n_eta, n_tau, n_nodes;
-    int n_fields;            // kNodeFixed + 2L + 1
+    int n_fields;            // f_pb + (LP+1)(LP+2)/2
+    int f_pa, f_pb;          // first Legendre field of each side
     int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
     int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
     // contraction blocks: rows of block s are the radial functions a >= radT_off[s]
@@ -74,6 +84,7 @@ struct NodeArgs {
 
 struct ContractArgs {
     const Meta2C* m;
+    int n_jobs;
     const int2* tiles;      // [n_tiles] (s | t << 8, a0 | b0 << 16)
     const double* phiT_T;   // [nrT+1][nfT] target radial functions, transposed
     const double* phiT_P;   // [nrP+1][nfP]
@@ -126,13 +137,22 @@ struct DirectArgs {         // D_T and D_P blocks of H from the per-job Frow / G
     double2* H;
 };
 
-struct LUArgs {
-    int N;
+// Blocked LU with partial pivoting of the S copies, one panel of kLUPanel
+// columns per pass: k_lu_panel factors the panel (rows k0..N-1) in registers,
+// k_lu_swap_trsm applies its row swaps to the other columns and solves the
+// U12 block row, k_lu_update subtracts L21 U12 from the trailing matrix on
+// MFMA.  perm accumulates the swaps as a row gather (y_perm[i] = y[perm[i]]).
+constexpr int kLUPanel = 16;
+constexpr int kLUMaxN = 1024;       // two rows per thread in the 512-thread panel kernel
+
+struct LUStepArgs {
+    int N, k0, nb;          // panel columns k0 .. k0 + nb - 1
     Jobs jobs;
     double2* LU;            // [path][slot][N*N] column-major, factorised in place
-    int* piv;               // [path][slot][N]
+    int* piv;               // [path][slot][N] LAPACK-style pivot rows (0-based)
+    int* perm;              // [path][slot][N]
     const int* paths;
-    int* flag;              // [1] first singular path + 1, [2] its pivot row
+    int* flag;              // [1] first singular path + 1, [2] its pivot column
 };
 
 struct Stage2CArgs {
@@ -143,25 +163,27 @@ struct Stage2CArgs {
     const double* vvec;
     const double2* H;
     const double2* LU;
-    const int* piv;
+    const int* perm;
     const double2* u_in;
+    double2* Y;             // [n_traj][n_pad] P (H u) between the two kernels of a stage
     double2* X;
     double2* Xacc;
     double2* u_out;
     int* flag;
 };
 
-hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
-hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
-hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
-hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st);
-hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st);
-hipError_t launch_lu(const LUArgs& a, int n_jobs, hipStream_t st);
-hipError_t launch_2c_stage(const Stage2CArgs& a, int n_paths, hipStream_t st);
+hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_lu_panel(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_lu_swap_trsm(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_lu_update(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,
-                            int slot, double* P, double* norm, hipStream_t st);
+                            int slot, double* P, double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_transpose_copy(const double2* src_colmajor, double2* dst_rowmajor, int N, hipStream_t st);
-int contract_smem_bytes(int n_w);
-hipError_t contract_set_smem(int bytes);
 
 }  // namespace wpccc

@@ -137,6 +137,7 @@ struct Group2C {
     int *d_radl_T = nullptr, *d_radl_P = nullptr;
     double2 *d_S = nullptr, *d_LU = nullptr, *d_H = nullptr;  // [path][slot][N*N]
     int* d_piv = nullptr;                                      // [path][slot][N]
+    int* d_perm = nullptr;                                     // [path][slot][N]
     int max_jobs = 0;
     double* d_nodes = nullptr;
     int* d_jst = nullptr;
@@ -153,20 +154,27 @@ struct Plan2C {
     std::vector<double> b, v;
     double *d_b = nullptr, *d_v = nullptr;
     int* d_flag = nullptr;  // [0] non-finite amplitude, [1] singular path + 1, [2] its pivot row
-    double2 *d_Ua = nullptr, *d_Ub = nullptr, *d_Xacc = nullptr;
+    double2 *d_Ua = nullptr, *d_Ub = nullptr, *d_Xacc = nullptr, *d_Y = nullptr;
     double *d_xlag = nullptr, *d_wlag = nullptr, *d_tleg = nullptr, *d_wleg = nullptr;
     long long bytes = 0;
+    KernelTimer* timer = nullptr;
     double slot_z[kSlots2C];
     bool slot_ok[kSlots2C] = {false, false, false};
 };
 
 namespace {
 
+// launch with optional event timing
+template <typename F>
+int timed(Plan2C* p, int id, F&& launch) {
+    return launched(launch(p->timer->open(id)), kKernelNames[id]);
+}
+
 void free_group(Group2C& g) {
     centre_free(g.cT);
     centre_free(g.cP);
     void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
-                    g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_nodes,  g.d_jst,    g.d_nact,
+                    g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_nodes,  g.d_jst,    g.d_nact,
                     g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
@@ -205,7 +213,9 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     m.n_eta = n_eta;
     m.n_tau = n_tau;
     m.n_nodes = n_eta * n_tau;
-    m.n_fields = kNodeFixed + 2 * m.L + 1;
+    m.f_pa = kFJ + 2 * m.L + 1;
+    m.f_pb = m.f_pa + (m.LT + 1) * (m.LT + 2) / 2;
+    m.n_fields = m.f_pb + (m.LP + 1) * (m.LP + 2) / 2;
     m.n_w = q_prior ? 3 : 2;
     m.q_prior = q_prior;
     for (int l = 0; l <= kMaxL + 1; ++l) {
@@ -282,6 +292,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_LU, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_H, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_piv, np * kSlots2C * m.N, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_perm, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nodes, J * m.n_fields * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_jst, J * 2 * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nact, J, tot))) return rc;
@@ -330,7 +341,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.PH = side ? g.d_PHP : g.d_PHT;
         a.nbF = (c.meta.n_frow + 255) / 256;
         a.nbP = (c.meta.n_states + 255) / 256;
-        if ((rc = launched(launch_setup_batch(a, c.meta, nj, st), "k_setup_batch"))) return rc;
+        if ((rc = timed(p, k2cSetup, [&](const LaunchEv& ev) { return launch_setup_batch(a, c.meta, nj, st, ev); }))) return rc;
     }
     {
         DirectArgs a;
@@ -349,7 +360,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.n_frowP = g.cP.meta.n_frow;
         a.n_gP = g.cP.meta.n_g;
         a.H = g.d_H;
-        if ((rc = launched(launch_2c_direct(a, g.m, nj, st), "k_2c_direct"))) return rc;
+        if ((rc = timed(p, k2cDirect, [&](const LaunchEv& ev) { return launch_2c_direct(a, g.m, nj, st, ev); }))) return rc;
     }
     {
         NodeArgs a;
@@ -365,11 +376,12 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.nodes = g.d_nodes;
         a.jst = g.d_jst;
         a.n_act = g.d_nact;
-        if ((rc = launched(launch_2c_nodes(a, g.m, nj, st), "k_2c_nodes"))) return rc;
+        if ((rc = timed(p, k2cNodes, [&](const LaunchEv& ev) { return launch_2c_nodes(a, g.m, nj, st, ev); }))) return rc;
     }
     {
         ContractArgs a;
         a.m = g.d_m;
+        a.n_jobs = nj;
         a.tiles = g.d_tiles;
         a.phiT_T = g.d_phiT_T;
         a.phiT_P = g.d_phiT_P;
@@ -379,7 +391,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.jst = g.d_jst;
         a.n_act = g.d_nact;
         a.tmol = g.d_tmol;
-        if ((rc = launched(launch_2c_contract(a, g.m, nj, st), "k_2c_contract"))) return rc;
+        if ((rc = timed(p, k2cContract, [&](const LaunchEv& ev) { return launch_2c_contract(a, g.m, nj, st, ev); }))) return rc;
     }
     {
         AssembleArgs a;
@@ -394,17 +406,22 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.S = g.d_S;
         a.LU = g.d_LU;
         a.H = g.d_H;
-        if ((rc = launched(launch_2c_assemble(a, g.m, nj, st), "k_2c_assemble"))) return rc;
+        if ((rc = timed(p, k2cAssemble, [&](const LaunchEv& ev) { return launch_2c_assemble(a, g.m, nj, st, ev); }))) return rc;
     }
-    {
-        LUArgs a;
-        a.N = g.m.N;
-        a.jobs = J;
-        a.LU = g.d_LU;
-        a.piv = g.d_piv;
-        a.paths = g.d_paths;
-        a.flag = p->d_flag;
-        if ((rc = launched(launch_lu(a, nj, st), "k_lu"))) return rc;
+    LUStepArgs a;
+    a.N = g.m.N;
+    a.jobs = J;
+    a.LU = g.d_LU;
+    a.piv = g.d_piv;
+    a.perm = g.d_perm;
+    a.paths = g.d_paths;
+    a.flag = p->d_flag;
+    for (int k0 = 0; k0 < a.N; k0 += kLUPanel) {
+        a.k0 = k0;
+        a.nb = std::min(kLUPanel, a.N - k0);
+        if ((rc = timed(p, kLuPanel, [&](const LaunchEv& ev) { return launch_lu_panel(a, nj, st, ev); }))) return rc;
+        if ((rc = timed(p, kLuSwap, [&](const LaunchEv& ev) { return launch_lu_swap_trsm(a, nj, st, ev); }))) return rc;
+        if ((rc = timed(p, kLuUpdate, [&](const LaunchEv& ev) { return launch_lu_update(a, nj, st, ev); }))) return rc;
     }
     return WPCCC_OK;
 }
@@ -422,13 +439,16 @@ int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, do
     a.vvec = p->d_v;
     a.H = g.d_H + (size_t)l0 * kSlots2C * NN;
     a.LU = g.d_LU + (size_t)l0 * kSlots2C * NN;
-    a.piv = g.d_piv + (size_t)l0 * kSlots2C * g.m.N;
+    a.perm = g.d_perm + (size_t)l0 * kSlots2C * g.m.N;
     a.u_in = u_in;
+    a.Y = p->d_Y;
     a.X = X;
     a.Xacc = p->d_Xacc;
     a.u_out = u_out;
     a.flag = p->d_flag;
-    return launched(launch_2c_stage(a, np, st), "k_2c_stage");
+    int rc = timed(p, k2cHu, [&](const LaunchEv& ev) { return launch_2c_hu(a, np, st, ev); });
+    if (rc) return rc;
+    return timed(p, k2cSolve, [&](const LaunchEv& ev) { return launch_2c_solve(a, np, st, ev); });
 }
 
 int find_slot(const Plan2C* p, double z) {
@@ -488,7 +508,7 @@ int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
 
 int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,
                   const int* set_of_traj, const double* b, const double* v, const wpccc_plan_opts& o,
-                  hipStream_t st, Plan2C** out) {
+                  KernelTimer* timer, hipStream_t st, Plan2C** out) {
     *out = nullptr;
     if (o.q_lower != WPCCC_Q_DAGGER && o.q_lower != WPCCC_Q_PRIOR) {
         set_error("wpccc_plan_create_2c: q_lower must be WPCCC_Q_DAGGER or WPCCC_Q_PRIOR");
@@ -517,6 +537,11 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     for (int s = 0; s < n_sets; ++s) {
         if ((rc = check_basis(targets[s]->hb, "target"))) return rc;
         if ((rc = check_basis(projectiles[s]->hb, "projectile"))) return rc;
+        if (targets[s]->hb.n_states + projectiles[s]->hb.n_states > kLUMaxN) {
+            set_error("wpccc_plan_create_2c: set %d has %d states; at most %d are supported", s,
+                      targets[s]->hb.n_states + projectiles[s]->hb.n_states, kLUMaxN);
+            return WPCCC_ENOTSUP;
+        }
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -529,6 +554,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
         set_error("wpccc_plan_create_2c: out of host memory");
         return WPCCC_ENOMEM;
     }
+    p->timer = timer;
     p->n_traj = n_traj;
     p->batched = o.batched ? 1 : 0;
     p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
@@ -570,6 +596,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     if ((rc = dev_alloc(&p->d_Ua, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
     if ((rc = dev_alloc(&p->d_Ub, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
     if ((rc = dev_alloc(&p->d_Xacc, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
+    if ((rc = dev_alloc(&p->d_Y, (size_t)n_traj * p->n_pad, tot))) return fail(rc);
     if ((rc = dev_alloc(&p->d_xlag, xl.size(), tot))) return fail(rc);
     if ((rc = dev_alloc(&p->d_wlag, wl.size(), tot))) return fail(rc);
     if ((rc = dev_alloc(&p->d_tleg, tl.size(), tot))) return fail(rc);
@@ -593,7 +620,8 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
 void plan2c_destroy(Plan2C* p) {
     if (!p) return;
     for (Group2C& g : p->groups) free_group(g);
-    void* bufs[] = {p->d_b, p->d_v, p->d_flag, p->d_Ua, p->d_Ub, p->d_Xacc, p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg};
+    void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Ua,   p->d_Ub,  p->d_Xacc,
+                    p->d_Y,    p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;
@@ -696,9 +724,10 @@ int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* Xv, voi
             for (int l0 = 0; l0 < npath; l0 += chunk)
                 if ((rc = enqueue_couplings(p, g, l0, std::min(chunk, npath - l0), 1, sl, zz, st))) return rc;
         }
-        if ((rc = launched(launch_2c_finish(X, g.d_S, g.m.N, p->n_pad, g.d_paths, npath, slot, (double*)P,
-                                            (double*)norm, st),
-                           "k_2c_finish")))
+        if ((rc = timed(p, k2cFinish, [&](const LaunchEv& ev) {
+                 return launch_2c_finish(X, g.d_S, g.m.N, p->n_pad, g.d_paths, npath, slot, (double*)P,
+                                         (double*)norm, st, ev);
+             })))
             return rc;
     }
     return WPCCC_OK;

@@ -119,19 +119,18 @@ class TwoCentreWorkload:
         return int(self.zgrid.size - 1)
 
 
-def two_centre_batched() -> TwoCentreWorkload:
-    """p + H with capture: three basis sizes per centre (bound n <= 6 plus 11, 13
-    or 15 Coulomb bins per l, l <= 4, 4000-point grid: 355, 405 or 455 states per
-    centre), 8 impact parameters b log-spaced 0.1..10 at each of v = 0.5, 1, 2
-    (v = 0.5 with the smallest basis, 2 with the largest), 24 paths in one batch,
-    256 x 512 spheroidal nodes, z from -40 to 40 with dz = 0.1."""
-    recs = [Recipe(6, 4, nb, 3.0, 4000) for nb in (11, 13, 15)]
+def two_centre_batched(v: float = 1.0) -> TwoCentreWorkload:
+    """p + H with capture, the same recipe on both centres (bound n <= 6 plus 20
+    Coulomb bins per l, 4000-point grid) at three sizes, l <= 1, 2, 3: 101, 221
+    and 382 states per centre (N = 202, 442, 764).  8 impact parameters b
+    log-spaced 0.2..10 for each size, 24 paths in one batch at speed v (0.5, 1
+    or 2 a.u.), 256 x 512 spheroidal nodes, z from -40 to 40 with dz = 0.1."""
+    recs = [Recipe(6, l, 20, 3.0, 4000) for l in (1, 2, 3)]
     k = np.arange(24) % 8
     s = np.arange(24) // 8
-    b = 0.1 * 100.0 ** (k / 7.0)
-    v = np.array([0.5, 1.0, 2.0])[s]
-    return TwoCentreWorkload("p+H 2C N=710..910 x24 b", "two-centre with capture, FP64, uneven bases",
-                             recs, recs, s.astype(np.int32), b, v, z_uniform(-40.0, 40.0, 0.1))
+    b = 0.2 * 50.0 ** (k / 7.0)
+    return TwoCentreWorkload(f"p+H 2C N=202/442/764 x24 b v={v:g}", "two-centre with capture, FP64, uneven bases",
+                             recs, recs, s.astype(np.int32), b, np.full(24, float(v)), z_uniform(-40.0, 40.0, 0.1))
 
 
 def two_centre_small() -> TwoCentreWorkload:
@@ -146,3 +145,30 @@ def two_centre_small() -> TwoCentreWorkload:
                              [t0, t1], [p0, p0], np.array([0, 1, 0], dtype=np.int32),
                              np.array([0.8, 1.5, 3.0]), np.array([0.5, 1.0, 2.0]),
                              z_uniform(-4.0, 4.0, 0.5), n_eta=24, n_tau=32)
+
+
+@dataclass
+class AdjointWorkload:
+    """Screened-potential gradients: one (a, c) for the batch, paths b, loss weights."""
+    name: str
+    basis: Recipe
+    a: float
+    c: float
+    b: np.ndarray
+    v: np.ndarray
+    weights: np.ndarray
+    zgrid: np.ndarray
+
+
+def adjoint_batch(n_states: int = 86) -> AdjointWorkload:
+    """The N = 86 single-path basis with the screened potential -(1 + a e^{-c r})/r:
+    numpy default_rng(5) draws a ~ U[0.2, 1.0], c ~ U[0.5, 2.0], 16 b log-uniform
+    in [0.3, 8] (sorted) and the loss weights w_i ~ U[0, 1], in that order;
+    v = 1, z from -40 to 40 with dz = 0.1."""
+    rng = np.random.default_rng(5)
+    a = float(rng.uniform(0.2, 1.0))
+    c = float(rng.uniform(0.5, 2.0))
+    b = np.sort(np.exp(rng.uniform(np.log(0.3), np.log(8.0), 16)))
+    w = rng.uniform(0.0, 1.0, n_states)
+    return AdjointWorkload("p+H 1C N=86 screened potential x16 b", Recipe(3, 2, 8, 3.0, 1500), a, c, b,
+                           np.ones(16), w, z_uniform(-40.0, 40.0, 0.1))

@@ -175,3 +175,31 @@ def test_2c_couplings_errors(bases):
     assert e.value.code == -1
     with pytest.raises(W.WpcccError):
         W.wpccc_plan_path_info(plan, 1)
+
+
+def test_2c_propagation_multiblock(bases):
+    """N = 146 (133 target + 13 projectile states): ten LU panels with a ragged
+    last one, three blocks of the triangular solves, several update tiles."""
+    (lt, ot), (lp, op) = bases["wide"], bases["p0"]
+    b, v, ne, nt = 1.3, 1.0, 32, 40
+    zg = np.linspace(-2.0, 0.0, 5)
+    print("2C propagation: N=146, 4 steps", flush=True)
+    plan = W.wpccc_plan_create_2c([lt], [lp], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=ne, n_tau=nt)
+    N, NT = W.wpccc_plan_path_info(plan, 0)
+    assert (N, NT) == (146, 133)
+    X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[0, 0] = 1.0
+    P = torch.empty((1, plan.n_pad), dtype=torch.float64, device="cuda")
+    nrm = torch.empty((1,), dtype=torch.float64, device="cuda")
+    W.wpccc_propagate(plan, zg, X, P, nrm)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    M = m_two_centre(ot, op, b, v, ne, nt, Q_PRIOR)
+    Xo = rk4_propagate(M, initial_state(N), zg)
+    Po = np.abs(Xo) ** 2
+    Pg = P.cpu().numpy()[0, :N]
+    ok = prob_ok(Pg, Po)
+    assert ok.all(), (np.abs(Pg - Po).max(), Po[~ok][:5], Pg[~ok][:5])
+    S1, _ = two_centre_matrices(ot, op, b, float(zg[-1]), v, ne, nt, Q_PRIOR)
+    no = (Xo.conj() @ S1 @ Xo).real
+    assert abs(nrm.cpu().numpy()[0] - no) <= 1e-12 * abs(no)

@@ -1,0 +1,156 @@
+"""GPU adjoint of the one-centre propagation with the screened target potential
+(through the C ABI and the torch.autograd binding).
+
+Tolerances
+----------
+* forward with the model potential vs the oracle: |dP| <= 1e-10 max(P, 1e-6);
+* reverse-mode gradients vs the oracle's forward-mode (tangent-linear)
+  gradients of the same discrete scheme: |dg| <= 1e-9 max(1, |g|) — both
+  differentiate Algorithm 1 exactly, so they differ by rounding only;
+* vs central differences of the GPU forward (delta = 1e-5 relative):
+  |dg| <= 1e-5 max(1, |g|);
+* different checkpoint intervals recompute the same states: bitwise equal.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2403_04252_amd as W
+from paper_2403_04252_amd import workloads as WL
+from oracle.propagate import initial_state, rk4_propagate
+from oracle.radial import BasisSpec as OSpec, build_basis
+from oracle.sensitivity import dm_model, loss_gradient, m_model, rk4_tangent
+
+pytestmark = pytest.mark.gpu
+
+P_FLOOR = 1e-6
+
+
+def lib_basis(rec):
+    return W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+
+
+def oracle_basis(rec):
+    return build_basis(OSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+
+
+REC = WL.Recipe(2, 1, 2, 2.0, 600, 60.0)   # N = 13: oracle tangents in seconds
+
+
+@pytest.fixture(scope="module")
+def small():
+    return lib_basis(REC), oracle_basis(REC)
+
+
+def _gpu_grad(lb, b, v, a, c, zg, wts, K=0):
+    plan = W.wpccc_plan_create(lb, b, v, model_a=a, model_c=c, checkpoint_every=K)
+    N = plan.n_states
+    X0 = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X0[:, 0] = 1.0
+    X = torch.empty_like(X0)
+    # forward alone gives the final state; gX = dL/d conj(X) = w X for L = sum w |X|^2
+    Xf = X0.clone()
+    W.wpccc_propagate(plan, zg, Xf)
+    gX = torch.zeros_like(X0)
+    gX[:, :N] = torch.as_tensor(wts, device="cuda") * Xf[:, :N]
+    grad = torch.empty((plan.n_traj, 3), dtype=torch.float64, device="cuda")
+    W.wpccc_adjoint(plan, zg, X0, gX, grad, X)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    assert torch.equal(X, Xf), "the adjoint's forward sweep must reproduce wpccc_propagate"
+    return Xf.cpu().numpy()[:, :N], grad.cpu().numpy()
+
+
+def test_model_potential_forward_parity(small):
+    lb, ob = small
+    a, c, v = 0.6, 1.1, 1.0
+    bs = [0.7, 2.5]
+    zg = np.linspace(-6.0, 6.0, 49)
+    print("model potential forward, 2 paths, 48 steps", flush=True)
+    plan = W.wpccc_plan_create(lb, bs, v, model_a=a, model_c=c)
+    X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    P = torch.empty((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
+    W.wpccc_propagate(plan, zg, X, P)
+    torch.cuda.synchronize()
+    N = plan.n_states
+    for j, b in enumerate(bs):
+        Xo = rk4_propagate(m_model(ob, b, v, a, c), initial_state(N), zg)
+        Po = np.abs(Xo) ** 2
+        Pg = P.cpu().numpy()[j, :N]
+        assert np.all(np.abs(Pg - Po) <= 1e-10 * np.maximum(Po, P_FLOOR)), (j, np.abs(Pg - Po).max())
+    # the potential changes the result
+    plan0 = W.wpccc_plan_create(lb, bs, v)
+    X0 = torch.zeros_like(X)
+    X0[:, 0] = 1.0
+    W.wpccc_propagate(plan0, zg, X0)
+    assert (X0 - X).abs().max().item() > 1e-3
+
+
+def test_adjoint_matches_oracle_tangent(small):
+    lb, ob = small
+    a, c, v = 0.6, 1.1, 1.0
+    bs = np.array([0.7, 1.6, 4.0])
+    zg = np.linspace(-6.0, 6.0, 49)
+    wts = np.random.default_rng(3).uniform(0.0, 1.0, ob.n_states)
+    print("adjoint vs oracle tangent, 3 paths, 48 steps", flush=True)
+    Xg, g = _gpu_grad(lb, bs, v, a, c, zg, wts, K=5)
+    for j, b in enumerate(bs):
+        X, dX = rk4_tangent(m_model(ob, b, v, a, c), dm_model(ob, b, v, a, c), initial_state(ob.n_states), zg)
+        L, go = loss_gradient(X, dX, wts)
+        for k in range(3):
+            assert abs(g[j, k] - go[k]) <= 1e-9 * max(1.0, abs(go[k])), (j, k, g[j, k], go[k])
+        print(f"  path {j}: grad a,c,b = {g[j]}, oracle {go}", flush=True)
+
+
+def test_checkpoint_interval_bitwise(small):
+    lb, _ = small
+    zg = np.linspace(-3.0, 3.0, 23)
+    wts = np.linspace(0.1, 1.0, 13)
+    grads = [_gpu_grad(lb, [0.9, 2.2], 1.0, 0.4, 0.9, zg, wts, K=K)[1] for K in (1, 5, 22, 0)]
+    for gk in grads[1:]:
+        assert np.array_equal(gk, grads[0])
+
+
+def test_adjoint_full_workload_vs_finite_differences():
+    """The screened-potential batch at full size (N = 86, 16 paths, 800 steps):
+    adjoint gradients against central differences of the GPU forward."""
+    wl = WL.adjoint_batch()
+    lb = lib_basis(wl.basis)
+    print("adjoint full workload: 16 paths x 800 steps", flush=True)
+    Xg, g = _gpu_grad(lb, wl.b, wl.v, wl.a, wl.c, wl.zgrid, wl.weights)
+
+    def loss(a, c, b):
+        plan = W.wpccc_plan_create(lb, b, wl.v, model_a=a, model_c=c)
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        W.wpccc_propagate(plan, wl.zgrid, X)
+        P = (X.abs() ** 2).cpu().numpy()[:, :plan.n_states]
+        return P @ wl.weights
+
+    d = 1e-5
+    fa = (loss(wl.a * (1 + d), wl.c, wl.b) - loss(wl.a * (1 - d), wl.c, wl.b)) / (2 * d * wl.a)
+    fc = (loss(wl.a, wl.c * (1 + d), wl.b) - loss(wl.a, wl.c * (1 - d), wl.b)) / (2 * d * wl.c)
+    fb = (loss(wl.a, wl.c, wl.b * (1 + d)) - loss(wl.a, wl.c, wl.b * (1 - d))) / (2 * d * wl.b)
+    for k, fd in enumerate([fa, fc, fb]):
+        err = np.abs(g[:, k] - fd)
+        assert np.all(err <= 1e-5 * np.maximum(1.0, np.abs(fd))), (k, err.max(), g[:, k][:4], fd[:4])
+    print(f"  max |adjoint - FD|: a {np.abs(g[:,0]-fa).max():.2e} c {np.abs(g[:,1]-fc).max():.2e} "
+          f"b {np.abs(g[:,2]-fb).max():.2e}", flush=True)
+
+
+def test_autograd_function(small):
+    from paper_2403_04252_amd.autograd import propagate_probabilities
+    lb, _ = small
+    zg = np.linspace(-3.0, 3.0, 25)
+    b = torch.tensor([0.8, 1.9], dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(0.5, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(1.2, dtype=torch.float64, requires_grad=True)
+    P = propagate_probabilities(b, a, c, lb, 1.0, zg)
+    wts = torch.linspace(0.0, 1.0, P.shape[1], dtype=torch.float64, device=P.device)
+    L = (P * wts).sum()
+    L.backward()
+    _, g = _gpu_grad(lb, b.detach().numpy(), 1.0, 0.5, 1.2, zg, wts.cpu().numpy())
+    assert np.allclose(b.grad.numpy(), g[:, 2], rtol=1e-12, atol=0)
+    assert abs(a.grad.item() - g[:, 0].sum()) <= 1e-12 * abs(g[:, 0].sum())
+    assert abs(c.grad.item() - g[:, 1].sum()) <= 1e-12 * abs(g[:, 1].sum())
