@@ -132,6 +132,8 @@ typedef struct {
     double model_a; /* 1C: screened target potential V(r) = -(1 + a e^{-c r})/r on the */
     double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
     int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
+    int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 8 or 16;
+                       0: chosen at plan creation by timing each on the plan's paths */
 } wpccc_plan_opts;
 
 /* Create a plan for n_traj paths with impact parameters b_host[j] > 0 and
@@ -169,6 +171,10 @@ int wpccc_plan_info(wpccc_plan_t plan, int* n_traj, int* n_states, int* n_pad,
                     long long* device_bytes);
 
 int wpccc_plan_destroy(wpccc_plan_t plan);
+
+/* Rows per workgroup of a one-centre plan's RK4 stage kernel (stage_rows as
+ * given, or as chosen by timing at plan creation). */
+int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows);
 
 /* Returns the first device-side error latched since the last call (after
  * synchronising `stream`), then clears it: WPCCC_OK, WPCCC_ENUMERIC or (2C)

@@ -19,7 +19,7 @@ __all__ = [
     "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_create_2c", "wpccc_plan_info",
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
-    "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint",
+    "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,7 +48,7 @@ class _PlanOpts(ctypes.Structure):
     _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int),
                 ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int),
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
-                ("checkpoint_every", ctypes.c_int)]
+                ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int)]
 
 
 @dataclass
@@ -96,6 +96,7 @@ def load_library():
         "wpccc_step": ([vp, vp, d, d, vp], i),
         "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
         "wpccc_adjoint": ([vp, pd, i, vp, vp, vp, vp, vp], i),
+        "wpccc_plan_stage_rows": ([vp, pi], i),
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
     }
@@ -201,14 +202,14 @@ def wpccc_basis_destroy(basis: Basis):
 
 def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
                       two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
-                      checkpoint_every: int = 0, stream=None) -> Plan:
+                      checkpoint_every: int = 0, stage_rows: int = 0, stream=None) -> Plan:
     """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
     model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
     opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
-                     float(model_a), float(model_c), int(checkpoint_every))
+                     float(model_a), float(model_c), int(checkpoint_every), int(stage_rows))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -218,6 +219,13 @@ def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
     p = Plan(h, basis, nt.value, ns.value, npad.value)
     p.device_bytes = nb.value
     return p
+
+
+def wpccc_plan_stage_rows(plan: Plan) -> int:
+    """Rows per workgroup of the plan's RK4 stage kernel (set or chosen by timing)."""
+    r = ctypes.c_int()
+    _check(load_library().wpccc_plan_stage_rows(plan.handle, ctypes.byref(r)))
+    return r.value
 
 
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
@@ -232,7 +240,7 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
         raise ValueError("targets and projectiles must pair up")
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
-    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0)
+    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

@@ -169,7 +169,7 @@ constexpr int kGBatch = 4;   // angular coefficients per thread held in register
 //   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
-template <int KIND>
+template <int KIND, int ROWS>
 __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
@@ -184,9 +184,9 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
 
     double2* xs = reinterpret_cast<double2*>(smem);                       // [N]
     double2* Ws = xs + N;                                                  // [rows][gcols]
-    double2* phs = Ws + kRowsPerBlock * gcols;                             // [n_f]
+    double2* phs = Ws + ROWS * gcols;                                      // [n_f]
     double* Fs = reinterpret_cast<double*>(phs + m.n_f);                  // [rows][nV]
-    double* Gs = Fs + kRowsPerBlock * nV;                                  // [nmp][gcols]
+    double* Gs = Fs + ROWS * nV;                                           // [nmp][gcols]
     double* rps = Gs + nmp * gcols;                                        // [kRpow]
     double* pbs = rps + kRpow;                                             // [kMaxPb]
     int2* gis = reinterpret_cast<int2*>(pbs + kMaxPb);                     // [gcols]
@@ -404,38 +404,33 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
 }
 
-// grid: x = (l', row chunk) pairs in l' order, y = path.
-__global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
-    extern __shared__ double2 smem2[];
+// grid: x = (l', chunk of ROWS rows) pairs in l' order, y = path.
+template <int KIND, int ROWS>
+__device__ void stage_entry(const StageArgs& a, char* smem) {
     const Meta& m = *a.meta;
     const int j = a.traj0 + blockIdx.y;
     int c = blockIdx.x, lp = 0;
     for (; lp < m.l_max; ++lp) {
-        const int nc = (m.n_l[lp] + kRowsPerBlock - 1) / kRowsPerBlock;
+        const int nc = (m.n_l[lp] + ROWS - 1) / ROWS;
         if (c < nc) break;
         c -= nc;
     }
-    const int row0 = c * kRowsPerBlock;
-    const int nrows = min(kRowsPerBlock, m.n_l[lp] - row0);
+    const int row0 = c * ROWS;
+    const int nrows = min(ROWS, m.n_l[lp] - row0);
     if (nrows <= 0) return;
-    stage_body<0>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+    stage_body<KIND, ROWS>(a, j, lp, row0, nrows, smem);
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
+    extern __shared__ double2 smem2[];
+    stage_entry<0, ROWS>(a, reinterpret_cast<char*>(smem2));
 }
 
 // Operator application with the grid of k_stage (see StageArgs).
 __global__ __launch_bounds__(kStageThreads) void k_apply(StageArgs a) {
     extern __shared__ double2 smem2[];
-    const Meta& m = *a.meta;
-    const int j = a.traj0 + blockIdx.y;
-    int c = blockIdx.x, lp = 0;
-    for (; lp < m.l_max; ++lp) {
-        const int nc = (m.n_l[lp] + kRowsPerBlock - 1) / kRowsPerBlock;
-        if (c < nc) break;
-        c -= nc;
-    }
-    const int row0 = c * kRowsPerBlock;
-    const int nrows = min(kRowsPerBlock, m.n_l[lp] - row0);
-    if (nrows <= 0) return;
-    stage_body<1>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+    stage_entry<1, kRowsPerBlock>(a, reinterpret_cast<char*>(smem2));
 }
 
 // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] += 2 gamma Re(dv^H dM/dc u),
@@ -612,12 +607,18 @@ __global__ void k_probabilities(const double2* __restrict__ X, int n_states, int
 
 }  // namespace
 
-int stage_smem_bytes(const Meta& m) {
+int stage_chunks(const Meta& m, int rows) {
+    int n = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) n += (m.n_l[lp] + rows - 1) / rows;
+    return n;
+}
+
+int stage_smem_bytes(const Meta& m, int rows) {
     int best = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
         const size_t nmp = 2 * lp + 1;
-        const size_t bytes = m.n_states * sizeof(double2) + (size_t)kRowsPerBlock * m.gcols[lp] * sizeof(double2) +
-                             (size_t)m.n_f * sizeof(double2) + (size_t)kRowsPerBlock * m.nV[lp] * sizeof(double) +
+        const size_t bytes = m.n_states * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
+                             (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
                              nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
                              (size_t)m.gcols[lp] * sizeof(int2);
         if ((int)bytes > best) best = (int)bytes;
@@ -626,9 +627,11 @@ int stage_smem_bytes(const Meta& m) {
 }
 
 hipError_t stage_set_smem_limit(int, int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* fns[] = {(const void*)k_stage<4>, (const void*)k_stage<8>, (const void*)k_stage<16>,
+                         (const void*)k_apply};
+    hipError_t e = hipSuccess;
+    for (const void* f : fns)
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 
@@ -680,8 +683,14 @@ hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st,
     return hipGetLastError();
 }
 
-hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_stage, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st, const LaunchEv& ev,
+                        int rows) {
+    const dim3 grid(stage_chunks(hm, rows), n_traj_launch), block(kStageThreads);
+    switch (rows) {
+        case 4: WPCCC_LAUNCH(ev, k_stage<4>, grid, block, smem, st, a); break;
+        case 16: WPCCC_LAUNCH(ev, k_stage<16>, grid, block, smem, st, a); break;
+        default: WPCCC_LAUNCH(ev, k_stage<8>, grid, block, smem, st, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ constexpr int kMaxLam = 2 * kMaxL;   // largest multipole order
 constexpr int kMaxPb = (kMaxLam + 1) * (kMaxLam + 2) / 2;
 constexpr int kSlots = 3;            // couplings kept for the diagnostic entry point
 constexpr int kStageThreads = 256;
-constexpr int kRowsPerBlock = 8;     // output rows n' per stage workgroup
+constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and k_stage's default)
 
 // Per-basis sizes passed to kernels by value.
 //
@@ -250,8 +250,9 @@ hipError_t launch_moments(const double* r, const double* w, const double* phiT, 
                           const int* db, const int* dl, int n_r, int n_f, int n_frow, double2* tab,
                           hipStream_t st);
 hipError_t launch_slot_setup(const SetupArgs& a, const Meta& host_meta, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+// rows: output rows n' per workgroup (4, 8 or 16; chosen per plan by timing)
 hipError_t launch_stage(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
-                        const LaunchEv& ev = LaunchEv{});
+                        const LaunchEv& ev = LaunchEv{}, int rows = kRowsPerBlock);
 hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const double* Frow, const double* G,
                                   const double2* PH, double Zp, double2* H, hipStream_t st,
                                   const LaunchEv& ev = LaunchEv{});
@@ -266,6 +267,7 @@ hipError_t launch_combine(double2* out, const double2* const* v, const double* c
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
                               hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);
-int stage_smem_bytes(const Meta& m);
+int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
+int stage_chunks(const Meta& m, int rows);
 
 }  // namespace wpccc

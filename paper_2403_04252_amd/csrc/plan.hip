@@ -55,7 +55,9 @@ struct wpccc_plan_s {
     double2 *d_lam = nullptr, *d_mu = nullptr, *d_nu = nullptr, *d_u2 = nullptr, *d_u3 = nullptr, *d_u4 = nullptr;
     double2 *d_ckpt = nullptr, *d_seg = nullptr;
     long long bytes = 0;
-    int stage_smem = 0;
+    int stage_smem = 0;       // k_apply (kRowsPerBlock rows)
+    int stage_rows = kRowsPerBlock;
+    int stage_smem_rows = 0;  // k_stage with stage_rows
     KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
@@ -115,7 +117,7 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.Xacc = p->d_Xacc;
     a.u_out = u_out;
     a.flag = p->d_flag;
-    hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem, st, p->timer.open(kStage));
+    hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem_rows, st, p->timer.open(kStage), p->stage_rows);
     return launched(e, "k_stage");
 }
 
@@ -218,6 +220,70 @@ int enqueue_combine(wpccc_plan_s* p, double2* out, std::initializer_list<std::pa
         ++n;
     }
     return launched(launch_combine(out, v, c, n, p->n_traj, p->c.meta.n_states, p->n_pad, st), "k_combine");
+}
+
+// Rows per workgroup of k_stage: each candidate is timed on ten stage
+// launches over the plan's paths (zero amplitudes, the same table traffic as
+// a real stage) and the fastest is kept.
+int tune_stage_rows(wpccc_plan_s* p, const int* cand, int n_cand, hipStream_t st) {
+    const Meta& m = p->c.meta;
+    const size_t V = (size_t)p->n_traj * p->n_pad * sizeof(double2);
+    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Ua, 0, V, st));
+    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Ub, 0, V, st));
+    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Xacc, 0, V, st));
+    const double pts[3] = {0.37, 0.38, 0.39};  // b > 0, so R > 0 at any z
+    int rc = enqueue_prologue(p, pts, 3, 0, p->n_traj, st);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    WPCCC_HIP_CHECK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return WPCCC_EHIP;
+    }
+    float best_ms = 1e30f;
+    int best = p->stage_rows;
+    for (int ci = 0; ci < n_cand && rc == WPCCC_OK; ++ci) {
+        const int rows = cand[ci];
+        const int smem = stage_smem_bytes(m, rows);
+        if (smem > 160 * 1024) continue;
+        StageArgs a{};
+        a.meta = p->c.d_meta;
+        a.tb = p->tables();
+        a.pt = p->points();
+        a.Zp = p->Zp;
+        a.p = 1;
+        a.h = 0.1;
+        a.n_pad = p->n_pad;
+        a.stage = 2;
+        a.traj0 = 0;
+        a.u_in = p->d_Ua;
+        a.X = p->d_Ua;
+        a.Xacc = p->d_Xacc;
+        a.u_out = p->d_Ub;
+        a.flag = p->d_flag;
+        hipError_t e = hipSuccess;
+        for (int it = 0; it < 2 && e == hipSuccess; ++it) e = launch_stage(a, m, p->n_traj, smem, st, LaunchEv{}, rows);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int it = 0; it < 10 && e == hipSuccess; ++it) e = launch_stage(a, m, p->n_traj, smem, st, LaunchEv{}, rows);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            set_error("stage tuning failed: %s", hipGetErrorString(e));
+            rc = WPCCC_EHIP;
+        } else if (ms < best_ms) {
+            best_ms = ms;
+            best = rows;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    p->stage_rows = best;
+    p->stage_smem_rows = stage_smem_bytes(m, best);
+    return WPCCC_OK;
 }
 
 }  // namespace
@@ -346,7 +412,14 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->ckpt_every = o.checkpoint_every;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
-    if (plan->stage_smem > 160 * 1024) {
+    if (o.stage_rows != 0 && o.stage_rows != 4 && o.stage_rows != 8 && o.stage_rows != 16) {
+        set_error("wpccc_plan_create: stage_rows must be 0, 4, 8 or 16");
+        free_plan(plan);
+        return WPCCC_EINVAL;
+    }
+    plan->stage_rows = o.stage_rows ? o.stage_rows : kRowsPerBlock;
+    plan->stage_smem_rows = stage_smem_bytes(m, plan->stage_rows);
+    if (plan->stage_smem > 160 * 1024 || plan->stage_smem_rows > 160 * 1024) {
         set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes)", plan->stage_smem);
         free_plan(plan);
         return WPCCC_ENOTSUP;
@@ -379,11 +452,17 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->d_vc, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess && plan->stage_smem > 64 * 1024) e = stage_set_smem_limit(m.l_max, plan->stage_smem);
+    const int smem16 = stage_smem_bytes(m, 16);
+    const int smem_max = std::min(160 * 1024, std::max(smem16, plan->stage_smem));
+    if (e == hipSuccess && smem_max > 64 * 1024) e = stage_set_smem_limit(m.l_max, smem_max);
     if (e != hipSuccess) {
         set_error("wpccc_plan_create: device setup failed: %s", hipGetErrorString(e));
         free_plan(plan);
         return WPCCC_EHIP;
+    }
+    if (o.stage_rows == 0) {
+        const int cand[3] = {4, 8, 16};
+        TRY(tune_stage_rows(plan, cand, 3, st));
     }
     *out = plan;
     return WPCCC_OK;
@@ -445,6 +524,15 @@ int wpccc_plan_path_info(wpccc_plan_t plan, int j, int* n_states, int* n_target)
     }
     if (n_states) *n_states = plan->c.meta.n_states;
     if (n_target) *n_target = plan->c.meta.n_states;
+    return WPCCC_OK;
+}
+
+int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows) {
+    if (!plan || !rows) {
+        set_error("wpccc_plan_stage_rows: NULL argument");
+        return WPCCC_EINVAL;
+    }
+    *rows = plan->p2c ? 0 : plan->stage_rows;
     return WPCCC_OK;
 }
 
