@@ -91,6 +91,20 @@ def profiled_traffic(summary, source):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def copy_calibration(torch, mib):
+    """One elementwise kernel that reads and writes mib MiB each (reference for
+    the FETCH_SIZE / WRITE_SIZE counters of a profiled run)."""
+    if mib <= 0:
+        return
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_propagation(W, plan, X, zgrid, K):
     """Advance every path by K RK4 steps along the grid (wrapping to the start)."""
     done = 0
@@ -207,14 +221,7 @@ def main():
                "steps": seq_steps}
         del plan_seq
 
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes n * 8 bytes
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(torch, args.copy_calibration)
 
     cpu = None
     prob_err = None
@@ -341,6 +348,7 @@ def bench_two_centre(args):
         kt[nm] = {"total_ms": ms, "launches": n}
     W.wpccc_plan_timing(plan, False)
     torch.cuda.synchronize()
+    copy_calibration(torch, args.copy_calibration)
 
     # algorithmic flops of the contraction over the timed steps: the first step
     # computes z, z_mid, z_new, later steps z_mid and z_new

@@ -134,7 +134,17 @@ typedef struct {
     int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
     int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 8 or 16;
                        0: chosen at plan creation by timing each on the plan's paths */
+    int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED: 2C overlap/transfer
+                       contractions with FP32 products summed in FP32 over each
+                       32-node chunk and in FP64 across chunks; LU, solves and
+                       RK4 stay FP64 */
+    int graph;      /* 1C, batched: replay each 64-step chunk of wpccc_propagate
+                       from a captured HIP graph (step lengths and positions
+                       read from device memory); 0: launch kernel by kernel */
 } wpccc_plan_opts;
+
+#define WPCCC_FP64  0
+#define WPCCC_MIXED 1
 
 /* Create a plan for n_traj paths with impact parameters b_host[j] > 0 and
  * speeds v_host[j] > 0 (a.u.), all expanded in `target`.  The basis must

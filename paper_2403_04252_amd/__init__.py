@@ -29,6 +29,8 @@ _lib = None
 WPCCC_OK = 0
 WPCCC_Q_DAGGER = 0
 WPCCC_Q_PRIOR = 1
+WPCCC_FP64 = 0
+WPCCC_MIXED = 1
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
 
 
@@ -48,7 +50,8 @@ class _PlanOpts(ctypes.Structure):
     _fields_ = [("Zp", ctypes.c_double), ("batched", ctypes.c_int), ("two_centre", ctypes.c_int),
                 ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int),
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
-                ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int)]
+                ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
+                ("precision", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 @dataclass
@@ -202,14 +205,16 @@ def wpccc_basis_destroy(basis: Basis):
 
 def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
                       two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
-                      checkpoint_every: int = 0, stage_rows: int = 0, stream=None) -> Plan:
+                      checkpoint_every: int = 0, stage_rows: int = 0, graph: bool = False,
+                      stream=None) -> Plan:
     """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
     model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
     opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
-                     float(model_a), float(model_c), int(checkpoint_every), int(stage_rows))
+                     float(model_a), float(model_c), int(checkpoint_every), int(stage_rows), 0,
+                     1 if graph else 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -229,7 +234,8 @@ def wpccc_plan_stage_rows(plan: Plan) -> int:
 
 
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
-                         n_eta: int = 0, n_tau: int = 0, batched: bool = True, stream=None) -> Plan:
+                         n_eta: int = 0, n_tau: int = 0, batched: bool = True, mixed: bool = False,
+                         stream=None) -> Plan:
     """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j]."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
@@ -240,7 +246,8 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
         raise ValueError("targets and projectiles must pair up")
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
-    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0)
+    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
+                     WPCCC_MIXED if mixed else WPCCC_FP64, 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     const Meta& m = *a.meta;
     const int j = a.traj0 + blockIdx.y;
     const int p = blockIdx.x;
-    const double z = a.z[p];
+    const double z = a.zdev ? a.zdev[(size_t)(*a.chunk) * kChunkPoints + p] : a.z[p];
     const double b = a.tb.bvec[j], v = a.tb.vvec[j];
     const double R = sqrt(b * b + z * z);
     const size_t jp = (size_t)j * a.pt.n_pts + p;
@@ -159,6 +159,22 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
 constexpr int kFBatch = 12;  // table entries per thread held in registers
 constexpr int kXBatch = 4;   // amplitudes per thread held in registers
 constexpr int kGBatch = 4;   // angular coefficients per thread held in registers
+
+// The RK4 combination of stage a.stage for output oi with slope K and step h.
+__device__ inline void rk4_update(const StageArgs& a, size_t oi, double2 K, double2 x0, double2 xa, double h) {
+    if (a.stage == 1) {
+        a.u_out[oi] = make_double2(x0.x + 0.5 * h * K.x, x0.y + 0.5 * h * K.y);
+        a.Xacc[oi] = make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
+    } else if (a.stage == 2 || a.stage == 3) {
+        const double c = (a.stage == 2) ? 0.5 * h : h;
+        a.u_out[oi] = make_double2(x0.x + c * K.x, x0.y + c * K.y);
+        a.Xacc[oi] = make_double2(xa.x + h / 3.0 * K.x, xa.y + h / 3.0 * K.y);
+    } else {
+        const double2 xn = make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
+        if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
+        a.X[oi] = xn;
+    }
+}
 
 // One stage for rows [row0, row0 + nrows) of the l' block, all nmp = 2l'+1 values of m'.
 // KIND 0: RK4 stage (k_stage); KIND 1: operator application (k_apply, see
@@ -378,17 +394,10 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             }
             if (a.out) a.out[oi] = make_double2(a.alpha * K.x + a.beta * x0.x, a.alpha * K.y + a.beta * x0.y);
             gval = 2.0 * a.gamma * (xa.x * K.x + xa.y * K.y);  // 2 gamma Re(conj(dv) K)
-        } else if (a.stage == 1) {
-            a.u_out[oi] = make_double2(x0.x + 0.5 * h * K.x, x0.y + 0.5 * h * K.y);
-            a.Xacc[oi] = make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
-        } else if (a.stage == 2 || a.stage == 3) {
-            const double c = (a.stage == 2) ? 0.5 * h : h;
-            a.u_out[oi] = make_double2(x0.x + c * K.x, x0.y + c * K.y);
-            a.Xacc[oi] = make_double2(xa.x + h / 3.0 * K.x, xa.y + h / 3.0 * K.y);
         } else {
-            const double2 xn = make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
-            if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
-            a.X[oi] = xn;
+            // graph replays read the step length from device memory
+            const double hh = a.hdev ? a.hdev[(size_t)(*a.chunk) * kChunkSteps + a.hidx] : h;
+            rk4_update(a, oi, K, x0, xa, hh);
         }
     }
     if (KIND == 1 && a.grad) {
@@ -487,6 +496,11 @@ __global__ __launch_bounds__(256) void k_model_dot(ModelArgs a) {
         atomicAdd(a.grad + (size_t)j * 3 + 0, 2.0 * a.gamma * ta);
         atomicAdd(a.grad + (size_t)j * 3 + 1, 2.0 * a.gamma * tc);
     }
+}
+
+__global__ void k_chunk_counter(int* chunk, int reset) {
+    if (reset) *chunk = 0;
+    else *chunk += 1;
 }
 
 struct Combine {
@@ -638,6 +652,11 @@ hipError_t stage_set_smem_limit(int, int bytes) {
 hipError_t launch_apply(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev) {
     WPCCC_LAUNCH(ev, k_apply, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_counter, dim3(1), dim3(1), 0, st, chunk, reset);
     return hipGetLastError();
 }
 

@@ -126,6 +126,19 @@ __global__ __launch_bounds__(256) void k_2c_nodes(NodeArgs a) {
 // weights w_k of the chunk, then A (32 rows) and B (32 columns) in LDS; each
 // wave owns one 16 x 16 quarter of the tile for all nk weights and feeds the
 // MFMA with (A w_k) and B, so B is staged once for every weight.
+//
+// MIXED: the products run on v_mfma_f32_16x16x4f32 (operands rounded to FP32,
+// accumulated in FP32 over the 32 nodes of a chunk) and each chunk's partial
+// sums are added to FP64 accumulators, so the FP32 accumulation error stays
+// that of a 32-term sum whatever the number of nodes.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Output row of register r in lane l of a 16 x 16 MFMA tile (column l % 16):
+// measured on gfx950, 4 r + l / 16 for the FP64 instruction; FP32 per kF32Row.
+__device__ inline int mfma_row_f64(int r, int l) { return 4 * r + (l >> 4); }
+__device__ inline int mfma_row_f32(int r, int l) { return kF32RowByLaneGroup ? 4 * (l >> 4) + r : 4 * r + (l >> 4); }
+
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
     __shared__ double As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
     __shared__ double wk[kNodeChunk][kMaxK];
@@ -219,13 +232,35 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
             Bs[k][rr] = vb;
         }
         __syncthreads();
+        if (!MIXED) {
 #pragma unroll
-        for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
-            const int kr = ks * 4 + lk;
-            const double av = As[kr][mt * 16 + li], bv = Bs[kr][nt * 16 + li];
+            for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
+                const int kr = ks * 4 + lk;
+                const double av = As[kr][mt * 16 + li], bv = Bs[kr][nt * 16 + li];
+#pragma unroll
+                for (int kk = 0; kk < kMaxK; ++kk)
+                    if (kk < nk) acc[kk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av * wk[kr][kk], bv, acc[kk], 0, 0, 0);
+            }
+        } else {
+            flt4 c32[kMaxK];
+#pragma unroll
+            for (int kk = 0; kk < kMaxK; ++kk) c32[kk] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
+                const int kr = ks * 4 + lk;
+                const double av = As[kr][mt * 16 + li];
+                const float bv = (float)Bs[kr][nt * 16 + li];
+#pragma unroll
+                for (int kk = 0; kk < kMaxK; ++kk)
+                    if (kk < nk)
+                        c32[kk] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)(av * wk[kr][kk]), bv, c32[kk], 0, 0, 0);
+            }
+            // chunk sums into the FP64 accumulators (register r keeps the FP32 layout)
 #pragma unroll
             for (int kk = 0; kk < kMaxK; ++kk)
-                if (kk < nk) acc[kk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av * wk[kr][kk], bv, acc[kk], 0, 0, 0);
+                if (kk < nk)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[kk][r] += (double)c32[kk][r];
         }
         __syncthreads();
     }
@@ -238,7 +273,7 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
         if (kk < nk) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = a0 + mt * 16 + 4 * r + lk;
+                const int i = a0 + mt * 16 + (MIXED ? mfma_row_f32(r, lane) : mfma_row_f64(r, lane));
                 if (i < nA && jj < nB) out[((size_t)kk * nA + i) * nB + jj] = acc[kk][r];
             }
         }
@@ -686,7 +721,11 @@ hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipS
 }
 
 hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_2c_contract, dim3(8 * ((hm.n_tiles * n_jobs + 7) / 8)), dim3(256), 0, st, a);
+    const dim3 grid(8 * ((hm.n_tiles * n_jobs + 7) / 8)), block(256);
+    if (hm.mixed)
+        WPCCC_LAUNCH(ev, k_2c_contract<true>, grid, block, 0, st, a);
+    else
+        WPCCC_LAUNCH(ev, k_2c_contract<false>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 

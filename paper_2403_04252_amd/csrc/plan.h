@@ -93,6 +93,10 @@ struct StageArgs {
     double2* Xacc;        // accumulator   [n_traj][n_pad]
     double2* u_out;       // next input    [n_traj][n_pad]
     int* flag;            // non-finite latch
+    // graph replays: h = hdev[*chunk * kChunkSteps + hidx] instead of h
+    const double* hdev;
+    const int* chunk;
+    int hidx;
     // operator application (k_apply): y = O u with O = M(z_p) (deriv 0),
     // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2), then
     //   out = alpha y + beta w            (out may be NULL, w may be NULL)
@@ -147,6 +151,9 @@ struct PrologueArgs {
     double z[kChunkPoints];  // z of each point of the chunk
     int n;                   // points in this launch
     int traj0;
+    // graph replays: z = zdev[*chunk * kChunkPoints + p] instead of z[p]
+    const double* zdev;
+    const int* chunk;
 };
 
 // Device tables of one centre's basis (moment tables, column maps, angular
@@ -261,6 +268,8 @@ hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int 
 hipError_t launch_apply(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev = LaunchEv{});
 hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st);
+// *chunk = value (reset) or *chunk += 1 (advance), one thread
+hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st);
 // out[j] = sum_k c[k] v[k][j] over the first n states of every path (k < n_terms <= 5)
 hipError_t launch_combine(double2* out, const double2* const* v, const double* c, int n_terms, int n_traj,
                           int n, int n_pad, hipStream_t st);

@@ -54,6 +54,16 @@ struct wpccc_plan_s {
     int adj_K = 0, adj_nck = 0;
     double2 *d_lam = nullptr, *d_mu = nullptr, *d_nu = nullptr, *d_u2 = nullptr, *d_u3 = nullptr, *d_u4 = nullptr;
     double2 *d_ckpt = nullptr, *d_seg = nullptr;
+    // graph replay of 64-step chunks (wpccc_propagate)
+    bool use_graph = false, capturing = false;
+    hipStream_t gstream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double2* gX = nullptr;
+    int g_cap = 0;                      // chunks the z/h arrays hold
+    double *d_zall = nullptr, *d_hall = nullptr, *h_zh = nullptr;  // h_zh: pinned staging
+    int* d_chunk = nullptr;
+    hipEvent_t g_copied = nullptr;
     long long bytes = 0;
     int stage_smem = 0;       // k_apply (kRowsPerBlock rows)
     int stage_rows = kRowsPerBlock;
@@ -78,6 +88,14 @@ void free_plan(wpccc_plan_s* p) {
     if (!p) return;
     if (p->p2c) plan2c_destroy(p->p2c);
     centre_free(p->c);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->gstream) (void)hipStreamDestroy(p->gstream);
+    if (p->g_copied) (void)hipEventDestroy(p->g_copied);
+    if (p->h_zh) (void)hipHostFree(p->h_zh);
+    if (p->d_zall) (void)hipFree(p->d_zall);
+    if (p->d_hall) (void)hipFree(p->d_hall);
+    if (p->d_chunk) (void)hipFree(p->d_chunk);
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
                     p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
                     p->d_vc,   p->d_lam,  p->d_mu,   p->d_nu,    p->d_u2,   p->d_u3,   p->d_u4,
@@ -96,6 +114,8 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     for (int i = 0; i < n; ++i) a.z[i] = z[i];
     a.n = n;
     a.traj0 = j0;
+    a.zdev = p->capturing ? p->d_zall : nullptr;
+    a.chunk = p->capturing ? p->d_chunk : nullptr;
     hipError_t e = launch_prologue(a, nj, st, p->timer.open(kPrologue));
     return launched(e, "k_prologue");
 }
@@ -117,6 +137,9 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.Xacc = p->d_Xacc;
     a.u_out = u_out;
     a.flag = p->d_flag;
+    a.hdev = p->capturing ? p->d_hall : nullptr;
+    a.chunk = p->capturing ? p->d_chunk : nullptr;
+    a.hidx = point / 2;
     hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem_rows, st, p->timer.open(kStage), p->stage_rows);
     return launched(e, "k_stage");
 }
@@ -220,6 +243,95 @@ int enqueue_combine(wpccc_plan_s* p, double2* out, std::initializer_list<std::pa
         ++n;
     }
     return launched(launch_combine(out, v, c, n, p->n_traj, p->c.meta.n_states, p->n_pad, st), "k_combine");
+}
+
+// Capture one chunk of kChunkSteps steps for all paths on X into plan->gexec:
+// the prologue reads its points from d_zall and the stages their step length
+// from d_hall at the chunk index *d_chunk, which the last node advances.
+int capture_chunk_graph(wpccc_plan_s* p, double2* X) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    p->gX = nullptr;
+    if (!p->gstream) WPCCC_HIP_CHECK(hipStreamCreate(&p->gstream));
+    WPCCC_HIP_CHECK(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeRelaxed));
+    const bool timing = p->timer.on;
+    p->timer.on = false;
+    p->capturing = true;
+    double dummy[kChunkPoints] = {0.0};
+    int rc = enqueue_prologue(p, dummy, kChunkPoints, 0, p->n_traj, p->gstream);
+    for (int i = 0; i < kChunkSteps && rc == WPCCC_OK; ++i) rc = enqueue_step(p, X, 0, p->n_traj, 2 * i, 0.0, p->gstream);
+    if (rc == WPCCC_OK) rc = launched(launch_chunk_counter(p->d_chunk, 0, p->gstream), "k_chunk_counter");
+    p->capturing = false;
+    p->timer.on = timing;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return WPCCC_EHIP;
+    }
+    p->graph = g;
+    WPCCC_HIP_CHECK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+    p->gX = X;
+    return WPCCC_OK;
+}
+
+// Steps [0, n_full * kChunkSteps) of the grid by graph replays on st.
+int propagate_graph(wpccc_plan_s* p, const double* zg, int n_full, double2* X, hipStream_t st) {
+    if (n_full > p->g_cap) {
+        if (p->g_copied) WPCCC_HIP_CHECK(hipEventSynchronize(p->g_copied));
+        WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+        if (p->h_zh) (void)hipHostFree(p->h_zh);
+        if (p->d_zall) (void)hipFree(p->d_zall);
+        if (p->d_hall) (void)hipFree(p->d_hall);
+        p->h_zh = nullptr;
+        p->d_zall = p->d_hall = nullptr;
+        p->g_cap = 0;
+        // the graph reads the old arrays: capture again
+        if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        const size_t nz = (size_t)n_full * kChunkPoints, nh = (size_t)n_full * kChunkSteps;
+        WPCCC_HIP_CHECK(hipHostMalloc((void**)&p->h_zh, (nz + nh) * sizeof(double), 0));
+        int rc;
+        if ((rc = dev_alloc(&p->d_zall, nz, p->bytes)) || (rc = dev_alloc(&p->d_hall, nh, p->bytes))) return rc;
+        if (!p->d_chunk && (rc = dev_alloc(&p->d_chunk, 1, p->bytes))) return rc;
+        if (!p->g_copied) WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->g_copied, hipEventDisableTiming));
+        p->g_cap = n_full;
+    }
+    // the staging buffer may still feed the previous call's copy
+    WPCCC_HIP_CHECK(hipEventSynchronize(p->g_copied));
+    double* hz = p->h_zh;
+    double* hh = p->h_zh + (size_t)p->g_cap * kChunkPoints;
+    for (int c = 0; c < n_full; ++c)
+        for (int i = 0; i <= kChunkSteps; ++i) {
+            const int s = c * kChunkSteps + i;
+            hz[(size_t)c * kChunkPoints + 2 * i] = zg[s];
+            if (i < kChunkSteps) {
+                hz[(size_t)c * kChunkPoints + 2 * i + 1] = 0.5 * (zg[s] + zg[s + 1]);
+                hh[(size_t)c * kChunkSteps + i] = zg[s + 1] - zg[s];
+            }
+        }
+    WPCCC_HIP_CHECK(hipMemcpyAsync(p->d_zall, hz, (size_t)n_full * kChunkPoints * sizeof(double),
+                                   hipMemcpyHostToDevice, st));
+    WPCCC_HIP_CHECK(hipMemcpyAsync(p->d_hall, hh, (size_t)n_full * kChunkSteps * sizeof(double),
+                                   hipMemcpyHostToDevice, st));
+    WPCCC_HIP_CHECK(hipEventRecord(p->g_copied, st));
+    int rc;
+    if (!p->gexec || p->gX != X) {
+        // the capture stream must not run ahead of work already queued on st
+        WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+        if ((rc = capture_chunk_graph(p, X))) return rc;
+    }
+    if ((rc = launched(launch_chunk_counter(p->d_chunk, 1, st), "k_chunk_counter"))) return rc;
+    for (int c = 0; c < n_full; ++c) WPCCC_HIP_CHECK(hipGraphLaunch(p->gexec, st));
+    return WPCCC_OK;
 }
 
 // Rows per workgroup of k_stage: each candidate is timed on ten stage
@@ -383,6 +495,11 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: use wpccc_plan_create_2c for the two-centre form");
         return WPCCC_EINVAL;
     }
+    if (o.precision != WPCCC_FP64) {
+        set_error("wpccc_plan_create: the one-centre path has no reduced-precision form (its radial "
+                  "integrals come from exact moment tables, not from a per-R contraction)");
+        return WPCCC_ENOTSUP;
+    }
     for (int j = 0; j < n_traj; ++j)
         if (!(b_host[j] > 0.0) || !(v_host[j] > 0.0) || !std::isfinite(b_host[j]) || !std::isfinite(v_host[j])) {
             set_error("wpccc_plan_create: path %d needs finite b > 0 and v > 0", j);
@@ -410,6 +527,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->n_pad = (N + 7) & ~7;
     TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp));
     plan->ckpt_every = o.checkpoint_every;
+    plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
     if (o.stage_rows != 0 && o.stage_rows != 4 && o.stage_rows != 8 && o.stage_rows != 16) {
@@ -642,11 +760,17 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
         }
     double2* X = (double2*)X_dev;
     const int chunk = plan->batched ? plan->n_traj : 1;
+    int first = 0;  // first grid point of the kernel-by-kernel part
+    if (plan->use_graph && plan->batched && (n_points - 1) >= kChunkSteps) {
+        const int n_full = (n_points - 1) / kChunkSteps;
+        if ((rc = propagate_graph(plan, zgrid_host, n_full, X, st))) return rc;
+        first = n_full * kChunkSteps;
+    }
     for (int j0 = 0; j0 < plan->n_traj; j0 += chunk) {
         const int nj = std::min(chunk, plan->n_traj - j0);
         // chunks of at most kChunkSteps steps share one prologue launch:
         // point 2i is zgrid[c0+i], point 2i+1 the midpoint of step c0+i
-        for (int c0 = 0; c0 + 1 < n_points; c0 += kChunkSteps) {
+        for (int c0 = first; c0 + 1 < n_points; c0 += kChunkSteps) {
             const int ns = std::min(kChunkSteps, n_points - 1 - c0);
             double pts[kChunkPoints];
             for (int i = 0; i <= ns; ++i) {

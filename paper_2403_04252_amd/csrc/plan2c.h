@@ -21,6 +21,9 @@ constexpr int kNodeChunk = 32;    // spheroidal nodes per contraction chunk (8 M
 constexpr int kTile = 32;         // rows (target) and columns (projectile) per contraction workgroup
 constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
 constexpr int kSlots2C = 3;
+// lane layout of the FP32 16x16x4 MFMA result: 1 if register r of lane l holds
+// row 4 (l / 16) + r, 0 if it holds row 4 r + l / 16 (as the FP64 instruction)
+constexpr int kF32RowByLaneGroup = 1;
 
 // Per-node fields of one coupling position ([field][n_nodes], SoA):
 constexpr int kFCos = 0;          // cos((v z / 2) eta tau)
@@ -45,6 +48,7 @@ struct Meta2C {
     int f_pa, f_pb;          // first Legendre field of each side
     int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
     int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
+    int mixed;               // 1: contraction products in FP32 (chunk sums promoted to FP64)
     // contraction blocks: rows of block s are the radial functions a >= radT_off[s]
     int radT_off[kMaxL + 2], radP_off[kMaxL + 2];
     int nA[kMaxL + 1], nB[kMaxL + 1];

@@ -150,7 +150,7 @@ struct Group2C {
 struct Plan2C {
     std::vector<Group2C> groups;
     std::vector<int> group_of, local_of;
-    int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0;
+    int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0, mixed = 0;
     std::vector<double> b, v;
     double *d_b = nullptr, *d_v = nullptr;
     int* d_flag = nullptr;  // [0] non-finite amplitude, [1] singular path + 1, [2] its pivot row
@@ -193,7 +193,7 @@ int check_basis(const HostBasis& hb, const char* who) {
 }
 
 // Meta2C of one basis pair.
-void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, Meta2C& m,
+void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, int mixed, Meta2C& m,
                std::vector<int2>& tiles) {
     std::memset(&m, 0, sizeof m);
     m.LT = tb.spec.l_max;
@@ -218,6 +218,7 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     m.n_fields = m.f_pb + (m.LP + 1) * (m.LP + 2) / 2;
     m.n_w = q_prior ? 3 : 2;
     m.q_prior = q_prior;
+    m.mixed = mixed;
     for (int l = 0; l <= kMaxL + 1; ++l) {
         m.radT_off[l] = l <= m.LT ? tb.rad_off[l] : tb.n_f;
         m.radP_off[l] = l <= m.LP ? pb.rad_off[l] : pb.n_f;
@@ -271,7 +272,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     int rc;
     if ((rc = centre_build(*g.tb, st, g.cT))) return rc;
     if ((rc = centre_build(*g.pb, st, g.cP))) return rc;
-    fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, g.m, g.tiles);
+    fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, p->mixed, g.m, g.tiles);
     long long& tot = p->bytes;
     tot += g.cT.bytes + g.cP.bytes;
     const Meta2C& m = g.m;
@@ -514,6 +515,10 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
         set_error("wpccc_plan_create_2c: q_lower must be WPCCC_Q_DAGGER or WPCCC_Q_PRIOR");
         return WPCCC_EINVAL;
     }
+    if (o.precision != WPCCC_FP64 && o.precision != WPCCC_MIXED) {
+        set_error("wpccc_plan_create_2c: precision must be WPCCC_FP64 or WPCCC_MIXED");
+        return WPCCC_EINVAL;
+    }
     if (o.n_eta < 4 || o.n_eta > 1024 || o.n_tau < 4 || o.n_tau > 4096) {
         set_error("wpccc_plan_create_2c: n_eta must be in [4, 1024] and n_tau in [4, 4096]");
         return WPCCC_EINVAL;
@@ -558,6 +563,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     p->n_traj = n_traj;
     p->batched = o.batched ? 1 : 0;
     p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
+    p->mixed = o.precision == WPCCC_MIXED;
     p->n_eta = o.n_eta;
     p->n_tau = o.n_tau;
     p->b.assign(b, b + n_traj);

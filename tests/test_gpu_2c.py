@@ -203,3 +203,34 @@ def test_2c_propagation_multiblock(bases):
     S1, _ = two_centre_matrices(ot, op, b, float(zg[-1]), v, ne, nt, Q_PRIOR)
     no = (Xo.conj() @ S1 @ Xo).real
     assert abs(nrm.cpu().numpy()[0] - no) <= 1e-12 * abs(no)
+
+
+def test_2c_mixed_precision(small_run, bases):
+    """Mixed form (FP32 products summed in FP32 per 32-node chunk, FP64
+    across chunks): couplings within 1e-5 of max|S|, max|H| and probabilities
+    within 1e-6 absolute or 1e-4 relative of the FP64 oracle."""
+    wl, lt, lp, ref = small_run
+    print("2C mixed: couplings and 16-step propagation", flush=True)
+    (ltb, otb), (lpb, opb) = bases["wide"], bases["t1"]
+    plan = W.wpccc_plan_create_2c([ltb], [lpb], 0, [1.2], [1.0], q_lower=W.WPCCC_Q_PRIOR, n_eta=40, n_tau=48,
+                                  mixed=True)
+    Sg, Hg = gpu_matrices(plan, 0, -1.5)
+    So, Ho = two_centre_matrices(otb, opb, 1.2, -1.5, 1.0, 40, 48, q_lower=Q_PRIOR)
+    eS = np.abs(Sg - So).max() / np.abs(So).max()
+    eH = np.abs(Hg - Ho).max() / np.abs(Ho).max()
+    print(f"  mixed rel err S {eS:.2e} H {eH:.2e}", flush=True)
+    assert eS <= 1e-5 and eH <= 1e-5
+    assert eS > 0.0   # the FP32 path is in use
+    planm = W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, n_eta=wl.n_eta, n_tau=wl.n_tau,
+                                   q_lower=_q_lower(wl.q_lower), mixed=True)
+    X = torch.zeros((planm.n_traj, planm.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    P = torch.empty((planm.n_traj, planm.n_pad), dtype=torch.float64, device="cuda")
+    W.wpccc_propagate(planm, wl.zgrid, X, P)
+    torch.cuda.synchronize()
+    for j, (Xo, _) in enumerate(ref):
+        N = Xo.size
+        Po = np.abs(Xo) ** 2
+        d = np.abs(P.cpu().numpy()[j, :N] - Po)
+        assert np.all((d <= 1e-6) | (d <= 1e-4 * Po)), (j, d.max())
+        print(f"  path {j}: mixed max|dP| {d.max():.2e}", flush=True)
