@@ -33,6 +33,7 @@ import numpy as np  # noqa: E402
 METRIC = "RK4 steps/s over batched b (plain FP64 vs mixed) at stated prob. error"
 P_FLOOR = 1e-6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -124,6 +125,9 @@ def main():
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: batched one-centre N=580 (the headline); c3: batched two-centre")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
+    ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
+    ap.add_argument("--no-2c", action="store_true",
+                    help="c2: skip the short two-centre measurement added to the output line")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true",
@@ -279,6 +283,15 @@ def main():
         "plain_fp64_sequential": seq,
         "kernel_times": kernel_times,
     }
+    if not args.no_2c:
+        # secondary: a few batched two-centre steps, FP64 and mixed
+        del plan
+        torch.cuda.empty_cache()
+        out["two_centre"] = {}
+        for mixed in (False, True):
+            r = two_centre_measure(args, 3, 1, mixed=mixed)
+            out["two_centre"]["mixed" if mixed else "fp64"] = {
+                k: r[k] for k in ("value", "unit", "ms_per_step", "roofline", "lu", "config")}
     print(json.dumps(out), flush=True)
 
 
@@ -304,7 +317,13 @@ def contract_flops(recT, recP, n_w, n_act):
 
 
 def bench_two_centre(args):
-    """Batched two-centre propagation (Eq. 1 with capture) on one GPU."""
+    """Batched two-centre propagation (Eq. 1 with capture) on one GPU: prints its own JSON line."""
+    out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed)
+    print(json.dumps(out), flush=True)
+
+
+def two_centre_measure(args, steps, warmup, mixed=False):
+    """Time `steps` RK4 steps of the batched two-centre workload; returns the result dict."""
     import torch
     from scipy.special import roots_laguerre
     import paper_2403_04252_amd as W
@@ -317,23 +336,24 @@ def bench_two_centre(args):
              for r in w.targets]
     ql = W.WPCCC_Q_PRIOR if w.q_lower == "prior" else W.WPCCC_Q_DAGGER
     t0 = time.perf_counter()
-    plan = W.wpccc_plan_create_2c(bases, bases, w.set_of, w.b, w.v, q_lower=ql, n_eta=w.n_eta, n_tau=w.n_tau)
+    plan = W.wpccc_plan_create_2c(bases, bases, w.set_of, w.b, w.v, q_lower=ql, n_eta=w.n_eta, n_tau=w.n_tau,
+                                  mixed=mixed)
     setup_s = time.perf_counter() - t0
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0
-    run_propagation(W, plan, X, w.zgrid, args.warmup)
+    run_propagation(W, plan, X, w.zgrid, warmup)
     torch.cuda.synchronize()
     X.zero_()
     X[:, 0] = 1.0
-    zs = w.zgrid[: args.steps + 1]
+    zs = w.zgrid[: steps + 1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     W.wpccc_propagate(plan, zs, X)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     W.wpccc_plan_status(plan)
-    value = n_traj * args.steps / wall
+    value = n_traj * steps / wall
 
     # per-kernel device time over the same steps (events on the library's stream)
     X.zero_()
@@ -355,7 +375,7 @@ def bench_two_centre(args):
     n_w = 3 if w.q_lower == "prior" else 2
     xl = roots_laguerre(w.n_eta)[0]
     fl = 0
-    for i in range(args.steps):
+    for i in range(steps):
         pos = [zs[i], 0.5 * (zs[i] + zs[i + 1]), zs[i + 1]] if i == 0 else [0.5 * (zs[i] + zs[i + 1]), zs[i + 1]]
         for j in range(n_traj):
             rec = w.targets[w.set_of[j]]
@@ -366,23 +386,24 @@ def bench_two_centre(args):
                 fl += contract_flops(rec, rec, n_w, n_act)
     c_ms = kt["k_2c_contract"]["total_ms"]
     achieved = fl / (c_ms * 1e-3) / 1e12
+    peak = FP32_MFMA_PEAK_TFLOPS if mixed else FP64_VECTOR_PEAK_TFLOPS
     roof = {"kernel": "k_2c_contract", "bound": "mfma", "achieved": achieved,
-            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": None, "avg_launch_us": c_ms / max(kt["k_2c_contract"]["launches"], 1) * 1e3,
             "launches": kt["k_2c_contract"]["launches"], "algorithmic_flops_total": fl}
     lu_fl = 0
     for j in range(n_traj):
         N = 2 * sum((2 * l + 1) * n for l, n in enumerate(n_per_l(w.targets[w.set_of[j]])))
-        lu_fl += (args.steps * 2 + 1) * 8.0 / 3.0 * N ** 3
+        lu_fl += (steps * 2 + 1) * 8.0 / 3.0 * N ** 3
     lu_ms = sum(kt[k]["total_ms"] for k in ("k_lu_panel", "k_lu_swap_trsm", "k_lu_update"))
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -391,7 +412,8 @@ def bench_two_centre(args):
         "config": {"workload": w.name + ": same recipe on both centres (n<=6 + 20 bins/l, l<=1/2/3), "
                                "4000-pt grid, 8 b log-spaced 0.2-10 per size, 256x512 nodes, "
                                f"z -40..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
-                   "form": "batched FP64", "n_paths": n_traj, "plan_setup_s": setup_s,
+                   "form": "batched mixed (FP32 contraction products)" if mixed else "batched FP64",
+                   "n_paths": n_traj, "plan_setup_s": setup_s,
                    "parallelism": "1 GPU, paths batched per basis size"},
         "roofline": roof,
         "lu": {"algorithmic_flops": lu_fl, "device_ms": lu_ms,
@@ -399,7 +421,7 @@ def bench_two_centre(args):
         "kernel_times": kt,
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -120,7 +120,7 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     return launched(e, "k_prologue");
 }
 
-int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double h, const double2* u_in,
+int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, int step, double h, const double2* u_in,
                   double2* X, double2* u_out, hipStream_t st) {
     StageArgs a;
     a.meta = p->c.d_meta;
@@ -139,7 +139,7 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
     a.flag = p->d_flag;
     a.hdev = p->capturing ? p->d_hall : nullptr;
     a.chunk = p->capturing ? p->d_chunk : nullptr;
-    a.hidx = point / 2;
+    a.hidx = step;
     hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem_rows, st, p->timer.open(kStage), p->stage_rows);
     return launched(e, "k_stage");
 }
@@ -149,10 +149,12 @@ int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, double 
 // so that no stage reads what it writes.
 int enqueue_step(wpccc_plan_s* p, double2* X, int j0, int nj, int pz, double h, hipStream_t st) {
     int rc;
-    if ((rc = enqueue_stage(p, j0, nj, 1, pz, h, X, X, p->d_Ua, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, h, p->d_Ua, X, p->d_Ub, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, h, p->d_Ub, X, p->d_Ua, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 4, pz + 2, h, p->d_Ua, X, nullptr, st))) return rc;
+    // the step's index within its chunk (graph replays read h at this index)
+    const int step = pz / 2;
+    if ((rc = enqueue_stage(p, j0, nj, 1, pz, step, h, X, X, p->d_Ua, st))) return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, step, h, p->d_Ua, X, p->d_Ub, st))) return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, step, h, p->d_Ub, X, p->d_Ua, st))) return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 4, pz + 2, step, h, p->d_Ua, X, nullptr, st))) return rc;
     return WPCCC_OK;
 }
 
