@@ -121,8 +121,8 @@ def test_step_parity(small):
         assert np.abs(Xg[j] - Xo).max() <= 1e-13, (j, np.abs(Xg[j] - Xo).max())
 
 
-def _propagate_gpu(lb, b, v, zgrid, Zp=1.0, batched=True):
-    plan = W.wpccc_plan_create(lb, b, v, Zp=Zp, batched=batched)
+def _propagate_gpu(lb, b, v, zgrid, Zp=1.0, batched=True, stage_rows=0):
+    plan = W.wpccc_plan_create(lb, b, v, Zp=Zp, batched=batched, stage_rows=stage_rows)
     X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0
     P = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
@@ -165,8 +165,9 @@ def test_batched_equals_sequential(small):
     rec, lb, ob = small
     b = [0.2, 0.9, 2.5, 6.0]
     zg = WL.z_uniform(-10.0, 5.0, 0.1)
-    Xb, Pb, _ = _propagate_gpu(lb, b, 1.0, zg, batched=True)
-    Xs, Ps, _ = _propagate_gpu(lb, b, 1.0, zg, batched=False)
+    # the same stage tiling for both (the timed choice may differ between plans)
+    Xb, Pb, _ = _propagate_gpu(lb, b, 1.0, zg, batched=True, stage_rows=8)
+    Xs, Ps, _ = _propagate_gpu(lb, b, 1.0, zg, batched=False, stage_rows=8)
     assert np.array_equal(Xb, Xs)
 
 

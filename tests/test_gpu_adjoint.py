@@ -43,7 +43,8 @@ def small():
 
 
 def _gpu_grad(lb, b, v, a, c, zg, wts, K=0):
-    plan = W.wpccc_plan_create(lb, b, v, model_a=a, model_c=c, checkpoint_every=K)
+    # fixed stage tiling: gradients from different plans are compared bitwise
+    plan = W.wpccc_plan_create(lb, b, v, model_a=a, model_c=c, checkpoint_every=K, stage_rows=8)
     N = plan.n_states
     X0 = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X0[:, 0] = 1.0
