@@ -158,6 +158,12 @@ struct Plan2C {
     double *d_xlag = nullptr, *d_wlag = nullptr, *d_tleg = nullptr, *d_wleg = nullptr;
     long long bytes = 0;
     KernelTimer* timer = nullptr;
+    // one stream per group (groups are independent within a step): the
+    // latency-bound LU panels and solves of one group overlap the contraction
+    // of another; fork and join on the caller's stream every step
+    std::vector<hipStream_t> gstreams;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     double slot_z[kSlots2C];
     bool slot_ok[kSlots2C] = {false, false, false};
 };
@@ -478,7 +484,15 @@ int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
     }
     for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
     int rc;
-    for (Group2C& g : p->groups) {
+    const bool fork = !p->gstreams.empty();
+    if (fork) WPCCC_HIP_CHECK(hipEventRecord(p->fork_ev, st));
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        Group2C& g = p->groups[gi];
+        hipStream_t gs = st;
+        if (fork) {
+            gs = p->gstreams[gi];
+            WPCCC_HIP_CHECK(hipStreamWaitEvent(gs, p->fork_ev, 0));
+        }
         const int npath = (int)g.paths.size();
         const int chunk = p->batched ? npath : 1;
         for (int l0 = 0; l0 < npath; l0 += chunk) {
@@ -486,15 +500,19 @@ int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
             if (!have0) {
                 const int sl[1] = {s0};
                 const double zz[1] = {z};
-                if ((rc = enqueue_couplings(p, g, l0, np, 1, sl, zz, st))) return rc;
+                if ((rc = enqueue_couplings(p, g, l0, np, 1, sl, zz, gs))) return rc;
             }
             const int sl[2] = {sm, sn};
             const double zz[2] = {zm, zn};
-            if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, st))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 1, s0, h, X, X, p->d_Ua, st))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 2, sm, h, p->d_Ua, X, p->d_Ub, st))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 3, sm, h, p->d_Ub, X, p->d_Ua, st))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 4, sn, h, p->d_Ua, X, nullptr, st))) return rc;
+            if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 1, s0, h, X, X, p->d_Ua, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 2, sm, h, p->d_Ua, X, p->d_Ub, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 3, sm, h, p->d_Ub, X, p->d_Ua, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 4, sn, h, p->d_Ua, X, nullptr, gs))) return rc;
+        }
+        if (fork) {
+            WPCCC_HIP_CHECK(hipEventRecord(p->join_ev[gi], gs));
+            WPCCC_HIP_CHECK(hipStreamWaitEvent(st, p->join_ev[gi], 0));
         }
     }
     // every path keeps its own slots, so they hold these positions for all paths
@@ -614,6 +632,28 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     if ((rc = upload(p->d_tleg, tl.data(), tl.size() * sizeof(double), st))) return fail(rc);
     if ((rc = upload(p->d_wleg, wt.data(), wt.size() * sizeof(double), st))) return fail(rc);
     hipError_t e = hipMemsetAsync(p->d_flag, 0, 4 * sizeof(int), st);
+    if (e == hipSuccess && p->groups.size() > 1) {
+        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        for (size_t gi = 0; gi < p->groups.size() && e == hipSuccess; ++gi) {
+            hipStream_t gs = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreate(&gs);  // default priority
+            if (e == hipSuccess) {
+                p->gstreams.push_back(gs);
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) p->join_ev.push_back(ev);
+            }
+        }
+        if (e != hipSuccess || p->join_ev.size() != p->groups.size()) {
+            // fall back to the caller's stream only
+            for (hipStream_t gs : p->gstreams) (void)hipStreamDestroy(gs);
+            for (hipEvent_t ev : p->join_ev) (void)hipEventDestroy(ev);
+            p->gstreams.clear();
+            p->join_ev.clear();
+            (void)hipGetLastError();
+            e = hipSuccess;
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         set_error("wpccc_plan_create_2c: device setup failed: %s", hipGetErrorString(e));
@@ -625,6 +665,12 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
 
 void plan2c_destroy(Plan2C* p) {
     if (!p) return;
+    for (hipStream_t gs : p->gstreams) {
+        (void)hipStreamSynchronize(gs);
+        (void)hipStreamDestroy(gs);
+    }
+    for (hipEvent_t ev : p->join_ev) (void)hipEventDestroy(ev);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     for (Group2C& g : p->groups) free_group(g);
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Ua,   p->d_Ub,  p->d_Xacc,
                     p->d_Y,    p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg};
