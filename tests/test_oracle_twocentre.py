@@ -179,16 +179,47 @@ def test_overlap_block_structure(bound2):
     assert np.abs(H2[n:, :n] - H[n:, :n]).max() > 1e-6
 
 
-def test_two_centre_rk4_conserves_norm_approximately(bound2):
-    """With the prior form the 2C equations conserve X^dag S X for exact
-    eigenstates; on a bound-only basis the drift is small and falls with h."""
+def test_prior_form_conserves_norm_on_bound_basis(bound2):
+    """With the prior lower-left block and exact eigenstates (bound hydrogen
+    states on a fine grid) X^dag S X is constant along the path; RK4 leaves a
+    drift that falls by more than 10x when h halves and is below 1e-8 at h = 0.05."""
     b = bound2
     M = m_two_centre(b, b, 1.5, 1.0, 24, 32, q_lower=Q_PRIOR)
-    S0, _ = two_centre_matrices(b, b, 1.5, -6.0, 1.0, 24, 32, q_lower=Q_PRIOR)
-    zg = np.linspace(-6.0, 6.0, 61)
-    X0 = initial_state(2 * b.n_states)
-    X0 = X0 / np.sqrt((X0.conj() @ S0 @ X0).real)
-    X = rk4_propagate(M, X0, zg)
-    S1, _ = two_centre_matrices(b, b, 1.5, 6.0, 1.0, 24, 32, q_lower=Q_PRIOR)
-    nrm = (X.conj() @ S1 @ X).real
-    assert abs(nrm - 1.0) < 2e-2
+    drift = []
+    for h in (0.1, 0.05):
+        zg = np.linspace(-4.0, 4.0, int(round(8.0 / h)) + 1)
+        S0, _ = two_centre_matrices(b, b, 1.5, zg[0], 1.0, 24, 32, q_lower=Q_PRIOR)
+        X0 = initial_state(2 * b.n_states)
+        X0 = X0 / np.sqrt((X0.conj() @ S0 @ X0).real)
+        X = rk4_propagate(M, X0, zg)
+        S1, _ = two_centre_matrices(b, b, 1.5, zg[-1], 1.0, 24, 32, q_lower=Q_PRIOR)
+        drift.append(abs((X.conj() @ S1 @ X).real - 1.0))
+    assert drift[1] < 1e-8 and drift[0] > 10 * drift[1], drift
+
+
+def test_dagger_form_balance_law(bound2):
+    """With the printed Q^dagger block H stays Hermitian while S changes, so
+    d(X^dag S X)/dz = X^dag (dS/dz) X: the change of X^dag S X over the path
+    equals the integral of X^dag (dS/dz) X (dS/dz by central differences,
+    Simpson's rule on the grid), up to an error of high order in h, while the
+    change itself is of order 1e-3."""
+    b = bound2
+    n = b.n_states
+
+    def S_of(z):
+        K = lab_matrix(b, b, 1.5, z, 1.0, 24, 32, "overlap") * np.exp(
+            1j * np.subtract.outer(b.eps, b.eps) * z)
+        return np.block([[np.eye(n), K], [K.conj().T, np.eye(n)]])
+
+    M = m_two_centre(b, b, 1.5, 1.0, 24, 32, q_lower=Q_DAGGER)
+    gaps = []
+    for h in (0.2, 0.1):
+        zg = np.linspace(-3.0, 3.0, int(round(6.0 / h)) + 1)
+        X, hist = rk4_propagate(M, initial_state(2 * n), zg, keep=True)
+        change = (X.conj() @ S_of(zg[-1]) @ X).real - 1.0
+        d = 1e-4
+        f = np.array([(x.conj() @ ((S_of(z + d) - S_of(z - d)) / (2 * d)) @ x).real for z, x in zip(zg, hist)])
+        integral = h / 3 * (f[0] + f[-1] + 4 * f[1:-1:2].sum() + 2 * f[2:-1:2].sum())
+        gaps.append(abs(change - integral))
+        assert abs(change) > 1e-3
+    assert gaps[1] < 2e-7 and gaps[0] > 10 * gaps[1], gaps
