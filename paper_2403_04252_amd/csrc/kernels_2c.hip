@@ -19,6 +19,8 @@
 // The LU factorisation of S is in kernels_lu.hip.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "plan2c.h"
 
 namespace wpccc {
@@ -118,33 +120,99 @@ __global__ __launch_bounds__(256) void k_2c_nodes(NodeArgs a) {
         for (int mm = 0; mm <= l; ++mm) nd[(m.f_pb + l * (l + 1) / 2 + mm) * nn + p] = pbar(l, mm, cB);
 }
 
+// Interpolated operands of one position.  grid: x = blocks of 64 nodes,
+// y = blocks of 64 rows (side T, then side P), z = job.  Each wave takes 16
+// nodes; per node its 64 lanes are 64 rows, so the five stencil values of
+// consecutive radial functions are consecutive doubles of phiT (coalesced).
+// The Legendre factors are staged through LDS with lanes over nodes, and the
+// 64 x 64 result tile is written back row by row with lanes over nodes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
+    __shared__ double tile[64][65];
+    __shared__ double sL[64][5];
+    __shared__ int sj[64];
+    const Meta2C& m = *a.m;
+    const int y = blockIdx.z;
+    const int nact = a.n_act[y];
+    const int p0 = blockIdx.x * 64;
+    if (p0 >= nact) return;
+    const int nbT = (m.rowsT + 63) / 64;
+    const bool sideP = (int)blockIdx.y >= nbT;
+    const int r0 = (sideP ? blockIdx.y - nbT : blockIdx.y) * 64;
+    const int rows = sideP ? m.rowsP : m.rowsT;
+    const int nf = sideP ? m.nfP : m.nfT;
+    const double* phiT = sideP ? a.phiT_P : a.phiT_T;
+    const int2* rinfo = sideP ? a.rinfoP : a.rinfoT;
+    const size_t nn = m.n_nodes;
+    const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
+    const int* js = a.jst + (size_t)y * 2 * nn + (sideP ? nn : 0);
+    const int fL = sideP ? kFLB : kFLA;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // stencils of the 64 nodes
+    for (int e = tid; e < 64 * 5; e += blockDim.x) {
+        const int k = e % 64, q = e / 64, p = p0 + k;
+        sL[k][q] = (p < nact) ? nd[(size_t)(fL + q) * nn + p] : 0.0;
+    }
+    if (tid < 64) sj[tid] = (p0 + tid < nact) ? js[p0 + tid] : -1;
+    // Legendre factor of each (row, node)
+    for (int e = tid; e < 64 * 64; e += blockDim.x) {
+        const int k = e % 64, r = e / 64, p = p0 + k;
+        double v = 0.0;
+        if (r0 + r < rows && p < nact) v = nd[(size_t)rinfo[r0 + r].y * nn + p];
+        tile[r][k] = v;
+    }
+    __syncthreads();
+    const int r = lane;
+    const bool okr = r0 + r < rows;
+    const int arad = okr ? rinfo[r0 + r].x : 0;
+    for (int kk = 0; kk < 16; ++kk) {
+        const int k = wave * 16 + kk;
+        const int j = sj[k];
+        double v = 0.0;
+        if (okr && j >= 0) {
+            const double* f = phiT + (size_t)j * nf + arad;
+            v = (sL[k][0] * f[0] + sL[k][1] * f[nf] + sL[k][2] * f[2 * nf] + sL[k][3] * f[3 * nf] +
+                 sL[k][4] * f[4 * nf]) * tile[r][k];
+        }
+        tile[r][k] = v;
+    }
+    __syncthreads();
+    T* out = reinterpret_cast<T*>(sideP ? a.BT : a.AT) + (size_t)y * rows * nn;
+    for (int e = tid; e < 64 * 64; e += blockDim.x) {
+        const int k = e % 64, rr = e / 64, p = p0 + k;
+        if (r0 + rr < rows && p < nact) out[(size_t)(r0 + rr) * nn + p] = (T)tile[rr][k];
+    }
+}
+
 // One workgroup per (job, tile) with an XCD-aware order: consecutive
 // workgroup ids go to the eight XCDs in turn, and the work items of XCD x are
 // the x-th eighth of the job-major list, so the tiles of one job (which
-// stream the same node fields) share an L2.  Per chunk of kNodeChunk nodes:
-// stage the Lagrange weights, stencil starts, Legendre values and the nk
-// weights w_k of the chunk, then A (32 rows) and B (32 columns) in LDS; each
-// wave owns one 16 x 16 quarter of the tile for all nk weights and feeds the
-// MFMA with (A w_k) and B, so B is staged once for every weight.
+// stream the same operand rows) share an L2.  Per chunk of kNodeChunk nodes
+// the 32 rows of A, the 32 columns of B and the node fields of the weights
+// are loaded into registers one chunk ahead (their latency overlaps the
+// MFMA of the current chunk), then staged in LDS; each wave owns one 16 x 16
+// quarter of the tile for all nk weights and feeds the MFMA with (A w_k) and B.
 //
-// MIXED: the products run on v_mfma_f32_16x16x4f32 (operands rounded to FP32,
+// MIXED: the products run on v_mfma_f32_16x16x4f32 (operands in FP32,
 // accumulated in FP32 over the 32 nodes of a chunk) and each chunk's partial
 // sums are added to FP64 accumulators, so the FP32 accumulation error stays
 // that of a 32-term sum whatever the number of nodes.
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-// Output row of register r in lane l of a 16 x 16 MFMA tile (column l % 16):
-// measured on gfx950, 4 r + l / 16 for the FP64 instruction; FP32 per kF32Row.
+// Output row of register r in lane l of a 16 x 16 MFMA tile (column l % 16),
+// measured on gfx950: 4 r + l / 16 for the FP64 instruction, 4 (l / 16) + r
+// for the FP32 one.
 __device__ inline int mfma_row_f64(int r, int l) { return 4 * r + (l >> 4); }
 __device__ inline int mfma_row_f32(int r, int l) { return kF32RowByLaneGroup ? 4 * (l >> 4) + r : 4 * r + (l >> 4); }
 
+constexpr int kWFields = 7;  // cos, sin, W_0..W_2, J_|s-t|, J_(s+t)
+
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
-    __shared__ double As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
+    typedef typename std::conditional<MIXED, float, double>::type T;
+    __shared__ T As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
+    __shared__ double fl[kWFields][kNodeChunk];
     __shared__ double wk[kNodeChunk][kMaxK];
-    __shared__ double sLA[kNodeChunk][5], sLB[kNodeChunk][5];
-    __shared__ double sPA[kNodeChunk][kMaxL + 1], sPB[kNodeChunk][kMaxL + 1];
-    __shared__ int sjA[kNodeChunk], sjB[kNodeChunk];
     const Meta2C& m = *a.m;
     const int total = m.n_tiles * a.n_jobs;
     const int per = (total + 7) / 8;
@@ -159,79 +227,56 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
     const int nA = m.nA[s], nB = m.nB[t];
     const size_t nn = m.n_nodes;
     const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
-    const int* js = a.jst + (size_t)y * 2 * nn;
     const int nact = a.n_act[y];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // fixed row (column) of this thread in the A (B) staging
-    const int rr = tid % kTile, k_first = tid / kTile;
-    const int ia = a0 + rr, ib = b0 + rr;
-    const bool okA = ia < nA, okB = ib < nB;
-    const int arad = m.radT_off[s] + (okA ? ia : 0), brad = m.radP_off[t] + (okB ? ib : 0);
-    const int la = a.radl_T[arad], lb = a.radl_P[brad];
-    const double* fA = a.phiT_T + arad;
-    const double* fB = a.phiT_P + brad;
+    // loader roles: row (column) lr of A (B), four consecutive nodes from kq;
+    // threads below kWFields * kNodeChunk also load one node field
+    const int lr = tid >> 3, kq = (tid & 7) * 4;
+    const bool okA = a0 + lr < nA, okB = b0 + lr < nB;
+    const T* arow = reinterpret_cast<const T*>(a.AT) + ((size_t)y * m.rowsT + m.rowT_off[s] + a0 + (okA ? lr : 0)) * nn;
+    const T* brow = reinterpret_cast<const T*>(a.BT) + ((size_t)y * m.rowsP + m.rowP_off[t] + b0 + (okB ? lr : 0)) * nn;
+    const int ffi = tid / kNodeChunk, fk = tid % kNodeChunk;
+    int fid = 0;
+    if (ffi < kWFields) {
+        const int ids[kWFields] = {kFCos, kFSin, kFW, kFW + 1, kFW + 2, kFJ + o1, kFJ + o2};
+        fid = ids[ffi];
+    }
     const int mt = wave & 1, nt = wave >> 1;
     const int li = lane & 15, lk = lane >> 4;
+
+    T ra[4], rb[4];
+    double rf = 0.0;
+    auto fetch = [&](int base) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int p = base + kq + e;
+            ra[e] = (okA && p < nact) ? arow[p] : (T)0;
+            rb[e] = (okB && p < nact) ? brow[p] : (T)0;
+        }
+        if (ffi < kWFields) rf = (base + fk < nact) ? nd[(size_t)fid * nn + base + fk] : 0.0;
+    };
 
     dbl4 acc[kMaxK];
 #pragma unroll
     for (int i = 0; i < kMaxK; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+    if (nact > 0) fetch(0);
     for (int base = 0; base < nact; base += kNodeChunk) {
-        // per-node data of the chunk
-        for (int e = tid; e < kNodeChunk * 10; e += blockDim.x) {
-            const int k = e % kNodeChunk, q = e / kNodeChunk, p = base + k;
-            const double val = (p < nact) ? nd[(size_t)(kFLA + q) * nn + p] : 0.0;
-            if (q < 5) sLA[k][q] = val;
-            else sLB[k][q - 5] = val;
-        }
-        if (tid < 2 * kNodeChunk) {
-            const int k = tid % kNodeChunk, side = tid / kNodeChunk, p = base + k;
-            const int jv = (p < nact) ? js[side * nn + p] : -1;
-            if (side == 0) sjA[k] = jv;
-            else sjB[k] = jv;
-        }
-        for (int e = tid; e < kNodeChunk * (kMaxL + 1) * 2; e += blockDim.x) {
-            const int k = e % kNodeChunk, rest = e / kNodeChunk;
-            const int side = rest / (kMaxL + 1), l = rest - side * (kMaxL + 1), p = base + k;
-            if (side == 0) {
-                if (l >= s && l <= m.LT)
-                    sPA[k][l] = (p < nact) ? nd[(size_t)(m.f_pa + l * (l + 1) / 2 + s) * nn + p] : 0.0;
-            } else {
-                if (l >= t && l <= m.LP)
-                    sPB[k][l] = (p < nact) ? nd[(size_t)(m.f_pb + l * (l + 1) / 2 + t) * nn + p] : 0.0;
-            }
-        }
-        for (int e = tid; e < kNodeChunk * nk; e += blockDim.x) {
-            const int k = e % kNodeChunk, kk = e / kNodeChunk, p = base + k;
-            const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
-            double val = 0.0;
-            if (p < nact)
-                val = nd[(size_t)(kFJ + (order == 0 ? o1 : o2)) * nn + p] *
-                      nd[(size_t)(trig ? kFSin : kFCos) * nn + p] * nd[(size_t)(kFW + w) * nn + p];
-            wk[k][kk] = val;
-        }
-        __syncthreads();
-        // interpolated radial functions times Legendre values
 #pragma unroll
-        for (int q = 0; q < kNodeChunk / 8; ++q) {
-            const int k = k_first + 8 * q;
-            double va = 0.0, vb = 0.0;
-            const int ja = sjA[k], jb = sjB[k];
-            if (okA && ja >= 0) {
-                const double* f = fA + (size_t)ja * m.nfT;
-                va = (sLA[k][0] * f[0] + sLA[k][1] * f[m.nfT] + sLA[k][2] * f[2 * m.nfT] +
-                      sLA[k][3] * f[3 * m.nfT] + sLA[k][4] * f[4 * m.nfT]) * sPA[k][la];
-            }
-            if (okB && jb >= 0) {
-                const double* f = fB + (size_t)jb * m.nfP;
-                vb = (sLB[k][0] * f[0] + sLB[k][1] * f[m.nfP] + sLB[k][2] * f[2 * m.nfP] +
-                      sLB[k][3] * f[3 * m.nfP] + sLB[k][4] * f[4 * m.nfP]) * sPB[k][lb];
-            }
-            As[k][rr] = va;
-            Bs[k][rr] = vb;
+        for (int e = 0; e < 4; ++e) {
+            As[kq + e][lr] = ra[e];
+            Bs[kq + e][lr] = rb[e];
+        }
+        if (ffi < kWFields) fl[ffi][fk] = rf;
+        __syncthreads();
+        for (int e = tid; e < kNodeChunk * nk; e += blockDim.x) {
+            const int k = e % kNodeChunk, kk = e / kNodeChunk;
+            const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
+            wk[k][kk] = fl[5 + order][k] * fl[trig][k] * fl[2 + w][k];
         }
         __syncthreads();
+        // next chunk's operands in flight during this chunk's MFMA
+        if (base + kNodeChunk < nact) fetch(base + kNodeChunk);
         if (!MIXED) {
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
@@ -248,12 +293,11 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
                 const int kr = ks * 4 + lk;
-                const double av = As[kr][mt * 16 + li];
-                const float bv = (float)Bs[kr][nt * 16 + li];
+                const float av = (float)As[kr][mt * 16 + li], bv = (float)Bs[kr][nt * 16 + li];
 #pragma unroll
                 for (int kk = 0; kk < kMaxK; ++kk)
                     if (kk < nk)
-                        c32[kk] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)(av * wk[kr][kk]), bv, c32[kk], 0, 0, 0);
+                        c32[kk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av * (float)wk[kr][kk], bv, c32[kk], 0, 0, 0);
             }
             // chunk sums into the FP64 accumulators (register r keeps the FP32 layout)
 #pragma unroll
@@ -264,8 +308,6 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
         }
         __syncthreads();
     }
-    // D[row][col] of a 16x16 tile: lane l, register r -> row 4 r + l / 16, col l % 16
-    // (A[i][k] in lane i + 16 k and B[k][j] in lane j + 16 k, as loaded above)
     double* out = a.tmol + (size_t)y * m.n_tmol + m.st_off[s][t];
     const int jj = b0 + nt * 16 + li;
 #pragma unroll
@@ -717,6 +759,15 @@ __global__ void k_transpose_copy(const double2* __restrict__ src, double2* __res
 
 hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     WPCCC_LAUNCH(ev, k_2c_nodes, dim3((hm.n_nodes + 255) / 256, n_jobs), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    const dim3 grid((hm.n_nodes + 63) / 64, (hm.rowsT + 63) / 64 + (hm.rowsP + 63) / 64, n_jobs), block(256);
+    if (hm.mixed)
+        WPCCC_LAUNCH(ev, k_2c_interp<float>, grid, block, 0, st, a);
+    else
+        WPCCC_LAUNCH(ev, k_2c_interp<double>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 

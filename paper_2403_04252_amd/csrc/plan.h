@@ -199,7 +199,7 @@ struct LaunchEv {
 // (wpccc_plan_timing / wpccc_plan_kernel_time).
 enum KernelId {
     kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
-    k2cNodes, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
+    k2cNodes, k2cInterp, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
     kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];

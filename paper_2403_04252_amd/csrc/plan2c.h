@@ -57,6 +57,9 @@ struct Meta2C {
     int stT_off[kMaxL + 2], stP_off[kMaxL + 2];  // state offsets per l
     int n_lT[kMaxL + 1], n_lP[kMaxL + 1];
     int n_tiles;
+    // interpolated operands: row r of side T is (s, i) with s = block, i < nA[s]
+    int rowsT, rowsP;                  // sum_s nA[s], sum_t nB[t]
+    int rowT_off[kMaxL + 1], rowP_off[kMaxL + 1];
 };
 
 // weights of the (s, t) block: Bessel orders |s-t| and s+t (one if s t = 0),
@@ -86,16 +89,30 @@ struct NodeArgs {
     int* n_act;           // [job] nodes in the active eta prefix
 };
 
+// k_2c_interp: the contraction operands of one position, once per job:
+//   AT[job][rowT_off[s] + i][p] = f_a(r_A(p)) Pbar_{l_a}^s(cos theta_A(p)),  a = radT_off[s] + i
+//   BT[job][rowP_off[t] + i][p] = f_b(r_B(p)) Pbar_{l_b}^t(cos theta_B(p)),  b = radP_off[t] + i
+// for active nodes p < n_act (node-contiguous rows, FP64, or FP32 in the mixed form).
+struct InterpArgs {
+    const Meta2C* m;
+    const double* phiT_T;   // [nrT+1][nfT] target radial functions, transposed
+    const double* phiT_P;   // [nrP+1][nfP]
+    const int2* rinfoT;     // [rowsT] (radial index a, node field of Pbar_{l_a}^s)
+    const int2* rinfoP;     // [rowsP]
+    const double* nodes;
+    const int* jst;
+    const int* n_act;
+    void* AT;               // [job][rowsT][n_nodes] double or float
+    void* BT;               // [job][rowsP][n_nodes]
+};
+
 struct ContractArgs {
     const Meta2C* m;
     int n_jobs;
     const int2* tiles;      // [n_tiles] (s | t << 8, a0 | b0 << 16)
-    const double* phiT_T;   // [nrT+1][nfT] target radial functions, transposed
-    const double* phiT_P;   // [nrP+1][nfP]
-    const int* radl_T;      // [nfT] l of each radial function
-    const int* radl_P;
+    const void* AT;         // interpolated operands (InterpArgs)
+    const void* BT;
     const double* nodes;
-    const int* jst;
     const int* n_act;
     double* tmol;           // [job][n_tmol]
 };
@@ -177,6 +194,7 @@ struct Stage2CArgs {
 };
 
 hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});

@@ -143,6 +143,8 @@ struct Group2C {
     int* d_jst = nullptr;
     int* d_nact = nullptr;
     double* d_tmol = nullptr;
+    int2 *d_rinfoT = nullptr, *d_rinfoP = nullptr;
+    void *d_AT = nullptr, *d_BT = nullptr;  // interpolated operands [job][rows][n_nodes]
     double *d_FrowT = nullptr, *d_GT = nullptr, *d_FrowP = nullptr, *d_GP = nullptr;
     double2 *d_PHT = nullptr, *d_PHP = nullptr;
 };
@@ -181,7 +183,8 @@ void free_group(Group2C& g) {
     centre_free(g.cP);
     void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
                     g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_nodes,  g.d_jst,    g.d_nact,
-                    g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP};
+                    g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP,
+                    g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
 }
@@ -248,6 +251,13 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
         }
     m.n_tmol = off;
     m.n_tiles = (int)tiles.size();
+    m.rowsT = m.rowsP = 0;
+    for (int l = 0; l <= kMaxL; ++l) {
+        m.rowT_off[l] = m.rowsT;
+        m.rowP_off[l] = m.rowsP;
+        m.rowsT += m.nA[l];
+        m.rowsP += m.nB[l];
+    }
 }
 
 std::vector<double> transposed_phi(const HostBasis& hb) {
@@ -288,6 +298,19 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     const size_t J = (size_t)g.max_jobs;
     const std::vector<double> phT = transposed_phi(*g.tb), phP = transposed_phi(*g.pb);
     const std::vector<int> rlT = radial_l(*g.tb), rlP = radial_l(*g.pb);
+    // operand rows: (radial index, node field of its Legendre factor) per (s, i)
+    std::vector<int2> riT, riP;
+    for (int s = 0; s <= m.LT; ++s)
+        for (int i = 0; i < m.nA[s]; ++i) {
+            const int a = m.radT_off[s] + i, l = rlT[a];
+            riT.push_back(make_int2(a, m.f_pa + l * (l + 1) / 2 + s));
+        }
+    for (int t = 0; t <= m.LP; ++t)
+        for (int i = 0; i < m.nB[t]; ++i) {
+            const int b = m.radP_off[t] + i, l = rlP[b];
+            riP.push_back(make_int2(b, m.f_pb + l * (l + 1) / 2 + t));
+        }
+    const size_t esz = p->mixed ? sizeof(float) : sizeof(double);
     if ((rc = dev_alloc(&g.d_m, 1, tot))) return rc;
     if ((rc = dev_alloc(&g.d_paths, np, tot))) return rc;
     if ((rc = dev_alloc(&g.d_tiles, g.tiles.size(), tot))) return rc;
@@ -304,6 +327,10 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_jst, J * 2 * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nact, J, tot))) return rc;
     if ((rc = dev_alloc(&g.d_tmol, J * m.n_tmol, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_rinfoT, riT.size(), tot))) return rc;
+    if ((rc = dev_alloc(&g.d_rinfoP, riP.size(), tot))) return rc;
+    if ((rc = dev_alloc_bytes(&g.d_AT, J * m.rowsT * (size_t)m.n_nodes * esz, tot))) return rc;
+    if ((rc = dev_alloc_bytes(&g.d_BT, J * m.rowsP * (size_t)m.n_nodes * esz, tot))) return rc;
     if ((rc = dev_alloc(&g.d_FrowT, J * g.cT.meta.n_frow, tot))) return rc;
     if ((rc = dev_alloc(&g.d_GT, J * g.cT.meta.n_g, tot))) return rc;
     if ((rc = dev_alloc(&g.d_PHT, J * m.NT, tot))) return rc;
@@ -317,6 +344,8 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = upload(g.d_phiT_P, phP.data(), phP.size() * sizeof(double), st))) return rc;
     if ((rc = upload(g.d_radl_T, rlT.data(), rlT.size() * sizeof(int), st))) return rc;
     if ((rc = upload(g.d_radl_P, rlP.data(), rlP.size() * sizeof(int), st))) return rc;
+    if ((rc = upload(g.d_rinfoT, riT.data(), riT.size() * sizeof(int2), st))) return rc;
+    if ((rc = upload(g.d_rinfoP, riP.data(), riP.size() * sizeof(int2), st))) return rc;
     // the host vectors above are released on return: wait for the copies
     WPCCC_HIP_CHECK(hipStreamSynchronize(st));
     return WPCCC_OK;
@@ -386,16 +415,26 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         if ((rc = timed(p, k2cNodes, [&](const LaunchEv& ev) { return launch_2c_nodes(a, g.m, nj, st, ev); }))) return rc;
     }
     {
+        InterpArgs ia;
+        ia.m = g.d_m;
+        ia.phiT_T = g.d_phiT_T;
+        ia.phiT_P = g.d_phiT_P;
+        ia.rinfoT = g.d_rinfoT;
+        ia.rinfoP = g.d_rinfoP;
+        ia.nodes = g.d_nodes;
+        ia.jst = g.d_jst;
+        ia.n_act = g.d_nact;
+        ia.AT = g.d_AT;
+        ia.BT = g.d_BT;
+        if ((rc = timed(p, k2cInterp, [&](const LaunchEv& ev) { return launch_2c_interp(ia, g.m, nj, st, ev); })))
+            return rc;
         ContractArgs a;
         a.m = g.d_m;
         a.n_jobs = nj;
         a.tiles = g.d_tiles;
-        a.phiT_T = g.d_phiT_T;
-        a.phiT_P = g.d_phiT_P;
-        a.radl_T = g.d_radl_T;
-        a.radl_P = g.d_radl_P;
+        a.AT = g.d_AT;
+        a.BT = g.d_BT;
         a.nodes = g.d_nodes;
-        a.jst = g.d_jst;
         a.n_act = g.d_nact;
         a.tmol = g.d_tmol;
         if ((rc = timed(p, k2cContract, [&](const LaunchEv& ev) { return launch_2c_contract(a, g.m, nj, st, ev); }))) return rc;
