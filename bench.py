@@ -70,9 +70,10 @@ def n_frow_entries(n_l, l_max):
     return sum(n_l[lp] * n_l[l] * (min(l, lp) + 1) for lp in range(l_max + 1) for l in range(l_max + 1))
 
 
-def profiled_traffic(summary, source):
-    """HBM bytes per launch recorded in profiles/<summary> by the FETCH_SIZE and
-    WRITE_SIZE counter runs, or None when the kernel source has changed since."""
+def profiled_traffic(summary, source, field="traffic_bytes_per_launch"):
+    """HBM bytes (per launch, or the given field) recorded in profiles/<summary>
+    by the FETCH_SIZE and WRITE_SIZE counter runs, or None when the kernel
+    source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_2403_04252_amd", "csrc", source)
@@ -87,9 +88,9 @@ def profiled_traffic(summary, source):
             k, _, v = line.strip().partition(":")
             fields[k.strip()] = v.strip()
     key = source.replace(".hip", "").replace("kernels_", "kernels_") + "_sha256"
-    if fields.get(key) != digest or "traffic_bytes_per_launch" not in fields:
+    if fields.get(key) != digest or field not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[field])
 
 
 def copy_calibration(torch, mib):
@@ -184,29 +185,47 @@ def main():
     # the same K steps again with per-kernel HIP events on the library's stream
     X.zero_()
     X[:, 0] = 1.0
+    persistent = W.wpccc_plan_stage_launch(plan) == W.WPCCC_LAUNCH_PERSISTENT
     W.wpccc_plan_timing(plan, True)
     run_propagation(W, plan, X, w.zgrid, args.steps)
     st_ms, st_n = W.wpccc_plan_kernel_time(plan, "k_stage")
+    ch_ms, ch_n = W.wpccc_plan_kernel_time(plan, "k_chunk")
     su_ms, su_n = W.wpccc_plan_kernel_time(plan, "k_prologue")
     W.wpccc_plan_timing(plan, False)
     torch.cuda.synchronize()
 
     stage_flops = stage_work(n_l, rec.l_max) * n_traj
-    stage_avg_s = st_ms / max(st_n, 1) * 1e-3
-    # algorithmic bytes of one k_stage launch: every path reads its rows of the
-    # moment table (one (A_k, B_k+1) pair of 16 B per radial-integral entry) and
-    # five amplitude vectors (u_in, X, Xacc in and out, u_out)
+    # algorithmic bytes of one stage pass over the batch: every path reads its
+    # rows of the moment table (one (A_k, B_k+1) pair of 16 B per
+    # radial-integral entry) and five amplitude vectors (u_in, X, Xacc in and
+    # out, u_out)
     n_entries = n_frow_entries(n_l, rec.l_max)
     stage_bytes = n_traj * (n_entries * 16 + 5 * n_states * 16)
-    achieved = stage_bytes / stage_avg_s / 1e9
-    roof = {"kernel": "k_stage", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+    passes = 4 * args.steps   # stage passes in the timed run
+    if persistent:
+        # k_chunk runs the four stages of up to 64 steps per launch
+        kname, k_ms, k_n = "k_chunk", ch_ms, ch_n
+    else:
+        kname, k_ms, k_n = "k_stage", st_ms, st_n
+    launch_s = k_ms / max(k_n, 1) * 1e-3
+    bytes_per_launch = stage_bytes * passes / max(k_n, 1)
+    achieved = bytes_per_launch / launch_s / 1e9
+    stage_pass_s = k_ms * 1e-3 / passes
+    roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic("k_stage_1c_N580x32.md", "kernels_1c.hip"),
-            "avg_launch_us": stage_avg_s * 1e6, "launches": st_n,
-            "algorithmic_bytes_per_launch": stage_bytes,
-            "flops_per_launch": stage_flops,
-            "fp64_alu_frac": stage_flops / stage_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+            "traffic": None if persistent else profiled_traffic("k_stage_1c_N580x32.md", "kernels_1c.hip"),
+            "avg_launch_us": launch_s * 1e6, "launches": k_n,
+            "stage_passes_per_launch": passes / max(k_n, 1),
+            "algorithmic_bytes_per_stage_pass": stage_bytes,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "flops_per_stage_pass": stage_flops,
+            "fp64_alu_frac": stage_flops / stage_pass_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "stage_rows": W.wpccc_plan_stage_rows(plan)}
+    if persistent:
+        t = profiled_traffic("k_chunk_1c_N580x32.md", "kernels_1c.hip", "traffic_bytes_per_stage_pass")
+        roof["traffic"] = None if t is None else t * passes / max(k_n, 1)
     kernel_times = {"k_stage": {"total_ms": st_ms, "launches": st_n},
+                    "k_chunk": {"total_ms": ch_ms, "launches": ch_n},
                     "k_prologue": {"total_ms": su_ms, "launches": su_n}}
 
     # plain FP64 form: the same paths one after another
@@ -275,7 +294,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "p+H single-centre N=580 (n<=6 + 20 bins/l, l<=4), 4000-pt grid, "
                                "32 b log-spaced 0.05-20, v=1, z -40..40 dz=0.1",
-                   "form": "batched FP64", "n_paths": n_traj, "n_states": n_states,
+                   "form": "batched FP64", "n_paths": n_traj,
+                   "stage_launch": "persistent" if persistent else "per stage", "n_states": n_states,
                    "n_radial": n_radial, "n_r": n_r, "parallelism": "1 GPU, paths batched"},
         "roofline": roof,
         "cpu_baseline": cpu,

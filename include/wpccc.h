@@ -132,8 +132,9 @@ typedef struct {
     double model_a; /* 1C: screened target potential V(r) = -(1 + a e^{-c r})/r on the */
     double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
     int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
-    int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 8 or 16;
-                       0: chosen at plan creation by timing each on the plan's paths */
+    int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 8,
+                       10, 12 or 16; 0: chosen at plan creation by timing each on
+                       the plan's paths */
     int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED: 2C overlap/transfer
                        contractions with FP32 products summed in FP32 over each
                        32-node chunk and in FP64 across chunks; LU, solves and
@@ -141,7 +142,21 @@ typedef struct {
     int graph;      /* 1C, batched: replay each 64-step chunk of wpccc_propagate
                        from a captured HIP graph (step lengths and positions
                        read from device memory); 0: launch kernel by kernel */
+    int stage_launch; /* 1C: how wpccc_propagate runs the RK4 stages of each
+                       64-step chunk outside graph replays:
+                       WPCCC_LAUNCH_AUTO (default): the faster of the two
+                       forms below, timed at plan creation;
+                       WPCCC_LAUNCH_STAGES: one launch per stage;
+                       WPCCC_LAUNCH_PERSISTENT: one cooperative launch per
+                       chunk whose workgroups stay resident and meet at a
+                       per-path barrier between stages (WPCCC_ENOTSUP at plan
+                       creation when its grid cannot be resident at once).
+                       Both forms give bitwise the same amplitudes. */
 } wpccc_plan_opts;
+
+#define WPCCC_LAUNCH_AUTO       0
+#define WPCCC_LAUNCH_STAGES     1
+#define WPCCC_LAUNCH_PERSISTENT 2
 
 #define WPCCC_FP64  0
 #define WPCCC_MIXED 1
@@ -186,9 +201,15 @@ int wpccc_plan_destroy(wpccc_plan_t plan);
  * given, or as chosen by timing at plan creation). */
 int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows);
 
+/* Launch form a one-centre plan's wpccc_propagate uses for its RK4 stages
+ * (WPCCC_LAUNCH_STAGES or WPCCC_LAUNCH_PERSISTENT, as requested or as chosen
+ * by timing at plan creation); WPCCC_LAUNCH_STAGES for a two-centre plan. */
+int wpccc_plan_stage_launch(wpccc_plan_t plan, int* launch);
+
 /* Returns the first device-side error latched since the last call (after
- * synchronising `stream`), then clears it: WPCCC_OK, WPCCC_ENUMERIC or (2C)
- * WPCCC_ESINGULAR with the path and pivot row in the message. */
+ * synchronising `stream`), then clears it: WPCCC_OK, WPCCC_ENUMERIC, (2C)
+ * WPCCC_ESINGULAR with the path and pivot row in the message, or WPCCC_EHIP
+ * when a barrier of the persistent stage kernel gave up waiting. */
 int wpccc_plan_status(wpccc_plan_t plan, void* stream);
 
 /* Couplings of path j at one z, with the interaction-picture phases

@@ -20,6 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
+    "wpccc_plan_stage_launch", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,6 +32,9 @@ WPCCC_Q_DAGGER = 0
 WPCCC_Q_PRIOR = 1
 WPCCC_FP64 = 0
 WPCCC_MIXED = 1
+WPCCC_LAUNCH_AUTO = 0
+WPCCC_LAUNCH_STAGES = 1
+WPCCC_LAUNCH_PERSISTENT = 2
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
 
 
@@ -51,7 +55,7 @@ class _PlanOpts(ctypes.Structure):
                 ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int),
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
                 ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
-                ("precision", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int)]
 
 
 @dataclass
@@ -100,6 +104,7 @@ def load_library():
         "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
         "wpccc_adjoint": ([vp, pd, i, vp, vp, vp, vp, vp], i),
         "wpccc_plan_stage_rows": ([vp, pi], i),
+        "wpccc_plan_stage_launch": ([vp, pi], i),
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
     }
@@ -206,15 +211,16 @@ def wpccc_basis_destroy(basis: Basis):
 def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
                       two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
                       checkpoint_every: int = 0, stage_rows: int = 0, graph: bool = False,
-                      stream=None) -> Plan:
+                      stage_launch: int = WPCCC_LAUNCH_AUTO, stream=None) -> Plan:
     """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
-    model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis."""
+    model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis;
+    stage_launch: WPCCC_LAUNCH_AUTO / _STAGES / _PERSISTENT."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
     opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
                      float(model_a), float(model_c), int(checkpoint_every), int(stage_rows), 0,
-                     1 if graph else 0)
+                     1 if graph else 0, int(stage_launch))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -233,6 +239,13 @@ def wpccc_plan_stage_rows(plan: Plan) -> int:
     return r.value
 
 
+def wpccc_plan_stage_launch(plan: Plan) -> int:
+    """WPCCC_LAUNCH_STAGES or WPCCC_LAUNCH_PERSISTENT: how the plan runs its RK4 stages."""
+    r = ctypes.c_int()
+    _check(load_library().wpccc_plan_stage_launch(plan.handle, ctypes.byref(r)))
+    return r.value
+
+
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
                          n_eta: int = 0, n_tau: int = 0, batched: bool = True, mixed: bool = False,
                          stream=None) -> Plan:
@@ -247,7 +260,7 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
     opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
-                     WPCCC_MIXED if mixed else WPCCC_FP64, 0)
+                     WPCCC_MIXED if mixed else WPCCC_FP64, 0, 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

@@ -185,8 +185,11 @@ __device__ inline void rk4_update(const StageArgs& a, size_t oi, double2 K, doub
 //   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
+// fresh = false reuses the point's F_l', G_l', phases and column info that an
+// earlier call of this workgroup left in LDS for the same point (k_chunk: a
+// point shared by consecutive stages), so only the stage input is loaded.
 template <int KIND, int ROWS>
-__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
+__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem, bool fresh = true) {
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
@@ -211,7 +214,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     const int k = a.pt.kidx[jp];
     const double2* row = T.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
     const int* cl = T.col_lam + m.col_off[lp];
-    const int totF = nrows * nV;
+    const int totF = fresh ? nrows * nV : 0;
     double2 tv[kFBatch];
     int lv[kFBatch];
 #pragma unroll
@@ -235,7 +238,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
     const double* gc = T.gcoef + m.g_off[lp];
     const int* gp = T.gpb + m.g_off[lp];
-    const int totG = nmp * gcols;
+    const int totG = fresh ? nmp * gcols : 0;
     double gcv[kGBatch];
     int gpv[kGBatch];
 #pragma unroll
@@ -268,11 +271,11 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             if (a.dv) xa = a.dv[oi];
         }
     }
-    for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
     const int deriv = (KIND == 1) ? a.deriv : 0;
     const double bj = T.bvec[j];
     const double Rz = sqrt(bj * bj + a.z * a.z);
-    if (deriv == 1) {
+    if (!fresh) {
+    } else if (deriv == 1) {
         // d/dR of R^-(lam+1) and R^lam
         if (tid <= m.lam_max) {
             double Rl = 1.0;
@@ -283,12 +286,15 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     } else if (tid < 2 * (m.lam_max + 1)) {
         rps[tid] = a.pt.rpow[jp * kRpow + tid];
     }
-    if (deriv == 2) {
-        if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
-    } else {
-        for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
+    if (fresh) {
+        for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
+        if (deriv == 2) {
+            if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
+        } else {
+            for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
+        }
+        for (int i = tid; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
     }
-    for (int i = tid; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
     __syncthreads();
 
     // phase 1
@@ -401,6 +407,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         }
     }
     if (KIND == 1 && a.grad) {
+        // this workgroup's share, summed in a fixed order by k_model_dot
         __shared__ double red[kStageThreads / 64];
         for (int off = 32; off > 0; off >>= 1) gval += __shfl_xor(gval, off, 64);
         if ((tid & 63) == 0) red[tid >> 6] = gval;
@@ -408,7 +415,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         if (tid == 0) {
             double sum = 0.0;
             for (int w = 0; w < B / 64; ++w) sum += red[w];
-            atomicAdd(a.grad + (size_t)j * 3 + a.gslot, sum);
+            a.grad[((size_t)j * 2 + a.gslot) * gridDim.x + blockIdx.x] = sum;
         }
     }
 }
@@ -426,7 +433,10 @@ __device__ void stage_entry(const StageArgs& a, char* smem) {
     }
     const int row0 = c * ROWS;
     const int nrows = min(ROWS, m.n_l[lp] - row0);
-    if (nrows <= 0) return;
+    if (nrows <= 0) {
+        if (KIND == 1 && a.grad && threadIdx.x == 0) a.grad[((size_t)j * 2 + a.gslot) * gridDim.x + blockIdx.x] = 0.0;
+        return;
+    }
     stage_body<KIND, ROWS>(a, j, lp, row0, nrows, smem);
 }
 
@@ -436,6 +446,89 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
     stage_entry<0, ROWS>(a, reinterpret_cast<char*>(smem2));
 }
 
+constexpr int kBarrierSpin = 1 << 22;  // polls (0.2 s or more) before a barrier gives up
+
+// Barrier of the workgroups of one path.  Every wave waits until its own
+// stores have reached the L2; thread 0 then arrives with an agent-scope
+// release (which writes back the L2 for the other XCDs), polls the counter
+// with relaxed loads until `target` workgroups have arrived and acquires at
+// agent scope once; the workgroup barrier orders the other waves' reads after
+// that acquire.  A wait longer than kBarrierSpin polls latches bit 2 of *flag
+// and returns false, so every workgroup still ends.
+__device__ bool path_barrier(int* cnt, int target, int* flag) {
+    __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int it = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++it > kBarrierSpin) {
+                atomicOr(flag, 2);
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__device__ inline int chunks_of(const Meta& m, int rows) {
+    int n = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) n += (m.n_l[lp] + rows - 1) / rows;
+    return n;
+}
+
+// All steps of a chunk for every path (see ChunkArgs).  grid: 8 x ceil(items
+// / 8) workgroups, items = paths x row chunks; consecutive workgroup ids go to
+// the eight XCDs in turn and the items of XCD x are the x-th eighth of the
+// path-major list, so the workgroups of a path share an XCD (and its L2).
+// Each workgroup keeps the couplings of its rows at the current point in LDS
+// and builds them only when the point changes: twice per step (midpoint and
+// end point) instead of four times.
+template <int ROWS>
+__global__ __launch_bounds__(kStageThreads) void k_chunk(ChunkArgs c) {
+    extern __shared__ double2 smem2[];
+    const Meta& m = *c.s.meta;
+    const int nwg = chunks_of(m, ROWS);
+    const int total = c.n_traj * nwg;
+    const int per = (total + 7) / 8;
+    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (W >= total) return;
+    const int jl = W / nwg;
+    const int j = c.s.traj0 + jl;
+    int ci = W - jl * nwg, lp = 0;
+    for (; lp < m.l_max; ++lp) {
+        const int nc = (m.n_l[lp] + ROWS - 1) / ROWS;
+        if (ci < nc) break;
+        ci -= nc;
+    }
+    const int row0 = ci * ROWS;
+    const int nrows = min(ROWS, m.n_l[lp] - row0);
+    StageArgs a = c.s;
+    int target = 0;
+    for (int i = 0; i < c.n_steps; ++i) {
+        a.h = c.h[i];
+        for (int stage = 1; stage <= 4; ++stage) {
+            a.stage = stage;
+            a.p = stage == 1 ? 2 * i : (stage == 4 ? 2 * i + 2 : 2 * i + 1);
+            a.u_in = stage == 1 ? c.s.X : (stage == 3 ? c.Ub : c.Ua);
+            a.u_out = stage == 1 ? c.Ua : (stage == 2 ? c.Ub : (stage == 3 ? c.Ua : nullptr));
+            // stage 3 repeats stage 2's point (the midpoint) and stage 1 of
+            // step i > 0 repeats stage 4's point of step i - 1
+            const bool fresh = stage == 2 || stage == 4 || i == 0;
+            if (nrows > 0) stage_body<0, ROWS>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2), fresh);
+            if (i + 1 == c.n_steps && stage == 4) break;
+            target += nwg;
+            if (!path_barrier(c.bar + (size_t)jl * kBarStride, target, c.s.flag)) return;
+        }
+    }
+}
+
 // Operator application with the grid of k_stage (see StageArgs).
 __global__ __launch_bounds__(kStageThreads) void k_apply(StageArgs a) {
     extern __shared__ double2 smem2[];
@@ -443,7 +536,8 @@ __global__ __launch_bounds__(kStageThreads) void k_apply(StageArgs a) {
 }
 
 // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] += 2 gamma Re(dv^H dM/dc u),
-// dM/dtheta = -(i/v) ph (dDeltaV/dtheta) conj(ph); one workgroup per path.
+// dM/dtheta = -(i/v) ph (dDeltaV/dtheta) conj(ph); grad[j][2] += the shares
+// gpart[j][0..2 n_part) of the b term; one workgroup per path.
 __global__ __launch_bounds__(256) void k_model_dot(ModelArgs a) {
     const Meta& m = *a.meta;
     const int j = a.traj0 + blockIdx.x;
@@ -495,6 +589,13 @@ __global__ __launch_bounds__(256) void k_model_dot(ModelArgs a) {
         }
         atomicAdd(a.grad + (size_t)j * 3 + 0, 2.0 * a.gamma * ta);
         atomicAdd(a.grad + (size_t)j * 3 + 1, 2.0 * a.gamma * tc);
+        if (a.gpart) {
+            // the b term: k_apply's per-workgroup shares in a fixed order
+            const double* gp = a.gpart + (size_t)j * 2 * a.n_part;
+            double tb = 0.0;
+            for (int i = 0; i < 2 * a.n_part; ++i) tb += gp[i];
+            atomicAdd(a.grad + (size_t)j * 3 + 2, tb);
+        }
     }
 }
 
@@ -641,11 +742,45 @@ int stage_smem_bytes(const Meta& m, int rows) {
 }
 
 hipError_t stage_set_smem_limit(int, int bytes) {
-    const void* fns[] = {(const void*)k_stage<4>, (const void*)k_stage<8>, (const void*)k_stage<16>,
-                         (const void*)k_apply};
+    const void* fns[] = {(const void*)k_stage<4>,  (const void*)k_stage<8>,  (const void*)k_stage<10>,
+                         (const void*)k_stage<12>, (const void*)k_stage<16>, (const void*)k_apply,
+                         (const void*)k_chunk<4>,  (const void*)k_chunk<8>,  (const void*)k_chunk<10>,
+                         (const void*)k_chunk<12>, (const void*)k_chunk<16>};
     hipError_t e = hipSuccess;
     for (const void* f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+int chunk_grid(const Meta& hm, int n_traj, int rows) { return 8 * ((n_traj * stage_chunks(hm, rows) + 7) / 8); }
+
+static const void* chunk_fn(int rows) {
+    switch (rows) {
+        case 4: return (const void*)k_chunk<4>;
+        case 10: return (const void*)k_chunk<10>;
+        case 12: return (const void*)k_chunk<12>;
+        case 16: return (const void*)k_chunk<16>;
+        default: return (const void*)k_chunk<8>;
+    }
+}
+
+bool chunk_fits(const Meta& hm, int n_traj, int rows, int smem) {
+    int dev = 0, n_cu = 0, per_cu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chunk_fn(rows), kStageThreads, smem) != hipSuccess)
+        return false;
+    return (long long)per_cu * n_cu >= chunk_grid(hm, n_traj, rows);
+}
+
+hipError_t launch_chunk(const ChunkArgs& a, const Meta& hm, int smem, int rows, hipStream_t st, const LaunchEv& ev) {
+    const dim3 grid(chunk_grid(hm, a.n_traj, rows)), block(kStageThreads);
+    ChunkArgs arg = a;
+    void* params[] = {&arg};
+    if (ev.a) (void)hipEventRecord(ev.a, st);
+    const hipError_t e = hipLaunchCooperativeKernel(chunk_fn(rows), grid, block, params, smem, st);
+    if (ev.b) (void)hipEventRecord(ev.b, st);
     return e;
 }
 
@@ -707,6 +842,8 @@ hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, i
     const dim3 grid(stage_chunks(hm, rows), n_traj_launch), block(kStageThreads);
     switch (rows) {
         case 4: WPCCC_LAUNCH(ev, k_stage<4>, grid, block, smem, st, a); break;
+        case 10: WPCCC_LAUNCH(ev, k_stage<10>, grid, block, smem, st, a); break;
+        case 12: WPCCC_LAUNCH(ev, k_stage<12>, grid, block, smem, st, a); break;
         case 16: WPCCC_LAUNCH(ev, k_stage<16>, grid, block, smem, st, a); break;
         default: WPCCC_LAUNCH(ev, k_stage<8>, grid, block, smem, st, a); break;
     }

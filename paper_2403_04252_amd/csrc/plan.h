@@ -16,6 +16,8 @@ constexpr int kMaxPb = (kMaxLam + 1) * (kMaxLam + 2) / 2;
 constexpr int kSlots = 3;            // couplings kept for the diagnostic entry point
 constexpr int kStageThreads = 256;
 constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and k_stage's default)
+constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
+constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
 
 // Per-basis sizes passed to kernels by value.
 //
@@ -100,15 +102,34 @@ struct StageArgs {
     // operator application (k_apply): y = O u with O = M(z_p) (deriv 0),
     // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2), then
     //   out = alpha y + beta w            (out may be NULL, w may be NULL)
-    //   grad[j][gslot] += 2 gamma Re(dv^H y)   (grad may be NULL)
+    //   grad[(j * 2 + gslot) * gridDim.x + blockIdx.x] = this workgroup's
+    //   share of 2 gamma Re(dv^H y)       (grad may be NULL; gslot 0 or 1)
     int deriv;
     double z;             // z of the point (deriv 1, 2)
     double alpha, beta, gamma;
     const double2* w;
     double2* out;
     const double2* dv;
-    double* grad;         // [n_traj][3]
+    double* grad;         // [n_traj][2][grid x] shares
     int gslot;
+};
+
+// ints between the barrier counters of two paths: one 256-byte line each, so
+// that the polls of different paths do not contend for one memory line
+constexpr int kBarStride = 64;
+
+// Persistent form of a propagation chunk (k_chunk): every workgroup of the
+// stage grid stays resident for all steps of the chunk and the workgroups of
+// one path meet at a barrier (bar[path], counted with agent-scope atomics)
+// between stages, instead of ending the kernel.
+struct ChunkArgs {
+    StageArgs s;          // per-plan fields; p, h, stage, u_in, u_out are set per stage
+    double2* Ua;
+    double2* Ub;
+    int n_steps;
+    double h[kChunkSteps];
+    int* bar;             // [n_traj][kBarStride], zero at launch (counter of path j at bar[j * kBarStride])
+    int n_traj;
 };
 
 // Radial blocks of the model potential on one basis (one-centre plans):
@@ -128,6 +149,8 @@ struct ModelArgs {
     const double2* dv;
     double gamma;
     double* grad;         // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] likewise for c
+    const double* gpart;  // [n_traj][2][n_part] shares of the b term (k_apply), added to grad[j][2]; may be NULL
+    int n_part;
 };
 
 struct SetupArgs {
@@ -140,9 +163,6 @@ struct SetupArgs {
     double2* PH;          // [N]
     int nbF, nbP;         // block ranges: Frow entries, phases, then G
 };
-
-constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
-constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
 
 struct PrologueArgs {
     const Meta* meta;
@@ -200,7 +220,7 @@ struct LaunchEv {
 enum KernelId {
     kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
     k2cNodes, k2cInterp, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
-    kNumKernels
+    kChunk, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 
@@ -276,6 +296,14 @@ hipError_t launch_combine(double2* out, const double2* const* v, const double* c
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
                               hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);
+// k_chunk with `rows` rows per workgroup as one cooperative launch; returns
+// hipErrorCooperativeLaunchTooLarge (and launches nothing) when the grid
+// cannot be resident at once
+hipError_t launch_chunk(const ChunkArgs& a, const Meta& host_meta, int smem, int rows, hipStream_t st,
+                        const LaunchEv& ev = LaunchEv{});
+// workgroups k_chunk needs for n_traj paths (rows per workgroup), and whether they fit at once
+int chunk_grid(const Meta& host_meta, int n_traj, int rows);
+bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
 int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
 int stage_chunks(const Meta& m, int rows);
 

@@ -68,6 +68,11 @@ struct wpccc_plan_s {
     int stage_smem = 0;       // k_apply (kRowsPerBlock rows)
     int stage_rows = kRowsPerBlock;
     int stage_smem_rows = 0;  // k_stage with stage_rows
+    // propagation chunks kernel by kernel (WPCCC_LAUNCH_STAGES) or as one
+    // persistent k_chunk launch (WPCCC_LAUNCH_PERSISTENT)
+    int launch = WPCCC_LAUNCH_STAGES;
+    int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
+    double* d_gpart = nullptr;  // [n_traj][2][n_chunks] per-workgroup shares of the b gradient
     KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
@@ -99,7 +104,7 @@ void free_plan(wpccc_plan_s* p) {
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
                     p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
                     p->d_vc,   p->d_lam,  p->d_mu,   p->d_nu,    p->d_u2,   p->d_u3,   p->d_u4,
-                    p->d_ckpt, p->d_seg};
+                    p->d_ckpt, p->d_seg,  p->d_bar,   p->d_gpart};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;
@@ -120,28 +125,50 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     return launched(e, "k_prologue");
 }
 
-int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, int step, double h, const double2* u_in,
-                  double2* X, double2* u_out, hipStream_t st) {
-    StageArgs a;
+// Fields of a stage launch shared by every stage of a propagation.
+StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
+    StageArgs a{};
     a.meta = p->c.d_meta;
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
-    a.p = point;
-    a.h = h;
     a.n_pad = p->n_pad;
-    a.stage = stage;
     a.traj0 = j0;
-    a.u_in = u_in;
     a.X = X;
     a.Xacc = p->d_Xacc;
-    a.u_out = u_out;
     a.flag = p->d_flag;
+    return a;
+}
+
+int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, int step, double h, const double2* u_in,
+                  double2* X, double2* u_out, hipStream_t st) {
+    StageArgs a = stage_args(p, j0, X);
+    a.p = point;
+    a.h = h;
+    a.stage = stage;
+    a.u_in = u_in;
+    a.u_out = u_out;
     a.hdev = p->capturing ? p->d_hall : nullptr;
     a.chunk = p->capturing ? p->d_chunk : nullptr;
     a.hidx = step;
     hipError_t e = launch_stage(a, p->c.meta, nj, p->stage_smem_rows, st, p->timer.open(kStage), p->stage_rows);
     return launched(e, "k_stage");
+}
+
+// Steps 0..ns-1 of the current prologue chunk (step lengths h[i]) for paths
+// [j0, j0+nj) as one persistent k_chunk launch with `rows` rows per workgroup.
+int enqueue_chunk(wpccc_plan_s* p, double2* X, int j0, int nj, const double* h, int ns, int rows, int smem,
+                  hipStream_t st) {
+    ChunkArgs c{};
+    c.s = stage_args(p, j0, X);
+    c.Ua = p->d_Ua;
+    c.Ub = p->d_Ub;
+    c.n_steps = ns;
+    for (int i = 0; i < ns; ++i) c.h[i] = h[i];
+    c.bar = p->d_bar;
+    c.n_traj = nj;
+    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_bar, 0, (size_t)nj * kBarStride * sizeof(int), st));
+    return launched(launch_chunk(c, p->c.meta, smem, rows, st, p->timer.open(kChunk)), "k_chunk");
 }
 
 // One RK4 step of length h for paths [j0, j0+nj) with M at the points pz (z),
@@ -217,7 +244,8 @@ int enqueue_grad_terms(wpccc_plan_s* p, int pt, double z, const double2* u, cons
                        double* grad, hipStream_t st) {
     int rc;
     for (int d = 1; d <= 2; ++d)
-        if ((rc = enqueue_apply(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, dv, gamma, 2, grad, st))) return rc;
+        if ((rc = enqueue_apply(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, dv, gamma, d - 1, p->d_gpart, st)))
+            return rc;
     ModelArgs m{};
     m.meta = p->c.d_meta;
     m.tb = p->tables();
@@ -231,6 +259,8 @@ int enqueue_grad_terms(wpccc_plan_s* p, int pt, double z, const double2* u, cons
     m.dv = dv;
     m.gamma = gamma;
     m.grad = grad;
+    m.gpart = p->d_gpart;
+    m.n_part = p->c.meta.n_chunks;
     return launched(launch_model_dot(m, p->n_traj, st), "k_model_dot");
 }
 
@@ -336,67 +366,100 @@ int propagate_graph(wpccc_plan_s* p, const double* zg, int n_full, double2* X, h
     return WPCCC_OK;
 }
 
-// Rows per workgroup of k_stage: each candidate is timed on ten stage
-// launches over the plan's paths (zero amplitudes, the same table traffic as
-// a real stage) and the fastest is kept.
-int tune_stage_rows(wpccc_plan_s* p, const int* cand, int n_cand, hipStream_t st) {
+// Stage configuration of a one-centre plan: rows per workgroup and launch
+// form (kernel by kernel, or the persistent k_chunk where its grid fits on
+// the device at once).  Each admissible candidate runs kTuneSteps RK4 steps
+// over the plan's launch batch from zero amplitudes (the table and state
+// traffic of a real step) and the fastest is kept.
+constexpr int kTuneSteps = 8;
+
+int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hipStream_t st) {
     const Meta& m = p->c.meta;
+    const int nj = p->batched ? p->n_traj : 1;
     const size_t V = (size_t)p->n_traj * p->n_pad * sizeof(double2);
-    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Ua, 0, V, st));
-    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Ub, 0, V, st));
-    WPCCC_HIP_CHECK(hipMemsetAsync(p->d_Xacc, 0, V, st));
-    const double pts[3] = {0.37, 0.38, 0.39};  // b > 0, so R > 0 at any z
-    int rc = enqueue_prologue(p, pts, 3, 0, p->n_traj, st);
+    double2* X = nullptr;
+    long long scratch_bytes = 0;
+    int rc = dev_alloc(&X, (size_t)p->n_traj * p->n_pad, scratch_bytes);
     if (rc) return rc;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    WPCCC_HIP_CHECK(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        set_error("hipEventCreate failed");
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    hipError_t e = hipMemsetAsync(X, 0, V, st);
+    for (double2* q : {p->d_Ua, p->d_Ub, p->d_Xacc})
+        if (e == hipSuccess) e = hipMemsetAsync(q, 0, V, st);
+    if (e == hipSuccess) e = hipEventCreate(&ev.e0);
+    if (e == hipSuccess) e = hipEventCreate(&ev.e1);
+    if (e != hipSuccess) {
+        (void)hipFree(X);
+        set_error("stage tuning failed: %s", hipGetErrorString(e));
         return WPCCC_EHIP;
     }
+    double pts[2 * kTuneSteps + 1], hs[kTuneSteps];
+    for (int i = 0; i <= 2 * kTuneSteps; ++i) pts[i] = 0.37 + 0.005 * i;  // b > 0, so R > 0 at any z
+    for (int i = 0; i < kTuneSteps; ++i) hs[i] = 0.01;
+    rc = enqueue_prologue(p, pts, 2 * kTuneSteps + 1, 0, nj, st);
+    const bool timing = p->timer.on;
+    p->timer.on = false;
     float best_ms = 1e30f;
-    int best = p->stage_rows;
+    int best_rows = 0, best_launch = 0;
+    const int saved_rows = p->stage_rows, saved_smem = p->stage_smem_rows;
+    auto time_it = [&](int rows, int launch, float* ms) -> int {
+        const int smem = stage_smem_bytes(m, rows);
+        p->stage_rows = rows;
+        p->stage_smem_rows = smem;
+        int r = WPCCC_OK;
+        for (int pass = 0; pass < 2 && r == WPCCC_OK; ++pass) {  // pass 0 warms up
+            if (pass == 1 && hipEventRecord(ev.e0, st) != hipSuccess) r = WPCCC_EHIP;
+            if (launch == WPCCC_LAUNCH_PERSISTENT) {
+                if (r == WPCCC_OK) r = enqueue_chunk(p, X, 0, nj, hs, kTuneSteps, rows, smem, st);
+            } else {
+                for (int i = 0; i < kTuneSteps && r == WPCCC_OK; ++i) r = enqueue_step(p, X, 0, nj, 2 * i, hs[i], st);
+            }
+        }
+        if (r == WPCCC_OK && (hipEventRecord(ev.e1, st) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess ||
+                              hipEventElapsedTime(ms, ev.e0, ev.e1) != hipSuccess)) {
+            set_error("stage tuning failed: %s", hipGetErrorString(hipGetLastError()));
+            r = WPCCC_EHIP;
+        }
+        return r;
+    };
     for (int ci = 0; ci < n_cand && rc == WPCCC_OK; ++ci) {
         const int rows = cand[ci];
         const int smem = stage_smem_bytes(m, rows);
         if (smem > 160 * 1024) continue;
-        StageArgs a{};
-        a.meta = p->c.d_meta;
-        a.tb = p->tables();
-        a.pt = p->points();
-        a.Zp = p->Zp;
-        a.p = 1;
-        a.h = 0.1;
-        a.n_pad = p->n_pad;
-        a.stage = 2;
-        a.traj0 = 0;
-        a.u_in = p->d_Ua;
-        a.X = p->d_Ua;
-        a.Xacc = p->d_Xacc;
-        a.u_out = p->d_Ub;
-        a.flag = p->d_flag;
-        hipError_t e = hipSuccess;
-        for (int it = 0; it < 2 && e == hipSuccess; ++it) e = launch_stage(a, m, p->n_traj, smem, st, LaunchEv{}, rows);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int it = 0; it < 10 && e == hipSuccess; ++it) e = launch_stage(a, m, p->n_traj, smem, st, LaunchEv{}, rows);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            set_error("stage tuning failed: %s", hipGetErrorString(e));
-            rc = WPCCC_EHIP;
-        } else if (ms < best_ms) {
-            best_ms = ms;
-            best = rows;
+        for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
+            if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
+            if (launch == WPCCC_LAUNCH_PERSISTENT && !chunk_fits(m, nj, rows, smem)) continue;
+            float ms = 0.f;
+            if ((rc = time_it(rows, launch, &ms))) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_rows = rows;
+                best_launch = launch;
+            }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    p->timer.on = timing;
+    const hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(X);
+    if (rc == WPCCC_OK && es != hipSuccess) {
+        set_error("stage tuning failed: %s", hipGetErrorString(es));
+        rc = WPCCC_EHIP;
+    }
     if (rc) return rc;
-    p->stage_rows = best;
-    p->stage_smem_rows = stage_smem_bytes(m, best);
+    if (!best_rows) {
+        p->stage_rows = saved_rows;
+        p->stage_smem_rows = saved_smem;
+        set_error("wpccc_plan_create: the persistent stage kernel's grid does not fit on the device at once");
+        return WPCCC_ENOTSUP;
+    }
+    p->stage_rows = best_rows;
+    p->stage_smem_rows = stage_smem_bytes(m, best_rows);
+    p->launch = best_launch;
     return WPCCC_OK;
 }
 
@@ -532,8 +595,14 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
-    if (o.stage_rows != 0 && o.stage_rows != 4 && o.stage_rows != 8 && o.stage_rows != 16) {
-        set_error("wpccc_plan_create: stage_rows must be 0, 4, 8 or 16");
+    if (o.stage_rows != 0 && o.stage_rows != 4 && o.stage_rows != 8 && o.stage_rows != 10 && o.stage_rows != 12 &&
+        o.stage_rows != 16) {
+        set_error("wpccc_plan_create: stage_rows must be 0, 4, 8, 10, 12 or 16");
+        free_plan(plan);
+        return WPCCC_EINVAL;
+    }
+    if (o.stage_launch < WPCCC_LAUNCH_AUTO || o.stage_launch > WPCCC_LAUNCH_PERSISTENT) {
+        set_error("wpccc_plan_create: stage_launch must be WPCCC_LAUNCH_AUTO, _STAGES or _PERSISTENT");
         free_plan(plan);
         return WPCCC_EINVAL;
     }
@@ -549,6 +618,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     TRY(dev_alloc(&plan->d_b, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_v, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_flag, 1, tot));
+    TRY(dev_alloc(&plan->d_bar, (size_t)n_traj * kBarStride, tot));
+    TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * 2 * m.n_chunks, tot));
     TRY(dev_alloc(&plan->d_Frow1, (size_t)m.n_frow, tot));
     TRY(dev_alloc(&plan->d_G1, (size_t)m.n_g, tot));
     TRY(dev_alloc(&plan->d_PH1, (size_t)N, tot));
@@ -580,9 +651,10 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         free_plan(plan);
         return WPCCC_EHIP;
     }
-    if (o.stage_rows == 0) {
-        const int cand[3] = {4, 8, 16};
-        TRY(tune_stage_rows(plan, cand, 3, st));
+    if (o.stage_rows == 0 || o.stage_launch != WPCCC_LAUNCH_STAGES) {
+        const int all[5] = {4, 8, 10, 12, 16};
+        const int* cand = o.stage_rows ? &o.stage_rows : all;
+        TRY(tune_stage(plan, cand, o.stage_rows ? 1 : 5, o.stage_launch, st));
     }
     *out = plan;
     return WPCCC_OK;
@@ -656,6 +728,15 @@ int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows) {
     return WPCCC_OK;
 }
 
+int wpccc_plan_stage_launch(wpccc_plan_t plan, int* launch) {
+    if (!plan || !launch) {
+        set_error("wpccc_plan_stage_launch: NULL argument");
+        return WPCCC_EINVAL;
+    }
+    *launch = plan->p2c ? WPCCC_LAUNCH_STAGES : plan->launch;
+    return WPCCC_OK;
+}
+
 int wpccc_plan_destroy(wpccc_plan_t plan) {
     if (plan) (void)hipDeviceSynchronize();
     free_plan(plan);
@@ -673,6 +754,10 @@ int wpccc_plan_status(wpccc_plan_t plan, void* stream) {
     WPCCC_HIP_CHECK(hipMemcpyAsync(&flag, plan->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     WPCCC_HIP_CHECK(hipStreamSynchronize(st));
     WPCCC_HIP_CHECK(hipMemsetAsync(plan->d_flag, 0, sizeof(int), st));
+    if (flag & 2) {
+        set_error("a path barrier of the persistent stage kernel timed out (results are incomplete)");
+        return WPCCC_EHIP;
+    }
     if (flag) {
         set_error("non-finite amplitude detected during propagation");
         return WPCCC_ENUMERIC;
@@ -780,10 +865,15 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
                 if (i < ns) pts[2 * i + 1] = 0.5 * (zgrid_host[c0 + i] + zgrid_host[c0 + i + 1]);
             }
             if ((rc = enqueue_prologue(plan, pts, 2 * ns + 1, j0, nj, st))) return rc;
-            for (int i = 0; i < ns; ++i) {
-                const double h = zgrid_host[c0 + i + 1] - zgrid_host[c0 + i];
-                if ((rc = enqueue_step(plan, X, j0, nj, 2 * i, h, st))) return rc;
+            double hs[kChunkSteps];
+            for (int i = 0; i < ns; ++i) hs[i] = zgrid_host[c0 + i + 1] - zgrid_host[c0 + i];
+            if (plan->launch == WPCCC_LAUNCH_PERSISTENT) {
+                if ((rc = enqueue_chunk(plan, X, j0, nj, hs, ns, plan->stage_rows, plan->stage_smem_rows, st)))
+                    return rc;
+                continue;
             }
+            for (int i = 0; i < ns; ++i)
+                if ((rc = enqueue_step(plan, X, j0, nj, 2 * i, hs[i], st))) return rc;
         }
     }
     if (P_dev || norm_dev) {
@@ -940,7 +1030,7 @@ namespace wpccc {
 const char* const kKernelNames[kNumKernels] = {
     "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
     "k_2c_nodes",     "k_2c_interp",   "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
-    "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish"};
+    "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish",  "k_chunk"};
 
 LaunchEv KernelTimer::open(int kernel) {
     LaunchEv ev;

@@ -212,26 +212,83 @@ def test_single_step_grid_and_errors(small):
 
 
 def test_stage_rows_variants_agree(large):
-    """k_stage with 4, 8 or 16 output rows per workgroup (and the timed
-    choice) runs the same arithmetic per output up to the order of its final
-    reduction: results agree to rounding."""
+    """k_stage with 4, 8, 10, 12 or 16 output rows per workgroup (and the
+    timed choice) runs the same arithmetic per output up to the order of its
+    final reduction: results agree to rounding."""
     rec, lb, _ = large
     w = WL.reduced(WL.single_centre_batched(), n_paths=5, n_steps=10)
     outs = {}
-    for rows in (4, 8, 16, 0):
+    for rows in (4, 8, 10, 12, 16, 0):
         print(f"stage rows {rows}", flush=True)
-        plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows)
+        plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows, stage_launch=W.WPCCC_LAUNCH_STAGES)
         if rows:
             assert W.wpccc_plan_stage_rows(plan) == rows
         else:
-            assert W.wpccc_plan_stage_rows(plan) in (4, 8, 16)
+            assert W.wpccc_plan_stage_rows(plan) in (4, 8, 10, 12, 16)
+        assert W.wpccc_plan_stage_launch(plan) == W.WPCCC_LAUNCH_STAGES
         X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
         X[:, 0] = 1.0
         W.wpccc_propagate(plan, w.zgrid, X)
         torch.cuda.synchronize()
         outs[rows] = X.cpu().numpy()
-    for rows in (4, 16, 0):
+    for rows in (4, 10, 12, 16, 0):
         assert np.abs(outs[rows] - outs[8]).max() <= 1e-13
+
+
+def _run_plan(plan, zg):
+    X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    W.wpccc_propagate(plan, zg, X)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    return X.cpu().numpy()
+
+
+def test_persistent_chunk_matches_stages(large):
+    """The persistent chunk kernel (all workgroups resident for a 64-step
+    chunk, per-path barriers between stages) runs the stage kernel's
+    arithmetic: bitwise the kernel-by-kernel result, for all 32 paths of the
+    N = 580 batch over 2 full chunks and a ragged one, for every row tiling
+    whose grid fits, and for one path per launch (batched = 0)."""
+    rec, lb, _ = large
+    w = WL.reduced(WL.single_centre_batched(), n_steps=150)
+    assert w.b.size == 32
+    fitted = []
+    for rows in (10, 12, 16, 8):
+        print(f"persistent vs stages, 32 paths x 150 steps, rows {rows}", flush=True)
+        try:
+            pp = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows, stage_launch=W.WPCCC_LAUNCH_PERSISTENT)
+        except W.WpcccError as e:
+            assert e.code == -6, str(e)   # grid larger than what can be resident at once
+            print(f"  rows {rows}: {e}", flush=True)
+            continue
+        fitted.append(rows)
+        assert W.wpccc_plan_stage_launch(pp) == W.WPCCC_LAUNCH_PERSISTENT
+        ps = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows, stage_launch=W.WPCCC_LAUNCH_STAGES)
+        Xp, Xs = _run_plan(pp, w.zgrid), _run_plan(ps, w.zgrid)
+        assert np.array_equal(Xp, Xs), (rows, np.abs(Xp - Xs).max())
+        # a second call on the same plan (barrier counters start again from zero)
+        assert np.array_equal(_run_plan(pp, w.zgrid[:70]), _run_plan(ps, w.zgrid[:70]))
+    assert 10 in fitted
+    # one path per launch sequence
+    sub = WL.reduced(WL.single_centre_batched(), n_paths=3, n_steps=70)
+    pp = W.wpccc_plan_create(lb, sub.b, sub.v, batched=False, stage_rows=8,
+                             stage_launch=W.WPCCC_LAUNCH_PERSISTENT)
+    ps = W.wpccc_plan_create(lb, sub.b, sub.v, stage_rows=8, stage_launch=W.WPCCC_LAUNCH_STAGES)
+    assert np.array_equal(_run_plan(pp, sub.zgrid), _run_plan(ps, sub.zgrid))
+
+
+def test_timed_launch_choice_is_valid(large):
+    """The default plan times both launch forms and keeps one; either gives the
+    kernel-by-kernel amplitudes of its row tiling bitwise."""
+    rec, lb, _ = large
+    w = WL.reduced(WL.single_centre_batched(), n_steps=70)
+    auto = W.wpccc_plan_create(lb, w.b, w.v)
+    rows, launch = W.wpccc_plan_stage_rows(auto), W.wpccc_plan_stage_launch(auto)
+    print(f"timed choice: rows {rows}, launch {launch}", flush=True)
+    assert launch in (W.WPCCC_LAUNCH_STAGES, W.WPCCC_LAUNCH_PERSISTENT)
+    ref = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows, stage_launch=W.WPCCC_LAUNCH_STAGES)
+    assert np.array_equal(_run_plan(auto, w.zgrid), _run_plan(ref, w.zgrid))
 
 
 def test_graph_replay_matches_eager(large):
