@@ -131,6 +131,10 @@ def main():
                     help="c2: skip the short two-centre measurement added to the output line")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-rows", type=int, default=0,
+                    help="c2: rows per workgroup of the RK4 stage kernels (0: chosen by timing at plan creation)")
+    ap.add_argument("--stage-launch", choices=["auto", "stages", "persistent"], default="auto",
+                    help="c2: kernel per stage, persistent chunk kernel, or the faster (timed at plan creation)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-path-per-launch comparison (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -161,7 +165,9 @@ def main():
     lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
     n_states, n_radial, n_r = W.wpccc_basis_info(lb)
     n_l = [rec.n_max - l + rec.n_bins for l in range(rec.l_max + 1)]
-    plan = W.wpccc_plan_create(lb, w.b, w.v)
+    launch = {"auto": W.WPCCC_LAUNCH_AUTO, "stages": W.WPCCC_LAUNCH_STAGES,
+              "persistent": W.WPCCC_LAUNCH_PERSISTENT}[args.stage_launch]
+    plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=args.stage_rows, stage_launch=launch)
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0

@@ -160,20 +160,111 @@ constexpr int kFBatch = 12;  // table entries per thread held in registers
 constexpr int kXBatch = 4;   // amplitudes per thread held in registers
 constexpr int kGBatch = 4;   // angular coefficients per thread held in registers
 
+// RK4 combinations (Algorithm 1) of stage `stage` with slope K and step h:
+// the next stage input (stages 1-3) and the new accumulator (stages 1-3) or
+// the new amplitude (stage 4).
+__device__ inline double2 rk4_next_input(int stage, double2 x0, double2 K, double h) {
+    const double c = (stage == 3) ? h : 0.5 * h;
+    return make_double2(x0.x + c * K.x, x0.y + c * K.y);
+}
+__device__ inline double2 rk4_accumulate(int stage, double2 x0, double2 xa, double2 K, double h) {
+    if (stage == 1) return make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
+    if (stage == 4) return make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
+    return make_double2(xa.x + h / 3.0 * K.x, xa.y + h / 3.0 * K.y);
+}
+
 // The RK4 combination of stage a.stage for output oi with slope K and step h.
 __device__ inline void rk4_update(const StageArgs& a, size_t oi, double2 K, double2 x0, double2 xa, double h) {
-    if (a.stage == 1) {
-        a.u_out[oi] = make_double2(x0.x + 0.5 * h * K.x, x0.y + 0.5 * h * K.y);
-        a.Xacc[oi] = make_double2(x0.x + h / 6.0 * K.x, x0.y + h / 6.0 * K.y);
-    } else if (a.stage == 2 || a.stage == 3) {
-        const double c = (a.stage == 2) ? 0.5 * h : h;
-        a.u_out[oi] = make_double2(x0.x + c * K.x, x0.y + c * K.y);
-        a.Xacc[oi] = make_double2(xa.x + h / 3.0 * K.x, xa.y + h / 3.0 * K.y);
+    if (a.stage < 4) {
+        a.u_out[oi] = rk4_next_input(a.stage, x0, K, h);
+        a.Xacc[oi] = rk4_accumulate(a.stage, x0, xa, K, h);
     } else {
-        const double2 xn = make_double2(xa.x + h / 6.0 * K.x, xa.y + h / 6.0 * K.y);
+        const double2 xn = rk4_accumulate(4, x0, xa, K, h);
         if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
         a.X[oi] = xn;
     }
+}
+
+// phase 2 of a stage: W[r][g] = sum_n F_l'[r][e0(g) + n] x'[xoff(g) + n]
+// for the workgroup's rows (LDS in, LDS out).  Each work item is one column g
+// and half of the rows (ROWS / 2 accumulators), so that every x' load serves
+// ROWS / 2 products; lanes of a wave take consecutive g (the F columns of one
+// (l, lambda) block are read as a broadcast).
+template <int ROWS>
+__device__ inline void stage_phase2(const double* Fs, const double2* xs, const int2* gis, double2* Ws, int nrows,
+                                    int gcols, int nV) {
+    constexpr int RB = (ROWS + 1) / 2;
+    const int B = blockDim.x, tid = threadIdx.x;
+    for (int it = tid; it < 2 * gcols; it += B) {
+        const int half = it >= gcols ? 1 : 0;
+        const int g = it - half * gcols;
+        const int r0 = half * RB;
+        if (r0 >= nrows) continue;
+        const int2 info = gis[g];
+        const int e0 = info.x & 0xffff, nl = info.x >> 16;
+        const double* f = Fs + r0 * nV + e0;
+        const double2* x = xs + info.y;
+        double re[RB], im[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) re[k] = im[k] = 0.0;
+#pragma unroll 2
+        for (int n = 0; n < nl; ++n) {
+            const double2 y = x[n];
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                // rows r0 + k >= nrows read rows of F that this stage did not
+                // fill (inside the ROWS-row buffer); their sums are dropped
+                const double fk = f[k * nV + n];
+                re[k] += fk * y.x;
+                im[k] += fk * y.y;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (r0 + k < nrows) Ws[(r0 + k) * gcols + g] = make_double2(re[k], im[k]);
+    }
+}
+
+// phase 3 of a stage: y[r][q'] = sum_g G_l'[q'][g] W[r][g] for output o =
+// (r, q') (o < n_out), summed by the S lanes s = 0..S-1 of the output; every
+// lane of the wave takes part in the reduction and returns the output's sum.
+__device__ inline double2 stage_phase3(const double* Gs, const double2* Ws, int o, int s, int S, int n_out, int nmp,
+                                       int gcols) {
+    double re = 0.0, im = 0.0;
+    if (o < n_out) {
+        const int r = o / nmp, qp = o - r * nmp;
+        const double* g = Gs + qp * gcols;
+        const double2* w = Ws + r * gcols;
+        double re1 = 0.0, im1 = 0.0;
+        int c = s;
+        for (; c + S < gcols; c += 2 * S) {
+            const double g0 = g[c], g1 = g[c + S];
+            const double2 w0 = w[c], w1 = w[c + S];
+            re += g0 * w0.x;
+            im += g0 * w0.y;
+            re1 += g1 * w1.x;
+            im1 += g1 * w1.y;
+        }
+        if (c < gcols) {
+            re += g[c] * w[c].x;
+            im += g[c] * w[c].y;
+        }
+        re += re1;
+        im += im1;
+    }
+    for (int off = S >> 1; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+    }
+    return make_double2(re, im);
+}
+
+// Lanes per output of phase 3: the largest power of two S <= 64 with
+// 2 n_out S <= B (so that every output keeps at least half the lanes busy).
+__device__ inline int phase3_lanes(int n_out, int B) {
+    int S = 1;
+    while (S < 64 && n_out * S * 2 <= B) S *= 2;
+    return S;
 }
 
 // One stage for rows [row0, row0 + nrows) of the l' block, all nmp = 2l'+1 values of m'.
@@ -251,8 +342,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
     // output-side values, prefetched by the thread that writes output o
     const int n_out = nrows * nmp;
-    int S = 1;
-    while (S < 64 && n_out * S * 2 <= B) S *= 2;
+    const int S = phase3_lanes(n_out, B);
     const int o = tid / S, s = tid - o * S;
     const bool writer = (o < n_out) && (s == 0);
     const double v = T.vvec[j];
@@ -331,65 +421,12 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
     __syncthreads();
 
-    // phase 2
-    {
-        for (int idx = tid; idx < nrows * gcols; idx += B) {
-            const int r = idx / gcols, g = idx - r * gcols;
-            const int2 info = gis[g];
-            const int e0 = info.x & 0xffff, nl = info.x >> 16;
-            const double* f = Fs + r * nV + e0;
-            const double2* x = xs + info.y;
-            double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-            int n = 0;
-            for (; n + 7 < nl; n += 8) {
-                const double f0 = f[n], f1 = f[n + 1], f2 = f[n + 2], f3 = f[n + 3];
-                const double f4 = f[n + 4], f5 = f[n + 5], f6 = f[n + 6], f7 = f[n + 7];
-                const double2 y0 = x[n], y1 = x[n + 1], y2 = x[n + 2], y3 = x[n + 3];
-                const double2 y4 = x[n + 4], y5 = x[n + 5], y6 = x[n + 6], y7 = x[n + 7];
-                re0 += f0 * y0.x + f1 * y1.x + f2 * y2.x + f3 * y3.x;
-                im0 += f0 * y0.y + f1 * y1.y + f2 * y2.y + f3 * y3.y;
-                re1 += f4 * y4.x + f5 * y5.x + f6 * y6.x + f7 * y7.x;
-                im1 += f4 * y4.y + f5 * y5.y + f6 * y6.y + f7 * y7.y;
-            }
-            for (; n < nl; ++n) {
-                re0 += f[n] * x[n].x;
-                im0 += f[n] * x[n].y;
-            }
-            Ws[idx] = make_double2(re0 + re1, im0 + im1);
-        }
-    }
+    stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
     __syncthreads();
-
-    // phase 3: outputs o = (r, q'), S lanes per output (S a power of two dividing 64)
-    double re = 0.0, im = 0.0;
-    if (o < n_out) {
-        const int r = o / nmp, qp = o - r * nmp;
-        const double* g = Gs + qp * gcols;
-        const double2* w = Ws + r * gcols;
-        double re1 = 0.0, im1 = 0.0;
-        int c = s;
-        for (; c + S < gcols; c += 2 * S) {
-            const double g0 = g[c], g1 = g[c + S];
-            const double2 w0 = w[c], w1 = w[c + S];
-            re += g0 * w0.x;
-            im += g0 * w0.y;
-            re1 += g1 * w1.x;
-            im1 += g1 * w1.y;
-        }
-        if (c < gcols) {
-            re += g[c] * w[c].x;
-            im += g[c] * w[c].y;
-        }
-        re += re1;
-        im += im1;
-    }
-    for (int off = S >> 1; off > 0; off >>= 1) {
-        re += __shfl_xor(re, off, 64);
-        im += __shfl_xor(im, off, 64);
-    }
+    const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
     double gval = 0.0;
     if (writer) {
-        const double2 py = cmul(phs[rad_o], make_double2(re, im));
+        const double2 py = cmul(phs[rad_o], y);
         const double sc = a.Zp / v;
         double2 K = make_double2(sc * py.y, -sc * py.x);  // -(i/v) Zp ph y
         const double h = a.h;
@@ -448,20 +485,26 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
 
 constexpr int kBarrierSpin = 1 << 22;  // polls (0.2 s or more) before a barrier gives up
 
-// Barrier of the workgroups of one path.  Every wave waits until its own
-// stores have reached the L2; thread 0 then arrives with an agent-scope
-// release (which writes back the L2 for the other XCDs), polls the counter
-// with relaxed loads until `target` workgroups have arrived and acquires at
-// agent scope once; the workgroup barrier orders the other waves' reads after
-// that acquire.  A wait longer than kBarrierSpin polls latches bit 2 of *flag
-// and returns false, so every workgroup still ends.
-__device__ bool path_barrier(int* cnt, int target, int* flag) {
-    __shared__ int ok;
+// Barrier of the workgroups of one path, in two halves so that loads that do
+// not depend on the other workgroups can be issued in between.
+// path_arrive: every wave waits until its own memory operations are done
+// (stores in the L2), then thread 0 arrives with an agent-scope release
+// (which writes the L2 back for the other XCDs).
+// path_wait: thread 0 polls the counter with relaxed loads until `target`
+// workgroups have arrived and acquires at agent scope once; the workgroup
+// barrier orders the other waves' reads after that acquire.  A wait longer
+// than kBarrierSpin polls latches bit 2 of *flag and returns false, so every
+// workgroup still ends.
+__device__ inline void path_arrive(int* cnt) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool path_wait(int* cnt, int target, int* flag) {
+    __shared__ int ok;
     if (threadIdx.x == 0) {
         ok = 1;
-        __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int it = 0;
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
@@ -483,17 +526,164 @@ __device__ inline int chunks_of(const Meta& m, int rows) {
     return n;
 }
 
+constexpr int kFPre = 14;  // table entries per thread k_chunk prefetches into registers
+
+// Per-thread state of a k_chunk workgroup, kept in registers across stages.
+struct ChunkRegs {
+    double2 tv[kFPre];     // the next new point's table entries (this thread's share) ...
+    double rp, pb;         // ... its R power, Pbar entry
+    double2 ph;            // ... and phase (radial function tid)
+    double gcv[kGBatch];   // angular coefficients of l' (constant)
+    int gpv[kGBatch];
+    int sv[kXBatch];       // radial index of the amplitudes this thread converts (constant)
+    double2 x0, xa;        // writer: amplitude at the start of the step, RK4 accumulator
+};
+
+// Loads of point p's data for the workgroup's rows into registers; they are
+// consumed by the next stage at a new point, after the path barrier.
+__device__ inline void chunk_prefetch(const StageArgs& a, int j, int lp, int row0, int nrows, int p, ChunkRegs& r) {
+    const Meta& m = *a.meta;
+    const int B = blockDim.x, tid = threadIdx.x, nV = m.nV[lp];
+    const size_t jp = (size_t)j * a.pt.n_pts + p;
+    const int k = a.pt.kidx[jp];
+    const double2* row = a.tb.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
+    const int totF = nrows * nV;
+#pragma unroll
+    for (int i = 0; i < kFPre; ++i) {
+        const int idx = tid + i * B;
+        if (idx < totF) r.tv[i] = row[idx];
+    }
+    if (tid < 2 * (m.lam_max + 1)) r.rp = a.pt.rpow[jp * kRpow + tid];
+    if (tid < (m.lam_max + 1) * (m.lam_max + 2) / 2) r.pb = a.pt.pbar[jp * kMaxPb + tid];
+    if (tid < m.n_f) r.ph = a.pt.ph[jp * m.n_f + tid];
+}
+
+// One RK4 stage of k_chunk for rows [row0, row0 + nrows) of l': the
+// arithmetic of stage_body (KIND 0), with the point's data taken from the
+// prefetch registers (fresh) or left in LDS by the previous stage (!fresh),
+// and the writer's X and accumulator kept in registers.
+template <int ROWS>
+__device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem, bool fresh,
+                            ChunkRegs& r) {
+    const Meta& m = *a.meta;
+    const Tables& T = a.tb;
+    const int N = m.n_states;
+    const int nmp = 2 * lp + 1;
+    const int nlp = m.n_l[lp];
+    const int nV = m.nV[lp];
+    const int gcols = m.gcols[lp];
+    const int B = blockDim.x;
+    const int tid = threadIdx.x;
+    const size_t jp = (size_t)j * a.pt.n_pts + a.p;
+
+    double2* xs = reinterpret_cast<double2*>(smem);
+    double2* Ws = xs + N;
+    double2* phs = Ws + ROWS * gcols;
+    double* Fs = reinterpret_cast<double*>(phs + m.n_f);
+    double* Gs = Fs + ROWS * nV;
+    double* rps = Gs + nmp * gcols;
+    double* pbs = rps + kRpow;
+    int2* gis = reinterpret_cast<int2*>(pbs + kMaxPb);
+    const int* cls = reinterpret_cast<const int*>(gis + gcols);  // multipole order of each F column
+
+    const double2* u = a.u_in + (size_t)j * a.n_pad;
+    double2 uv[kXBatch];
+#pragma unroll
+    for (int i = 0; i < kXBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < N) uv[i] = u[idx];
+    }
+    if (fresh) {
+        if (tid < 2 * (m.lam_max + 1)) rps[tid] = r.rp;
+        if (tid < (m.lam_max + 1) * (m.lam_max + 2) / 2) pbs[tid] = r.pb;
+        if (tid < m.n_f) phs[tid] = r.ph;
+        for (int i = tid + B; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < kXBatch; ++i) {
+        const int idx = tid + i * B;
+        if (idx < N) {
+            const double2 ph = phs[r.sv[i]], x = uv[i];
+            xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+        }
+    }
+    for (int idx = tid + kXBatch * B; idx < N; idx += B) {
+        const double2 ph = phs[T.st_rad[idx]], x = u[idx];
+        xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+    }
+    if (fresh) {
+        const int totF = nrows * nV;
+#pragma unroll
+        for (int i = 0; i < kFPre; ++i) {
+            const int idx = tid + i * B;
+            if (idx < totF) {
+                const int l0 = cls[idx % nV];
+                Fs[idx] = r.tv[i].x * rps[2 * l0] + r.tv[i].y * rps[2 * l0 + 1];
+            }
+        }
+        if (totF > kFPre * B) {
+            const double2* row = T.tab + (size_t)a.pt.kidx[jp] * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
+            for (int idx = tid + kFPre * B; idx < totF; idx += B) {
+                const double2 t0 = row[idx];
+                const int l0 = cls[idx % nV];
+                Fs[idx] = t0.x * rps[2 * l0] + t0.y * rps[2 * l0 + 1];
+            }
+        }
+        const int totG = nmp * gcols;
+#pragma unroll
+        for (int i = 0; i < kGBatch; ++i) {
+            const int idx = tid + i * B;
+            if (idx < totG) Gs[idx] = r.gpv[i] >= 0 ? r.gcv[i] * pbs[r.gpv[i]] : 0.0;
+        }
+        const double* gc = T.gcoef + m.g_off[lp];
+        const int* gp = T.gpb + m.g_off[lp];
+        for (int idx = tid + kGBatch * B; idx < totG; idx += B) {
+            const int p = gp[idx];
+            Gs[idx] = p >= 0 ? gc[idx] * pbs[p] : 0.0;
+        }
+    }
+    __syncthreads();
+
+    stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
+    __syncthreads();
+    const int n_out = nrows * nmp;
+    const int S = phase3_lanes(n_out, B);
+    const int o = tid / S, s = tid - o * S;
+    const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
+    if (o < n_out && s == 0) {
+        const int rr = o / nmp, qp = o - rr * nmp;
+        const size_t oi = (size_t)j * a.n_pad + m.state_off[lp] + qp * nlp + row0 + rr;
+        const double2 py = cmul(phs[m.rad_off[lp] + row0 + rr], y);
+        const double sc = a.Zp / T.vvec[j];
+        const double2 K = make_double2(sc * py.y, -sc * py.x);  // -(i/v) Zp ph y
+        if (a.stage < 4) {
+            a.u_out[oi] = rk4_next_input(a.stage, r.x0, K, a.h);
+            r.xa = rk4_accumulate(a.stage, r.x0, r.xa, K, a.h);
+        } else {
+            const double2 xn = rk4_accumulate(4, r.x0, r.xa, K, a.h);
+            if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
+            a.X[oi] = xn;
+            r.x0 = xn;
+        }
+    }
+}
+
 // All steps of a chunk for every path (see ChunkArgs).  grid: 8 x ceil(items
 // / 8) workgroups, items = paths x row chunks; consecutive workgroup ids go to
 // the eight XCDs in turn and the items of XCD x are the x-th eighth of the
 // path-major list, so the workgroups of a path share an XCD (and its L2).
 // Each workgroup keeps the couplings of its rows at the current point in LDS
-// and builds them only when the point changes: twice per step (midpoint and
-// end point) instead of four times.
+// and builds them only when the point changes (twice per step: midpoint and
+// end point); the loads for the next new point are issued before the path
+// barrier that precedes it, so their latency overlaps the wait.
 template <int ROWS>
-__global__ __launch_bounds__(kStageThreads) void k_chunk(ChunkArgs c) {
+__global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
     extern __shared__ double2 smem2[];
+    char* smem = reinterpret_cast<char*>(smem2);
     const Meta& m = *c.s.meta;
+    const Tables& T = c.s.tb;
     const int nwg = chunks_of(m, ROWS);
     const int total = c.n_traj * nwg;
     const int per = (total + 7) / 8;
@@ -509,7 +699,41 @@ __global__ __launch_bounds__(kStageThreads) void k_chunk(ChunkArgs c) {
     }
     const int row0 = ci * ROWS;
     const int nrows = min(ROWS, m.n_l[lp] - row0);
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int N = m.n_states, nmp = 2 * lp + 1, nV = m.nV[lp], gcols = m.gcols[lp];
+
+    // constants of the workgroup's rows
+    ChunkRegs r;
+    {
+        const double* gc = T.gcoef + m.g_off[lp];
+        const int* gp = T.gpb + m.g_off[lp];
+#pragma unroll
+        for (int i = 0; i < kGBatch; ++i) {
+            const int idx = tid + i * B;
+            r.gcv[i] = idx < nmp * gcols ? gc[idx] : 0.0;
+            r.gpv[i] = idx < nmp * gcols ? gp[idx] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < kXBatch; ++i) {
+            const int idx = tid + i * B;
+            r.sv[i] = idx < N ? T.st_rad[idx] : 0;
+        }
+        double* Fs = reinterpret_cast<double*>(reinterpret_cast<double2*>(smem) + N + ROWS * gcols + m.n_f);
+        int2* gis = reinterpret_cast<int2*>(Fs + ROWS * nV + nmp * gcols + kRpow + kMaxPb);
+        for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
+        int* cls = reinterpret_cast<int*>(gis + gcols);
+        for (int i = tid; i < nV; i += B) cls[i] = T.col_lam[m.col_off[lp] + i];
+        const int n_out = nrows * nmp;
+        const int S = phase3_lanes(n_out, B);
+        const int o = tid / S;
+        r.x0 = r.xa = make_double2(0.0, 0.0);
+        if (o < n_out && tid - o * S == 0) {
+            const int rr = o / nmp, qp = o - rr * nmp;
+            r.x0 = c.s.X[(size_t)j * c.s.n_pad + m.state_off[lp] + qp * m.n_l[lp] + row0 + rr];
+        }
+    }
     StageArgs a = c.s;
+    chunk_prefetch(a, j, lp, row0, nrows, 0, r);
     int target = 0;
     for (int i = 0; i < c.n_steps; ++i) {
         a.h = c.h[i];
@@ -521,10 +745,14 @@ __global__ __launch_bounds__(kStageThreads) void k_chunk(ChunkArgs c) {
             // stage 3 repeats stage 2's point (the midpoint) and stage 1 of
             // step i > 0 repeats stage 4's point of step i - 1
             const bool fresh = stage == 2 || stage == 4 || i == 0;
-            if (nrows > 0) stage_body<0, ROWS>(a, j, lp, row0, nrows, reinterpret_cast<char*>(smem2), fresh);
+            chunk_stage<ROWS>(a, j, lp, row0, nrows, smem, fresh, r);
             if (i + 1 == c.n_steps && stage == 4) break;
+            int* bar = c.bar + (size_t)jl * kBarStride;
+            path_arrive(bar);
+            // the next stage at a new point: stage 2 (midpoint) or 4 (end point)
+            if (stage == 1 || stage == 3) chunk_prefetch(a, j, lp, row0, nrows, 2 * i + (stage == 1 ? 1 : 2), r);
             target += nwg;
-            if (!path_barrier(c.bar + (size_t)jl * kBarStride, target, c.s.flag)) return;
+            if (!path_wait(bar, target, c.s.flag)) return;
         }
     }
 }
@@ -736,6 +964,19 @@ int stage_smem_bytes(const Meta& m, int rows) {
                              (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
                              nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
                              (size_t)m.gcols[lp] * sizeof(int2);
+        if ((int)bytes > best) best = (int)bytes;
+    }
+    return best;
+}
+
+int chunk_smem_bytes(const Meta& m, int rows) {
+    int best = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) {
+        const size_t nmp = 2 * lp + 1;
+        const size_t bytes = m.n_states * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
+                             (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
+                             nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
+                             (size_t)m.gcols[lp] * sizeof(int2) + (size_t)m.nV[lp] * sizeof(int);
         if ((int)bytes > best) best = (int)bytes;
     }
     return best;

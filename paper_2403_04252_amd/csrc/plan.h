@@ -305,6 +305,8 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& host_meta, int smem, int
 int chunk_grid(const Meta& host_meta, int n_traj, int rows);
 bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
 int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
+// LDS of k_chunk: the stage layout plus the multipole order of each F column
+int chunk_smem_bytes(const Meta& m, int rows);
 int stage_chunks(const Meta& m, int rows);
 
 }  // namespace wpccc

@@ -71,6 +71,7 @@ struct wpccc_plan_s {
     // propagation chunks kernel by kernel (WPCCC_LAUNCH_STAGES) or as one
     // persistent k_chunk launch (WPCCC_LAUNCH_PERSISTENT)
     int launch = WPCCC_LAUNCH_STAGES;
+    int chunk_smem = 0;       // k_chunk with stage_rows
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
     double* d_gpart = nullptr;  // [n_traj][2][n_chunks] per-workgroup shares of the b gradient
     KernelTimer timer;
@@ -415,7 +416,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
         for (int pass = 0; pass < 2 && r == WPCCC_OK; ++pass) {  // pass 0 warms up
             if (pass == 1 && hipEventRecord(ev.e0, st) != hipSuccess) r = WPCCC_EHIP;
             if (launch == WPCCC_LAUNCH_PERSISTENT) {
-                if (r == WPCCC_OK) r = enqueue_chunk(p, X, 0, nj, hs, kTuneSteps, rows, smem, st);
+                if (r == WPCCC_OK) r = enqueue_chunk(p, X, 0, nj, hs, kTuneSteps, rows, chunk_smem_bytes(m, rows), st);
             } else {
                 for (int i = 0; i < kTuneSteps && r == WPCCC_OK; ++i) r = enqueue_step(p, X, 0, nj, 2 * i, hs[i], st);
             }
@@ -433,7 +434,9 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
         if (smem > 160 * 1024) continue;
         for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
             if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
-            if (launch == WPCCC_LAUNCH_PERSISTENT && !chunk_fits(m, nj, rows, smem)) continue;
+            if (launch == WPCCC_LAUNCH_PERSISTENT &&
+                (chunk_smem_bytes(m, rows) > 160 * 1024 || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
+                continue;
             float ms = 0.f;
             if ((rc = time_it(rows, launch, &ms))) break;
             if (ms < best_ms) {
@@ -459,6 +462,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     }
     p->stage_rows = best_rows;
     p->stage_smem_rows = stage_smem_bytes(m, best_rows);
+    p->chunk_smem = chunk_smem_bytes(m, best_rows);
     p->launch = best_launch;
     return WPCCC_OK;
 }
@@ -643,7 +647,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->d_vc, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    const int smem16 = stage_smem_bytes(m, 16);
+    const int smem16 = chunk_smem_bytes(m, 16);
     const int smem_max = std::min(160 * 1024, std::max(smem16, plan->stage_smem));
     if (e == hipSuccess && smem_max > 64 * 1024) e = stage_set_smem_limit(m.l_max, smem_max);
     if (e != hipSuccess) {
@@ -651,10 +655,20 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         free_plan(plan);
         return WPCCC_EHIP;
     }
-    if (o.stage_rows == 0 || o.stage_launch != WPCCC_LAUNCH_STAGES) {
+    if (o.stage_rows == 0 || o.stage_launch == WPCCC_LAUNCH_AUTO) {
         const int all[5] = {4, 8, 10, 12, 16};
         const int* cand = o.stage_rows ? &o.stage_rows : all;
         TRY(tune_stage(plan, cand, o.stage_rows ? 1 : 5, o.stage_launch, st));
+    } else if (o.stage_launch == WPCCC_LAUNCH_PERSISTENT) {
+        // nothing to choose: check that the grid can be resident at once
+        const int nj = plan->batched ? n_traj : 1;
+        plan->chunk_smem = chunk_smem_bytes(m, plan->stage_rows);
+        if (plan->chunk_smem > 160 * 1024 || !chunk_fits(m, nj, plan->stage_rows, plan->chunk_smem)) {
+            set_error("wpccc_plan_create: the persistent stage kernel's grid does not fit on the device at once");
+            free_plan(plan);
+            return WPCCC_ENOTSUP;
+        }
+        plan->launch = WPCCC_LAUNCH_PERSISTENT;
     }
     *out = plan;
     return WPCCC_OK;
@@ -868,7 +882,7 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
             double hs[kChunkSteps];
             for (int i = 0; i < ns; ++i) hs[i] = zgrid_host[c0 + i + 1] - zgrid_host[c0 + i];
             if (plan->launch == WPCCC_LAUNCH_PERSISTENT) {
-                if ((rc = enqueue_chunk(plan, X, j0, nj, hs, ns, plan->stage_rows, plan->stage_smem_rows, st)))
+                if ((rc = enqueue_chunk(plan, X, j0, nj, hs, ns, plan->stage_rows, plan->chunk_smem, st)))
                     return rc;
                 continue;
             }
