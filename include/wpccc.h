@@ -133,8 +133,9 @@ typedef struct {
     double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
     int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
     int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 8,
-                       10, 12 or 16; 0: chosen at plan creation by timing each on
-                       the plan's paths */
+                       10, 12 or 16, with rows x (2 l_max + 1) <= 256
+                       (WPCCC_EINVAL otherwise); 0: chosen at plan creation by
+                       timing each admissible value on the plan's paths */
     int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED: 2C overlap/transfer
                        contractions with FP32 products summed in FP32 over each
                        32-node chunk and in FP64 across chunks; LU, solves and

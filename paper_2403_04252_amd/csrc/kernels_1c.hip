@@ -261,11 +261,16 @@ __device__ inline double2 stage_phase3(const double* Gs, const double2* Ws, int 
 
 // Lanes per output of phase 3: the largest power of two S <= 64 with
 // 2 n_out S <= B (so that every output keeps at least half the lanes busy).
+// Every output has a lane group when n_out <= B (phase3_fits).
 __device__ inline int phase3_lanes(int n_out, int B) {
     int S = 1;
     while (S < 64 && n_out * S * 2 <= B) S *= 2;
     return S;
 }
+
+// Whether a tile of `rows` rows gives every output of blocks of up to
+// nmp_max = 2 l_max + 1 values of m' a lane of the stage workgroup.
+__host__ __device__ inline bool phase3_fits(int rows, int nmp_max) { return rows * nmp_max <= kStageThreads; }
 
 // One stage for rows [row0, row0 + nrows) of the l' block, all nmp = 2l'+1 values of m'.
 // KIND 0: RK4 stage (k_stage); KIND 1: operator application (k_apply, see
@@ -477,10 +482,45 @@ __device__ void stage_entry(const StageArgs& a, char* smem) {
     stage_body<KIND, ROWS>(a, j, lp, row0, nrows, smem);
 }
 
+__device__ inline int chunks_of(const Meta& m, int rows) {
+    int n = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) n += (m.n_l[lp] + rows - 1) / rows;
+    return n;
+}
+
+// Work item of workgroup bx in a one-dimensional grid of 8 x ceil(items / 8)
+// workgroups over items = paths x row chunks (path-major): consecutive
+// workgroup ids go to the eight XCDs in turn and the items of XCD x are the
+// x-th eighth of the list, so the workgroups of a path share an XCD (and its
+// L2, which then serves the path's stage input to all of them).  Returns
+// false for the padding workgroups.
+template <int ROWS>
+__device__ inline bool xcd_item(const Meta& m, int n_paths, int bx, int* jl, int* lp, int* row0, int* nrows) {
+    const int nwg = chunks_of(m, ROWS);
+    const int total = n_paths * nwg;
+    const int per = (total + 7) / 8;
+    const int W = (bx % 8) * per + bx / 8;
+    if (W >= total) return false;
+    *jl = W / nwg;
+    int ci = W - *jl * nwg, l = 0;
+    for (; l < m.l_max; ++l) {
+        const int nc = (m.n_l[l] + ROWS - 1) / ROWS;
+        if (ci < nc) break;
+        ci -= nc;
+    }
+    *lp = l;
+    *row0 = ci * ROWS;
+    *nrows = min(ROWS, m.n_l[l] - *row0);
+    return *nrows > 0;
+}
+
+// One RK4 stage for a.n_paths paths from a.traj0 (grid of xcd_item).
 template <int ROWS>
 __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
-    stage_entry<0, ROWS>(a, reinterpret_cast<char*>(smem2));
+    int jl, lp, row0, nrows;
+    if (!xcd_item<ROWS>(*a.meta, a.n_paths, blockIdx.x, &jl, &lp, &row0, &nrows)) return;
+    stage_body<0, ROWS>(a, a.traj0 + jl, lp, row0, nrows, reinterpret_cast<char*>(smem2));
 }
 
 constexpr int kBarrierSpin = 1 << 22;  // polls (0.2 s or more) before a barrier gives up
@@ -518,12 +558,6 @@ __device__ bool path_wait(int* cnt, int target, int* flag) {
     }
     __syncthreads();
     return ok != 0;
-}
-
-__device__ inline int chunks_of(const Meta& m, int rows) {
-    int n = 0;
-    for (int lp = 0; lp <= m.l_max; ++lp) n += (m.n_l[lp] + rows - 1) / rows;
-    return n;
 }
 
 constexpr int kFPre = 14;  // table entries per thread k_chunk prefetches into registers
@@ -685,20 +719,9 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
     const Meta& m = *c.s.meta;
     const Tables& T = c.s.tb;
     const int nwg = chunks_of(m, ROWS);
-    const int total = c.n_traj * nwg;
-    const int per = (total + 7) / 8;
-    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (W >= total) return;
-    const int jl = W / nwg;
+    int jl, lp, row0, nrows;
+    if (!xcd_item<ROWS>(m, c.n_traj, blockIdx.x, &jl, &lp, &row0, &nrows)) return;
     const int j = c.s.traj0 + jl;
-    int ci = W - jl * nwg, lp = 0;
-    for (; lp < m.l_max; ++lp) {
-        const int nc = (m.n_l[lp] + ROWS - 1) / ROWS;
-        if (ci < nc) break;
-        ci -= nc;
-    }
-    const int row0 = ci * ROWS;
-    const int nrows = min(ROWS, m.n_l[lp] - row0);
     const int B = blockDim.x, tid = threadIdx.x;
     const int N = m.n_states, nmp = 2 * lp + 1, nV = m.nV[lp], gcols = m.gcols[lp];
 
@@ -969,6 +992,8 @@ int stage_smem_bytes(const Meta& m, int rows) {
     return best;
 }
 
+bool stage_rows_fit(const Meta& m, int rows) { return phase3_fits(rows, 2 * m.l_max + 1); }
+
 int chunk_smem_bytes(const Meta& m, int rows) {
     int best = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
@@ -1080,13 +1105,15 @@ hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st,
 
 hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st, const LaunchEv& ev,
                         int rows) {
-    const dim3 grid(stage_chunks(hm, rows), n_traj_launch), block(kStageThreads);
+    const dim3 grid(8 * ((n_traj_launch * stage_chunks(hm, rows) + 7) / 8)), block(kStageThreads);
+    StageArgs a1 = a;
+    a1.n_paths = n_traj_launch;
     switch (rows) {
-        case 4: WPCCC_LAUNCH(ev, k_stage<4>, grid, block, smem, st, a); break;
-        case 10: WPCCC_LAUNCH(ev, k_stage<10>, grid, block, smem, st, a); break;
-        case 12: WPCCC_LAUNCH(ev, k_stage<12>, grid, block, smem, st, a); break;
-        case 16: WPCCC_LAUNCH(ev, k_stage<16>, grid, block, smem, st, a); break;
-        default: WPCCC_LAUNCH(ev, k_stage<8>, grid, block, smem, st, a); break;
+        case 4: WPCCC_LAUNCH(ev, k_stage<4>, grid, block, smem, st, a1); break;
+        case 10: WPCCC_LAUNCH(ev, k_stage<10>, grid, block, smem, st, a1); break;
+        case 12: WPCCC_LAUNCH(ev, k_stage<12>, grid, block, smem, st, a1); break;
+        case 16: WPCCC_LAUNCH(ev, k_stage<16>, grid, block, smem, st, a1); break;
+        default: WPCCC_LAUNCH(ev, k_stage<8>, grid, block, smem, st, a1); break;
     }
     return hipGetLastError();
 }

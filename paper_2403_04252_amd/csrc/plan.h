@@ -15,6 +15,9 @@ constexpr int kMaxLam = 2 * kMaxL;   // largest multipole order
 constexpr int kMaxPb = (kMaxLam + 1) * (kMaxLam + 2) / 2;
 constexpr int kSlots = 3;            // couplings kept for the diagnostic entry point
 constexpr int kStageThreads = 256;
+// dynamic LDS a stage workgroup may request: the CU's 160 KB less room for
+// the kernels' few static LDS words
+constexpr int kMaxDynLds = 160 * 1024 - 1024;
 constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and k_stage's default)
 constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
 constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
@@ -90,6 +93,7 @@ struct StageArgs {
     int n_pad;
     int stage;            // 1..4
     int traj0;
+    int n_paths;          // paths of a k_stage launch (set by launch_stage)
     const double2* u_in;  // stage input   [n_traj][n_pad]
     double2* X;           // amplitudes    [n_traj][n_pad]
     double2* Xacc;        // accumulator   [n_traj][n_pad]
@@ -305,6 +309,9 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& host_meta, int smem, int
 int chunk_grid(const Meta& host_meta, int n_traj, int rows);
 bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
 int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
+// whether the stage kernels can use `rows` rows per workgroup for this basis
+// (every output of a workgroup needs a lane of the phase-3 reduction)
+bool stage_rows_fit(const Meta& m, int rows);
 // LDS of k_chunk: the stage layout plus the multipole order of each F column
 int chunk_smem_bytes(const Meta& m, int rows);
 int stage_chunks(const Meta& m, int rows);

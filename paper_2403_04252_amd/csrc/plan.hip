@@ -431,11 +431,11 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     for (int ci = 0; ci < n_cand && rc == WPCCC_OK; ++ci) {
         const int rows = cand[ci];
         const int smem = stage_smem_bytes(m, rows);
-        if (smem > 160 * 1024) continue;
+        if (smem > kMaxDynLds || !stage_rows_fit(m, rows)) continue;
         for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
             if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
             if (launch == WPCCC_LAUNCH_PERSISTENT &&
-                (chunk_smem_bytes(m, rows) > 160 * 1024 || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
+                (chunk_smem_bytes(m, rows) > kMaxDynLds || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
                 continue;
             float ms = 0.f;
             if ((rc = time_it(rows, launch, &ms))) break;
@@ -612,7 +612,13 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     }
     plan->stage_rows = o.stage_rows ? o.stage_rows : kRowsPerBlock;
     plan->stage_smem_rows = stage_smem_bytes(m, plan->stage_rows);
-    if (plan->stage_smem > 160 * 1024 || plan->stage_smem_rows > 160 * 1024) {
+    if (!stage_rows_fit(m, plan->stage_rows)) {
+        set_error("wpccc_plan_create: stage_rows %d is too many for l_max = %d (rows x (2 l_max + 1) must not "
+                  "exceed %d)", plan->stage_rows, m.l_max, kStageThreads);
+        free_plan(plan);
+        return WPCCC_EINVAL;
+    }
+    if (plan->stage_smem > kMaxDynLds || plan->stage_smem_rows > kMaxDynLds) {
         set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes)", plan->stage_smem);
         free_plan(plan);
         return WPCCC_ENOTSUP;
@@ -648,7 +654,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         e = hipMemcpyAsync(plan->d_vc, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     const int smem16 = chunk_smem_bytes(m, 16);
-    const int smem_max = std::min(160 * 1024, std::max(smem16, plan->stage_smem));
+    const int smem_max = std::min(kMaxDynLds, std::max(smem16, plan->stage_smem));
     if (e == hipSuccess && smem_max > 64 * 1024) e = stage_set_smem_limit(m.l_max, smem_max);
     if (e != hipSuccess) {
         set_error("wpccc_plan_create: device setup failed: %s", hipGetErrorString(e));
@@ -663,7 +669,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         // nothing to choose: check that the grid can be resident at once
         const int nj = plan->batched ? n_traj : 1;
         plan->chunk_smem = chunk_smem_bytes(m, plan->stage_rows);
-        if (plan->chunk_smem > 160 * 1024 || !chunk_fits(m, nj, plan->stage_rows, plan->chunk_smem)) {
+        if (plan->chunk_smem > kMaxDynLds || !chunk_fits(m, nj, plan->stage_rows, plan->chunk_smem)) {
             set_error("wpccc_plan_create: the persistent stage kernel's grid does not fit on the device at once");
             free_plan(plan);
             return WPCCC_ENOTSUP;

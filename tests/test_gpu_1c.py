@@ -235,6 +235,18 @@ def test_stage_rows_variants_agree(large):
         assert np.abs(outs[rows] - outs[8]).max() <= 1e-13
 
 
+def test_stage_rows_limit():
+    """Every output of a stage workgroup needs a lane of the phase-3
+    reduction: rows x (2 l_max + 1) <= 256, so 16 rows are refused for
+    l_max = 8 while the timed choice stays within the limit."""
+    lb = lib_basis(WL.Recipe(2, 8, 1, 2.0, 300, 60.0))
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create(lb, [1.0], [1.0], stage_rows=16)
+    assert e.value.code == -1
+    plan = W.wpccc_plan_create(lb, [1.0, 2.0], [1.0, 1.0])
+    assert W.wpccc_plan_stage_rows(plan) * 17 <= 256
+
+
 def _run_plan(plan, zg):
     X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0
