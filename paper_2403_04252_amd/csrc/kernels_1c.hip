@@ -156,7 +156,9 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     for (int f = t; f < m.n_f; f += blockDim.x) a.pt.ph[jp * m.n_f + f] = phase(a.tb.rad_eps[f], z, v);
 }
 
-constexpr int kFBatch = 12;  // table entries per thread held in registers
+// table entries per thread held in registers by a stage workgroup of `rows`
+// rows (about 1.5 per row and thread; the rest is loaded where it is used)
+constexpr int fbatch(int rows) { return rows >= 8 ? 12 : (rows * 3 + 1) / 2; }
 constexpr int kXBatch = 4;   // amplitudes per thread held in registers
 constexpr int kGBatch = 4;   // angular coefficients per thread held in registers
 
@@ -311,10 +313,11 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     const double2* row = T.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
     const int* cl = T.col_lam + m.col_off[lp];
     const int totF = fresh ? nrows * nV : 0;
-    double2 tv[kFBatch];
-    int lv[kFBatch];
+    constexpr int FB = fbatch(ROWS);
+    double2 tv[FB];
+    int lv[FB];
 #pragma unroll
-    for (int i = 0; i < kFBatch; ++i) {
+    for (int i = 0; i < FB; ++i) {
         const int idx = tid + i * B;
         if (idx < totF) {
             tv[i] = row[idx];
@@ -406,11 +409,11 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
     }
 #pragma unroll
-    for (int i = 0; i < kFBatch; ++i) {
+    for (int i = 0; i < FB; ++i) {
         const int idx = tid + i * B;
         if (idx < totF) Fs[idx] = tv[i].x * rps[2 * lv[i]] + tv[i].y * rps[2 * lv[i] + 1];
     }
-    for (int idx = tid + kFBatch * B; idx < totF; idx += B) {
+    for (int idx = tid + FB * B; idx < totF; idx += B) {
         const double2 t0 = row[idx];
         const int l0 = cl[idx % nV];
         Fs[idx] = t0.x * rps[2 * l0] + t0.y * rps[2 * l0 + 1];
@@ -514,9 +517,11 @@ __device__ inline bool xcd_item(const Meta& m, int n_paths, int bx, int* jl, int
     return *nrows > 0;
 }
 
-// One RK4 stage for a.n_paths paths from a.traj0 (grid of xcd_item).
+// One RK4 stage for a.n_paths paths from a.traj0 (grid of xcd_item).  Small
+// row tiles ask for registers that leave room for four workgroups per CU
+// (their LDS does), larger ones for three.
 template <int ROWS>
-__global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
     int jl, lp, row0, nrows;
     if (!xcd_item<ROWS>(*a.meta, a.n_paths, blockIdx.x, &jl, &lp, &row0, &nrows)) return;
@@ -560,11 +565,14 @@ __device__ bool path_wait(int* cnt, int target, int* flag) {
     return ok != 0;
 }
 
-constexpr int kFPre = 14;  // table entries per thread k_chunk prefetches into registers
+// table entries per thread k_chunk prefetches into registers (14 covers
+// 12 rows of 300 columns; smaller tiles need fewer)
+constexpr int fpre(int rows) { return rows >= 10 ? 14 : fbatch(rows) + 1; }
 
 // Per-thread state of a k_chunk workgroup, kept in registers across stages.
+template <int FP>
 struct ChunkRegs {
-    double2 tv[kFPre];     // the next new point's table entries (this thread's share) ...
+    double2 tv[FP];     // the next new point's table entries (this thread's share) ...
     double rp, pb;         // ... its R power, Pbar entry
     double2 ph;            // ... and phase (radial function tid)
     double gcv[kGBatch];   // angular coefficients of l' (constant)
@@ -575,7 +583,8 @@ struct ChunkRegs {
 
 // Loads of point p's data for the workgroup's rows into registers; they are
 // consumed by the next stage at a new point, after the path barrier.
-__device__ inline void chunk_prefetch(const StageArgs& a, int j, int lp, int row0, int nrows, int p, ChunkRegs& r) {
+template <int FP>
+__device__ inline void chunk_prefetch(const StageArgs& a, int j, int lp, int row0, int nrows, int p, ChunkRegs<FP>& r) {
     const Meta& m = *a.meta;
     const int B = blockDim.x, tid = threadIdx.x, nV = m.nV[lp];
     const size_t jp = (size_t)j * a.pt.n_pts + p;
@@ -583,7 +592,7 @@ __device__ inline void chunk_prefetch(const StageArgs& a, int j, int lp, int row
     const double2* row = a.tb.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
     const int totF = nrows * nV;
 #pragma unroll
-    for (int i = 0; i < kFPre; ++i) {
+    for (int i = 0; i < FP; ++i) {
         const int idx = tid + i * B;
         if (idx < totF) r.tv[i] = row[idx];
     }
@@ -598,7 +607,8 @@ __device__ inline void chunk_prefetch(const StageArgs& a, int j, int lp, int row
 // and the writer's X and accumulator kept in registers.
 template <int ROWS>
 __device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem, bool fresh,
-                            ChunkRegs& r) {
+                            ChunkRegs<fpre(ROWS)>& r) {
+    constexpr int FP = fpre(ROWS);
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
@@ -650,16 +660,16 @@ __device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nro
     if (fresh) {
         const int totF = nrows * nV;
 #pragma unroll
-        for (int i = 0; i < kFPre; ++i) {
+        for (int i = 0; i < FP; ++i) {
             const int idx = tid + i * B;
             if (idx < totF) {
                 const int l0 = cls[idx % nV];
                 Fs[idx] = r.tv[i].x * rps[2 * l0] + r.tv[i].y * rps[2 * l0 + 1];
             }
         }
-        if (totF > kFPre * B) {
+        if (totF > FP * B) {
             const double2* row = T.tab + (size_t)a.pt.kidx[jp] * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
-            for (int idx = tid + kFPre * B; idx < totF; idx += B) {
+            for (int idx = tid + FP * B; idx < totF; idx += B) {
                 const double2 t0 = row[idx];
                 const int l0 = cls[idx % nV];
                 Fs[idx] = t0.x * rps[2 * l0] + t0.y * rps[2 * l0 + 1];
@@ -726,7 +736,7 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
     const int N = m.n_states, nmp = 2 * lp + 1, nV = m.nV[lp], gcols = m.gcols[lp];
 
     // constants of the workgroup's rows
-    ChunkRegs r;
+    ChunkRegs<fpre(ROWS)> r;
     {
         const double* gc = T.gcoef + m.g_off[lp];
         const int* gp = T.gpb + m.g_off[lp];
@@ -1008,10 +1018,9 @@ int chunk_smem_bytes(const Meta& m, int rows) {
 }
 
 hipError_t stage_set_smem_limit(int, int bytes) {
-    const void* fns[] = {(const void*)k_stage<4>,  (const void*)k_stage<8>,  (const void*)k_stage<10>,
-                         (const void*)k_stage<12>, (const void*)k_stage<16>, (const void*)k_apply,
-                         (const void*)k_chunk<4>,  (const void*)k_chunk<8>,  (const void*)k_chunk<10>,
-                         (const void*)k_chunk<12>, (const void*)k_chunk<16>};
+#define WPCCC_FN_PAIR(R) (const void*)k_stage<R>, (const void*)k_chunk<R>,
+    const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR)(const void*)k_apply};
+#undef WPCCC_FN_PAIR
     hipError_t e = hipSuccess;
     for (const void* f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1022,11 +1031,11 @@ int chunk_grid(const Meta& hm, int n_traj, int rows) { return 8 * ((n_traj * sta
 
 static const void* chunk_fn(int rows) {
     switch (rows) {
-        case 4: return (const void*)k_chunk<4>;
-        case 10: return (const void*)k_chunk<10>;
-        case 12: return (const void*)k_chunk<12>;
-        case 16: return (const void*)k_chunk<16>;
-        default: return (const void*)k_chunk<8>;
+#define WPCCC_CASE(R) \
+    case R: return (const void*)k_chunk<R>;
+        WPCCC_STAGE_ROWS(WPCCC_CASE)
+#undef WPCCC_CASE
+        default: return nullptr;
     }
 }
 
@@ -1035,6 +1044,7 @@ bool chunk_fits(const Meta& hm, int n_traj, int rows, int smem) {
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (!chunk_fn(rows)) return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chunk_fn(rows), kStageThreads, smem) != hipSuccess)
         return false;
     return (long long)per_cu * n_cu >= chunk_grid(hm, n_traj, rows);
@@ -1045,6 +1055,7 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& hm, int smem, int rows, 
     ChunkArgs arg = a;
     void* params[] = {&arg};
     if (ev.a) (void)hipEventRecord(ev.a, st);
+    if (!chunk_fn(rows)) return hipErrorInvalidValue;
     const hipError_t e = hipLaunchCooperativeKernel(chunk_fn(rows), grid, block, params, smem, st);
     if (ev.b) (void)hipEventRecord(ev.b, st);
     return e;
@@ -1109,11 +1120,12 @@ hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, i
     StageArgs a1 = a;
     a1.n_paths = n_traj_launch;
     switch (rows) {
-        case 4: WPCCC_LAUNCH(ev, k_stage<4>, grid, block, smem, st, a1); break;
-        case 10: WPCCC_LAUNCH(ev, k_stage<10>, grid, block, smem, st, a1); break;
-        case 12: WPCCC_LAUNCH(ev, k_stage<12>, grid, block, smem, st, a1); break;
-        case 16: WPCCC_LAUNCH(ev, k_stage<16>, grid, block, smem, st, a1); break;
-        default: WPCCC_LAUNCH(ev, k_stage<8>, grid, block, smem, st, a1); break;
+#define WPCCC_CASE(R)                                               \
+    case R: WPCCC_LAUNCH(ev, k_stage<R>, grid, block, smem, st, a1); \
+        break;
+        WPCCC_STAGE_ROWS(WPCCC_CASE)
+#undef WPCCC_CASE
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -19,6 +19,10 @@ constexpr int kStageThreads = 256;
 // the kernels' few static LDS words
 constexpr int kMaxDynLds = 160 * 1024 - 1024;
 constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and k_stage's default)
+// row tilings the stage kernels are built for (X-macro over the values)
+#define WPCCC_STAGE_ROWS(X) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
+constexpr int kStageRowsList[] = {4, 5, 6, 7, 8, 10, 12, 16};
+constexpr int kNumStageRows = sizeof(kStageRowsList) / sizeof(kStageRowsList[0]);
 constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
 constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
 

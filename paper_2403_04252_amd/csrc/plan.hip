@@ -599,9 +599,10 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
-    if (o.stage_rows != 0 && o.stage_rows != 4 && o.stage_rows != 8 && o.stage_rows != 10 && o.stage_rows != 12 &&
-        o.stage_rows != 16) {
-        set_error("wpccc_plan_create: stage_rows must be 0, 4, 8, 10, 12 or 16");
+    bool rows_ok = o.stage_rows == 0;
+    for (int r : kStageRowsList) rows_ok = rows_ok || o.stage_rows == r;
+    if (!rows_ok) {
+        set_error("wpccc_plan_create: stage_rows must be 0, 4, 5, 6, 7, 8, 10, 12 or 16");
         free_plan(plan);
         return WPCCC_EINVAL;
     }
@@ -662,9 +663,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_EHIP;
     }
     if (o.stage_rows == 0 || o.stage_launch == WPCCC_LAUNCH_AUTO) {
-        const int all[5] = {4, 8, 10, 12, 16};
-        const int* cand = o.stage_rows ? &o.stage_rows : all;
-        TRY(tune_stage(plan, cand, o.stage_rows ? 1 : 5, o.stage_launch, st));
+        const int* cand = o.stage_rows ? &o.stage_rows : kStageRowsList;
+        TRY(tune_stage(plan, cand, o.stage_rows ? 1 : kNumStageRows, o.stage_launch, st));
     } else if (o.stage_launch == WPCCC_LAUNCH_PERSISTENT) {
         // nothing to choose: check that the grid can be resident at once
         const int nj = plan->batched ? n_traj : 1;

@@ -212,26 +212,26 @@ def test_single_step_grid_and_errors(small):
 
 
 def test_stage_rows_variants_agree(large):
-    """k_stage with 4, 8, 10, 12 or 16 output rows per workgroup (and the
-    timed choice) runs the same arithmetic per output up to the order of its
-    final reduction: results agree to rounding."""
+    """k_stage with 4, 5, 6, 7, 8, 10, 12 or 16 output rows per workgroup (and
+    the timed choice) runs the same arithmetic per output up to the order of
+    its final reduction: results agree to rounding."""
     rec, lb, _ = large
     w = WL.reduced(WL.single_centre_batched(), n_paths=5, n_steps=10)
     outs = {}
-    for rows in (4, 8, 10, 12, 16, 0):
+    for rows in (4, 5, 6, 7, 8, 10, 12, 16, 0):
         print(f"stage rows {rows}", flush=True)
         plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=rows, stage_launch=W.WPCCC_LAUNCH_STAGES)
         if rows:
             assert W.wpccc_plan_stage_rows(plan) == rows
         else:
-            assert W.wpccc_plan_stage_rows(plan) in (4, 8, 10, 12, 16)
+            assert W.wpccc_plan_stage_rows(plan) in (4, 5, 6, 7, 8, 10, 12, 16)
         assert W.wpccc_plan_stage_launch(plan) == W.WPCCC_LAUNCH_STAGES
         X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
         X[:, 0] = 1.0
         W.wpccc_propagate(plan, w.zgrid, X)
         torch.cuda.synchronize()
         outs[rows] = X.cpu().numpy()
-    for rows in (4, 10, 12, 16, 0):
+    for rows in (4, 5, 6, 7, 10, 12, 16, 0):
         assert np.abs(outs[rows] - outs[8]).max() <= 1e-13
 
 
