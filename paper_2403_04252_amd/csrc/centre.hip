@@ -59,7 +59,8 @@ void block_columns(const Meta& m, int lp, int l, int lam, int& e0, int& g0) {
 }  // namespace
 
 void centre_free(Centre& c) {
-    void* bufs[] = {c.d_meta, c.d_eps, c.d_gcoef, c.d_rad_eps, c.d_col_lam, c.d_gpb, c.d_st_rad, c.d_gcol, c.d_tab};
+    void* bufs[] = {c.d_meta,   c.d_eps,  c.d_gcoef, c.d_rad_eps, c.d_col_lam,
+                    c.d_gpb,    c.d_st_rad, c.d_st_xs, c.d_gcol,  c.d_tab};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     c = Centre{};
@@ -104,6 +105,21 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a,
         m.state_off[l] = l <= m.l_max ? hb.state_off[l] : N;
         m.rad_off[l] = l <= m.l_max ? hb.rad_off[l] : hb.n_f;
     }
+    // x' in LDS: rows (l, q) of N_l values at an odd stride (in 16-byte
+    // units), so that lanes reading different q of one l hit different banks
+    m.n_xs = 0;
+    for (int l = 0; l <= kMaxL; ++l) {
+        m.xs_off[l] = m.n_xs;
+        m.xs_stride[l] = 0;
+        if (l > m.l_max) continue;
+        m.xs_stride[l] = m.n_l[l] | 1;
+        m.n_xs += (2 * l + 1) * m.xs_stride[l];
+    }
+    std::vector<int> st_xs((size_t)N);
+    for (int l = 0; l <= m.l_max; ++l)
+        for (int q = 0; q <= 2 * l; ++q)
+            for (int n = 0; n < m.n_l[l]; ++n)
+                st_xs[(size_t)m.state_off[l] + q * m.n_l[l] + n] = m.xs_off[l] + q * m.xs_stride[l] + n;
     m.n_frow = m.n_g = m.n_chunks = m.n_cols = m.n_gcols = 0;
     for (int lp = 0; lp <= kMaxL; ++lp) {
         m.nV[lp] = m.gcols[lp] = 0;
@@ -136,7 +152,7 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a,
                     a_off_of_col.push_back(hb.rad_off[l] + n);
                 }
                 for (int q = 0; q <= 2 * l; ++q)
-                    gcol.push_back(gcol_pack(e0, m.n_l[l], m.state_off[l] + q * m.n_l[l]));
+                    gcol.push_back(gcol_pack(e0, m.n_l[l], m.xs_off[l] + q * m.xs_stride[l]));
             }
         col_lam.insert(col_lam.end(), lam_of_col.begin(), lam_of_col.end());
         for (int np = 0; np < m.n_l[lp]; ++np)
@@ -188,6 +204,7 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a,
     A(dev_alloc(&c.d_meta, 1, tot));
     A(dev_alloc(&c.d_eps, (size_t)N, tot));
     A(dev_alloc(&c.d_st_rad, (size_t)N, tot));
+    A(dev_alloc(&c.d_st_xs, (size_t)N, tot));
     A(dev_alloc(&c.d_rad_eps, (size_t)m.n_f, tot));
     A(dev_alloc(&c.d_gcoef, (size_t)m.n_g, tot));
     A(dev_alloc(&c.d_gpb, (size_t)m.n_g, tot));
@@ -210,6 +227,7 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a,
     up(c.d_meta, &c.meta, sizeof(Meta));
     up(c.d_eps, hb.eps.data(), (size_t)N * sizeof(double));
     up(c.d_st_rad, hb.st_i.data(), (size_t)N * sizeof(int));
+    up(c.d_st_xs, st_xs.data(), (size_t)N * sizeof(int));
     up(c.d_rad_eps, hb.rad_eps.data(), (size_t)m.n_f * sizeof(double));
     up(c.d_gcoef, gcoef.data(), gcoef.size() * sizeof(double));
     up(c.d_gpb, gpb.data(), gpb.size() * sizeof(int));

@@ -299,8 +299,8 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     const int tid = threadIdx.x;
     const size_t jp = (size_t)j * a.pt.n_pts + a.p;
 
-    double2* xs = reinterpret_cast<double2*>(smem);                       // [N]
-    double2* Ws = xs + N;                                                  // [rows][gcols]
+    double2* xs = reinterpret_cast<double2*>(smem);                       // [n_xs] (xs_off, xs_stride)
+    double2* Ws = xs + m.n_xs;                                             // [rows][gcols]
     double2* phs = Ws + ROWS * gcols;                                      // [n_f]
     double* Fs = reinterpret_cast<double*>(phs + m.n_f);                  // [rows][nV]
     double* Gs = Fs + ROWS * nV;                                           // [nmp][gcols]
@@ -332,7 +332,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         const int idx = tid + i * B;
         if (idx < N) {
             uv[i] = u[idx];
-            sv[i] = T.st_rad[idx];
+            sv[i] = T.st_rad[idx] | (T.st_xs[idx] << 16);
         }
     }
     const double* gc = T.gcoef + m.g_off[lp];
@@ -400,13 +400,13 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     for (int i = 0; i < kXBatch; ++i) {
         const int idx = tid + i * B;
         if (idx < N) {
-            const double2 ph = phs[sv[i]], x = uv[i];
-            xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+            const double2 ph = phs[sv[i] & 0xffff], x = uv[i];
+            xs[sv[i] >> 16] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
         }
     }
     for (int idx = tid + kXBatch * B; idx < N; idx += B) {
         const double2 ph = phs[T.st_rad[idx]], x = u[idx];
-        xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+        xs[T.st_xs[idx]] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
     }
 #pragma unroll
     for (int i = 0; i < FB; ++i) {
@@ -577,7 +577,7 @@ struct ChunkRegs {
     double2 ph;            // ... and phase (radial function tid)
     double gcv[kGBatch];   // angular coefficients of l' (constant)
     int gpv[kGBatch];
-    int sv[kXBatch];       // radial index of the amplitudes this thread converts (constant)
+    int sv[kXBatch];       // radial index | LDS position << 16 of the amplitudes this thread converts (constant)
     double2 x0, xa;        // writer: amplitude at the start of the step, RK4 accumulator
 };
 
@@ -621,7 +621,7 @@ __device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nro
     const size_t jp = (size_t)j * a.pt.n_pts + a.p;
 
     double2* xs = reinterpret_cast<double2*>(smem);
-    double2* Ws = xs + N;
+    double2* Ws = xs + m.n_xs;
     double2* phs = Ws + ROWS * gcols;
     double* Fs = reinterpret_cast<double*>(phs + m.n_f);
     double* Gs = Fs + ROWS * nV;
@@ -649,13 +649,13 @@ __device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nro
     for (int i = 0; i < kXBatch; ++i) {
         const int idx = tid + i * B;
         if (idx < N) {
-            const double2 ph = phs[r.sv[i]], x = uv[i];
-            xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+            const double2 ph = phs[r.sv[i] & 0xffff], x = uv[i];
+            xs[r.sv[i] >> 16] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
         }
     }
     for (int idx = tid + kXBatch * B; idx < N; idx += B) {
         const double2 ph = phs[T.st_rad[idx]], x = u[idx];
-        xs[idx] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+        xs[T.st_xs[idx]] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
     }
     if (fresh) {
         const int totF = nrows * nV;
@@ -749,9 +749,9 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
 #pragma unroll
         for (int i = 0; i < kXBatch; ++i) {
             const int idx = tid + i * B;
-            r.sv[i] = idx < N ? T.st_rad[idx] : 0;
+            r.sv[i] = idx < N ? (T.st_rad[idx] | (T.st_xs[idx] << 16)) : 0;
         }
-        double* Fs = reinterpret_cast<double*>(reinterpret_cast<double2*>(smem) + N + ROWS * gcols + m.n_f);
+        double* Fs = reinterpret_cast<double*>(reinterpret_cast<double2*>(smem) + m.n_xs + ROWS * gcols + m.n_f);
         int2* gis = reinterpret_cast<int2*>(Fs + ROWS * nV + nmp * gcols + kRpow + kMaxPb);
         for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
         int* cls = reinterpret_cast<int*>(gis + gcols);
@@ -993,7 +993,7 @@ int stage_smem_bytes(const Meta& m, int rows) {
     int best = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
         const size_t nmp = 2 * lp + 1;
-        const size_t bytes = m.n_states * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
+        const size_t bytes = m.n_xs * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
                              (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
                              nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
                              (size_t)m.gcols[lp] * sizeof(int2);
@@ -1008,7 +1008,7 @@ int chunk_smem_bytes(const Meta& m, int rows) {
     int best = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
         const size_t nmp = 2 * lp + 1;
-        const size_t bytes = m.n_states * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
+        const size_t bytes = m.n_xs * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
                              (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
                              nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
                              (size_t)m.gcols[lp] * sizeof(int2) + (size_t)m.nV[lp] * sizeof(int);

@@ -49,12 +49,16 @@ struct Meta {
     int gcols[kMaxL + 1];     // columns of G_l'
     int g_off[kMaxL + 1];     // offset of G_l' in a G array
     int gcol_off[kMaxL + 1];  // offset of l' in gcol_info
+    int xs_off[kMaxL + 1];    // LDS position of x'_{l, q=0, n=0} in the stage kernels
+    int xs_stride[kMaxL + 1]; // LDS stride between q rows of l: N_l rounded up to an odd number
+    int n_xs;                 // LDS length (complex) of x' in the stage kernels
 };
 
 __host__ __device__ inline int pb_index(int lam, int mu) { return lam * (lam + 1) / 2 + mu; }
 
 // G column info: x = e0 | (N_l << 16) (F column block start, block width),
-// y = state offset of x'_{l, q, 0} (the input states the column contracts with)
+// y = LDS position of x'_{l, q, 0} (the input states the column contracts
+// with) in the stage kernels' padded layout (xs_off, xs_stride)
 __host__ __device__ inline int2 gcol_pack(int e0, int nl, int xoff) { return make_int2(e0 | (nl << 16), xoff); }
 
 // Basis tables shared by every launch of a plan.
@@ -66,6 +70,7 @@ struct Tables {
     const int* gpb;         // [n_g] pb_index(lambda, |mu|) or -1
     const double* eps;      // [N] state energies
     const int* st_rad;      // [N] radial index of each state
+    const int* st_xs;       // [N] LDS position of each state's x' (xs_off, xs_stride)
     const double* rad_eps;  // [n_f] energy of each radial function
     const double* bvec;     // [n_traj]
     const double* vvec;     // [n_traj]
@@ -190,7 +195,7 @@ struct Centre {
     Meta meta{};
     Meta* d_meta = nullptr;
     double *d_eps = nullptr, *d_gcoef = nullptr, *d_rad_eps = nullptr;
-    int *d_col_lam = nullptr, *d_gpb = nullptr, *d_st_rad = nullptr;
+    int *d_col_lam = nullptr, *d_gpb = nullptr, *d_st_rad = nullptr, *d_st_xs = nullptr;
     int2* d_gcol = nullptr;
     double2* d_tab = nullptr;
     long long bytes = 0;
@@ -203,6 +208,7 @@ struct Centre {
         t.gpb = d_gpb;
         t.eps = d_eps;
         t.st_rad = d_st_rad;
+        t.st_xs = d_st_xs;
         t.rad_eps = d_rad_eps;
         t.bvec = bvec;
         t.vvec = vvec;
