@@ -184,19 +184,6 @@ __global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
     }
 }
 
-// One workgroup per (job, tile) with an XCD-aware order: consecutive
-// workgroup ids go to the eight XCDs in turn, and the work items of XCD x are
-// the x-th eighth of the job-major list, so the tiles of one job (which
-// stream the same operand rows) share an L2.  Per chunk of kNodeChunk nodes
-// the 32 rows of A, the 32 columns of B and the node fields of the weights
-// are loaded into registers one chunk ahead (their latency overlaps the
-// MFMA of the current chunk), then staged in LDS; each wave owns one 16 x 16
-// quarter of the tile for all nk weights and feeds the MFMA with (A w_k) and B.
-//
-// MIXED: the products run on v_mfma_f32_16x16x4f32 (operands in FP32,
-// accumulated in FP32 over the 32 nodes of a chunk) and each chunk's partial
-// sums are added to FP64 accumulators, so the FP32 accumulation error stays
-// that of a 32-term sum whatever the number of nodes.
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 // Output row of register r in lane l of a 16 x 16 MFMA tile (column l % 16),
@@ -207,27 +194,39 @@ __device__ inline int mfma_row_f32(int r, int l) { return kF32RowByLaneGroup ? 4
 
 constexpr int kWFields = 7;  // cos, sin, W_0..W_2, J_|s-t|, J_(s+t)
 
-template <bool MIXED>
-__global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
+// Work of one wave in a 32 x 32 tile with nk weights: KPW weights (kk0 ..
+// kk0 + KPW - 1) times SPW of the four 16 x 16 subtiles.  SPW = 4: the wave
+// covers the whole tile and kk0 = wave * KPW (nk = 4 KPW); SPW = 2: the wave
+// covers the two subtiles of row half mt = wave / 2 and kk0 = (wave % 2) KPW
+// (nk = 2 KPW).  One LDS read of an A value then serves 2 KPW products, one
+// of a B value KPW * SPW / 2, and one of a weight SPW.
+template <typename T>
+struct ContractLds {
+    T As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
+    double fl[kWFields][kNodeChunk];
+    double wk[kNodeChunk][kMaxK];
+};
+
+template <bool MIXED, int KPW, int SPW>
+__device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0,
+                              ContractLds<typename std::conditional<MIXED, float, double>::type>& L) {
     typedef typename std::conditional<MIXED, float, double>::type T;
-    __shared__ T As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
-    __shared__ double fl[kWFields][kNodeChunk];
-    __shared__ double wk[kNodeChunk][kMaxK];
+    auto& As = L.As;
+    auto& Bs = L.Bs;
+    auto& fl = L.fl;
+    auto& wk = L.wk;
     const Meta2C& m = *a.m;
-    const int total = m.n_tiles * a.n_jobs;
-    const int per = (total + 7) / 8;
-    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (W >= total) return;
-    const int y = W / m.n_tiles;
-    const int2 tl = a.tiles[W - y * m.n_tiles];
-    const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
     const int n_w = m.n_w;
     const int nk = st_nk(s, t, n_w);
     const int o1 = abs(s - t), o2 = s + t;
     const int nA = m.nA[s], nB = m.nB[t];
     const size_t nn = m.n_nodes;
     const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
-    const int nact = a.n_act[y];
+    // this work item's node range [p_begin, p_end) (whole chunks)
+    const int nact_all = a.n_act[y];
+    const int span = ((nact_all + m.n_split - 1) / m.n_split + kNodeChunk - 1) / kNodeChunk * kNodeChunk;
+    const int p_begin = piece * span;
+    const int nact = min(nact_all, p_begin + span);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     // loader roles: row (column) lr of A (B), four consecutive nodes from kq;
     // threads below kWFields * kNodeChunk also load one node field
@@ -241,8 +240,17 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
         const int ids[kWFields] = {kFCos, kFSin, kFW, kFW + 1, kFW + 2, kFJ + o1, kFJ + o2};
         fid = ids[ffi];
     }
-    const int mt = wave & 1, nt = wave >> 1;
+    // this wave's weights and subtiles
+    const int kk0 = SPW == 4 ? wave * KPW : (wave & 1) * KPW;
+    const int mt0 = SPW == 4 ? 0 : (wave >> 1);
+    constexpr int NMT = SPW == 4 ? 2 : 1;   // row halves covered by the wave
     const int li = lane & 15, lk = lane >> 4;
+    // 16 x 16 subtiles wholly outside the block are skipped (wave-uniform)
+    bool okm[NMT], okn[2];
+#pragma unroll
+    for (int u = 0; u < NMT; ++u) okm[u] = a0 + (mt0 + u) * 16 < nA;
+    okn[0] = true;
+    okn[1] = b0 + 16 < nB;
 
     T ra[4], rb[4];
     double rf = 0.0;
@@ -256,12 +264,16 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
         if (ffi < kWFields) rf = (base + fk < nact) ? nd[(size_t)fid * nn + base + fk] : 0.0;
     };
 
-    dbl4 acc[kMaxK];
+    dbl4 acc[KPW][NMT][2];
 #pragma unroll
-    for (int i = 0; i < kMaxK; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < KPW; ++i)
+#pragma unroll
+        for (int u = 0; u < NMT; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) acc[i][u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    if (nact > 0) fetch(0);
-    for (int base = 0; base < nact; base += kNodeChunk) {
+    if (p_begin < nact) fetch(p_begin);
+    for (int base = p_begin; base < nact; base += kNodeChunk) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             As[kq + e][lr] = ra[e];
@@ -281,44 +293,115 @@ __global__ __launch_bounds__(256) void k_2c_contract(ContractArgs a) {
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
                 const int kr = ks * 4 + lk;
-                const double av = As[kr][mt * 16 + li], bv = Bs[kr][nt * 16 + li];
+                double av[NMT], bv[2];
 #pragma unroll
-                for (int kk = 0; kk < kMaxK; ++kk)
-                    if (kk < nk) acc[kk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av * wk[kr][kk], bv, acc[kk], 0, 0, 0);
+                for (int u = 0; u < NMT; ++u) av[u] = As[kr][(mt0 + u) * 16 + li];
+                bv[0] = Bs[kr][li];
+                bv[1] = Bs[kr][16 + li];
+#pragma unroll
+                for (int i = 0; i < KPW; ++i) {
+                    const double w = wk[kr][kk0 + i];
+#pragma unroll
+                    for (int u = 0; u < NMT; ++u) {
+                        if (!okm[u]) continue;
+                        const double aw = av[u] * w;
+                        acc[i][u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv[0], acc[i][u][0], 0, 0, 0);
+                        if (okn[1]) acc[i][u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv[1], acc[i][u][1], 0, 0, 0);
+                    }
+                }
             }
         } else {
-            flt4 c32[kMaxK];
+            flt4 c32[KPW][NMT][2];
 #pragma unroll
-            for (int kk = 0; kk < kMaxK; ++kk) c32[kk] = flt4{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < KPW; ++i)
+#pragma unroll
+                for (int u = 0; u < NMT; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) c32[i][u][v] = flt4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
                 const int kr = ks * 4 + lk;
-                const float av = (float)As[kr][mt * 16 + li], bv = (float)Bs[kr][nt * 16 + li];
+                float av[NMT], bv[2];
 #pragma unroll
-                for (int kk = 0; kk < kMaxK; ++kk)
-                    if (kk < nk)
-                        c32[kk] = __builtin_amdgcn_mfma_f32_16x16x4f32(av * (float)wk[kr][kk], bv, c32[kk], 0, 0, 0);
+                for (int u = 0; u < NMT; ++u) av[u] = (float)As[kr][(mt0 + u) * 16 + li];
+                bv[0] = (float)Bs[kr][li];
+                bv[1] = (float)Bs[kr][16 + li];
+#pragma unroll
+                for (int i = 0; i < KPW; ++i) {
+                    const float w = (float)wk[kr][kk0 + i];
+#pragma unroll
+                    for (int u = 0; u < NMT; ++u) {
+                        if (!okm[u]) continue;
+                        const float aw = av[u] * w;
+                        c32[i][u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv[0], c32[i][u][0], 0, 0, 0);
+                        if (okn[1]) c32[i][u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv[1], c32[i][u][1], 0, 0, 0);
+                    }
+                }
             }
             // chunk sums into the FP64 accumulators (register r keeps the FP32 layout)
 #pragma unroll
-            for (int kk = 0; kk < kMaxK; ++kk)
-                if (kk < nk)
+            for (int i = 0; i < KPW; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[kk][r] += (double)c32[kk][r];
+                for (int u = 0; u < NMT; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[i][u][v][r] += (double)c32[i][u][v][r];
         }
         __syncthreads();
     }
-    double* out = a.tmol + (size_t)y * m.n_tmol + m.st_off[s][t];
-    const int jj = b0 + nt * 16 + li;
+    double* out = a.tmol + ((size_t)y * m.n_split + piece) * m.n_tmol + m.st_off[s][t];
 #pragma unroll
-    for (int kk = 0; kk < kMaxK; ++kk) {
-        if (kk < nk) {
+    for (int i = 0; i < KPW; ++i) {
+        const int kk = kk0 + i;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = a0 + mt * 16 + (MIXED ? mfma_row_f32(r, lane) : mfma_row_f64(r, lane));
-                if (i < nA && jj < nB) out[((size_t)kk * nA + i) * nB + jj] = acc[kk][r];
+        for (int u = 0; u < NMT; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int jj = b0 + v * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ii = a0 + (mt0 + u) * 16 + (MIXED ? mfma_row_f32(r, lane) : mfma_row_f64(r, lane));
+                    if (kk < nk && ii < nA && jj < nB) out[((size_t)kk * nA + ii) * nB + jj] = acc[i][u][v][r];
+                }
             }
-        }
+    }
+}
+
+// One workgroup per (job, tile) with an XCD-aware order: consecutive
+// workgroup ids go to the eight XCDs in turn, and the work items of XCD x are
+// the x-th eighth of the job-major list, so the tiles of one job (which
+// stream the same operand rows) share an L2.  Per chunk of kNodeChunk nodes
+// the 32 rows of A, the 32 columns of B and the node fields of the weights
+// are loaded into registers one chunk ahead (their latency overlaps the MFMA
+// of the current chunk), then staged in LDS; the waves split the nk weights
+// and the four 16 x 16 subtiles as contract_tile describes and feed the MFMA
+// with (A w_k) and B.
+//
+// MIXED: the products run on v_mfma_f32_16x16x4f32 (operands in FP32,
+// accumulated in FP32 over the 32 nodes of a chunk) and each chunk's partial
+// sums are added to FP64 accumulators, so the FP32 accumulation error stays
+// that of a 32-term sum whatever the number of nodes.
+template <bool MIXED>
+__global__ __launch_bounds__(256, MIXED ? 2 : 3) void k_2c_contract(ContractArgs a) {
+    const Meta2C& m = *a.m;
+    const int per_job = m.n_tiles * m.n_split;
+    const int total = per_job * a.n_jobs;
+    const int per = (total + 7) / 8;
+    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (W >= total) return;
+    const int y = W / per_job;
+    const int rem = W - y * per_job;
+    const int piece = rem / m.n_tiles;
+    const int2 tl = a.tiles[rem - piece * m.n_tiles];
+    const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
+    __shared__ ContractLds<typename std::conditional<MIXED, float, double>::type> L;
+    switch (st_nk(s, t, m.n_w)) {
+        case 2: contract_tile<MIXED, 1, 2>(a, y, piece, s, t, a0, b0, L); break;
+        case 4: contract_tile<MIXED, 1, 4>(a, y, piece, s, t, a0, b0, L); break;
+        case 6: contract_tile<MIXED, 3, 2>(a, y, piece, s, t, a0, b0, L); break;
+        case 8: contract_tile<MIXED, 2, 4>(a, y, piece, s, t, a0, b0, L); break;
+        default: contract_tile<MIXED, 3, 4>(a, y, piece, s, t, a0, b0, L); break;
     }
 }
 
@@ -398,7 +481,7 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
     const int ma = ra / m.n_lT[la] - la, na = ra % m.n_lT[la];
     const int mb = rb / m.n_lP[lb] - lb, nb = rb % m.n_lP[lb];
     const int arad = m.radT_off[la] + na, brad = m.radP_off[lb] + nb;
-    const double* tm = a.tmol + (size_t)blockIdx.y * m.n_tmol;
+    const double* tm = a.tmol + (size_t)blockIdx.y * m.n_split * m.n_tmol;
     const int n_w = m.n_w;
     double acc[kMaxW][2];
     for (int w = 0; w < kMaxW; ++w) acc[w][0] = acc[w][1] = 0.0;
@@ -424,8 +507,12 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
             const size_t blk = (size_t)m.nA[s] * nBt;
             const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
             for (int w = 0; w < n_w; ++w) {
-                const double tc = base[(size_t)((order * 2 + 0) * n_w + w) * blk];
-                const double ts = base[(size_t)((order * 2 + 1) * n_w + w) * blk];
+                // partial sums of the node ranges, in range order
+                double tc = 0.0, ts = 0.0;
+                for (int q = 0; q < m.n_split; ++q) {
+                    tc += base[(size_t)q * m.n_tmol + (size_t)((order * 2 + 0) * n_w + w) * blk];
+                    ts += base[(size_t)q * m.n_tmol + (size_t)((order * 2 + 1) * n_w + w) * blk];
+                }
                 acc[w][0] += c * (pr * tc - pi * ts);
                 acc[w][1] += c * (pr * ts + pi * tc);
             }
@@ -772,7 +859,7 @@ hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, h
 }
 
 hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    const dim3 grid(8 * ((hm.n_tiles * n_jobs + 7) / 8)), block(256);
+    const dim3 grid(8 * ((hm.n_tiles * hm.n_split * n_jobs + 7) / 8)), block(256);
     if (hm.mixed)
         WPCCC_LAUNCH(ev, k_2c_contract<true>, grid, block, 0, st, a);
     else

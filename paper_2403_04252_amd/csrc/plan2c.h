@@ -19,6 +19,11 @@ namespace wpccc {
 constexpr int kMaxW = 3;          // weights: overlap, target potential, projectile potential
 constexpr int kNodeChunk = 32;    // spheroidal nodes per contraction chunk (8 MFMA k-steps of 4)
 constexpr int kTile = 32;         // rows (target) and columns (projectile) per contraction workgroup
+// node ranges per contraction tile: the work items of a launch differ in
+// their weight count (4 to 12) and node count, so several shorter items per
+// tile let the dispatcher balance them over the CUs (partial sums per range
+// are added in a fixed order when the blocks are assembled)
+constexpr int kContractSplit = 8;
 constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
 constexpr int kSlots2C = 3;
 // lane layout of the FP32 16x16x4 MFMA result: 1 if register r of lane l holds
@@ -57,6 +62,7 @@ struct Meta2C {
     int stT_off[kMaxL + 2], stP_off[kMaxL + 2];  // state offsets per l
     int n_lT[kMaxL + 1], n_lP[kMaxL + 1];
     int n_tiles;
+    int n_split;             // node ranges per contraction tile; tmol holds one partial sum per range
     // interpolated operands: row r of side T is (s, i) with s = block, i < nA[s]
     int rowsT, rowsP;                  // sum_s nA[s], sum_t nB[t]
     int rowT_off[kMaxL + 1], rowP_off[kMaxL + 1];
@@ -114,7 +120,7 @@ struct ContractArgs {
     const void* BT;
     const double* nodes;
     const int* n_act;
-    double* tmol;           // [job][n_tmol]
+    double* tmol;           // [job][n_split][n_tmol]: partial sums over the node ranges
 };
 
 struct AssembleArgs {
@@ -125,7 +131,7 @@ struct AssembleArgs {
     const double* vvec;
     const double* epsT;     // [NT]
     const double* epsP;     // [NP]
-    const double* tmol;     // [job][n_tmol]
+    const double* tmol;     // [job][n_split][n_tmol] (summed over the ranges)
     double2* S;             // [path][slot][N*N] column-major
     double2* LU;            // copy of S for the factorisation
     double2* H;             // [path][slot][N*N] row-major

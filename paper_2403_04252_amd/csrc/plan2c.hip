@@ -251,6 +251,7 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
         }
     m.n_tmol = off;
     m.n_tiles = (int)tiles.size();
+    m.n_split = kContractSplit;
     m.rowsT = m.rowsP = 0;
     for (int l = 0; l <= kMaxL; ++l) {
         m.rowT_off[l] = m.rowsT;
@@ -326,7 +327,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_nodes, J * m.n_fields * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_jst, J * 2 * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nact, J, tot))) return rc;
-    if ((rc = dev_alloc(&g.d_tmol, J * m.n_tmol, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_tmol, J * (size_t)m.n_split * m.n_tmol, tot))) return rc;
     if ((rc = dev_alloc(&g.d_rinfoT, riT.size(), tot))) return rc;
     if ((rc = dev_alloc(&g.d_rinfoP, riP.size(), tot))) return rc;
     if ((rc = dev_alloc_bytes(&g.d_AT, J * m.rowsT * (size_t)m.n_nodes * esz, tot))) return rc;
