@@ -200,12 +200,19 @@ constexpr int kWFields = 7;  // cos, sin, W_0..W_2, J_|s-t|, J_(s+t)
 // covers the two subtiles of row half mt = wave / 2 and kk0 = (wave % 2) KPW
 // (nk = 2 KPW).  One LDS read of an A value then serves 2 KPW products, one
 // of a B value KPW * SPW / 2, and one of a weight SPW.
+// LDS of a contraction workgroup.  As[node][row] and Bs[node][col] hold one
+// chunk of operands at a row pitch of kPitch elements with the row index
+// XOR-ed by 4 (node / 4): the MFMA reads (16 rows of 4 nodes per wave) and the
+// staging writes (8 rows of 8 node quads per wave) then spread over the 64
+// LDS banks with the fewest passes (pitch 40 for FP64, 48 for FP32).
 template <typename T>
 struct ContractLds {
-    T As[kNodeChunk][kTile], Bs[kNodeChunk][kTile];
+    static constexpr int kPitch = sizeof(T) == 8 ? 40 : 48;
+    T As[kNodeChunk][kPitch], Bs[kNodeChunk][kPitch];
     double fl[kWFields][kNodeChunk];
     double wk[kNodeChunk][kMaxK];
 };
+__device__ inline int lds_swz(int node) { return 4 * ((node >> 2) & 7); }
 
 template <bool MIXED, int KPW, int SPW>
 __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0,
@@ -276,8 +283,8 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     for (int base = p_begin; base < nact; base += kNodeChunk) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            As[kq + e][lr] = ra[e];
-            Bs[kq + e][lr] = rb[e];
+            As[kq + e][lr ^ lds_swz(kq + e)] = ra[e];
+            Bs[kq + e][lr ^ lds_swz(kq + e)] = rb[e];
         }
         if (ffi < kWFields) fl[ffi][fk] = rf;
         __syncthreads();
@@ -293,11 +300,12 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
                 const int kr = ks * 4 + lk;
+                const int sw = lds_swz(kr);
                 double av[NMT], bv[2];
 #pragma unroll
-                for (int u = 0; u < NMT; ++u) av[u] = As[kr][(mt0 + u) * 16 + li];
-                bv[0] = Bs[kr][li];
-                bv[1] = Bs[kr][16 + li];
+                for (int u = 0; u < NMT; ++u) av[u] = As[kr][((mt0 + u) * 16 + li) ^ sw];
+                bv[0] = Bs[kr][li ^ sw];
+                bv[1] = Bs[kr][(16 + li) ^ sw];
 #pragma unroll
                 for (int i = 0; i < KPW; ++i) {
                     const double w = wk[kr][kk0 + i];
@@ -321,11 +329,12 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 #pragma unroll
             for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
                 const int kr = ks * 4 + lk;
+                const int sw = lds_swz(kr);
                 float av[NMT], bv[2];
 #pragma unroll
-                for (int u = 0; u < NMT; ++u) av[u] = (float)As[kr][(mt0 + u) * 16 + li];
-                bv[0] = (float)Bs[kr][li];
-                bv[1] = (float)Bs[kr][16 + li];
+                for (int u = 0; u < NMT; ++u) av[u] = (float)As[kr][((mt0 + u) * 16 + li) ^ sw];
+                bv[0] = (float)Bs[kr][li ^ sw];
+                bv[1] = (float)Bs[kr][(16 + li) ^ sw];
 #pragma unroll
                 for (int i = 0; i < KPW; ++i) {
                     const float w = (float)wk[kr][kk0 + i];
