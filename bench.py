@@ -386,8 +386,8 @@ def two_centre_measure(args, steps, warmup, mixed=False):
     X[:, 0] = 1.0
     W.wpccc_plan_timing(plan, True)
     W.wpccc_propagate(plan, zs, X)
-    names = ["k_2c_contract", "k_2c_interp", "k_2c_nodes", "k_2c_assemble", "k_setup_batch", "k_2c_direct", "k_lu_panel",
-             "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve"]
+    names = ["k_2c_contract", "k_2c_reduce", "k_2c_interp", "k_2c_nodes", "k_2c_assemble", "k_setup_batch",
+             "k_2c_direct", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve"]
     kt = {}
     for nm in names:
         ms, n = W.wpccc_plan_kernel_time(plan, nm)

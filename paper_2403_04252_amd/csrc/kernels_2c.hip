@@ -414,6 +414,18 @@ __global__ __launch_bounds__(256, MIXED ? 2 : 3) void k_2c_contract(ContractArgs
     }
 }
 
+// Sum of the node-range partial sums of the contraction into range 0, in
+// range order: tmol[job][0][e] = ((T_0 + T_1) + T_2) + ...; grid: x over
+// n_tmol / 256, y = job.
+__global__ __launch_bounds__(256) void k_2c_reduce(double* __restrict__ tmol, int n_tmol, int n_split) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_tmol) return;
+    double* t = tmol + (size_t)blockIdx.y * n_split * n_tmol + e;
+    double acc = t[0];
+    for (int q = 1; q < n_split; ++q) acc += t[(size_t)q * n_tmol];
+    t[0] = acc;
+}
+
 // Wigner d^l_{mq}(theta) by Wigner's sum (convention d^1_{10} = -sin(theta)/sqrt 2).
 __device__ double wigner_d(int l, int mm, int q, double c, double s) {
     double fac[2 * kMaxL + 2];
@@ -516,12 +528,8 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
             const size_t blk = (size_t)m.nA[s] * nBt;
             const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
             for (int w = 0; w < n_w; ++w) {
-                // partial sums of the node ranges, in range order
-                double tc = 0.0, ts = 0.0;
-                for (int q = 0; q < m.n_split; ++q) {
-                    tc += base[(size_t)q * m.n_tmol + (size_t)((order * 2 + 0) * n_w + w) * blk];
-                    ts += base[(size_t)q * m.n_tmol + (size_t)((order * 2 + 1) * n_w + w) * blk];
-                }
+                const double tc = base[(size_t)((order * 2 + 0) * n_w + w) * blk];
+                const double ts = base[(size_t)((order * 2 + 1) * n_w + w) * blk];
                 acc[w][0] += c * (pr * tc - pi * ts);
                 acc[w][1] += c * (pr * ts + pi * tc);
             }
@@ -873,6 +881,12 @@ hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_job
         WPCCC_LAUNCH(ev, k_2c_contract<true>, grid, block, 0, st, a);
     else
         WPCCC_LAUNCH(ev, k_2c_contract<false>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_2c_reduce(double* tmol, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    if (hm.n_split < 2) return hipSuccess;
+    WPCCC_LAUNCH(ev, k_2c_reduce, dim3((hm.n_tmol + 255) / 256, n_jobs), dim3(256), 0, st, tmol, hm.n_tmol, hm.n_split);
     return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ struct AssembleArgs {
     const double* vvec;
     const double* epsT;     // [NT]
     const double* epsP;     // [NP]
-    const double* tmol;     // [job][n_split][n_tmol] (summed over the ranges)
+    const double* tmol;     // [job][n_split][n_tmol]: range 0 holds the sum (k_2c_reduce)
     double2* S;             // [path][slot][N*N] column-major
     double2* LU;            // copy of S for the factorisation
     double2* H;             // [path][slot][N*N] row-major
@@ -202,6 +202,8 @@ struct Stage2CArgs {
 hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+// adds the node-range partial sums of tmol into range 0 (nothing when n_split is 1)
+hipError_t launch_2c_reduce(double* tmol, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_assemble(const AssembleArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_setup_batch(const SetupBatchArgs& a, const Meta& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});

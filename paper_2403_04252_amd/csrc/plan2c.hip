@@ -439,6 +439,8 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.n_act = g.d_nact;
         a.tmol = g.d_tmol;
         if ((rc = timed(p, k2cContract, [&](const LaunchEv& ev) { return launch_2c_contract(a, g.m, nj, st, ev); }))) return rc;
+        if ((rc = timed(p, k2cReduce, [&](const LaunchEv& ev) { return launch_2c_reduce(g.d_tmol, g.m, nj, st, ev); })))
+            return rc;
     }
     {
         AssembleArgs a;
