@@ -711,12 +711,16 @@ __global__ __launch_bounds__(256) void k_2c_hu(Stage2CArgs a) {
 }
 
 constexpr int kSolveBlock = 32;
+// threads of a k_2c_solve workgroup (one per path): the block updates are
+// matrix-vector products over up to N rows, so more threads keep more LU
+// loads in flight on the path's CU
+constexpr int kSolveThreads = 1024;
 
 // y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update; one workgroup per
 // path.  The triangular solves go by blocks of 32 rows: the diagonal block is
 // staged in LDS and solved by one wave with lane shuffles, then all waves
 // update the rows below (above) it from the column-major factors.
-__global__ __launch_bounds__(256) void k_2c_solve(Stage2CArgs a) {
+__global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
     extern __shared__ double2 ys[];      // [N]
     __shared__ double2 blk[kSolveBlock][kSolveBlock + 1];
     const int pl = blockIdx.x;
@@ -749,6 +753,7 @@ __global__ __launch_bounds__(256) void k_2c_solve(Stage2CArgs a) {
         __syncthreads();
         for (int i = kb + nbk + tid; i < N; i += blockDim.x) {
             double re = 0.0, im = 0.0;
+#pragma unroll 8
             for (int c = 0; c < nbk; ++c) {
                 const double2 l = LU[i + (size_t)(kb + c) * N], x = ys[kb + c];
                 re += l.x * x.x - l.y * x.y;
@@ -787,6 +792,7 @@ __global__ __launch_bounds__(256) void k_2c_solve(Stage2CArgs a) {
         __syncthreads();
         for (int i = tid; i < kb; i += blockDim.x) {
             double re = 0.0, im = 0.0;
+#pragma unroll 8
             for (int c = 0; c < nbk; ++c) {
                 const double2 uu = LU[i + (size_t)(kb + c) * N], x = ys[kb + c];
                 re += uu.x * x.x - uu.y * x.y;
@@ -914,7 +920,7 @@ hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const
 }
 
 hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_2c_solve, dim3(n_paths), dim3(256), a.N * sizeof(double2), st, a);
+    WPCCC_LAUNCH(ev, k_2c_solve, dim3(n_paths), dim3(kSolveThreads), a.N * sizeof(double2), st, a);
     return hipGetLastError();
 }
 
