@@ -235,6 +235,27 @@ def test_stage_rows_variants_agree(large):
         assert np.abs(outs[rows] - outs[8]).max() <= 1e-13
 
 
+def test_large_l_basis_parity():
+    """l_max = 6 (multipoles to 12, Pbar_12^mu, 13 values of m' per output
+    row, angular factors of 13 x 252 per l' block): two paths, 10 steps,
+    against the oracle.  Larger l_max is refused with WPCCC_ENOTSUP: the
+    angular factors of the largest l' block (21 x 946 at l_max = 10) no
+    longer fit the stage workgroup's LDS."""
+    rec = WL.Recipe(2, 6, 1, 2.0, 300, 60.0)
+    lb, ob = lib_basis(rec), oracle_basis(rec)
+    w = WL.reduced(WL.single_centre_batched(), n_paths=2, n_steps=10)
+    print("l_max = 6 basis, 2 paths x 10 steps", flush=True)
+    X, P, _ = _propagate_gpu(lb, w.b, w.v, w.zgrid)
+    for j in range(2):
+        Xo = propagate_one_centre(ob, w.b[j], w.v[j], w.zgrid)
+        assert np.abs(X[j] - Xo).max() <= 1e-12, (j, np.abs(X[j] - Xo).max())
+        assert prob_ok(P[j], probabilities(Xo)).all()
+    big = lib_basis(WL.Recipe(2, 10, 1, 2.0, 300, 60.0))
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create(big, [1.0], [1.0])
+    assert e.value.code == -6
+
+
 def test_stage_rows_limit():
     """Every output of a stage workgroup needs a lane of the phase-3
     reduction: rows x (2 l_max + 1) <= 256, so 16 rows are refused for

@@ -234,3 +234,38 @@ def test_2c_mixed_precision(small_run, bases):
         d = np.abs(P.cpu().numpy()[j, :N] - Po)
         assert np.all((d <= 1e-6) | (d <= 1e-4 * Po)), (j, d.max())
         print(f"  path {j}: mixed max|dP| {d.max():.2e}", flush=True)
+
+
+def test_2c_step_at_large_n():
+    """One RK4 step at N = 924 (462 states per centre: ten 16-column LU panels
+    short of the 1024-state limit of the LU kernels, 29 solve blocks) against
+    numpy applied to the device's own S and H at z, z + h/2 and z + h: the LU,
+    the solves and the RK4 update at a size the oracle cannot reach in
+    seconds.  |dX| <= 1e-10 (unit-norm X; S is an overlap matrix close to I)."""
+    rec = WL.Recipe(6, 3, 25, 3.0, 600, 60.0)
+    lb = lib_basis(rec)
+    b, v, z, h = 1.5, 1.0, -3.0, 0.1
+    plan = W.wpccc_plan_create_2c([lb], [lb], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=48, n_tau=64)
+    N, NT = W.wpccc_plan_path_info(plan, 0)
+    print(f"2C one step at N = {N}", flush=True)
+    assert N == 924 and NT == 462
+    rng = np.random.default_rng(11)
+    x0 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    x0 /= np.linalg.norm(x0)
+    X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[0, :N] = torch.as_tensor(x0, device="cuda")
+    W.wpccc_step(plan, X, z, h)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    Ms = []
+    for zz in (z, z + 0.5 * h, z + h):
+        S, H = gpu_matrices(plan, 0, zz)
+        Ms.append(-1j / v * np.linalg.solve(S, H))
+    k1 = Ms[0] @ x0
+    k2 = Ms[1] @ (x0 + 0.5 * h * k1)
+    k3 = Ms[1] @ (x0 + 0.5 * h * k2)
+    k4 = Ms[2] @ (x0 + h * k3)
+    x1 = x0 + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    err = np.abs(X.cpu().numpy()[0, :N] - x1).max()
+    print(f"  max |dX| {err:.2e}", flush=True)
+    assert err <= 1e-10
