@@ -251,6 +251,18 @@ def main():
         del plan_seq
 
     copy_calibration(torch, args.copy_calibration)
+    # sustained HBM rate of a plain copy (torch elementwise, 1 GiB read + 1 GiB written)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    roof["measured_copy_GBs"] = 5 * 2 * src.numel() * 8 / (time.perf_counter() - t0) / 1e9
+    roof["frac_of_measured_copy"] = roof["achieved"] / roof["measured_copy_GBs"]
+    del src, dst
 
     cpu = None
     prob_err = None
@@ -413,10 +425,14 @@ def two_centre_measure(args, steps, warmup, mixed=False):
     c_ms = kt["k_2c_contract"]["total_ms"]
     achieved = fl / (c_ms * 1e-3) / 1e12
     peak = FP32_MFMA_PEAK_TFLOPS if mixed else FP64_VECTOR_PEAK_TFLOPS
+    # sustained rate of back-to-back independent 16x16x4 MFMAs on this device
+    ceil64, ceil32 = W.wpccc_measure_mfma()
+    ceiling = ceil32 if mixed else ceil64
     roof = {"kernel": "k_2c_contract", "bound": "mfma", "achieved": achieved,
             "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": None, "avg_launch_us": c_ms / max(kt["k_2c_contract"]["launches"], 1) * 1e3,
-            "launches": kt["k_2c_contract"]["launches"], "algorithmic_flops_total": fl}
+            "launches": kt["k_2c_contract"]["launches"], "algorithmic_flops_total": fl,
+            "measured_mfma_ceiling": ceiling, "frac_of_measured_ceiling": achieved / ceiling}
     lu_fl = 0
     for j in range(n_traj):
         N = 2 * sum((2 * l + 1) * n for l, n in enumerate(n_per_l(w.targets[w.set_of[j]])))

@@ -261,7 +261,7 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Diagnostics: per-kernel device time with HIP events.                      */
+/* Diagnostics: per-kernel device time with HIP events; device ceilings.    */
 /* ------------------------------------------------------------------------ */
 
 /* enable != 0: from now on every kernel launch of this plan is bracketed by a
@@ -276,6 +276,14 @@ int wpccc_plan_timing(wpccc_plan_t plan, int enable);
  * Errors: WPCCC_EINVAL (unknown kernel name). */
 int wpccc_plan_kernel_time(wpccc_plan_t plan, const char* kernel, double* total_ms,
                            long long* launches);
+
+/* Sustained matrix-core rates of the current device, measured with
+ * back-to-back independent v_mfma_f64_16x16x4f64 (tflops_f64) and
+ * v_mfma_f32_16x16x4f32 (tflops_f32) on every CU (four workgroups of four
+ * waves each, eight accumulators per wave; about 40 ms on `stream`, which is
+ * synchronised).  The ceiling the contraction kernels can reach, next to the
+ * published peaks.  Either pointer may be NULL.  Errors: WPCCC_EHIP. */
+int wpccc_measure_mfma(double* tflops_f64, double* tflops_f32, void* stream);
 
 #ifdef __cplusplus
 }

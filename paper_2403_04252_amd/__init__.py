@@ -20,7 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
-    "wpccc_plan_stage_launch", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
+    "wpccc_plan_stage_launch", "wpccc_measure_mfma", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +107,7 @@ def load_library():
         "wpccc_plan_stage_launch": ([vp, pi], i),
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
+        "wpccc_measure_mfma": ([pd, pd, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -346,3 +347,10 @@ def wpccc_plan_kernel_time(plan: Plan, kernel: str):
     _check(load_library().wpccc_plan_kernel_time(plan.handle, kernel.encode(), ctypes.byref(ms),
                                                  ctypes.byref(n)))
     return ms.value, n.value
+
+
+def wpccc_measure_mfma(stream=None):
+    """Sustained (FP64, FP32) 16x16x4 MFMA rates of the current device in TFLOP/s."""
+    f64, f32 = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().wpccc_measure_mfma(ctypes.byref(f64), ctypes.byref(f32), _stream_ptr(stream)))
+    return f64.value, f32.value

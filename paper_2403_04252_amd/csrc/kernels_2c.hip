@@ -936,3 +936,78 @@ hipError_t launch_transpose_copy(const double2* src, double2* dst, int N, hipStr
 }
 
 }  // namespace wpccc
+
+// ---------------------------------------------------------------------------
+// Sustained matrix-core rate: every wave issues iters x 8 independent MFMAs
+// (eight accumulators, so no MFMA waits for another's result).
+namespace wpccc {
+namespace {
+
+template <bool F64>
+__global__ __launch_bounds__(256) void k_mfma_rate(double* out, int iters) {
+    const double a = 1.0 + threadIdx.x * 1e-9, b = 1.0 - threadIdx.x * 1e-9;
+    double s = 0.0;
+    if (F64) {
+        dbl4 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    } else {
+        flt4 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    }
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;   // keeps the products live
+}
+
+}  // namespace
+
+hipError_t measure_mfma(double* tf64, double* tf32, hipStream_t st) {
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int grid = 4 * n_cu, iters = 8000;
+    double* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipMalloc(&out, (size_t)grid * 256 * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const double flops = (double)grid * 4 * iters * 8 * 2048.0;  // 4 waves, 8 MFMAs of 16 x 16 x 4 x 2
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        for (int f64 = 1; f64 >= 0 && e == hipSuccess; --f64) {
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) {
+                if (f64)
+                    hipLaunchKernelGGL(k_mfma_rate<true>, dim3(grid), dim3(256), 0, st, out, iters);
+                else
+                    hipLaunchKernelGGL(k_mfma_rate<false>, dim3(grid), dim3(256), 0, st, out, iters);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && pass == 1) {   // pass 0 warms the clocks
+                double* dst = f64 ? tf64 : tf32;
+                if (dst) *dst = flops / ((double)ms * 1e-3) / 1e12;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (out) (void)hipFree(out);
+    return e;
+}
+
+}  // namespace wpccc

@@ -272,6 +272,10 @@ inline int dev_alloc(T** p, size_t count, long long& total) {
 }
 int launched(hipError_t e, const char* what);
 
+// sustained FP64 / FP32 16x16x4 MFMA rates of the current device in TFLOP/s,
+// synchronising st (kernels_2c.hip)
+hipError_t measure_mfma(double* tflops_f64, double* tflops_f32, hipStream_t st);
+
 // two-centre plan (plan2c.hip)
 struct Plan2C;
 int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles, int n_sets, int n_traj,

@@ -489,6 +489,16 @@ extern "C" {
 
 const char* wpccc_last_error(void) { return g_err.c_str(); }
 
+int wpccc_measure_mfma(double* tflops_f64, double* tflops_f32, void* stream) {
+    clear_error();
+    const hipError_t e = measure_mfma(tflops_f64, tflops_f32, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("wpccc_measure_mfma: %s", hipGetErrorString(e));
+        return WPCCC_EHIP;
+    }
+    return WPCCC_OK;
+}
+
 const char* wpccc_version(void) { return "0.3.0"; }
 
 int wpccc_basis(const wpccc_basis_spec* spec, wpccc_basis_t* out) {
