@@ -3,7 +3,10 @@
 // One RK4 stage of Algorithm 1 for every path of the batch is one launch of
 // k_stage: from (b, z, v) and the basis tables it forms, per workgroup, the
 // part of M(z) = -(i/v) Zp D_T(b, z) it needs and applies it to the stage
-// input, then writes the RK4 combination of that stage.  D_T (Eq. D1) is
+// input, then writes the RK4 combination of that stage.  k_chunk runs the
+// same stages for up to 64 steps in one persistent launch (per-path
+// barriers between stages); k_apply applies M or its derivatives for the
+// adjoint.  D_T (Eq. D1) is
 // never formed: its (l'm', lm) block is sum_lambda c Pbar_lambda^|m'-m| F_lambda
 // with F_lambda the N_l' x N_l matrix of Eq. D2 radial integrals, so
 //   y_{l'm'}[n'] = sum_{l, lambda, q} G_l'[m'][(l,lambda), q] sum_n F_l'[n'][(l,lambda), n] x'_{l q n}
@@ -465,7 +468,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
 }
 
-// grid: x = (l', chunk of ROWS rows) pairs in l' order, y = path.
+// k_apply's grid: x = (l', chunk of ROWS rows) pairs in l' order, y = path.
 template <int KIND, int ROWS>
 __device__ void stage_entry(const StageArgs& a, char* smem) {
     const Meta& m = *a.meta;

@@ -18,7 +18,7 @@ constexpr int kStageThreads = 256;
 // dynamic LDS a stage workgroup may request: the CU's 160 KB less room for
 // the kernels' few static LDS words
 constexpr int kMaxDynLds = 160 * 1024 - 1024;
-constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and k_stage's default)
+constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and the untimed default of k_stage)
 // row tilings the stage kernels are built for (X-macro over the values)
 #define WPCCC_STAGE_ROWS(X) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
 constexpr int kStageRowsList[] = {4, 5, 6, 7, 8, 10, 12, 16};
