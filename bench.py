@@ -131,6 +131,7 @@ def main():
                     help="c2: skip the short two-centre measurement added to the output line")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing line")
     ap.add_argument("--stage-rows", type=int, default=0,
                     help="c2: rows per workgroup of the RK4 stage kernels (0: chosen by timing at plan creation)")
     ap.add_argument("--stage-launch", choices=["auto", "stages", "persistent"], default="auto",
@@ -321,6 +322,8 @@ def main():
         "plain_fp64_sequential": seq,
         "kernel_times": kernel_times,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_measure(torch, W, WL)
     if not args.no_2c:
         # secondary: a few batched two-centre steps, FP64 and mixed
         del plan
@@ -331,6 +334,42 @@ def main():
             out["two_centre"]["mixed" if mixed else "fp64"] = {
                 k: r[k] for k in ("value", "unit", "ms_per_step", "roofline", "lu", "config")}
     print(json.dumps(out), flush=True)
+
+
+def adjoint_measure(torch, W, WL):
+    """Gradients of a weighted sum of final probabilities with respect to the
+    screened-potential parameters and b (16 paths, N = 86, 800 steps): the
+    reverse sweep's wall time against the forward propagation's."""
+    wl = WL.adjoint_batch()
+    rec = wl.basis
+    lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+    plan = W.wpccc_plan_create(lb, wl.b, wl.v, model_a=wl.a, model_c=wl.c)
+    N = plan.n_states
+    X0 = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X0[:, 0] = 1.0
+    Xf = X0.clone()
+    W.wpccc_propagate(plan, wl.zgrid, Xf)        # warm-up and the final state
+    torch.cuda.synchronize()
+    Xf.copy_(X0)
+    t0 = time.perf_counter()
+    W.wpccc_propagate(plan, wl.zgrid, Xf)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    gX = torch.zeros_like(X0)
+    gX[:, :N] = torch.as_tensor(wl.weights, device="cuda") * Xf[:, :N]
+    grad = torch.empty((plan.n_traj, 3), dtype=torch.float64, device="cuda")
+    X = torch.empty_like(X0)
+    W.wpccc_adjoint(plan, wl.zgrid, X0, gX, grad, X)   # warm-up (workspace allocation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W.wpccc_adjoint(plan, wl.zgrid, X0, gX, grad, X)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    W.wpccc_plan_status(plan)
+    steps = wl.zgrid.size - 1
+    return {"workload": "p+H 1C N=86 screened potential, 16 b, 800 steps (gradients in a, c, b)",
+            "forward_ms": t_fwd * 1e3, "adjoint_ms": t_adj * 1e3, "adjoint_over_forward": t_adj / t_fwd,
+            "value": plan.n_traj * steps / t_adj, "unit": "trajectory-steps/s (forward + reverse sweep)"}
 
 
 def n_per_l(rec):

@@ -131,7 +131,8 @@ typedef struct {
     int n_tau;      /* 2C: Gauss-Legendre nodes in tau (0 means 512) */
     double model_a; /* 1C: screened target potential V(r) = -(1 + a e^{-c r})/r on the */
     double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
-    int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: ~sqrt(steps)) */
+    int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: every step
+                             when all states take at most 256 MiB, else ~sqrt(steps)) */
     int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 5,
                        6, 7, 8, 10, 12 or 16, with rows x (2 l_max + 1) <= 256
                        (WPCCC_EINVAL otherwise); 0: chosen at plan creation by

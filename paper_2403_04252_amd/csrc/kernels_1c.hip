@@ -794,9 +794,9 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
 }
 
 // Operator application with the grid of k_stage (see StageArgs).
-__global__ __launch_bounds__(kStageThreads) void k_apply(StageArgs a) {
+__global__ __launch_bounds__(kStageThreads) void k_apply(ApplyArgs a) {
     extern __shared__ double2 smem2[];
-    stage_entry<1, kRowsPerBlock>(a, reinterpret_cast<char*>(smem2));
+    stage_entry<1, kRowsPerBlock>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
 }
 
 // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] += 2 gamma Re(dv^H dM/dc u),
@@ -1064,9 +1064,9 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& hm, int smem, int rows, 
     return e;
 }
 
-hipError_t launch_apply(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st,
+hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& hm, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_apply, dim3(hm.n_chunks, n_traj_launch), dim3(kStageThreads), smem, st, a);
+    WPCCC_LAUNCH(ev, k_apply, dim3(hm.n_chunks, n_traj_launch, n_ops), dim3(kStageThreads), smem, st, a);
     return hipGetLastError();
 }
 

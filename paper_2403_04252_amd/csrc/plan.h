@@ -131,6 +131,12 @@ struct StageArgs {
 // that the polls of different paths do not contend for one memory line
 constexpr int kBarStride = 64;
 
+// Up to three operator applications of one k_apply launch (grid z selects
+// one; they share the launch's point slot and run side by side).
+struct ApplyArgs {
+    StageArgs s[3];
+};
+
 // Persistent form of a propagation chunk (k_chunk): every workgroup of the
 // stage grid stays resident for all steps of the chunk and the workgroups of
 // one path meet at a barrier (bar[path], counted with agent-scope atomics)
@@ -303,7 +309,7 @@ hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const do
                                   const LaunchEv& ev = LaunchEv{});
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
                                 double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
-hipError_t launch_apply(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
+hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev = LaunchEv{});
 hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st);
 // *chunk = value (reset) or *chunk += 1 (advance), one thread

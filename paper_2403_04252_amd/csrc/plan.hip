@@ -214,9 +214,9 @@ int forward_step(wpccc_plan_s* p, double2* X, double z, double h, hipStream_t st
 }
 
 // out = alpha O u + beta w and/or grad[.][gslot] += 2 gamma Re(dv^H O u), O at point slot pt.
-int enqueue_apply(wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha, const double2* w,
-                  double beta, double2* out, const double2* dv, double gamma, int gslot, double* grad,
-                  hipStream_t st) {
+StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha,
+                     const double2* w, double beta, double2* out, const double2* dv, double gamma, int gslot,
+                     double* grad) {
     StageArgs a{};
     a.meta = p->c.d_meta;
     a.tb = p->tables();
@@ -237,16 +237,29 @@ int enqueue_apply(wpccc_plan_s* p, int pt, double z, int deriv, const double2* u
     a.dv = dv;
     a.grad = grad;
     a.gslot = gslot;
-    return launched(launch_apply(a, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
+    return a;
 }
 
-// grad += 2 gamma Re(dv^H dM/dtheta u) for theta = a, c, b at point slot pt.
-int enqueue_grad_terms(wpccc_plan_s* p, int pt, double z, const double2* u, const double2* dv, double gamma,
-                       double* grad, hipStream_t st) {
-    int rc;
+int enqueue_apply(wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha, const double2* w,
+                  double beta, double2* out, const double2* dv, double gamma, int gslot, double* grad,
+                  hipStream_t st) {
+    ApplyArgs a{};
+    a.s[0] = apply_args(p, pt, z, deriv, u, alpha, w, beta, out, dv, gamma, gslot, grad);
+    return launched(launch_apply(a, 1, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
+}
+
+// One reverse stage at point slot pt: out = alpha M v (M^H v = -M v), and
+// grad += 2 gamma Re(v^H dM/dtheta u) for theta = a, c, b.  The three
+// applications (M v, the two b-derivative terms on u) share one launch;
+// k_model_dot then adds the a and c terms and the b shares.
+int enqueue_reverse_stage(wpccc_plan_s* p, int pt, double z, const double2* v, double alpha, double2* out,
+                          const double2* u, double gamma, double* grad, hipStream_t st) {
+    ApplyArgs a{};
+    a.s[0] = apply_args(p, pt, z, 0, v, alpha, nullptr, 0.0, out, nullptr, 0.0, 0, nullptr);
     for (int d = 1; d <= 2; ++d)
-        if ((rc = enqueue_apply(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, dv, gamma, d - 1, p->d_gpart, st)))
-            return rc;
+        a.s[d] = apply_args(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, v, gamma, d - 1, p->d_gpart);
+    int rc = launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
+    if (rc) return rc;
     ModelArgs m{};
     m.meta = p->c.d_meta;
     m.tb = p->tables();
@@ -257,7 +270,7 @@ int enqueue_grad_terms(wpccc_plan_s* p, int pt, double z, const double2* u, cons
     m.va = p->d_va;
     m.vc = p->d_vc;
     m.u = u;
-    m.dv = dv;
+    m.dv = v;
     m.gamma = gamma;
     m.grad = grad;
     m.gpart = p->d_gpart;
@@ -374,6 +387,7 @@ int propagate_graph(wpccc_plan_s* p, const double* zg, int n_full, double2* X, h
 // traffic of a real step), once to warm up and kTunePasses times timed; the
 // candidate with the fastest pass is kept.
 constexpr int kTuneSteps = 8;
+constexpr double kAdjointStoreAll = 256.0 * (1 << 20);  // bytes of stored states below which nothing is recomputed
 constexpr int kTunePasses = 3;
 
 int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hipStream_t st) {
@@ -942,7 +956,11 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
         }
     hipStream_t st = (hipStream_t)stream;
     const int n_steps = n_points - 1;
-    int K = plan->ckpt_every > 0 ? plan->ckpt_every : (int)std::ceil(std::sqrt((double)n_steps));
+    // default: every state when they take at most kAdjointStoreAll bytes (no
+    // recomputation), else about sqrt(n_steps) checkpoints
+    const double all_bytes = (double)n_steps * plan->n_traj * plan->n_pad * sizeof(double2);
+    int K = plan->ckpt_every > 0 ? plan->ckpt_every
+                                 : (all_bytes <= kAdjointStoreAll ? 1 : (int)std::ceil(std::sqrt((double)n_steps)));
     K = std::max(1, std::min(K, n_steps));
     const int n_ck = (n_steps + K - 1) / K;
     const size_t V = (size_t)plan->n_traj * plan->n_pad;
@@ -1005,24 +1023,17 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
             if ((rc = enqueue_apply(plan, 1, zm, 0, plan->d_u3, h, x, 1.0, plan->d_u4, nullptr, 0.0, 0, nullptr, st)))
                 return rc;
             // stage 4: mu4 = h/6 lambda, nu4 = M3^H mu4 = -M3 mu4
-            if ((rc = enqueue_apply(plan, 2, z1, 0, lam, -h / 6.0, nullptr, 0.0, nu[3], nullptr, 0.0, 0, nullptr, st)))
+            if ((rc = enqueue_reverse_stage(plan, 2, z1, lam, -h / 6.0, nu[3], plan->d_u4, h / 6.0, grad, st)))
                 return rc;
-            if ((rc = enqueue_grad_terms(plan, 2, z1, plan->d_u4, lam, h / 6.0, grad, st))) return rc;
             // stage 3: mu3 = h/3 lambda + h nu4
             if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {h, nu[3]}}, st))) return rc;
-            if ((rc = enqueue_apply(plan, 1, zm, 0, mu, -1.0, nullptr, 0.0, nu[2], nullptr, 0.0, 0, nullptr, st)))
-                return rc;
-            if ((rc = enqueue_grad_terms(plan, 1, zm, plan->d_u3, mu, 1.0, grad, st))) return rc;
+            if ((rc = enqueue_reverse_stage(plan, 1, zm, mu, -1.0, nu[2], plan->d_u3, 1.0, grad, st))) return rc;
             // stage 2: mu2 = h/3 lambda + h/2 nu3
             if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {0.5 * h, nu[2]}}, st))) return rc;
-            if ((rc = enqueue_apply(plan, 1, zm, 0, mu, -1.0, nullptr, 0.0, nu[1], nullptr, 0.0, 0, nullptr, st)))
-                return rc;
-            if ((rc = enqueue_grad_terms(plan, 1, zm, plan->d_u2, mu, 1.0, grad, st))) return rc;
+            if ((rc = enqueue_reverse_stage(plan, 1, zm, mu, -1.0, nu[1], plan->d_u2, 1.0, grad, st))) return rc;
             // stage 1: mu1 = h/6 lambda + h/2 nu2
             if ((rc = enqueue_combine(plan, mu, {{h / 6.0, lam}, {0.5 * h, nu[1]}}, st))) return rc;
-            if ((rc = enqueue_apply(plan, 0, z0, 0, mu, -1.0, nullptr, 0.0, nu[0], nullptr, 0.0, 0, nullptr, st)))
-                return rc;
-            if ((rc = enqueue_grad_terms(plan, 0, z0, x, mu, 1.0, grad, st))) return rc;
+            if ((rc = enqueue_reverse_stage(plan, 0, z0, mu, -1.0, nu[0], x, 1.0, grad, st))) return rc;
             // lambda_n = lambda_(n+1) + nu1 + nu2 + nu3 + nu4
             if ((rc = enqueue_combine(plan, lam, {{1.0, lam}, {1.0, nu[0]}, {1.0, nu[1]}, {1.0, nu[2]}, {1.0, nu[3]}},
                                       st)))
