@@ -131,8 +131,9 @@ typedef struct {
     int n_tau;      /* 2C: Gauss-Legendre nodes in tau (0 means 512) */
     double model_a; /* 1C: screened target potential V(r) = -(1 + a e^{-c r})/r on the */
     double model_c; /*     fixed basis: DeltaV = -a e^{-c r}/r is added to D_T (a = 0: none) */
-    int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: every step
-                             when all states take at most 256 MiB, else ~sqrt(steps)) */
+    int checkpoint_every; /* wpccc_adjoint: steps between stored states (0: no
+                             checkpoints, every state and stage input of the grid
+                             kept, when they take at most 256 MiB; else ~sqrt(steps)) */
     int stage_rows; /* 1C: output rows per workgroup of the RK4 stage kernel, 4, 5,
                        6, 7, 8, 10, 12 or 16, with rows x (2 l_max + 1) <= 256
                        (WPCCC_EINVAL otherwise); 0: chosen at plan creation by
@@ -247,7 +248,8 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
 /* Gradients of a real loss of the final amplitudes (1C; Algorithm 1 on the
  * given grid differentiated exactly, reverse mode): the forward propagation
  * from X0 stores the state every `checkpoint_every` steps, the reverse sweep
- * recomputes each segment and runs the adjoint of every RK4 step,
+ * recomputes each segment (keeping its states and RK4 stage inputs) and runs
+ * the adjoint of every RK4 step,
  *   lambda_n = A_n^H lambda_(n+1),
  *   dL/dtheta += 2 Re(mu_k^H (dM/dtheta) u_k)  over the four stages,
  * with M^H = -M (Hermitian D_T) and dM/dtheta for theta = a, c (model

@@ -186,7 +186,7 @@ __device__ inline void rk4_update(const StageArgs& a, size_t oi, double2 K, doub
     } else {
         const double2 xn = rk4_accumulate(4, x0, xa, K, h);
         if (!isfinite(xn.x) || !isfinite(xn.y)) atomicOr(a.flag, 1);
-        a.X[oi] = xn;
+        (a.Xout ? a.Xout : a.X)[oi] = xn;
     }
 }
 
@@ -327,14 +327,27 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             lv[i] = cl[idx % nV];
         }
     }
+    // stage input (KIND 1: v = cu1 u_in + cu2 u_in2)
     const double2* u = a.u_in + (size_t)j * a.n_pad;
+    const double2* u2 = (KIND == 1 && a.u_in2) ? a.u_in2 + (size_t)j * a.n_pad : nullptr;
+    auto load_u = [&](int idx) -> double2 {
+        if (KIND == 0) return u[idx];
+        const double2 x = u[idx];
+        double2 r = make_double2(a.cu1 * x.x, a.cu1 * x.y);
+        if (u2) {
+            const double2 y = u2[idx];
+            r.x += a.cu2 * y.x;
+            r.y += a.cu2 * y.y;
+        }
+        return r;
+    };
     double2 uv[kXBatch];
     int sv[kXBatch];
 #pragma unroll
     for (int i = 0; i < kXBatch; ++i) {
         const int idx = tid + i * B;
         if (idx < N) {
-            uv[i] = u[idx];
+            uv[i] = load_u(idx);
             sv[i] = T.st_rad[idx] | (T.st_xs[idx] << 16);
         }
     }
@@ -368,8 +381,23 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             if (a.stage < 4) x0 = a.X[oi];
             if (a.stage > 1) xa = a.Xacc[oi];
         } else {
-            if (a.w) x0 = a.w[oi];
-            if (a.dv) xa = a.dv[oi];
+            // x0 = sum of the added vectors, xa = d = cd1 dv + cd2 dv2
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (a.w[k]) {
+                    const double2 t = a.w[k][oi];
+                    x0.x += t.x;
+                    x0.y += t.y;
+                }
+            if (a.dv) {
+                const double2 t = a.dv[oi];
+                xa = make_double2(a.cd1 * t.x, a.cd1 * t.y);
+                if (a.dv2) {
+                    const double2 t2 = a.dv2[oi];
+                    xa.x += a.cd2 * t2.x;
+                    xa.y += a.cd2 * t2.y;
+                }
+            }
         }
     }
     const int deriv = (KIND == 1) ? a.deriv : 0;
@@ -408,7 +436,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         }
     }
     for (int idx = tid + kXBatch * B; idx < N; idx += B) {
-        const double2 ph = phs[T.st_rad[idx]], x = u[idx];
+        const double2 ph = phs[T.st_rad[idx]], x = load_u(idx);
         xs[T.st_xs[idx]] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
     }
 #pragma unroll
@@ -435,7 +463,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
     __syncthreads();
     const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
-    double gval = 0.0;
+    double gval = 0.0, gma = 0.0, gmc = 0.0;
     if (writer) {
         const double2 py = cmul(phs[rad_o], y);
         const double sc = a.Zp / v;
@@ -446,8 +474,31 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
                 const double f = deriv == 1 ? bj / Rz : -a.z * bj / (Rz * Rz * Rz);
                 K = make_double2(f * K.x, f * K.y);
             }
-            if (a.out) a.out[oi] = make_double2(a.alpha * K.x + a.beta * x0.x, a.alpha * K.y + a.beta * x0.y);
-            gval = 2.0 * a.gamma * (xa.x * K.x + xa.y * K.y);  // 2 gamma Re(conj(dv) K)
+            if (a.out) a.out[oi] = make_double2(a.alpha * K.x + x0.x, a.alpha * K.y + x0.y);
+            gval = 2.0 * a.gamma * (xa.x * K.x + xa.y * K.y);  // 2 gamma Re(conj(d) K)
+            if (a.model) {
+                // (dDeltaV/dtheta)_{n' n} x'_n over the radial block of (l', q'):
+                // dM/dtheta v = -(i/v) ph (dDeltaV/dtheta) conj(ph) v and x' = conj(ph) v
+                const int r = o / nmp, qp = o - r * nmp;
+                int vo = 0;
+                for (int l = 0; l < lp; ++l) vo += m.n_l[l] * m.n_l[l];
+                const double* fa = a.va + vo + (size_t)(row0 + r) * nlp;
+                const double* fc = a.vc + vo + (size_t)(row0 + r) * nlp;
+                const double2* xq = xs + m.xs_off[lp] + qp * m.xs_stride[lp];
+                double2 ca = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
+                for (int n = 0; n < nlp; ++n) {
+                    const double2 x = xq[n];
+                    ca.x += fa[n] * x.x;
+                    ca.y += fa[n] * x.y;
+                    cc.x += fc[n] * x.x;
+                    cc.y += fc[n] * x.y;
+                }
+                const double2 p = phs[rad_o];
+                const double2 t = make_double2(xa.x * p.x + xa.y * p.y, xa.x * p.y - xa.y * p.x);  // conj(d) p
+                // 2 gamma Re(-(i/v) t c) = 2 gamma Im(t c) / v
+                gma = 2.0 * a.gamma * (t.x * ca.y + t.y * ca.x) / v;
+                gmc = 2.0 * a.gamma * (t.x * cc.y + t.y * cc.x) / v;
+            }
         } else {
             // graph replays read the step length from device memory
             const double hh = a.hdev ? a.hdev[(size_t)(*a.chunk) * kChunkSteps + a.hidx] : h;
@@ -455,15 +506,33 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         }
     }
     if (KIND == 1 && a.grad) {
-        // this workgroup's share, summed in a fixed order by k_model_dot
-        __shared__ double red[kStageThreads / 64];
-        for (int off = 32; off > 0; off >>= 1) gval += __shfl_xor(gval, off, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = gval;
+        // this workgroup's shares, accumulated over the launches in its own
+        // slots and summed in a fixed order by k_grad_sum
+        __shared__ double red[3][kStageThreads / 64];
+        for (int off = 32; off > 0; off >>= 1) {
+            gval += __shfl_xor(gval, off, 64);
+            gma += __shfl_xor(gma, off, 64);
+            gmc += __shfl_xor(gmc, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            red[0][tid >> 6] = gval;
+            red[1][tid >> 6] = gma;
+            red[2][tid >> 6] = gmc;
+        }
         __syncthreads();
         if (tid == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < B / 64; ++w) sum += red[w];
-            a.grad[((size_t)j * 2 + a.gslot) * gridDim.x + blockIdx.x] = sum;
+            double sb = 0.0, sa = 0.0, sc = 0.0;
+            for (int w = 0; w < B / 64; ++w) {
+                sb += red[0][w];
+                sa += red[1][w];
+                sc += red[2][w];
+            }
+            double* g = a.grad + (size_t)j * kGradSlots * gridDim.x + blockIdx.x;
+            g[a.gslot * gridDim.x] += sb;
+            if (a.model) {
+                g[2 * gridDim.x] += sa;
+                g[3 * gridDim.x] += sc;
+            }
         }
     }
 }
@@ -481,10 +550,7 @@ __device__ void stage_entry(const StageArgs& a, char* smem) {
     }
     const int row0 = c * ROWS;
     const int nrows = min(ROWS, m.n_l[lp] - row0);
-    if (nrows <= 0) {
-        if (KIND == 1 && a.grad && threadIdx.x == 0) a.grad[((size_t)j * 2 + a.gslot) * gridDim.x + blockIdx.x] = 0.0;
-        return;
-    }
+    if (nrows <= 0) return;
     stage_body<KIND, ROWS>(a, j, lp, row0, nrows, smem);
 }
 
@@ -799,93 +865,26 @@ __global__ __launch_bounds__(kStageThreads) void k_apply(ApplyArgs a) {
     stage_entry<1, kRowsPerBlock>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
 }
 
-// grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] += 2 gamma Re(dv^H dM/dc u),
-// dM/dtheta = -(i/v) ph (dDeltaV/dtheta) conj(ph); grad[j][2] += the shares
-// gpart[j][0..2 n_part) of the b term; one workgroup per path.
-__global__ __launch_bounds__(256) void k_model_dot(ModelArgs a) {
-    const Meta& m = *a.meta;
-    const int j = a.traj0 + blockIdx.x;
-    const size_t jp = (size_t)j * a.pt.n_pts + a.p;
-    const double2* ph = a.pt.ph + jp * m.n_f;
-    const double2* u = a.u + (size_t)j * a.n_pad;
-    const double2* dv = a.dv + (size_t)j * a.n_pad;
-    const double v = a.tb.vvec[j];
-    double sa = 0.0, sc = 0.0;
-    for (int row = threadIdx.x; row < m.n_states; row += blockDim.x) {
-        int lp = 0;
-        while (lp < m.l_max && row >= m.state_off[lp + 1]) ++lp;
-        const int nl = m.n_l[lp];
-        const int rr = row - m.state_off[lp], q = rr / nl, np = rr - q * nl;
-        const int base = m.state_off[lp] + q * nl, rad0 = m.rad_off[lp];
-        int vo = 0;
-        for (int l = 0; l < lp; ++l) vo += m.n_l[l] * m.n_l[l];
-        double2 ca = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
-        for (int n = 0; n < nl; ++n) {
-            const double2 p = ph[rad0 + n], x = u[base + n];
-            const double2 ut = make_double2(p.x * x.x + p.y * x.y, p.x * x.y - p.y * x.x);  // conj(p) x
-            const double fa = a.va[vo + np * nl + n], fc = a.vc[vo + np * nl + n];
-            ca.x += fa * ut.x;
-            ca.y += fa * ut.y;
-            cc.x += fc * ut.x;
-            cc.y += fc * ut.y;
-        }
-        const double2 d = dv[row], p = ph[rad0 + np];
-        const double2 t = make_double2(d.x * p.x + d.y * p.y, d.x * p.y - d.y * p.x);  // conj(d) p
-        // Re(-(i/v) t c) = Im(t c) / v
-        sa += (t.x * ca.y + t.y * ca.x) / v;
-        sc += (t.x * cc.y + t.y * cc.x) / v;
+// grad[j] = (dL/da, dL/dc, dL/db): the k_apply shares of path j (slots 2, 3
+// and 0 + 1 of gpart[j][kGradSlots][n_part]) summed in a fixed order, so that
+// the result does not depend on the order in which workgroups ran.
+__global__ __launch_bounds__(64) void k_grad_sum(const double* __restrict__ gpart, int n_part,
+                                                 double* __restrict__ grad) {
+    const int j = blockIdx.x, t = threadIdx.x;
+    if (t >= 3) return;
+    const double* g = gpart + (size_t)j * kGradSlots * n_part;
+    double s = 0.0;
+    if (t < 2) {
+        for (int i = 0; i < n_part; ++i) s += g[(2 + t) * n_part + i];
+    } else {
+        for (int i = 0; i < 2 * n_part; ++i) s += g[i];
     }
-    __shared__ double ra[4], rc[4];
-    for (int off = 32; off > 0; off >>= 1) {
-        sa += __shfl_xor(sa, off, 64);
-        sc += __shfl_xor(sc, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        ra[threadIdx.x >> 6] = sa;
-        rc[threadIdx.x >> 6] = sc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0.0, tc = 0.0;
-        for (int w = 0; w < (int)blockDim.x / 64; ++w) {
-            ta += ra[w];
-            tc += rc[w];
-        }
-        atomicAdd(a.grad + (size_t)j * 3 + 0, 2.0 * a.gamma * ta);
-        atomicAdd(a.grad + (size_t)j * 3 + 1, 2.0 * a.gamma * tc);
-        if (a.gpart) {
-            // the b term: k_apply's per-workgroup shares in a fixed order
-            const double* gp = a.gpart + (size_t)j * 2 * a.n_part;
-            double tb = 0.0;
-            for (int i = 0; i < 2 * a.n_part; ++i) tb += gp[i];
-            atomicAdd(a.grad + (size_t)j * 3 + 2, tb);
-        }
-    }
+    grad[(size_t)j * 3 + t] = s;
 }
 
 __global__ void k_chunk_counter(int* chunk, int reset) {
     if (reset) *chunk = 0;
     else *chunk += 1;
-}
-
-struct Combine {
-    const double2* v[5];
-    double c[5];
-};
-
-// out = sum_k c_k v_k per path; grid (state blocks, path)
-__global__ __launch_bounds__(256) void k_combine(double2* __restrict__ out, Combine cb, int n_terms, int n,
-                                                 int n_pad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const size_t oi = (size_t)blockIdx.y * n_pad + i;
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < n_terms; ++k) {
-        const double2 x = cb.v[k][oi];
-        s.x += cb.c[k] * x.x;
-        s.y += cb.c[k] * x.y;
-    }
-    out[oi] = s;
 }
 
 // tab[k][idx[e]].y += val[e] for every grid node k; grid (entries, nodes)
@@ -1075,19 +1074,8 @@ hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st) {
-    hipLaunchKernelGGL(k_model_dot, dim3(n_traj_launch), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_combine(double2* out, const double2* const* v, const double* c, int n_terms, int n_traj, int n,
-                          int n_pad, hipStream_t st) {
-    Combine cb{};
-    for (int k = 0; k < n_terms && k < 5; ++k) {
-        cb.v[k] = v[k];
-        cb.c[k] = c[k];
-    }
-    hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256, n_traj), dim3(256), 0, st, out, cb, n_terms, n, n_pad);
+hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_traj, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_sum, dim3(n_traj), dim3(64), 0, st, gpart, n_part, grad);
     return hipGetLastError();
 }
 

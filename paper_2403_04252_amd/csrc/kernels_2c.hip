@@ -193,6 +193,7 @@ __device__ inline int mfma_row_f64(int r, int l) { return 4 * r + (l >> 4); }
 __device__ inline int mfma_row_f32(int r, int l) { return kF32RowByLaneGroup ? 4 * (l >> 4) + r : 4 * r + (l >> 4); }
 
 constexpr int kWFields = 7;  // cos, sin, W_0..W_2, J_|s-t|, J_(s+t)
+constexpr int kStageThreads2C = 256;  // threads of a contraction workgroup
 
 // Work of one wave in a 32 x 32 tile with nk weights: KPW weights (kk0 ..
 // kk0 + KPW - 1) times SPW of the four 16 x 16 subtiles.  SPW = 4: the wave
@@ -205,19 +206,28 @@ constexpr int kWFields = 7;  // cos, sin, W_0..W_2, J_|s-t|, J_(s+t)
 // XOR-ed by 4 (node / 4): the MFMA reads (16 rows of 4 nodes per wave) and the
 // staging writes (8 rows of 8 node quads per wave) then spread over the 64
 // LDS banks with the fewest passes (pitch 40 for FP64, 48 for FP32).
-template <typename T>
+template <typename T, int NC>
 struct ContractLds {
     static constexpr int kPitch = sizeof(T) == 8 ? 40 : 48;
-    T As[kNodeChunk][kPitch], Bs[kNodeChunk][kPitch];
-    double fl[kWFields][kNodeChunk];
-    double wk[kNodeChunk][kMaxK];
+    T As[NC][kPitch], Bs[NC][kPitch];
+    double fl[kWFields][NC];
+    double wk[NC][kMaxK];
 };
+
+// Nodes per chunk: kNodeChunk for FP64; twice that for the FP32 products,
+// whose MFMA is three times faster, so that the per-chunk staging and the
+// FP64 accumulation of the chunk sums are spread over more products.
+template <bool MIXED>
+constexpr int contract_chunk() { return MIXED ? 2 * kNodeChunk : kNodeChunk; }
 __device__ inline int lds_swz(int node) { return 4 * ((node >> 2) & 7); }
 
 template <bool MIXED, int KPW, int SPW>
 __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0,
-                              ContractLds<typename std::conditional<MIXED, float, double>::type>& L) {
+                              ContractLds<typename std::conditional<MIXED, float, double>::type,
+                                          contract_chunk<MIXED>()>& L) {
     typedef typename std::conditional<MIXED, float, double>::type T;
+    constexpr int NC = contract_chunk<MIXED>();   // nodes per chunk
+    constexpr int NPT = NC / 8;                   // nodes per loader thread and row
     auto& As = L.As;
     auto& Bs = L.Bs;
     auto& fl = L.fl;
@@ -231,21 +241,35 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
     // this work item's node range [p_begin, p_end) (whole chunks)
     const int nact_all = a.n_act[y];
-    const int span = ((nact_all + m.n_split - 1) / m.n_split + kNodeChunk - 1) / kNodeChunk * kNodeChunk;
+    const int span = ((nact_all + m.n_split - 1) / m.n_split + NC - 1) / NC * NC;
     const int p_begin = piece * span;
     const int nact = min(nact_all, p_begin + span);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // loader roles: row (column) lr of A (B), four consecutive nodes from kq;
-    // threads below kWFields * kNodeChunk also load one node field
-    const int lr = tid >> 3, kq = (tid & 7) * 4;
+    // loader roles: row (column) lr of A (B), NPT consecutive nodes from kq;
+    // up to two node fields of the weights per thread (field ffi + q * 256 / NC)
+    const int lr = tid >> 3, kq = (tid & 7) * NPT;
     const bool okA = a0 + lr < nA, okB = b0 + lr < nB;
     const T* arow = reinterpret_cast<const T*>(a.AT) + ((size_t)y * m.rowsT + m.rowT_off[s] + a0 + (okA ? lr : 0)) * nn;
     const T* brow = reinterpret_cast<const T*>(a.BT) + ((size_t)y * m.rowsP + m.rowP_off[t] + b0 + (okB ? lr : 0)) * nn;
-    const int ffi = tid / kNodeChunk, fk = tid % kNodeChunk;
-    int fid = 0;
-    if (ffi < kWFields) {
+    const int ffi = tid / NC, fk = tid % NC;
+    constexpr int kFStep = kStageThreads2C / NC;
+    int fid[2] = {0, 0};
+    {
         const int ids[kWFields] = {kFCos, kFSin, kFW, kFW + 1, kFW + 2, kFJ + o1, kFJ + o2};
-        fid = ids[ffi];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (ffi + q * kFStep < kWFields) fid[q] = ids[ffi + q * kFStep];
+    }
+    // weight roles: node fk, weights kk = ffi + q * kFStep (q < kWIt) as the
+    // fl rows of its three factors (Bessel order, cos/sin, quadrature weight)
+    // packed in 4-bit fields, -1 past nk
+    constexpr int kWIt = (NC * kMaxK + kStageThreads2C - 1) / kStageThreads2C;
+    int wsel[kWIt];
+#pragma unroll
+    for (int q = 0; q < kWIt; ++q) {
+        const int kk = ffi + q * kFStep;
+        const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
+        wsel[q] = kk < nk ? (5 + order) | (trig << 4) | ((2 + w) << 8) : -1;
     }
     // this wave's weights and subtiles
     const int kk0 = SPW == 4 ? wave * KPW : (wave & 1) * KPW;
@@ -259,16 +283,18 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     okn[0] = true;
     okn[1] = b0 + 16 < nB;
 
-    T ra[4], rb[4];
-    double rf = 0.0;
+    T ra[NPT], rb[NPT];
+    double rf[2] = {0.0, 0.0};
     auto fetch = [&](int base) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NPT; ++e) {
             const int p = base + kq + e;
             ra[e] = (okA && p < nact) ? arow[p] : (T)0;
             rb[e] = (okB && p < nact) ? brow[p] : (T)0;
         }
-        if (ffi < kWFields) rf = (base + fk < nact) ? nd[(size_t)fid * nn + base + fk] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (ffi + q * kFStep < kWFields) rf[q] = (base + fk < nact) ? nd[(size_t)fid[q] * nn + base + fk] : 0.0;
     };
 
     dbl4 acc[KPW][NMT][2];
@@ -280,25 +306,26 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
             for (int v = 0; v < 2; ++v) acc[i][u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     if (p_begin < nact) fetch(p_begin);
-    for (int base = p_begin; base < nact; base += kNodeChunk) {
+    for (int base = p_begin; base < nact; base += NC) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NPT; ++e) {
             As[kq + e][lr ^ lds_swz(kq + e)] = ra[e];
             Bs[kq + e][lr ^ lds_swz(kq + e)] = rb[e];
         }
-        if (ffi < kWFields) fl[ffi][fk] = rf;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (ffi + q * kFStep < kWFields) fl[ffi + q * kFStep][fk] = rf[q];
         __syncthreads();
-        for (int e = tid; e < kNodeChunk * nk; e += blockDim.x) {
-            const int k = e % kNodeChunk, kk = e / kNodeChunk;
-            const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
-            wk[k][kk] = fl[5 + order][k] * fl[trig][k] * fl[2 + w][k];
-        }
+#pragma unroll
+        for (int q = 0; q < kWIt; ++q)
+            if (wsel[q] >= 0)
+                wk[fk][ffi + q * kFStep] = fl[wsel[q] & 15][fk] * fl[(wsel[q] >> 4) & 15][fk] * fl[wsel[q] >> 8][fk];
         __syncthreads();
         // next chunk's operands in flight during this chunk's MFMA
-        if (base + kNodeChunk < nact) fetch(base + kNodeChunk);
+        if (base + NC < nact) fetch(base + NC);
         if (!MIXED) {
 #pragma unroll
-            for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
+            for (int ks = 0; ks < NC / 4; ++ks) {
                 const int kr = ks * 4 + lk;
                 const int sw = lds_swz(kr);
                 double av[NMT], bv[2];
@@ -326,8 +353,8 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
                 for (int u = 0; u < NMT; ++u)
 #pragma unroll
                     for (int v = 0; v < 2; ++v) c32[i][u][v] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < kNodeChunk / 4; ++ks) {
+#pragma unroll 8
+            for (int ks = 0; ks < NC / 4; ++ks) {
                 const int kr = ks * 4 + lk;
                 const int sw = lds_swz(kr);
                 float av[NMT], bv[2];
@@ -380,19 +407,19 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 // One workgroup per (job, tile) with an XCD-aware order: consecutive
 // workgroup ids go to the eight XCDs in turn, and the work items of XCD x are
 // the x-th eighth of the job-major list, so the tiles of one job (which
-// stream the same operand rows) share an L2.  Per chunk of kNodeChunk nodes
-// the 32 rows of A, the 32 columns of B and the node fields of the weights
-// are loaded into registers one chunk ahead (their latency overlaps the MFMA
+// stream the same operand rows) share an L2.  Per chunk of nodes (32, or 64
+// for the FP32 products) the 32 rows of A, the 32 columns of B and the node
+// fields of the weights are loaded into registers one chunk ahead (their latency overlaps the MFMA
 // of the current chunk), then staged in LDS; the waves split the nk weights
 // and the four 16 x 16 subtiles as contract_tile describes and feed the MFMA
 // with (A w_k) and B.
 //
 // MIXED: the products run on v_mfma_f32_16x16x4f32 (operands in FP32,
-// accumulated in FP32 over the 32 nodes of a chunk) and each chunk's partial
+// accumulated in FP32 over the 64 nodes of a chunk) and each chunk's partial
 // sums are added to FP64 accumulators, so the FP32 accumulation error stays
-// that of a 32-term sum whatever the number of nodes.
+// that of a 64-term sum whatever the number of nodes.
 template <bool MIXED>
-__global__ __launch_bounds__(256, MIXED ? 2 : 3) void k_2c_contract(ContractArgs a) {
+__global__ __launch_bounds__(kStageThreads2C, MIXED ? 2 : 3) void k_2c_contract(ContractArgs a) {
     const Meta2C& m = *a.m;
     const int per_job = m.n_tiles * m.n_split;
     const int total = per_job * a.n_jobs;
@@ -404,7 +431,7 @@ __global__ __launch_bounds__(256, MIXED ? 2 : 3) void k_2c_contract(ContractArgs
     const int piece = rem / m.n_tiles;
     const int2 tl = a.tiles[rem - piece * m.n_tiles];
     const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
-    __shared__ ContractLds<typename std::conditional<MIXED, float, double>::type> L;
+    __shared__ ContractLds<typename std::conditional<MIXED, float, double>::type, contract_chunk<MIXED>()> L;
     switch (st_nk(s, t, m.n_w)) {
         case 2: contract_tile<MIXED, 1, 2>(a, y, piece, s, t, a0, b0, L); break;
         case 4: contract_tile<MIXED, 1, 4>(a, y, piece, s, t, a0, b0, L); break;
@@ -882,7 +909,7 @@ hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, h
 }
 
 hipError_t launch_2c_contract(const ContractArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    const dim3 grid(8 * ((hm.n_tiles * hm.n_split * n_jobs + 7) / 8)), block(256);
+    const dim3 grid(8 * ((hm.n_tiles * hm.n_split * n_jobs + 7) / 8)), block(kStageThreads2C);
     if (hm.mixed)
         WPCCC_LAUNCH(ev, k_2c_contract<true>, grid, block, 0, st, a);
     else

@@ -105,6 +105,7 @@ struct StageArgs {
     int n_paths;          // paths of a k_stage launch (set by launch_stage)
     const double2* u_in;  // stage input   [n_traj][n_pad]
     double2* X;           // amplitudes    [n_traj][n_pad]
+    double2* Xout;        // stage 4 writes the step's result here (NULL: in place in X)
     double2* Xacc;        // accumulator   [n_traj][n_pad]
     double2* u_out;       // next input    [n_traj][n_pad]
     int* flag;            // non-finite latch
@@ -112,20 +113,38 @@ struct StageArgs {
     const double* hdev;
     const int* chunk;
     int hidx;
-    // operator application (k_apply): y = O u with O = M(z_p) (deriv 0),
-    // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2), then
-    //   out = alpha y + beta w            (out may be NULL, w may be NULL)
-    //   grad[(j * 2 + gslot) * gridDim.x + blockIdx.x] = this workgroup's
-    //   share of 2 gamma Re(dv^H y)       (grad may be NULL; gslot 0 or 1)
+    // operator application (k_apply): y = O v with O = M(z_p) (deriv 0),
+    // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2) applied to
+    // v = cu1 u_in + cu2 u_in2 (u_in2 may be NULL), then
+    //   out = alpha y + w[0] + ... + w[3]   (out may be NULL, unused w[k] NULL)
+    //   grad[(j * kGradSlots + gslot) * gridDim.x + blockIdx.x] += this
+    //   workgroup's share of 2 gamma Re(d^H y), d = cd1 dv + cd2 dv2
+    //   (grad may be NULL; gslot 0 or 1)
+    // and, with model != 0, the shares of 2 gamma Re(d^H dM/da v) and
+    // 2 gamma Re(d^H dM/dc v) in slots 2 and 3, from the radial blocks of the
+    // model potential (one-centre plans):
+    //   va[vo(l) + n' N_l + n] = -sum_i w_i r_i f f e^{-c r_i}       (d DeltaV / da)
+    //   vc[vo(l) + n' N_l + n] = +a sum_i w_i r_i^2 f f e^{-c r_i}   (d DeltaV / dc)
+    // with vo(l) = sum_{l'' < l} N_l''^2
     int deriv;
     double z;             // z of the point (deriv 1, 2)
-    double alpha, beta, gamma;
-    const double2* w;
+    double cu1, cu2;
+    const double2* u_in2;
+    double alpha, gamma;
+    const double2* w[4];
     double2* out;
     const double2* dv;
-    double* grad;         // [n_traj][2][grid x] shares
+    const double2* dv2;
+    double cd1, cd2;
+    double* grad;         // [n_traj][kGradSlots][grid x] shares
     int gslot;
+    int model;
+    const double* va;
+    const double* vc;
 };
+
+// gradient share slots of k_apply per path: b (deriv 1), b (deriv 2), a, c
+constexpr int kGradSlots = 4;
 
 // ints between the barrier counters of two paths: one 256-byte line each, so
 // that the polls of different paths do not contend for one memory line
@@ -149,27 +168,6 @@ struct ChunkArgs {
     double h[kChunkSteps];
     int* bar;             // [n_traj][kBarStride], zero at launch (counter of path j at bar[j * kBarStride])
     int n_traj;
-};
-
-// Radial blocks of the model potential on one basis (one-centre plans):
-//   va[vo(l) + n' N_l + n] = -sum_i w_i r_i f f e^{-c r_i}        (d DeltaV / da)
-//   vc[vo(l) + n' N_l + n] = +a sum_i w_i r_i^2 f f e^{-c r_i}    (d DeltaV / dc)
-// with vo(l) = sum_{l'' < l} N_l''^2.
-struct ModelArgs {
-    const Meta* meta;
-    Tables tb;
-    PointArrays pt;
-    int p;
-    int traj0;
-    int n_pad;
-    const double* va;
-    const double* vc;
-    const double2* u;
-    const double2* dv;
-    double gamma;
-    double* grad;         // grad[j][0] += 2 gamma Re(dv^H dM/da u), grad[j][1] likewise for c
-    const double* gpart;  // [n_traj][2][n_part] shares of the b term (k_apply), added to grad[j][2]; may be NULL
-    int n_part;
 };
 
 struct SetupArgs {
@@ -266,7 +264,7 @@ struct KernelTimer {
 // sees D_T + DeltaV (projectile charge Zp)
 int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a = 0.0, double model_c = 0.0,
                  double Zp = 1.0);
-// radial blocks va, vc of the model potential (layout of ModelArgs)
+// radial blocks va, vc of the model potential (layout of StageArgs::va, vc)
 void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& va, std::vector<double>& vc);
 void centre_free(Centre& c);
 
@@ -311,12 +309,11 @@ hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int 
                                 double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev = LaunchEv{});
-hipError_t launch_model_dot(const ModelArgs& a, int n_traj_launch, hipStream_t st);
+// grad[j][0..2] = (a, c, b) sums of the k_apply shares gpart[j][kGradSlots][n_part]
+// in a fixed order; one workgroup per path
+hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_traj, hipStream_t st);
 // *chunk = value (reset) or *chunk += 1 (advance), one thread
 hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st);
-// out[j] = sum_k c[k] v[k][j] over the first n states of every path (k < n_terms <= 5)
-hipError_t launch_combine(double2* out, const double2* const* v, const double* c, int n_terms, int n_traj,
-                          int n, int n_pad, hipStream_t st);
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
                               hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);

@@ -52,8 +52,8 @@ struct wpccc_plan_s {
     double *d_va = nullptr, *d_vc = nullptr;
     int ckpt_every = 0;
     int adj_K = 0, adj_nck = 0;
-    double2 *d_lam = nullptr, *d_mu = nullptr, *d_nu = nullptr, *d_u2 = nullptr, *d_u3 = nullptr, *d_u4 = nullptr;
-    double2 *d_ckpt = nullptr, *d_seg = nullptr;
+    double2 *d_lam = nullptr, *d_nu = nullptr;   // [2][n_traj][n_pad], [3][n_traj][n_pad]
+    double2 *d_ckpt = nullptr, *d_seg = nullptr;  // checkpoints; segment store (states, stage inputs)
     // graph replay of 64-step chunks (wpccc_propagate)
     bool use_graph = false, capturing = false;
     hipStream_t gstream = nullptr;
@@ -73,7 +73,7 @@ struct wpccc_plan_s {
     int launch = WPCCC_LAUNCH_STAGES;
     int chunk_smem = 0;       // k_chunk with stage_rows
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
-    double* d_gpart = nullptr;  // [n_traj][2][n_chunks] per-workgroup shares of the b gradient
+    double* d_gpart = nullptr;  // [n_traj][kGradSlots][n_chunks] per-workgroup gradient shares (k_apply)
     KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
@@ -104,8 +104,7 @@ void free_plan(wpccc_plan_s* p) {
     if (p->d_chunk) (void)hipFree(p->d_chunk);
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
                     p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
-                    p->d_vc,   p->d_lam,  p->d_mu,   p->d_nu,    p->d_u2,   p->d_u3,   p->d_u4,
-                    p->d_ckpt, p->d_seg,  p->d_bar,   p->d_gpart};
+                    p->d_vc,   p->d_lam,  p->d_nu,   p->d_ckpt,  p->d_seg,  p->d_bar,  p->d_gpart};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;
@@ -142,8 +141,9 @@ StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
 }
 
 int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, int step, double h, const double2* u_in,
-                  double2* X, double2* u_out, hipStream_t st) {
+                  double2* X, double2* u_out, hipStream_t st, double2* Xout = nullptr) {
     StageArgs a = stage_args(p, j0, X);
+    a.Xout = Xout;
     a.p = point;
     a.h = h;
     a.stage = stage;
@@ -205,18 +205,44 @@ int check_grid(const double* zgrid, int n_points) {
     return WPCCC_OK;
 }
 
-// One RK4 step z -> z + h of every path (prologue for its three points).
-int forward_step(wpccc_plan_s* p, double2* X, double z, double h, hipStream_t st) {
-    const double pts[3] = {z, z + 0.5 * h, z + h};
-    int rc = enqueue_prologue(p, pts, 3, 0, p->n_traj, st);
-    if (rc) return rc;
-    return enqueue_step(p, X, 0, p->n_traj, 0, h, st);
+// Point slots of the adjoint's steps: steps [c0, c0 + kChunkSteps) share one
+// prologue launch (point 2i is zgrid[c0+i], point 2i+1 the midpoint of step
+// c0+i, as in wpccc_propagate); returns the first slot of step n, after a
+// prologue launch when step n is not in the loaded chunk.
+struct AdjointPoints {
+    const double* zg;
+    int n_steps;
+    int loaded = -1;
+    int slot(wpccc_plan_s* p, int n, hipStream_t st, int* rc) {
+        const int c = n / kChunkSteps, c0 = c * kChunkSteps;
+        if (c != loaded) {
+            const int ns = std::min(kChunkSteps, n_steps - c0);
+            double pts[kChunkPoints];
+            for (int i = 0; i <= ns; ++i) {
+                pts[2 * i] = zg[c0 + i];
+                if (i < ns) pts[2 * i + 1] = 0.5 * (zg[c0 + i] + zg[c0 + i + 1]);
+            }
+            if ((*rc = enqueue_prologue(p, pts, 2 * ns + 1, 0, p->n_traj, st))) return 0;
+            loaded = c;
+        }
+        return 2 * (n - c0);
+    }
+};
+
+// One RK4 step of every path from x (point slots pz, pz+1, pz+2) that keeps
+// its stage inputs u2, u3, u4 and writes its result to xn (x is only read).
+int stored_step(wpccc_plan_s* p, int pz, double h, double2* x, double2* xn, double2* u2, double2* u3, double2* u4,
+                hipStream_t st) {
+    int rc;
+    const int nj = p->n_traj;
+    if ((rc = enqueue_stage(p, 0, nj, 1, pz, 0, h, x, x, u2, st))) return rc;
+    if ((rc = enqueue_stage(p, 0, nj, 2, pz + 1, 0, h, u2, x, u3, st))) return rc;
+    if ((rc = enqueue_stage(p, 0, nj, 3, pz + 1, 0, h, u3, x, u4, st))) return rc;
+    return enqueue_stage(p, 0, nj, 4, pz + 2, 0, h, u4, x, nullptr, st, xn);
 }
 
-// out = alpha O u + beta w and/or grad[.][gslot] += 2 gamma Re(dv^H O u), O at point slot pt.
-StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha,
-                     const double2* w, double beta, double2* out, const double2* dv, double gamma, int gslot,
-                     double* grad) {
+// Fields of a k_apply operation at point slot pt (z of the point).
+StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv) {
     StageArgs a{};
     a.meta = p->c.d_meta;
     a.tb = p->tables();
@@ -225,70 +251,52 @@ StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv, const d
     a.p = pt;
     a.n_pad = p->n_pad;
     a.traj0 = 0;
-    a.u_in = u;
     a.flag = p->d_flag;
     a.deriv = deriv;
     a.z = z;
-    a.alpha = alpha;
-    a.beta = beta;
-    a.gamma = gamma;
-    a.w = w;
-    a.out = out;
-    a.dv = dv;
-    a.grad = grad;
-    a.gslot = gslot;
+    a.cu1 = 1.0;
+    a.cd1 = 1.0;
+    a.gamma = 1.0;
     return a;
 }
 
-int enqueue_apply(wpccc_plan_s* p, int pt, double z, int deriv, const double2* u, double alpha, const double2* w,
-                  double beta, double2* out, const double2* dv, double gamma, int gslot, double* grad,
-                  hipStream_t st) {
+// One reverse RK4 stage at point slot pt with the stage's adjoint input
+// mu = c1 v1 + c2 v2 (v2 may be NULL) and forward stage input u:
+//   out = M^H mu + sum of w = -M mu + sum of w      (M^H = -M)
+//   gradient shares += 2 Re(mu^H dM/dtheta u), theta = b (two terms), a, c.
+// The three applications (M mu and the two b-derivative terms on u, the
+// first of which also forms the a and c terms) share one k_apply launch.
+int enqueue_reverse_stage(wpccc_plan_s* p, int pt, double z, const double2* v1, double c1, const double2* v2,
+                          double c2, double2* out, std::initializer_list<const double2*> w, const double2* u,
+                          hipStream_t st) {
     ApplyArgs a{};
-    a.s[0] = apply_args(p, pt, z, deriv, u, alpha, w, beta, out, dv, gamma, gslot, grad);
-    return launched(launch_apply(a, 1, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
-}
-
-// One reverse stage at point slot pt: out = alpha M v (M^H v = -M v), and
-// grad += 2 gamma Re(v^H dM/dtheta u) for theta = a, c, b.  The three
-// applications (M v, the two b-derivative terms on u) share one launch;
-// k_model_dot then adds the a and c terms and the b shares.
-int enqueue_reverse_stage(wpccc_plan_s* p, int pt, double z, const double2* v, double alpha, double2* out,
-                          const double2* u, double gamma, double* grad, hipStream_t st) {
-    ApplyArgs a{};
-    a.s[0] = apply_args(p, pt, z, 0, v, alpha, nullptr, 0.0, out, nullptr, 0.0, 0, nullptr);
-    for (int d = 1; d <= 2; ++d)
-        a.s[d] = apply_args(p, pt, z, d, u, 0.0, nullptr, 0.0, nullptr, v, gamma, d - 1, p->d_gpart);
-    int rc = launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
-    if (rc) return rc;
-    ModelArgs m{};
-    m.meta = p->c.d_meta;
-    m.tb = p->tables();
-    m.pt = p->points();
-    m.p = pt;
-    m.traj0 = 0;
-    m.n_pad = p->n_pad;
-    m.va = p->d_va;
-    m.vc = p->d_vc;
-    m.u = u;
-    m.dv = v;
-    m.gamma = gamma;
-    m.grad = grad;
-    m.gpart = p->d_gpart;
-    m.n_part = p->c.meta.n_chunks;
-    return launched(launch_model_dot(m, p->n_traj, st), "k_model_dot");
-}
-
-int enqueue_combine(wpccc_plan_s* p, double2* out, std::initializer_list<std::pair<double, const double2*>> terms,
-                    hipStream_t st) {
-    const double2* v[5];
-    double c[5];
-    int n = 0;
-    for (auto& t : terms) {
-        c[n] = t.first;
-        v[n] = t.second;
-        ++n;
+    StageArgs& m = a.s[0];
+    m = apply_args(p, pt, z, 0);
+    m.u_in = v1;
+    m.cu1 = c1;
+    m.u_in2 = v2;
+    m.cu2 = c2;
+    m.alpha = -1.0;
+    m.out = out;
+    int k = 0;
+    for (const double2* x : w) m.w[k++] = x;
+    for (int d = 1; d <= 2; ++d) {
+        StageArgs& g = a.s[d];
+        g = apply_args(p, pt, z, d);
+        g.u_in = u;
+        g.dv = v1;
+        g.cd1 = c1;
+        g.dv2 = v2;
+        g.cd2 = c2;
+        g.grad = p->d_gpart;
+        g.gslot = d - 1;
+        if (d == 1) {
+            g.model = 1;
+            g.va = p->d_va;
+            g.vc = p->d_vc;
+        }
     }
-    return launched(launch_combine(out, v, c, n, p->n_traj, p->c.meta.n_states, p->n_pad, st), "k_combine");
+    return launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
 }
 
 // Capture one chunk of kChunkSteps steps for all paths on X into plan->gexec:
@@ -387,7 +395,7 @@ int propagate_graph(wpccc_plan_s* p, const double* zg, int n_full, double2* X, h
 // traffic of a real step), once to warm up and kTunePasses times timed; the
 // candidate with the fastest pass is kept.
 constexpr int kTuneSteps = 8;
-constexpr double kAdjointStoreAll = 256.0 * (1 << 20);  // bytes of stored states below which nothing is recomputed
+constexpr double kAdjointStoreAll = 256.0 * (1 << 20);  // bytes of stored states and stage inputs below which nothing is recomputed
 constexpr int kTunePasses = 3;
 
 int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hipStream_t st) {
@@ -661,7 +669,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     TRY(dev_alloc(&plan->d_v, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_flag, 1, tot));
     TRY(dev_alloc(&plan->d_bar, (size_t)n_traj * kBarStride, tot));
-    TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * 2 * m.n_chunks, tot));
+    TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * kGradSlots * m.n_chunks, tot));
     TRY(dev_alloc(&plan->d_Frow1, (size_t)m.n_frow, tot));
     TRY(dev_alloc(&plan->d_G1, (size_t)m.n_g, tot));
     TRY(dev_alloc(&plan->d_PH1, (size_t)N, tot));
@@ -956,91 +964,102 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
         }
     hipStream_t st = (hipStream_t)stream;
     const int n_steps = n_points - 1;
-    // default: every state when they take at most kAdjointStoreAll bytes (no
-    // recomputation), else about sqrt(n_steps) checkpoints
-    const double all_bytes = (double)n_steps * plan->n_traj * plan->n_pad * sizeof(double2);
+    const size_t V = (size_t)plan->n_traj * plan->n_pad;
+    // segments of K steps: the reverse sweep recomputes a segment from its
+    // checkpoint keeping every state and stage input (4 K + 1 vectors), then
+    // runs its steps backwards.  Default: one segment over the whole grid (no
+    // checkpoints, nothing recomputed) when it takes at most kAdjointStoreAll
+    // bytes, else about sqrt(n_steps) steps per segment.
+    const double all_bytes = (4.0 * n_steps + 1.0) * V * sizeof(double2);
     int K = plan->ckpt_every > 0 ? plan->ckpt_every
-                                 : (all_bytes <= kAdjointStoreAll ? 1 : (int)std::ceil(std::sqrt((double)n_steps)));
+                                 : (all_bytes <= kAdjointStoreAll ? n_steps : (int)std::ceil(std::sqrt((double)n_steps)));
     K = std::max(1, std::min(K, n_steps));
     const int n_ck = (n_steps + K - 1) / K;
-    const size_t V = (size_t)plan->n_traj * plan->n_pad;
     if (K > plan->adj_K || n_ck > plan->adj_nck || !plan->d_lam) {
-        void* old[] = {plan->d_lam, plan->d_mu, plan->d_nu, plan->d_u2, plan->d_u3, plan->d_u4, plan->d_ckpt,
-                       plan->d_seg};
+        void* old[] = {plan->d_lam, plan->d_nu, plan->d_ckpt, plan->d_seg};
         (void)hipStreamSynchronize(st);
         for (void* q : old)
             if (q) (void)hipFree(q);
-        plan->d_lam = plan->d_mu = plan->d_nu = plan->d_u2 = plan->d_u3 = plan->d_u4 = nullptr;
-        plan->d_ckpt = plan->d_seg = nullptr;
+        plan->d_lam = plan->d_nu = plan->d_ckpt = plan->d_seg = nullptr;
         plan->adj_K = std::max(K, plan->adj_K);
         plan->adj_nck = std::max(n_ck, plan->adj_nck);
         long long& tot = plan->bytes;
-        if ((rc = dev_alloc(&plan->d_lam, V, tot)) || (rc = dev_alloc(&plan->d_mu, V, tot)) ||
-            (rc = dev_alloc(&plan->d_nu, 4 * V, tot)) || (rc = dev_alloc(&plan->d_u2, V, tot)) ||
-            (rc = dev_alloc(&plan->d_u3, V, tot)) || (rc = dev_alloc(&plan->d_u4, V, tot)) ||
+        if ((rc = dev_alloc(&plan->d_lam, 2 * V, tot)) || (rc = dev_alloc(&plan->d_nu, 3 * V, tot)) ||
             (rc = dev_alloc(&plan->d_ckpt, (size_t)plan->adj_nck * V, tot)) ||
-            (rc = dev_alloc(&plan->d_seg, (size_t)plan->adj_K * V, tot))) {
+            (rc = dev_alloc(&plan->d_seg, (size_t)(4 * plan->adj_K + 1) * V, tot))) {
             plan->adj_K = plan->adj_nck = 0;
             return rc;
         }
+        // the stage kernels write the states only: the padding entries of the
+        // stored states (copied out as the final amplitudes) stay zero
+        WPCCC_HIP_CHECK(hipMemsetAsync(plan->d_seg, 0, (size_t)(4 * plan->adj_K + 1) * V * sizeof(double2), st));
     }
     const size_t VB = V * sizeof(double2);
-    double2* lam = plan->d_lam;
-    double2* mu = plan->d_mu;
-    double2* nu[4] = {plan->d_nu, plan->d_nu + V, plan->d_nu + 2 * V, plan->d_nu + 3 * V};
-    double* grad = (double*)grad_dev;
-    // forward sweep with checkpoints (the working state lives in seg[0])
-    double2* xw = plan->d_seg;
-    WPCCC_HIP_CHECK(hipMemcpyAsync(xw, X0_dev, VB, hipMemcpyDeviceToDevice, st));
-    for (int n = 0; n < n_steps; ++n) {
-        if (n % K == 0)
-            WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_ckpt + (size_t)(n / K) * V, xw, VB, hipMemcpyDeviceToDevice, st));
-        if ((rc = forward_step(plan, xw, zgrid_host[n], zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+    // segment store: states x_0..x_K, then (u2, u3, u4) of each step
+    double2* seg = plan->d_seg;
+    auto xs_of = [&](int i) { return seg + (size_t)i * V; };
+    auto us_of = [&](int i, int k) { return seg + (size_t)(K + 1 + 3 * i + k) * V; };
+    AdjointPoints pts{zgrid_host, n_steps};
+    // forward sweep with a checkpoint every K steps (not needed for one segment)
+    if (n_ck > 1) {
+        double2* xw = xs_of(0);
+        WPCCC_HIP_CHECK(hipMemcpyAsync(xw, X0_dev, VB, hipMemcpyDeviceToDevice, st));
+        for (int n = 0; n < n_steps; ++n) {
+            if (n % K == 0)
+                WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_ckpt + (size_t)(n / K) * V, xw, VB, hipMemcpyDeviceToDevice, st));
+            const int pz = pts.slot(plan, n, st, &rc);
+            if (rc) return rc;
+            if ((rc = enqueue_step(plan, xw, 0, plan->n_traj, pz, zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+        }
+        if (X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xw, VB, hipMemcpyDeviceToDevice, st));
     }
-    if (X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xw, VB, hipMemcpyDeviceToDevice, st));
-    // reverse sweep
+    // reverse sweep; lambda alternates between two buffers, nu4, nu3, nu2 are
+    // the adjoint applications of stages 4, 3, 2 of the current step
+    double2* lam = plan->d_lam;
+    double2* lam_next = plan->d_lam + V;
+    double2* nu4 = plan->d_nu;
+    double2* nu3 = plan->d_nu + V;
+    double2* nu2 = plan->d_nu + 2 * V;
     WPCCC_HIP_CHECK(hipMemcpyAsync(lam, gX_dev, VB, hipMemcpyDeviceToDevice, st));
-    WPCCC_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)plan->n_traj * 3 * sizeof(double), st));
+    WPCCC_HIP_CHECK(hipMemsetAsync(plan->d_gpart, 0,
+                                   (size_t)plan->n_traj * kGradSlots * plan->c.meta.n_chunks * sizeof(double), st));
     for (int s = n_ck - 1; s >= 0; --s) {
         const int n0 = s * K, n1 = std::min(n0 + K, n_steps);
-        WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_seg, plan->d_ckpt + (size_t)s * V, VB, hipMemcpyDeviceToDevice, st));
-        for (int n = n0; n + 1 < n1; ++n) {
-            double2* nxt = plan->d_seg + (size_t)(n - n0 + 1) * V;
-            WPCCC_HIP_CHECK(hipMemcpyAsync(nxt, nxt - V, VB, hipMemcpyDeviceToDevice, st));
-            if ((rc = forward_step(plan, nxt, zgrid_host[n], zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+        const void* x0 = n_ck > 1 ? (const void*)(plan->d_ckpt + (size_t)s * V) : X0_dev;
+        WPCCC_HIP_CHECK(hipMemcpyAsync(xs_of(0), x0, VB, hipMemcpyDeviceToDevice, st));
+        for (int n = n0; n < n1; ++n) {
+            const int i = n - n0;
+            const int pz = pts.slot(plan, n, st, &rc);
+            if (rc) return rc;
+            if ((rc = stored_step(plan, pz, zgrid_host[n + 1] - zgrid_host[n], xs_of(i), xs_of(i + 1), us_of(i, 0),
+                                  us_of(i, 1), us_of(i, 2), st)))
+                return rc;
         }
+        if (n_ck == 1 && X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xs_of(n1 - n0), VB, hipMemcpyDeviceToDevice, st));
         for (int n = n1 - 1; n >= n0; --n) {
-            const double2* x = plan->d_seg + (size_t)(n - n0) * V;
+            const int i = n - n0;
+            const int pz = pts.slot(plan, n, st, &rc);
+            if (rc) return rc;
             const double z0 = zgrid_host[n], z1 = zgrid_host[n + 1], zm = 0.5 * (z0 + z1), h = z1 - z0;
-            const double pts[3] = {z0, zm, z1};
-            if ((rc = enqueue_prologue(plan, pts, 3, 0, plan->n_traj, st))) return rc;
-            // stage inputs of the forward step
-            if ((rc = enqueue_apply(plan, 0, z0, 0, x, 0.5 * h, x, 1.0, plan->d_u2, nullptr, 0.0, 0, nullptr, st)))
-                return rc;
-            if ((rc = enqueue_apply(plan, 1, zm, 0, plan->d_u2, 0.5 * h, x, 1.0, plan->d_u3, nullptr, 0.0, 0, nullptr,
-                                    st)))
-                return rc;
-            if ((rc = enqueue_apply(plan, 1, zm, 0, plan->d_u3, h, x, 1.0, plan->d_u4, nullptr, 0.0, 0, nullptr, st)))
-                return rc;
-            // stage 4: mu4 = h/6 lambda, nu4 = M3^H mu4 = -M3 mu4
-            if ((rc = enqueue_reverse_stage(plan, 2, z1, lam, -h / 6.0, nu[3], plan->d_u4, h / 6.0, grad, st)))
+            // stage 4: mu4 = h/6 lambda
+            if ((rc = enqueue_reverse_stage(plan, pz + 2, z1, lam, h / 6.0, nullptr, 0.0, nu4, {}, us_of(i, 2), st)))
                 return rc;
             // stage 3: mu3 = h/3 lambda + h nu4
-            if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {h, nu[3]}}, st))) return rc;
-            if ((rc = enqueue_reverse_stage(plan, 1, zm, mu, -1.0, nu[2], plan->d_u3, 1.0, grad, st))) return rc;
-            // stage 2: mu2 = h/3 lambda + h/2 nu3
-            if ((rc = enqueue_combine(plan, mu, {{h / 3.0, lam}, {0.5 * h, nu[2]}}, st))) return rc;
-            if ((rc = enqueue_reverse_stage(plan, 1, zm, mu, -1.0, nu[1], plan->d_u2, 1.0, grad, st))) return rc;
-            // stage 1: mu1 = h/6 lambda + h/2 nu2
-            if ((rc = enqueue_combine(plan, mu, {{h / 6.0, lam}, {0.5 * h, nu[1]}}, st))) return rc;
-            if ((rc = enqueue_reverse_stage(plan, 0, z0, mu, -1.0, nu[0], x, 1.0, grad, st))) return rc;
-            // lambda_n = lambda_(n+1) + nu1 + nu2 + nu3 + nu4
-            if ((rc = enqueue_combine(plan, lam, {{1.0, lam}, {1.0, nu[0]}, {1.0, nu[1]}, {1.0, nu[2]}, {1.0, nu[3]}},
-                                      st)))
+            if ((rc = enqueue_reverse_stage(plan, pz + 1, zm, lam, h / 3.0, nu4, h, nu3, {}, us_of(i, 1), st)))
                 return rc;
+            // stage 2: mu2 = h/3 lambda + h/2 nu3
+            if ((rc = enqueue_reverse_stage(plan, pz + 1, zm, lam, h / 3.0, nu3, 0.5 * h, nu2, {}, us_of(i, 0), st)))
+                return rc;
+            // stage 1: mu1 = h/6 lambda + h/2 nu2, and
+            // lambda_n = lambda_(n+1) + nu1 + nu2 + nu3 + nu4 with nu1 = M^H mu1
+            if ((rc = enqueue_reverse_stage(plan, pz, z0, lam, h / 6.0, nu2, 0.5 * h, lam_next, {lam, nu2, nu3, nu4},
+                                            xs_of(i), st)))
+                return rc;
+            std::swap(lam, lam_next);
         }
     }
-    return WPCCC_OK;
+    return launched(launch_grad_sum(plan->d_gpart, plan->c.meta.n_chunks, (double*)grad_dev, plan->n_traj, st),
+                    "k_grad_sum");
 }
 
 int wpccc_plan_timing(wpccc_plan_t plan, int enable) {

@@ -17,7 +17,7 @@
 namespace wpccc {
 
 constexpr int kMaxW = 3;          // weights: overlap, target potential, projectile potential
-constexpr int kNodeChunk = 32;    // spheroidal nodes per contraction chunk (8 MFMA k-steps of 4)
+constexpr int kNodeChunk = 32;    // spheroidal nodes per FP64 contraction chunk (8 MFMA k-steps of 4)
 constexpr int kTile = 32;         // rows (target) and columns (projectile) per contraction workgroup
 // node ranges per contraction tile: the work items of a launch differ in
 // their weight count (4 to 12) and node count, so several shorter items per
