@@ -286,11 +286,8 @@ __host__ __device__ inline bool phase3_fits(int rows, int nmp_max) { return rows
 //   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
-// fresh = false reuses the point's F_l', G_l', phases and column info that an
-// earlier call of this workgroup left in LDS for the same point (k_chunk: a
-// point shared by consecutive stages), so only the stage input is loaded.
 template <int KIND, int ROWS>
-__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem, bool fresh = true) {
+__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
@@ -315,16 +312,22 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     const int k = a.pt.kidx[jp];
     const double2* row = T.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
     const int* cl = T.col_lam + m.col_off[lp];
-    const int totF = fresh ? nrows * nV : 0;
+    const int totF = nrows * nV;
     constexpr int FB = fbatch(ROWS);
     double2 tv[FB];
     int lv[FB];
+    // Every lane loads (past the end: a clamped, in-bounds index whose value
+    // is not used), so that all loads of phase 0 are issued back to back
+    // before the first wait: one memory round trip instead of one per batch.
+    {
+        int q = tid % nV;
+        const int dq = B % nV;
 #pragma unroll
-    for (int i = 0; i < FB; ++i) {
-        const int idx = tid + i * B;
-        if (idx < totF) {
-            tv[i] = row[idx];
-            lv[i] = cl[idx % nV];
+        for (int i = 0; i < FB; ++i) {
+            tv[i] = row[min(tid + i * B, totF - 1)];
+            lv[i] = cl[q];
+            q += dq;
+            if (q >= nV) q -= nV;
         }
     }
     // stage input (KIND 1: v = cu1 u_in + cu2 u_in2)
@@ -342,27 +345,24 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         return r;
     };
     double2 uv[kXBatch];
-    int sv[kXBatch];
+    int sr[kXBatch], sx[kXBatch];  // radial index and LDS position of each amplitude
 #pragma unroll
     for (int i = 0; i < kXBatch; ++i) {
-        const int idx = tid + i * B;
-        if (idx < N) {
-            uv[i] = load_u(idx);
-            sv[i] = T.st_rad[idx] | (T.st_xs[idx] << 16);
-        }
+        const int idx = min(tid + i * B, N - 1);
+        uv[i] = load_u(idx);
+        sr[i] = T.st_rad[idx];
+        sx[i] = T.st_xs[idx];
     }
     const double* gc = T.gcoef + m.g_off[lp];
     const int* gp = T.gpb + m.g_off[lp];
-    const int totG = fresh ? nmp * gcols : 0;
+    const int totG = nmp * gcols;
     double gcv[kGBatch];
     int gpv[kGBatch];
 #pragma unroll
     for (int i = 0; i < kGBatch; ++i) {
-        const int idx = tid + i * B;
-        if (idx < totG) {
-            gcv[i] = gc[idx];
-            gpv[i] = gp[idx];
-        }
+        const int idx = min(tid + i * B, totG - 1);
+        gcv[i] = gc[idx];
+        gpv[i] = gp[idx];
     }
     // output-side values, prefetched by the thread that writes output o
     const int n_out = nrows * nmp;
@@ -403,8 +403,16 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     const int deriv = (KIND == 1) ? a.deriv : 0;
     const double bj = T.bvec[j];
     const double Rz = sqrt(bj * bj + a.z * a.z);
-    if (!fresh) {
-    } else if (deriv == 1) {
+    // the point's tables and the column descriptors, one entry per thread
+    // (larger tables: the rest is loaded below)
+    const int n_rp = 2 * (m.lam_max + 1), n_pb = (m.lam_max + 1) * (m.lam_max + 2) / 2;
+    const int2 gv = T.gcol_info[m.gcol_off[lp] + min(tid, gcols - 1)];
+    const double rpv = a.pt.rpow[jp * kRpow + min(tid, n_rp - 1)];
+    const double pbv = a.pt.pbar[jp * kMaxPb + min(tid, n_pb - 1)];
+    const double2 phv = a.pt.ph[jp * m.n_f + min(tid, m.n_f - 1)];
+    // every load above is issued before any of their values is used
+    __builtin_amdgcn_sched_barrier(0);
+    if (deriv == 1) {
         // d/dR of R^-(lam+1) and R^lam
         if (tid <= m.lam_max) {
             double Rl = 1.0;
@@ -412,18 +420,19 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
             rps[2 * tid] = -(tid + 1.0) / (Rl * Rz * Rz);
             rps[2 * tid + 1] = tid > 0 ? tid * Rl / Rz : 0.0;
         }
-    } else if (tid < 2 * (m.lam_max + 1)) {
-        rps[tid] = a.pt.rpow[jp * kRpow + tid];
+    } else if (tid < n_rp) {
+        rps[tid] = rpv;
     }
-    if (fresh) {
-        for (int i = tid; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
-        if (deriv == 2) {
-            if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
-        } else {
-            for (int i = tid; i < (m.lam_max + 1) * (m.lam_max + 2) / 2; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
-        }
-        for (int i = tid; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
+    if (tid < gcols) gis[tid] = gv;
+    for (int i = tid + B; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
+    if (deriv == 2) {
+        if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
+    } else {
+        if (tid < n_pb) pbs[tid] = pbv;
+        for (int i = tid + B; i < n_pb; i += B) pbs[i] = a.pt.pbar[jp * kMaxPb + i];
     }
+    if (tid < m.n_f) phs[tid] = phv;
+    for (int i = tid + B; i < m.n_f; i += B) phs[i] = a.pt.ph[jp * m.n_f + i];
     __syncthreads();
 
     // phase 1
@@ -431,8 +440,8 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     for (int i = 0; i < kXBatch; ++i) {
         const int idx = tid + i * B;
         if (idx < N) {
-            const double2 ph = phs[sv[i] & 0xffff], x = uv[i];
-            xs[sv[i] >> 16] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
+            const double2 ph = phs[sr[i]], x = uv[i];
+            xs[sx[i]] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
         }
     }
     for (int idx = tid + kXBatch * B; idx < N; idx += B) {
