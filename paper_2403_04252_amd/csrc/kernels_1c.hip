@@ -287,14 +287,15 @@ __host__ __device__ inline bool phase3_fits(int rows, int nmp_max) { return rows
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
 template <int KIND, int ROWS>
-__device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrows, char* smem) {
+__device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* smem) {
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
-    const int nmp = 2 * lp + 1;
-    const int nlp = m.n_l[lp];
-    const int nV = m.nV[lp];
-    const int gcols = m.gcols[lp];
+    const int row0 = t.row0, nrows = t.nrows;
+    const int nmp = t.nmp;
+    const int nlp = t.n_l;
+    const int nV = t.nV;
+    const int gcols = t.gcols;
     const int B = blockDim.x;
     const int tid = threadIdx.x;
     const size_t jp = (size_t)j * a.pt.n_pts + a.p;
@@ -310,8 +311,8 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
 
     // phase 0
     const int k = a.pt.kidx[jp];
-    const double2* row = T.tab + (size_t)k * m.n_frow + m.frow_off[lp] + (size_t)row0 * nV;
-    const int* cl = T.col_lam + m.col_off[lp];
+    const double2* row = T.tab + (size_t)k * m.n_frow + t.frow_off + (size_t)row0 * nV;
+    const int* cl = T.col_lam + t.col_off;
     const int totF = nrows * nV;
     constexpr int FB = fbatch(ROWS);
     double2 tv[FB];
@@ -353,8 +354,8 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         sr[i] = T.st_rad[idx];
         sx[i] = T.st_xs[idx];
     }
-    const double* gc = T.gcoef + m.g_off[lp];
-    const int* gp = T.gpb + m.g_off[lp];
+    const double* gc = T.gcoef + t.g_off;
+    const int* gp = T.gpb + t.g_off;
     const int totG = nmp * gcols;
     double gcv[kGBatch];
     int gpv[kGBatch];
@@ -375,8 +376,8 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     double2 x0 = make_double2(0.0, 0.0), xa = make_double2(0.0, 0.0);
     if (writer) {
         const int r = o / nmp, qp = o - r * nmp;
-        oi = (size_t)j * a.n_pad + m.state_off[lp] + qp * nlp + row0 + r;
-        rad_o = m.rad_off[lp] + row0 + r;
+        oi = (size_t)j * a.n_pad + t.state_off + qp * nlp + row0 + r;
+        rad_o = t.rad_off + row0 + r;
         if (KIND == 0) {
             if (a.stage < 4) x0 = a.X[oi];
             if (a.stage > 1) xa = a.Xacc[oi];
@@ -406,7 +407,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     // the point's tables and the column descriptors, one entry per thread
     // (larger tables: the rest is loaded below)
     const int n_rp = 2 * (m.lam_max + 1), n_pb = (m.lam_max + 1) * (m.lam_max + 2) / 2;
-    const int2 gv = T.gcol_info[m.gcol_off[lp] + min(tid, gcols - 1)];
+    const int2 gv = T.gcol_info[t.gcol_off + min(tid, gcols - 1)];
     const double rpv = a.pt.rpow[jp * kRpow + min(tid, n_rp - 1)];
     const double pbv = a.pt.pbar[jp * kMaxPb + min(tid, n_pb - 1)];
     const double2 phv = a.pt.ph[jp * m.n_f + min(tid, m.n_f - 1)];
@@ -424,7 +425,7 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
         rps[tid] = rpv;
     }
     if (tid < gcols) gis[tid] = gv;
-    for (int i = tid + B; i < gcols; i += B) gis[i] = T.gcol_info[m.gcol_off[lp] + i];
+    for (int i = tid + B; i < gcols; i += B) gis[i] = T.gcol_info[t.gcol_off + i];
     if (deriv == 2) {
         if (tid <= m.lam_max) legendre_column_dx(m.lam_max, tid, a.z / Rz, pbs);
     } else {
@@ -489,11 +490,9 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
                 // (dDeltaV/dtheta)_{n' n} x'_n over the radial block of (l', q'):
                 // dM/dtheta v = -(i/v) ph (dDeltaV/dtheta) conj(ph) v and x' = conj(ph) v
                 const int r = o / nmp, qp = o - r * nmp;
-                int vo = 0;
-                for (int l = 0; l < lp; ++l) vo += m.n_l[l] * m.n_l[l];
-                const double* fa = a.va + vo + (size_t)(row0 + r) * nlp;
-                const double* fc = a.vc + vo + (size_t)(row0 + r) * nlp;
-                const double2* xq = xs + m.xs_off[lp] + qp * m.xs_stride[lp];
+                const double* fa = a.va + t.vo + (size_t)(row0 + r) * nlp;
+                const double* fc = a.vc + t.vo + (size_t)(row0 + r) * nlp;
+                const double2* xq = xs + t.xs_off + qp * t.xs_stride;
                 double2 ca = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
                 for (int n = 0; n < nlp; ++n) {
                     const double2 x = xq[n];
@@ -546,21 +545,12 @@ __device__ void stage_body(const StageArgs& a, int j, int lp, int row0, int nrow
     }
 }
 
-// k_apply's grid: x = (l', chunk of ROWS rows) pairs in l' order, y = path.
+// k_apply's grid: x = row tile of a path (a.tiles, l' order), y = path.
 template <int KIND, int ROWS>
 __device__ void stage_entry(const StageArgs& a, char* smem) {
-    const Meta& m = *a.meta;
-    const int j = a.traj0 + blockIdx.y;
-    int c = blockIdx.x, lp = 0;
-    for (; lp < m.l_max; ++lp) {
-        const int nc = (m.n_l[lp] + ROWS - 1) / ROWS;
-        if (c < nc) break;
-        c -= nc;
-    }
-    const int row0 = c * ROWS;
-    const int nrows = min(ROWS, m.n_l[lp] - row0);
-    if (nrows <= 0) return;
-    stage_body<KIND, ROWS>(a, j, lp, row0, nrows, smem);
+    const StageTile t = a.tiles[blockIdx.x];
+    if (t.nrows <= 0) return;
+    stage_body<KIND, ROWS>(a, a.traj0 + blockIdx.y, t, smem);
 }
 
 __device__ inline int chunks_of(const Meta& m, int rows) {
@@ -601,9 +591,16 @@ __device__ inline bool xcd_item(const Meta& m, int n_paths, int bx, int* jl, int
 template <int ROWS>
 __global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
-    int jl, lp, row0, nrows;
-    if (!xcd_item<ROWS>(*a.meta, a.n_paths, blockIdx.x, &jl, &lp, &row0, &nrows)) return;
-    stage_body<0, ROWS>(a, a.traj0 + jl, lp, row0, nrows, reinterpret_cast<char*>(smem2));
+    // work item W of the path-major list of a.n_paths x a.nwg row tiles, in
+    // the XCD order of xcd_item; the tile (one 64-byte load) holds the
+    // per-l' offsets, so no loop over the basis blocks precedes the loads
+    const int total = a.n_paths * a.nwg;
+    const int per = (total + 7) / 8;
+    const int W = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (W >= total) return;
+    const int jl = W / a.nwg;
+    const StageTile t = a.tiles[W - jl * a.nwg];
+    stage_body<0, ROWS>(a, a.traj0 + jl, t, reinterpret_cast<char*>(smem2));
 }
 
 constexpr int kBarrierSpin = 1 << 22;  // polls (0.2 s or more) before a barrier gives up
@@ -998,6 +995,34 @@ int stage_chunks(const Meta& m, int rows) {
     int n = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) n += (m.n_l[lp] + rows - 1) / rows;
     return n;
+}
+
+void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out) {
+    out.clear();
+    int vo = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) {
+        for (int r0 = 0; r0 < m.n_l[lp]; r0 += rows) {
+            StageTile t{};
+            t.lp = lp;
+            t.row0 = r0;
+            t.nrows = std::min(rows, m.n_l[lp] - r0);
+            t.nmp = 2 * lp + 1;
+            t.nV = m.nV[lp];
+            t.gcols = m.gcols[lp];
+            t.frow_off = m.frow_off[lp];
+            t.col_off = m.col_off[lp];
+            t.g_off = m.g_off[lp];
+            t.gcol_off = m.gcol_off[lp];
+            t.state_off = m.state_off[lp];
+            t.rad_off = m.rad_off[lp];
+            t.n_l = m.n_l[lp];
+            t.xs_off = m.xs_off[lp];
+            t.xs_stride = m.xs_stride[lp];
+            t.vo = vo;
+            out.push_back(t);
+        }
+        vo += m.n_l[lp] * m.n_l[lp];
+    }
 }
 
 int stage_smem_bytes(const Meta& m, int rows) {

@@ -92,8 +92,21 @@ struct PointArrays {
 
 constexpr int kRpow = 2 * (kMaxLam + 1);
 
+// One row tile of a one-centre stage grid (rows [row0, row0 + nrows) of the
+// l' block) with the per-l' offsets the stage kernels need, so that a
+// workgroup gets its work from one 64-byte load.  The tiles of one path are
+// listed in l' order; vo = sum of N_l^2 over l < l' (model potential blocks).
+struct alignas(64) StageTile {
+    int lp, row0, nrows, nmp;
+    int nV, gcols, frow_off, col_off;
+    int g_off, gcol_off, state_off, rad_off;
+    int n_l, xs_off, xs_stride, vo;
+};
+
 struct StageArgs {
     const Meta* meta;     // device copy (indexed per lane: kept out of kernel arguments)
+    const StageTile* tiles;  // [nwg] the row tiles of one path for this launch's tiling
+    int nwg;
     Tables tb;
     PointArrays pt;
     double Zp;
@@ -326,6 +339,8 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& host_meta, int smem, int
 int chunk_grid(const Meta& host_meta, int n_traj, int rows);
 bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
 int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
+// the row tiles of one path for `rows` rows per workgroup, l' order
+void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out);
 // whether the stage kernels can use `rows` rows per workgroup for this basis
 // (every output of a workgroup needs a lane of the phase-3 reduction)
 bool stage_rows_fit(const Meta& m, int rows);

@@ -74,6 +74,8 @@ struct wpccc_plan_s {
     int chunk_smem = 0;       // k_chunk with stage_rows
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
     double* d_gpart = nullptr;  // [n_traj][kGradSlots][n_chunks] per-workgroup gradient shares (k_apply)
+    StageTile* d_tiles = nullptr;  // the row tiles of every tiling in kStageRowsList, one after another
+    int tile_off[kNumStageRows] = {}, tile_n[kNumStageRows] = {};
     KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
@@ -104,7 +106,8 @@ void free_plan(wpccc_plan_s* p) {
     if (p->d_chunk) (void)hipFree(p->d_chunk);
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
                     p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
-                    p->d_vc,   p->d_lam,  p->d_nu,   p->d_ckpt,  p->d_seg,  p->d_bar,  p->d_gpart};
+                    p->d_vc,   p->d_lam,  p->d_nu,   p->d_ckpt,  p->d_seg,  p->d_bar,  p->d_gpart,
+                    p->d_tiles};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;
@@ -125,10 +128,20 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     return launched(e, "k_prologue");
 }
 
+// The row tiles of a tiling (`rows` from kStageRowsList).
+void set_tiles(const wpccc_plan_s* p, int rows, StageArgs& a) {
+    for (int i = 0; i < kNumStageRows; ++i)
+        if (kStageRowsList[i] == rows) {
+            a.tiles = p->d_tiles + p->tile_off[i];
+            a.nwg = p->tile_n[i];
+        }
+}
+
 // Fields of a stage launch shared by every stage of a propagation.
 StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
     StageArgs a{};
     a.meta = p->c.d_meta;
+    set_tiles(p, p->stage_rows, a);
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -245,6 +258,7 @@ int stored_step(wpccc_plan_s* p, int pz, double h, double2* x, double2* xn, doub
 StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv) {
     StageArgs a{};
     a.meta = p->c.d_meta;
+    set_tiles(p, kRowsPerBlock, a);
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -670,6 +684,15 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     TRY(dev_alloc(&plan->d_flag, 1, tot));
     TRY(dev_alloc(&plan->d_bar, (size_t)n_traj * kBarStride, tot));
     TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * kGradSlots * m.n_chunks, tot));
+    std::vector<StageTile> tiles;
+    for (int i = 0; i < kNumStageRows; ++i) {
+        std::vector<StageTile> t;
+        stage_tiles(m, kStageRowsList[i], t);
+        plan->tile_off[i] = (int)tiles.size();
+        plan->tile_n[i] = (int)t.size();
+        tiles.insert(tiles.end(), t.begin(), t.end());
+    }
+    TRY(dev_alloc(&plan->d_tiles, tiles.size(), tot));
     TRY(dev_alloc(&plan->d_Frow1, (size_t)m.n_frow, tot));
     TRY(dev_alloc(&plan->d_G1, (size_t)m.n_g, tot));
     TRY(dev_alloc(&plan->d_PH1, (size_t)N, tot));
@@ -688,6 +711,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->d_v, v_host, (size_t)n_traj * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(plan->d_flag, 0, sizeof(int), st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->d_tiles, tiles.data(), tiles.size() * sizeof(StageTile), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->d_va, va.data(), va.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
