@@ -1141,7 +1141,7 @@ hipError_t launch_slot_setup(const SetupArgs& a, const Meta& hm, hipStream_t st,
 
 hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, int smem, hipStream_t st, const LaunchEv& ev,
                         int rows) {
-    const dim3 grid(8 * ((n_traj_launch * stage_chunks(hm, rows) + 7) / 8)), block(kStageThreads);
+    const dim3 grid(8 * ((n_traj_launch * a.nwg + 7) / 8)), block(kStageThreads);
     StageArgs a1 = a;
     a1.n_paths = n_traj_launch;
     switch (rows) {
