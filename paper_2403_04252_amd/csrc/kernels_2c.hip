@@ -211,7 +211,7 @@ struct ContractLds {
     static constexpr int kPitch = sizeof(T) == 8 ? 40 : 48;
     T As[NC][kPitch], Bs[NC][kPitch];
     double fl[kWFields][NC];
-    double wk[NC][kMaxK];
+    T wk[NC][kMaxK];   // weights w_k(p), formed in FP64 and stored in the product precision
 };
 
 // Nodes per chunk: kNodeChunk for FP64; twice that for the FP32 products,
@@ -221,8 +221,96 @@ template <bool MIXED>
 constexpr int contract_chunk() { return MIXED ? 2 * kNodeChunk : kNodeChunk; }
 __device__ inline int lds_swz(int node) { return 4 * ((node >> 2) & 7); }
 
-template <bool MIXED, int KPW, int SPW>
-__device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0,
+// The MFMAs of one chunk for the wave's active subtiles: row halves
+// mt0 .. mt0 + NA - 1 and column halves 0 .. NV - 1 (subtiles wholly outside
+// the block are left out at compile time, so the k-step loop has no
+// branches), KPW weights from kk0.  MIXED: FP32 products summed over the
+// chunk in FP32 MFMA accumulators, then added to the FP64 ones.
+template <bool MIXED, int KPW, int NMT, int NA, int NV, typename T, int NC>
+__device__ __forceinline__ void chunk_mfma(const ContractLds<T, NC>& L, int mt0, int kk0, int li, int lk,
+                                           bool r2, bool c2, dbl4 (&acc)[KPW][NMT][2]) {
+    constexpr int NKS = NC / 4;
+    T av[2][NA], bv[2][NV], w[2][KPW];
+    auto load = [&](int ks, int b) {
+        const int kr = ks * 4 + lk;
+        const int sw = lds_swz(kr);
+#pragma unroll
+        for (int u = 0; u < NA; ++u) av[b][u] = L.As[kr][((mt0 + u) * 16 + li) ^ sw];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bv[b][v] = L.Bs[kr][(v * 16 + li) ^ sw];
+#pragma unroll
+        for (int i = 0; i < KPW; ++i) w[b][i] = L.wk[kr][kk0 + i];
+    };
+    if (!MIXED) {
+        // FP64: one variant per weight split (NA = NMT, NV = 2) that skips
+        // the second row half (!r2) and column half (!c2) at run time; an
+        // FP64 MFMA is long enough that the branches cost little, and one
+        // variant instead of four keeps the kernel's code in the instruction
+        // cache
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            load(ks, 0);
+#pragma unroll
+            for (int i = 0; i < KPW; ++i)
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    if (u > 0 && !r2) continue;
+                    const double aw = (double)av[0][u] * (double)w[0][i];
+                    acc[i][u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, (double)bv[0][0], acc[i][u][0], 0, 0, 0);
+                    if (NV > 1 && c2)
+                        acc[i][u][NV - 1] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(aw, (double)bv[0][NV - 1], acc[i][u][NV - 1], 0, 0, 0);
+                }
+        }
+    } else {
+        // FP32: k-steps in pairs, buffer 0 holding the even step and buffer 1
+        // the odd one (NKS is even), the next step's operands read while the
+        // current step's MFMAs issue
+        flt4 c32[KPW][NA][NV];
+#pragma unroll
+        for (int i = 0; i < KPW; ++i)
+#pragma unroll
+            for (int u = 0; u < NA; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) c32[i][u][v] = flt4{0.f, 0.f, 0.f, 0.f};
+        auto step = [&](int b) {
+#pragma unroll
+            for (int i = 0; i < KPW; ++i)
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    const float aw = (float)av[b][u] * (float)w[b][i];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        c32[i][u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, (float)bv[b][v], c32[i][u][v], 0, 0, 0);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        load(0, 0);
+#pragma unroll 1
+        for (int ks = 0; ks < NKS; ks += 2) {
+            load(ks + 1, 1);
+            step(0);
+            if (ks + 2 < NKS) load(ks + 2, 0);
+            step(1);
+        }
+        // chunk sums into the FP64 accumulators (register r keeps the FP32 layout)
+#pragma unroll
+        for (int i = 0; i < KPW; ++i)
+#pragma unroll
+            for (int u = 0; u < NA; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[i][u][v][r] += (double)c32[i][u][v][r];
+    }
+}
+
+// NA, NV: active row halves (of the wave's NMT) and column halves of the
+// tile, fixed per workgroup: subtiles wholly outside the block are left out
+// at compile time.  SPW = 2: NA = 1 for every wave, and a wave whose row
+// half lies outside the block skips its MFMAs (one branch per chunk).
+template <bool MIXED, int KPW, int SPW, int NA, int NV>
+__device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0, bool r2, bool c2,
                               ContractLds<typename std::conditional<MIXED, float, double>::type,
                                           contract_chunk<MIXED>()>& L) {
     typedef typename std::conditional<MIXED, float, double>::type T;
@@ -276,12 +364,8 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     const int mt0 = SPW == 4 ? 0 : (wave >> 1);
     constexpr int NMT = SPW == 4 ? 2 : 1;   // row halves covered by the wave
     const int li = lane & 15, lk = lane >> 4;
-    // 16 x 16 subtiles wholly outside the block are skipped (wave-uniform)
-    bool okm[NMT], okn[2];
-#pragma unroll
-    for (int u = 0; u < NMT; ++u) okm[u] = a0 + (mt0 + u) * 16 < nA;
-    okn[0] = true;
-    okn[1] = b0 + 16 < nB;
+    // SPW = 2: whether the wave's row half lies inside the block (wave-uniform)
+    const bool rows_in = SPW == 4 || a0 + mt0 * 16 < nA;
 
     T ra[NPT], rb[NPT];
     double rf[2] = {0.0, 0.0};
@@ -323,67 +407,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
         __syncthreads();
         // next chunk's operands in flight during this chunk's MFMA
         if (base + NC < nact) fetch(base + NC);
-        if (!MIXED) {
-#pragma unroll
-            for (int ks = 0; ks < NC / 4; ++ks) {
-                const int kr = ks * 4 + lk;
-                const int sw = lds_swz(kr);
-                double av[NMT], bv[2];
-#pragma unroll
-                for (int u = 0; u < NMT; ++u) av[u] = As[kr][((mt0 + u) * 16 + li) ^ sw];
-                bv[0] = Bs[kr][li ^ sw];
-                bv[1] = Bs[kr][(16 + li) ^ sw];
-#pragma unroll
-                for (int i = 0; i < KPW; ++i) {
-                    const double w = wk[kr][kk0 + i];
-#pragma unroll
-                    for (int u = 0; u < NMT; ++u) {
-                        if (!okm[u]) continue;
-                        const double aw = av[u] * w;
-                        acc[i][u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv[0], acc[i][u][0], 0, 0, 0);
-                        if (okn[1]) acc[i][u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv[1], acc[i][u][1], 0, 0, 0);
-                    }
-                }
-            }
-        } else {
-            flt4 c32[KPW][NMT][2];
-#pragma unroll
-            for (int i = 0; i < KPW; ++i)
-#pragma unroll
-                for (int u = 0; u < NMT; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v) c32[i][u][v] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-            for (int ks = 0; ks < NC / 4; ++ks) {
-                const int kr = ks * 4 + lk;
-                const int sw = lds_swz(kr);
-                float av[NMT], bv[2];
-#pragma unroll
-                for (int u = 0; u < NMT; ++u) av[u] = (float)As[kr][((mt0 + u) * 16 + li) ^ sw];
-                bv[0] = (float)Bs[kr][li ^ sw];
-                bv[1] = (float)Bs[kr][(16 + li) ^ sw];
-#pragma unroll
-                for (int i = 0; i < KPW; ++i) {
-                    const float w = (float)wk[kr][kk0 + i];
-#pragma unroll
-                    for (int u = 0; u < NMT; ++u) {
-                        if (!okm[u]) continue;
-                        const float aw = av[u] * w;
-                        c32[i][u][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv[0], c32[i][u][0], 0, 0, 0);
-                        if (okn[1]) c32[i][u][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv[1], c32[i][u][1], 0, 0, 0);
-                    }
-                }
-            }
-            // chunk sums into the FP64 accumulators (register r keeps the FP32 layout)
-#pragma unroll
-            for (int i = 0; i < KPW; ++i)
-#pragma unroll
-                for (int u = 0; u < NMT; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[i][u][v][r] += (double)c32[i][u][v][r];
-        }
+        if (rows_in) chunk_mfma<MIXED, KPW, NMT, NA, NV>(L, mt0, kk0, li, lk, r2, c2, acc);
         __syncthreads();
     }
     double* out = a.tmol + ((size_t)y * m.n_split + piece) * m.n_tmol + m.st_off[s][t];
@@ -391,9 +415,9 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     for (int i = 0; i < KPW; ++i) {
         const int kk = kk0 + i;
 #pragma unroll
-        for (int u = 0; u < NMT; ++u)
+        for (int u = 0; u < NA; ++u)
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
+            for (int v = 0; v < NV; ++v) {
                 const int jj = b0 + v * 16 + li;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -432,13 +456,27 @@ __global__ __launch_bounds__(kStageThreads2C, MIXED ? 2 : 3) void k_2c_contract(
     const int2 tl = a.tiles[rem - piece * m.n_tiles];
     const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
     __shared__ ContractLds<typename std::conditional<MIXED, float, double>::type, contract_chunk<MIXED>()> L;
+    // second row / column half of the 32 x 32 tile inside the block
+    const bool r2 = a0 + 16 < m.nA[s], c2 = b0 + 16 < m.nB[t];
+    // FP32 products: one compiled variant per set of active subtiles; FP64:
+    // one variant that tests r2 and c2 at run time
+#define WPCCC_TILE4(KPW)                                                                          \
+    if (!MIXED || (r2 && c2)) contract_tile<MIXED, KPW, 4, 2, 2>(a, y, piece, s, t, a0, b0, r2, c2, L); \
+    else if (r2) contract_tile<MIXED, KPW, 4, 2, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);              \
+    else if (c2) contract_tile<MIXED, KPW, 4, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);              \
+    else contract_tile<MIXED, KPW, 4, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
+#define WPCCC_TILE2(KPW)                                                                          \
+    if (!MIXED || c2) contract_tile<MIXED, KPW, 2, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);         \
+    else contract_tile<MIXED, KPW, 2, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
     switch (st_nk(s, t, m.n_w)) {
-        case 2: contract_tile<MIXED, 1, 2>(a, y, piece, s, t, a0, b0, L); break;
-        case 4: contract_tile<MIXED, 1, 4>(a, y, piece, s, t, a0, b0, L); break;
-        case 6: contract_tile<MIXED, 3, 2>(a, y, piece, s, t, a0, b0, L); break;
-        case 8: contract_tile<MIXED, 2, 4>(a, y, piece, s, t, a0, b0, L); break;
-        default: contract_tile<MIXED, 3, 4>(a, y, piece, s, t, a0, b0, L); break;
+        case 2: WPCCC_TILE2(1) break;
+        case 4: WPCCC_TILE4(1) break;
+        case 6: WPCCC_TILE2(3) break;
+        case 8: WPCCC_TILE4(2) break;
+        default: WPCCC_TILE4(3) break;
     }
+#undef WPCCC_TILE4
+#undef WPCCC_TILE2
 }
 
 // Sum of the node-range partial sums of the contraction into range 0, in
