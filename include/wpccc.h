@@ -140,7 +140,7 @@ typedef struct {
                        timing each admissible value on the plan's paths */
     int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED: 2C overlap/transfer
                        contractions with FP32 products summed in FP32 over each
-                       32-node chunk and in FP64 across chunks; LU, solves and
+                       64-node chunk and in FP64 across chunks; LU, solves and
                        RK4 stay FP64 */
     int graph;      /* 1C, batched: replay each 64-step chunk of wpccc_propagate
                        from a captured HIP graph (step lengths and positions
