@@ -123,8 +123,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed RK4 steps, each over all paths (default 800; 20 for c3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 40; 2 for c3)")
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: batched one-centre N=580 (the headline); c3: batched two-centre")
+    ap.add_argument("--workload", choices=["c2", "c3", "sweep"], default="c2",
+                    help="c2: batched one-centre N=580 (the headline); c3: batched two-centre; "
+                         "sweep: one-centre throughput against basis size (paper shape N_l = 42 - l)")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
     ap.add_argument("--no-2c", action="store_true",
@@ -152,6 +153,10 @@ def main():
         args.steps = 20 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         return bench_two_centre(args)
+    if args.workload == "sweep":
+        args.steps = 200 if args.steps is None else args.steps
+        args.warmup = 20 if args.warmup is None else args.warmup
+        return bench_sweep(args)
     args.steps = 800 if args.steps is None else args.steps
     args.warmup = 40 if args.warmup is None else args.warmup
 
@@ -334,6 +339,62 @@ def main():
             out["two_centre"]["mixed" if mixed else "fp64"] = {
                 k: r[k] for k in ("value", "unit", "ms_per_step", "roofline", "lu", "config")}
     print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args):
+    """One-centre batched throughput against basis size with the paper's basis
+    shape, N_l = 42 - l radial functions per l (bound n <= 10 plus 32 Coulomb
+    wave-packet bins per l), l_max = 0..6, on a 2000-point grid; 8 paths with b
+    log-spaced 0.2..10, v = 2, dz = 0.1 from z = -40.  Prints one JSON line with
+    one entry per l_max (sizes the stage kernel's LDS cannot hold are listed as
+    unsupported)."""
+    import torch
+    import paper_2403_04252_amd as W
+    from paper_2403_04252_amd import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    b = 0.2 * 50.0 ** (np.arange(8) / 7.0)
+    v = np.full(8, 2.0)
+    zg = WL.z_uniform(-40.0, -40.0 + 0.1 * (args.warmup + args.steps), 0.1)
+    rows = []
+    for l_max in range(7):
+        rec = WL.Recipe(10, l_max, 32, 3.0, 2000)
+        lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+        n_states = W.wpccc_basis_info(lb)[0]
+        entry = {"l_max": l_max, "n_states": n_states}
+        print(f"sweep l_max {l_max}: N = {n_states}", file=sys.stderr, flush=True)
+        try:
+            t0 = time.perf_counter()
+            plan = W.wpccc_plan_create(lb, b, v)
+            entry["plan_setup_s"] = time.perf_counter() - t0
+        except W.WpcccError as e:
+            entry["unsupported"] = str(e)
+            rows.append(entry)
+            continue
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        W.wpccc_propagate(plan, zg[: args.warmup + 1], X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W.wpccc_propagate(plan, zg[args.warmup:], X)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        W.wpccc_plan_status(plan)
+        entry.update({"value": plan.n_traj * args.steps / wall, "unit": "trajectory-steps/s",
+                      "us_per_batched_step": wall / args.steps * 1e6,
+                      "stage_rows": W.wpccc_plan_stage_rows(plan),
+                      "device_bytes": plan.device_bytes})
+        rows.append(entry)
+        del plan, X
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "RK4 steps/s over batched b against basis size", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                      "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..6, "
+                                             "2000-pt grid, 8 b log-spaced 0.2-10, v=2, dz=0.1",
+                                 "parallelism": "1 GPU, paths batched"},
+                      "sweep": rows}), flush=True)
 
 
 def adjoint_measure(torch, W, WL):
