@@ -146,7 +146,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(paths shard across GPUs without communication; see DESIGN.md). "
+              f"(paths are independent and would shard across GPUs without communication). "
               f"--gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c3":
