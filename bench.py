@@ -145,7 +145,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path "
               f"(paths are independent and would shard across GPUs without communication). "
               f"--gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
