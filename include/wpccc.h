@@ -53,7 +53,7 @@ extern "C" {
 #define WPCCC_EHIP      -3   /* a HIP runtime call failed (no device, launch error) */
 #define WPCCC_ESINGULAR -4   /* exact zero pivot in an LU factorisation */
 #define WPCCC_ENUMERIC  -5   /* non-finite amplitude detected on the device */
-#define WPCCC_ENOTSUP   -6   /* requested form not available in this build */
+#define WPCCC_ENOTSUP   -6   /* requested form or size not supported by the library */
 
 typedef struct wpccc_basis_s* wpccc_basis_t;
 typedef struct wpccc_plan_s* wpccc_plan_t;
