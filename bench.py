@@ -344,7 +344,7 @@ def main():
 def bench_sweep(args):
     """One-centre batched throughput against basis size with the paper's basis
     shape, N_l = 42 - l radial functions per l (bound n <= 10 plus 32 Coulomb
-    wave-packet bins per l), l_max = 0..6, on a 2000-point grid; 8 paths with b
+    wave-packet bins per l), l_max = 0..8, on a 2000-point grid; 8 paths with b
     log-spaced 0.2..10, v = 2, dz = 0.1 from z = -40.  Prints one JSON line with
     one entry per l_max (sizes the stage kernel's LDS cannot hold are listed as
     unsupported)."""
@@ -358,7 +358,7 @@ def bench_sweep(args):
     v = np.full(8, 2.0)
     zg = WL.z_uniform(-40.0, -40.0 + 0.1 * (args.warmup + args.steps), 0.1)
     rows = []
-    for l_max in range(7):
+    for l_max in range(9):
         rec = WL.Recipe(10, l_max, 32, 3.0, 2000)
         lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
         n_states = W.wpccc_basis_info(lb)[0]
@@ -391,7 +391,7 @@ def bench_sweep(args):
     print(json.dumps({"metric": "RK4 steps/s over batched b against basis size", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
                       "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..6, "
+                      "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..8, "
                                              "2000-pt grid, 8 b log-spaced 0.2-10, v=2, dz=0.1",
                                  "parallelism": "1 GPU, paths batched"},
                       "sweep": rows}), flush=True)

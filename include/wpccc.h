@@ -169,7 +169,8 @@ typedef struct {
  * outlive the plan.  Uploads the basis, builds the radial moment tables on
  * the device (synchronously on `stream`) and allocates the per-path
  * workspace.  opts may be NULL (defaults).
- * Errors: WPCCC_EINVAL, WPCCC_ENOMEM, WPCCC_EHIP, WPCCC_ENOTSUP. */
+ * Errors: WPCCC_EINVAL, WPCCC_ENOMEM, WPCCC_EHIP, WPCCC_ENOTSUP (a basis
+ * whose stage workgroup does not fit the LDS at any admissible tiling). */
 int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host,
                       const double* v_host, const wpccc_plan_opts* opts,
                       void* stream, wpccc_plan_t* out);
@@ -259,7 +260,8 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
  *   gX_dev    complex [n_traj][n_pad], dL/d conj(X) at the last point (read)
  *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
  * Device memory for the checkpoints is allocated by the first call.  Errors:
- * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan). */
+ * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, or
+ * a basis whose operator kernel does not fit the LDS at 8 rows per workgroup). */
 int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 

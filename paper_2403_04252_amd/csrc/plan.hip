@@ -66,6 +66,7 @@ struct wpccc_plan_s {
     hipEvent_t g_copied = nullptr;
     long long bytes = 0;
     int stage_smem = 0;       // k_apply (kRowsPerBlock rows)
+    bool apply_ok = true;     // k_apply's LDS fits (wpccc_adjoint is available)
     int stage_rows = kRowsPerBlock;
     int stage_smem_rows = 0;  // k_stage with stage_rows
     // propagation chunks kernel by kernel (WPCCC_LAUNCH_STAGES) or as one
@@ -664,7 +665,16 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         free_plan(plan);
         return WPCCC_EINVAL;
     }
-    plan->stage_rows = o.stage_rows ? o.stage_rows : kRowsPerBlock;
+    // untimed default tiling: kRowsPerBlock rows, or the largest admissible
+    // smaller tiling whose LDS fits (large bases)
+    int rows0 = o.stage_rows;
+    if (!rows0) {
+        rows0 = kRowsPerBlock;
+        if (stage_smem_bytes(m, rows0) > kMaxDynLds)
+            for (int r : kStageRowsList)
+                if (r < kRowsPerBlock && stage_smem_bytes(m, r) <= kMaxDynLds) rows0 = r;
+    }
+    plan->stage_rows = rows0;
     plan->stage_smem_rows = stage_smem_bytes(m, plan->stage_rows);
     if (!stage_rows_fit(m, plan->stage_rows)) {
         set_error("wpccc_plan_create: stage_rows %d is too many for l_max = %d (rows x (2 l_max + 1) must not "
@@ -672,11 +682,14 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         free_plan(plan);
         return WPCCC_EINVAL;
     }
-    if (plan->stage_smem > kMaxDynLds || plan->stage_smem_rows > kMaxDynLds) {
-        set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes)", plan->stage_smem);
+    if (plan->stage_smem_rows > kMaxDynLds) {
+        set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes at %d rows)",
+                  plan->stage_smem_rows, plan->stage_rows);
         free_plan(plan);
         return WPCCC_ENOTSUP;
     }
+    // the adjoint's operator kernel (k_apply, kRowsPerBlock rows)
+    plan->apply_ok = plan->stage_smem <= kMaxDynLds;
     long long& tot = plan->bytes;
     tot = plan->c.bytes;
     TRY(dev_alloc(&plan->d_b, (size_t)n_traj, tot));
@@ -977,6 +990,10 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
     }
     if (plan->p2c) {
         set_error("wpccc_adjoint: one-centre plans only");
+        return WPCCC_ENOTSUP;
+    }
+    if (!plan->apply_ok) {
+        set_error("wpccc_adjoint: basis too large for the operator kernel's LDS (%d bytes)", plan->stage_smem);
         return WPCCC_ENOTSUP;
     }
     int rc = check_grid(zgrid_host, n_points);

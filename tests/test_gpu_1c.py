@@ -256,6 +256,36 @@ def test_large_l_basis_parity():
     assert e.value.code == -6
 
 
+def test_paper_shape_l6_smaller_tiles():
+    """The paper's basis shape at l_max = 6 (N_l = 42 - l radial functions per
+    l, N = 1855): a stage tile of 8 rows (and the adjoint's operator kernel)
+    no longer fits the LDS, so the plan times the smaller tilings that do.
+    One path, 6 steps, against the oracle; 8 rows explicitly and the adjoint
+    are refused with WPCCC_ENOTSUP."""
+    rec = WL.Recipe(10, 6, 32, 3.0, 300, 100.0)
+    lb, ob = lib_basis(rec), oracle_basis(rec)
+    zg = np.linspace(-3.0, -2.4, 7)
+    print("paper shape l_max = 6 (N = 1855), 1 path x 6 steps", flush=True)
+    plan = W.wpccc_plan_create(lb, [1.5], [2.0])
+    assert plan.n_states == 1855
+    rows = W.wpccc_plan_stage_rows(plan)
+    print(f"  timed tiling: {rows} rows", flush=True)
+    assert rows < 8
+    X, P, _ = _propagate_gpu(lb, [1.5], [2.0], zg)
+    Xo = propagate_one_centre(ob, 1.5, 2.0, zg)
+    assert np.abs(X[0] - Xo).max() <= 1e-12, np.abs(X[0] - Xo).max()
+    assert prob_ok(P[0], probabilities(Xo)).all()
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create(lb, [1.5], [2.0], stage_rows=8)
+    assert e.value.code == -6
+    X0 = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X0[:, 0] = 1.0
+    grad = torch.empty((plan.n_traj, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_adjoint(plan, zg, X0, X0.clone(), grad)
+    assert e.value.code == -6
+
+
 def test_stage_rows_limit():
     """Every output of a stage workgroup needs a lane of the phase-3
     reduction: rows x (2 l_max + 1) <= 256, so 16 rows are refused for
