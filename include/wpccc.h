@@ -226,6 +226,21 @@ int wpccc_plan_status(wpccc_plan_t plan, void* stream);
 int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev,
                     void* stream);
 
+/* Allocation-free form of wpccc_couplings for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, output and errors as
+ * wpccc_couplings for a one-centre plan; the per-point intermediates
+ * (radial integrals, angular factors, phases) go to a fixed device array of
+ * 8 MiB that the library holds on each GPU until the process ends (its
+ * address is looked up once per device, on the first call there) instead of
+ * the plan's workspace.  The call allocates nothing and calls no allocating
+ * routine.  Every call on one GPU shares that array: calls that overlap in
+ * time on one GPU (other streams or threads) race and must be serialised by
+ * the caller.  Errors: as wpccc_couplings; WPCCC_ENOTSUP for a two-centre
+ * plan or a basis whose intermediates exceed the 8 MiB. */
+int wpccc_couplings_noalloc(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev,
+                            void* stream);
+
 /* One RK4 step of Algorithm 1 from z to z + h for every path of the plan:
  * M is evaluated at z, z + h/2 and z + h.  X_dev: complex [n_traj][n_pad],
  * updated in place (entries beyond N are left untouched).

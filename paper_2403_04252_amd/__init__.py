@@ -18,7 +18,7 @@ __all__ = [
     "wpccc_version", "wpccc_basis", "wpccc_basis_info", "wpccc_basis_export",
     "wpccc_basis_destroy", "wpccc_plan_create", "wpccc_plan_create_2c", "wpccc_plan_info",
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
-    "wpccc_plan_status", "wpccc_couplings", "wpccc_step", "wpccc_propagate",
+    "wpccc_plan_status", "wpccc_couplings", "wpccc_couplings_noalloc", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
     "wpccc_plan_stage_launch", "wpccc_measure_mfma", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
@@ -100,6 +100,7 @@ def load_library():
         "wpccc_plan_destroy": ([vp], i),
         "wpccc_plan_status": ([vp, vp], i),
         "wpccc_couplings": ([vp, i, d, vp, vp, vp], i),
+        "wpccc_couplings_noalloc": ([vp, i, d, vp, vp, vp], i),
         "wpccc_step": ([vp, vp, d, d, vp], i),
         "wpccc_propagate": ([vp, pd, i, vp, vp, vp, vp], i),
         "wpccc_adjoint": ([vp, pd, i, vp, vp, vp, vp, vp], i),
@@ -306,6 +307,15 @@ def wpccc_couplings(plan: Plan, j: int, z: float, H, S=None, stream=None):
     _check(load_library().wpccc_couplings(plan.handle, int(j), float(z),
                                           _dev_ptr(H, "complex128", (N, N), "H"),
                                           _dev_ptr(S, "complex128", (N, N), "S"), _stream_ptr(stream)))
+
+
+def wpccc_couplings_noalloc(plan: Plan, j: int, z: float, H, S=None, stream=None):
+    """As wpccc_couplings (one-centre plans), with the library's fixed per-device
+    scratch array instead of the plan's workspace: allocates nothing."""
+    N = wpccc_plan_path_info(plan, j)[0]
+    _check(load_library().wpccc_couplings_noalloc(plan.handle, int(j), float(z),
+                                                  _dev_ptr(H, "complex128", (N, N), "H"),
+                                                  _dev_ptr(S, "complex128", (N, N), "S"), _stream_ptr(stream)))
 
 
 def wpccc_step(plan: Plan, X, z: float, h: float, stream=None):

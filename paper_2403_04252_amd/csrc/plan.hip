@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string>
@@ -862,6 +863,93 @@ int wpccc_plan_status(wpccc_plan_t plan, void* stream) {
     return WPCCC_OK;
 }
 
+}  // extern "C"
+
+// Device scratch of wpccc_couplings_noalloc: the radial integrals, angular
+// factors and phases of one path at one point, each part starting on a
+// 256-byte boundary.  Each GPU the library runs on holds its own copy for the
+// life of the process; host code uses only the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// Argument checks shared by wpccc_couplings and wpccc_couplings_noalloc for a
+// one-centre plan.
+int couplings_1c_check(const char* fn, wpccc_plan_t plan, int j, double z, void* S_dev) {
+    if (j < 0 || j >= plan->n_traj) {
+        set_error("%s: path index out of range", fn);
+        return WPCCC_EINVAL;
+    }
+    if (S_dev) {
+        set_error("%s: S_dev must be NULL for a one-centre plan", fn);
+        return WPCCC_EINVAL;
+    }
+    if (!(std::sqrt(plan->b[j] * plan->b[j] + z * z) > 0.0)) {
+        set_error("%s: R = 0", fn);
+        return WPCCC_EINVAL;
+    }
+    return WPCCC_OK;
+}
+
+// Dense one-centre couplings of path j at z: k_slot_setup fills the radial
+// integrals Frow, the angular factors G and the phases PH of the point (every
+// element is written), k_couplings_dense combines them into H.
+int couplings_1c(wpccc_plan_t plan, int j, double z, double* Frow, double* G, double2* PH, void* H_dev,
+                 hipStream_t st) {
+    const Meta& m = plan->c.meta;
+    SetupArgs a;
+    a.meta = plan->c.d_meta;
+    a.tb = plan->tables();
+    a.z = z;
+    a.j = j;
+    a.Frow = Frow;
+    a.G = G;
+    a.PH = PH;
+    a.nbF = (m.n_frow + 255) / 256;
+    a.nbP = (m.n_states + 255) / 256;
+    hipError_t e = launch_slot_setup(a, m, st, plan->timer.open(kSetup));
+    int rc = launched(e, "k_slot_setup");
+    if (rc) return rc;
+    e = launch_couplings_dense(plan->c.d_meta, m, Frow, G, PH, plan->Zp, (double2*)H_dev, st,
+                               plan->timer.open(kDense));
+    return launched(e, "k_couplings_dense");
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+    int dev = 0;
+    WPCCC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("wpccc_couplings_noalloc: device ordinal %d beyond the library's %d", dev, kMaxDevices);
+        return WPCCC_ENOTSUP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("wpccc_couplings_noalloc: hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return WPCCC_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return WPCCC_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
 int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev, void* stream) {
     clear_error();
     if (!plan || !H_dev || !std::isfinite(z)) {
@@ -870,35 +958,37 @@ int wpccc_couplings(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev
     }
     hipStream_t st = (hipStream_t)stream;
     if (plan->p2c) return plan2c_couplings(plan->p2c, j, z, H_dev, S_dev, st);
-    if (j < 0 || j >= plan->n_traj) {
-        set_error("wpccc_couplings: path index out of range");
-        return WPCCC_EINVAL;
-    }
-    if (S_dev) {
-        set_error("wpccc_couplings: S_dev must be NULL for a one-centre plan");
-        return WPCCC_EINVAL;
-    }
-    if (!(std::sqrt(plan->b[j] * plan->b[j] + z * z) > 0.0)) {
-        set_error("wpccc_couplings: R = 0");
-        return WPCCC_EINVAL;
-    }
-    const Meta& m = plan->c.meta;
-    SetupArgs a;
-    a.meta = plan->c.d_meta;
-    a.tb = plan->tables();
-    a.z = z;
-    a.j = j;
-    a.Frow = plan->d_Frow1;
-    a.G = plan->d_G1;
-    a.PH = plan->d_PH1;
-    a.nbF = (m.n_frow + 255) / 256;
-    a.nbP = (m.n_states + 255) / 256;
-    hipError_t e = launch_slot_setup(a, m, st, plan->timer.open(kSetup));
-    int rc = launched(e, "k_slot_setup");
+    const int rc = couplings_1c_check("wpccc_couplings", plan, j, z, S_dev);
     if (rc) return rc;
-    e = launch_couplings_dense(plan->c.d_meta, m, plan->d_Frow1, plan->d_G1, plan->d_PH1, plan->Zp,
-                               (double2*)H_dev, st, plan->timer.open(kDense));
-    return launched(e, "k_couplings_dense");
+    return couplings_1c(plan, j, z, plan->d_Frow1, plan->d_G1, plan->d_PH1, H_dev, st);
+}
+
+int wpccc_couplings_noalloc(wpccc_plan_t plan, int j, double z, void* H_dev, void* S_dev, void* stream) {
+    clear_error();
+    if (!plan || !H_dev || !std::isfinite(z)) {
+        set_error("wpccc_couplings_noalloc: bad plan, H_dev or z");
+        return WPCCC_EINVAL;
+    }
+    if (plan->p2c) {
+        set_error("wpccc_couplings_noalloc: one-centre plans only");
+        return WPCCC_ENOTSUP;
+    }
+    int rc = couplings_1c_check("wpccc_couplings_noalloc", plan, j, z, S_dev);
+    if (rc) return rc;
+    const Meta& m = plan->c.meta;
+    const size_t nF = align256((size_t)m.n_frow * sizeof(double));
+    const size_t nG = align256((size_t)m.n_g * sizeof(double));
+    const size_t need = nF + nG + align256((size_t)m.n_states * sizeof(double2));
+    if (need > kNoAllocScratchBytes) {
+        set_error("wpccc_couplings_noalloc: the basis needs %zu bytes of scratch, more than the %zu the "
+                  "library holds per device", need, kNoAllocScratchBytes);
+        return WPCCC_ENOTSUP;
+    }
+    void* base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    char* s = static_cast<char*>(base);
+    return couplings_1c(plan, j, z, reinterpret_cast<double*>(s), reinterpret_cast<double*>(s + nF),
+                        reinterpret_cast<double2*>(s + nF + nG), H_dev, (hipStream_t)stream);
 }
 
 int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream) {
