@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
     ap.add_argument("--no-2c", action="store_true",
                     help="c2: skip the short two-centre measurement added to the output line")
+    ap.add_argument("--no-seeded", action="store_true",
+                    help="c2: skip the seeded 64-path FP64 / mixed comparison added to the output line")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing line")
@@ -193,6 +195,8 @@ def main():
     W.wpccc_plan_status(plan)
     wall = t1 - t0
     value = n_traj * args.steps / wall
+    # probability error of the timed run against the oracle's stored full paths
+    golden_err = golden_prob_error(torch, X, n_states, w, args.steps, "c2_paths.npz")
 
     # the same K steps again with per-kernel HIP events on the library's stream
     X.zero_()
@@ -271,7 +275,7 @@ def main():
     del src, dst
 
     cpu = None
-    prob_err = None
+    prob_err_sample = None
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_info
         from oracle.propagate import probabilities, propagate_one_centre
@@ -286,10 +290,14 @@ def main():
         t0 = time.perf_counter()
         Xo = propagate_one_centre(ob, w.b[0], w.v[0], zs)
         dt = time.perf_counter() - t0
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        blas = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        affinity = len(os.sched_getaffinity(0))
+        threads = min(blas, affinity)
         cpu = {"value": S / dt, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
+               "affinity_cores": affinity,
                "sample": f"path b={w.b[0]:.4g} of the workload, first {S} of its 800 RK4 steps "
-                         f"(numpy FP64, {threads} BLAS threads), basis setup excluded"}
+                         f"(numpy FP64, {blas} BLAS threads on {affinity} cores of the affinity mask), "
+                         f"basis setup excluded"}
         # probability error of the GPU path on the same sample
         plan1 = W.wpccc_plan_create(lb, w.b[:1], w.v[:1])
         X1 = torch.zeros((1, plan1.n_pad), dtype=torch.complex128, device="cuda")
@@ -299,9 +307,10 @@ def main():
         Pg = (X1.abs() ** 2).cpu().numpy()[0, :n_states]
         Po = probabilities(Xo)
         dP = np.abs(Pg - Po)
-        prob_err = {"max_abs": float(dP.max()),
-                    "max_rel_floored": float((dP / np.maximum(Po, P_FLOOR)).max()),
-                    "floor": P_FLOOR, "sample": cpu["sample"]}
+        prob_err_sample = {"max_abs": float(dP.max()),
+                           "max_rel_floored": float((dP / np.maximum(Po, P_FLOOR)).max()),
+                           "floor": P_FLOOR, "sample": cpu["sample"]}
+    prob_err = golden_err if golden_err is not None else prob_err_sample
 
     out = {
         "metric": METRIC,
@@ -324,21 +333,95 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "prob_error": prob_err,
+        "prob_error_cpu_sample": prob_err_sample,
         "plain_fp64_sequential": seq,
         "kernel_times": kernel_times,
     }
+    if not args.no_seeded:
+        out["seeded_fp64_vs_mixed"] = seeded_measure(torch, W, WL)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_measure(torch, W, WL)
     if not args.no_2c:
-        # secondary: a few batched two-centre steps, FP64 and mixed
+        # secondary: batched two-centre steps through closest approach, FP64
+        # and mixed, at each of the workload's three speeds
         del plan
         torch.cuda.empty_cache()
         out["two_centre"] = {}
-        for mixed in (False, True):
-            r = two_centre_measure(args, 3, 1, mixed=mixed)
-            out["two_centre"]["mixed" if mixed else "fp64"] = {
-                k: r[k] for k in ("value", "unit", "ms_per_step", "roofline", "lu", "config")}
+        for v in (0.5, 1.0, 2.0):
+            args.v = v
+            pair = two_centre_pair(args, 20, 1)
+            out["two_centre"][f"v={v:g}"] = pair
     print(json.dumps(out), flush=True)
+
+
+def golden_prob_error(torch, X, n_states, w, steps, name):
+    """max |dP| (absolute and relative with the floor) of the final probabilities
+    of a whole-grid run against the oracle's stored paths (tests/golden/),
+    or None when the run did not cover the whole grid or nothing is stored."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if steps != w.zgrid.size - 1 or not os.path.exists(path):
+        return None
+    g = np.load(path)
+    Pg = (X.abs() ** 2).cpu().numpy()[:, :n_states]
+    dmax = rmax = 0.0
+    for k, j in enumerate(g["paths"]):
+        d = np.abs(Pg[j] - g["P"][k])
+        dmax = max(dmax, float(d.max()))
+        rmax = max(rmax, float((d / np.maximum(g["P"][k], P_FLOOR)).max()))
+    return {"max_abs": dmax, "max_rel_floored": rmax, "floor": P_FLOOR,
+            "sample": f"final probabilities of paths {list(map(int, g['paths']))} after all "
+                      f"{steps} steps of the timed run against the FP64 oracle's stored paths"}
+
+
+def seeded_measure(torch, W, WL, repeats=3):
+    """The seeded workload (the N = 580 basis, 64 impact parameters, all 800
+    steps) in FP64 and in the reduced-precision form: rates (median of
+    `repeats` whole-grid runs after one warm-up) and every probability of the
+    mixed run against the FP64 run and against the oracle's stored paths."""
+    w = WL.single_centre_seeded()
+    rec = w.basis
+    lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+    res, Pf = {}, {}
+    for mixed in (False, True):
+        plan = W.wpccc_plan_create(lb, w.b, w.v, mixed=mixed)
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        times = []
+        for rep in range(repeats + 1):
+            X.zero_()
+            X[:, 0] = 1.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            W.wpccc_propagate(plan, w.zgrid, X)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t0)
+        W.wpccc_plan_status(plan)
+        wall = float(np.median(times))
+        steps = w.zgrid.size - 1
+        Pf[mixed] = (X.abs() ** 2).cpu().numpy()[:, :plan.n_states]
+        res["mixed" if mixed else "fp64"] = {
+            "value": plan.n_traj * steps / wall, "unit": "trajectory-steps/s", "ms_per_step": wall / steps * 1e3,
+            "dtype": "f64 (moment tables f32)" if mixed else "f64", "stage_rows": W.wpccc_plan_stage_rows(plan),
+            "device_bytes": plan.device_bytes}
+        del plan
+    d = np.abs(Pf[True] - Pf[False])
+    res["mixed"]["prob_error_vs_fp64_gpu"] = {
+        "max_abs": float(d.max()), "max_rel": float((d / np.maximum(Pf[False], 1e-300)).max()),
+        "within_bar": bool(np.all((d <= 1e-6) | (d <= 1e-4 * Pf[False]))),
+        "sample": "every probability of all 64 paths after 800 steps"}
+    g = os.path.join(ROOT, "tests", "golden", "c4_paths.npz")
+    if os.path.exists(g):
+        g = np.load(g)
+        for key, P in (("fp64", Pf[False]), ("mixed", Pf[True])):
+            dd = np.concatenate([np.abs(P[j] - g["P"][k]) for k, j in enumerate(g["paths"])])
+            ref = np.concatenate([g["P"][k] for k in range(len(g["paths"]))])
+            res[key]["prob_error_vs_oracle"] = {
+                "max_abs": float(dd.max()), "max_rel_floored": float((dd / np.maximum(ref, P_FLOOR)).max()),
+                "floor": P_FLOOR, "sample": f"paths {list(map(int, g['paths']))} of 64, oracle's stored run"}
+    res["mixed_over_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    res["workload"] = ("p+H 1C N=580 (n<=6 + 20 bins/l, l<=4), 4000-pt grid, 64 b log-uniform 0.05-20 "
+                       "(default_rng(4)), v=1, z -40..40 dz=0.1")
+    return res
 
 
 def bench_sweep(args):
@@ -460,8 +543,31 @@ def bench_two_centre(args):
     print(json.dumps(out), flush=True)
 
 
-def two_centre_measure(args, steps, warmup, mixed=False):
-    """Time `steps` RK4 steps of the batched two-centre workload; returns the result dict."""
+def two_centre_pair(args, steps, warmup, z0=-1.0):
+    """FP64 and mixed two-centre rates over `steps` steps of 0.1 from z0 (through
+    closest approach by default), both from the same seeded random state, and
+    the mixed probabilities against the FP64 ones at the end of the stretch."""
+    r64 = two_centre_measure(args, steps, warmup, mixed=False, z0=z0)
+    rmx = two_centre_measure(args, steps, warmup, mixed=True, z0=z0)
+    P64, Pmx = r64.pop("P_final"), rmx.pop("P_final")
+    d = np.abs(Pmx - P64)
+    keep = ("value", "unit", "ms_per_step", "roofline", "lu", "config", "kernel_times")
+    out = {"fp64": {k: r64[k] for k in keep}, "mixed": {k: rmx[k] for k in keep}}
+    out["fp64"]["dtype"] = "f64"
+    out["mixed"]["dtype"] = "f64 (contraction products f32)"
+    out["mixed"]["prob_error_vs_fp64_gpu"] = {
+        "max_abs": float(d.max()), "max_rel": float((d / np.maximum(P64, 1e-300)).max()),
+        "within_bar": bool(np.all((d <= 1e-6) | (d <= 1e-4 * P64))),
+        "sample": f"every probability of the 24 paths after the {steps} timed steps from a seeded random state"}
+    out["mixed_over_fp64"] = rmx["value"] / r64["value"]
+    return out
+
+
+def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
+    """Time `steps` RK4 steps of the batched two-centre workload; returns the
+    result dict.  z0 None: the workload's grid from its start, amplitudes from
+    e_0; else `steps` steps of 0.1 from z0 from a seeded random state (the
+    final probabilities are returned as "P_final")."""
     import torch
     from scipy.special import roots_laguerre
     import paper_2403_04252_amd as W
@@ -479,12 +585,20 @@ def two_centre_measure(args, steps, warmup, mixed=False):
     setup_s = time.perf_counter() - t0
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
-    X[:, 0] = 1.0
-    run_propagation(W, plan, X, w.zgrid, warmup)
+    if z0 is None:
+        zs = w.zgrid[: steps + 1]
+        X0 = X.clone()
+        X0[:, 0] = 1.0
+    else:
+        zs = z0 + 0.1 * np.arange(steps + 1)
+        X0 = X.clone()
+        for j in range(n_traj):
+            N = W.wpccc_plan_path_info(plan, j)[0]
+            X0[j, :N] = torch.from_numpy(WL.random_state(1, N, seed=100 + j)[0]).cuda()
+    X.copy_(X0)
+    run_propagation(W, plan, X, zs, warmup)
     torch.cuda.synchronize()
-    X.zero_()
-    X[:, 0] = 1.0
-    zs = w.zgrid[: steps + 1]
+    X.copy_(X0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     W.wpccc_propagate(plan, zs, X)
@@ -492,10 +606,10 @@ def two_centre_measure(args, steps, warmup, mixed=False):
     wall = time.perf_counter() - t0
     W.wpccc_plan_status(plan)
     value = n_traj * steps / wall
+    P_final = (X.abs() ** 2).cpu().numpy()
 
     # per-kernel device time over the same steps (events on the library's stream)
-    X.zero_()
-    X[:, 0] = 1.0
+    X.copy_(X0)
     W.wpccc_plan_timing(plan, True)
     W.wpccc_propagate(plan, zs, X)
     names = ["k_2c_contract", "k_2c_reduce", "k_2c_interp", "k_2c_nodes", "k_2c_assemble", "k_setup_batch",
@@ -553,7 +667,7 @@ def two_centre_measure(args, steps, warmup, mixed=False):
         "data": "synthetic",
         "config": {"workload": w.name + ": same recipe on both centres (n<=6 + 20 bins/l, l<=1/2/3), "
                                "4000-pt grid, 8 b log-spaced 0.2-10 per size, 256x512 nodes, "
-                               f"z -40..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
+                               f"z {zs[0]:.1f}..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
                    "form": "batched mixed (FP32 contraction products)" if mixed else "batched FP64",
                    "n_paths": n_traj, "plan_setup_s": setup_s,
                    "parallelism": "1 GPU, paths batched per basis size"},
@@ -563,6 +677,8 @@ def two_centre_measure(args, steps, warmup, mixed=False):
         "kernel_times": kt,
         "cpu_baseline": None,
     }
+    if z0 is not None:
+        out["P_final"] = P_final
     return out
 
 

@@ -138,10 +138,16 @@ typedef struct {
                        6, 7, 8, 10, 12 or 16, with rows x (2 l_max + 1) <= 256
                        (WPCCC_EINVAL otherwise); 0: chosen at plan creation by
                        timing each admissible value on the plan's paths */
-    int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED: 2C overlap/transfer
+    int precision;  /* WPCCC_FP64 (default) or WPCCC_MIXED.  2C: overlap/transfer
                        contractions with FP32 products summed in FP32 over each
-                       64-node chunk and in FP64 across chunks; LU, solves and
-                       RK4 stay FP64 */
+                       64-node chunk and in FP64 across chunks.  1C: the radial
+                       moment tables of Eq. D2 stored in FP32 in scaled form,
+                       (A_k / r_k^(lam+1), B_(k+1) r_(k+1)^lam), read at half the
+                       bytes and combined with the R factors in FP64 (one
+                       rounding per stored integral).  LU, solves, the angular
+                       sums and RK4 stay FP64.  A 1C mixed plan runs one launch
+                       per stage (WPCCC_ENOTSUP with WPCCC_LAUNCH_PERSISTENT)
+                       and has no adjoint. */
     int graph;      /* 1C, batched: replay each 64-step chunk of wpccc_propagate
                        from a captured HIP graph (step lengths and positions
                        read from device memory); 0: launch kernel by kernel */
@@ -275,8 +281,9 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
  *   gX_dev    complex [n_traj][n_pad], dL/d conj(X) at the last point (read)
  *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
  * Device memory for the checkpoints is allocated by the first call.  Errors:
- * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, or
- * a basis whose operator kernel does not fit the LDS at 8 rows per workgroup). */
+ * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, a
+ * WPCCC_MIXED plan, or a basis whose operator kernel does not fit the LDS at 8
+ * rows per workgroup). */
 int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 

@@ -23,6 +23,9 @@
 // in a different association order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <type_traits>
+
 #include "plan.h"
 
 namespace wpccc {
@@ -110,15 +113,17 @@ __device__ void legendre_column_dx(int lam_max, int mu, double x, double* pb) {
     }
 }
 
-// Last grid node with r_k <= R; the nodes r_k = r_max (k/n_r)^2 are recomputed
-// in registers with the same arithmetic as the host grid.
+// Grid node r_k = r_max (k/n_r)^2, with the same arithmetic as the host grid.
+__device__ inline double node_r(int k, double r_max, int n_r) {
+    const double x = (double)k / n_r;
+    return r_max * x * x;
+}
+
+// Last grid node with r_k <= R (nodes recomputed in registers).
 __device__ inline int grid_index(double R, double r_max, int n_r) {
     int k = (int)floor(n_r * sqrt(fmin(R / r_max, 1.0)));
     k = max(0, min(k, n_r));
-    auto rk = [&](int q) {
-        const double x = (double)q / n_r;
-        return r_max * x * x;
-    };
+    auto rk = [&](int q) { return node_r(q, r_max, n_r); };
     while (k < n_r && rk(k + 1) <= R) ++k;
     while (k > 0 && rk(k) > R) --k;
     return k;
@@ -129,6 +134,50 @@ __device__ inline double radial_at(double2 ab, double R, int lam) {
     double Rl = 1.0;
     for (int q = 0; q < lam; ++q) Rl *= R;
     return ab.x / (Rl * R) + ab.y * Rl;
+}
+
+// The R factors of the scaled FP32 table at node k <= R's interval:
+// (r_k/R)^(lam+1) (0 at k = 0) and (R/r_(k+1))^lam (0 at k = n_r), both in
+// [0, 1] because r_k <= R < r_(k+1).
+__device__ inline void scaled_factors(double R, int k, int lam, double r_max, int n_r, double* fa, double* fb) {
+    const double qa = k > 0 ? node_r(k, r_max, n_r) / R : 0.0;
+    const double qb = k < n_r ? R / node_r(k + 1, r_max, n_r) : 0.0;
+    double a = qa, b = 1.0;
+    for (int q = 0; q < lam; ++q) {
+        a *= qa;
+        b *= qb;
+    }
+    *fa = a;
+    *fb = k < n_r ? b : 0.0;
+}
+
+// Scaled single-precision copy of the moment table, one thread per (entry d,
+// node k): x = A_k / r_k^(lam+1) (0 at k = 0), y = B_(k+1) r_(k+1)^lam (0 at
+// k = n_r).  F(R) = x (r_k/R)^(lam+1) + y (R/r_(k+1))^lam is the same
+// quadrature as the FP64 table's; the stored values are of the size of the
+// integrals (no powers of r that leave FP32's range), rounded once.
+__global__ void k_table_f32(const double2* __restrict__ tab, const int* __restrict__ dl, int n_frow, int n_r,
+                            double r_max, float2* __restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (d >= n_frow) return;
+    const int lam = dl[d];
+    const size_t i = (size_t)k * n_frow + d;
+    const double2 ab = tab[i];
+    double x = 0.0, y = 0.0;
+    if (k > 0) {
+        const double rk = node_r(k, r_max, n_r);
+        double p = rk;
+        for (int q = 0; q < lam; ++q) p *= rk;
+        x = ab.x / p;
+    }
+    if (k < n_r) {
+        const double rk1 = node_r(k + 1, r_max, n_r);
+        double p = 1.0;
+        for (int q = 0; q < lam; ++q) p *= rk1;
+        y = ab.y * p;
+    }
+    out[i] = make_float2((float)x, (float)y);
 }
 
 __device__ inline double2 phase(double eps, double z, double v) {
@@ -148,12 +197,17 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     const double R = sqrt(b * b + z * z);
     const size_t jp = (size_t)j * a.pt.n_pts + p;
     const int t = threadIdx.x;
-    if (t == 0) a.pt.kidx[jp] = grid_index(R, m.r_max, m.n_r);
+    const int k = grid_index(R, m.r_max, m.n_r);
+    if (t == 0) a.pt.kidx[jp] = k;
     if (t <= m.lam_max) {
-        double Rl = 1.0;
-        for (int q = 0; q < t; ++q) Rl *= R;
-        a.pt.rpow[jp * kRpow + 2 * t] = 1.0 / (Rl * R);
-        a.pt.rpow[jp * kRpow + 2 * t + 1] = Rl;
+        if (a.tb.tab32) {
+            scaled_factors(R, k, t, m.r_max, m.n_r, &a.pt.rpow[jp * kRpow + 2 * t], &a.pt.rpow[jp * kRpow + 2 * t + 1]);
+        } else {
+            double Rl = 1.0;
+            for (int q = 0; q < t; ++q) Rl *= R;
+            a.pt.rpow[jp * kRpow + 2 * t] = 1.0 / (Rl * R);
+            a.pt.rpow[jp * kRpow + 2 * t + 1] = Rl;
+        }
         legendre_column(m.lam_max, t, z / R, a.pt.pbar + jp * kMaxPb);
     }
     for (int f = t; f < m.n_f; f += blockDim.x) a.pt.ph[jp * m.n_f + f] = phase(a.tb.rad_eps[f], z, v);
@@ -281,13 +335,20 @@ __host__ __device__ inline bool phase3_fits(int rows, int nmp_max) { return rows
 // KIND 0: RK4 stage (k_stage); KIND 1: operator application (k_apply, see
 // StageArgs) with the same three phases.
 //   phase 0: every independent global load of the stage is issued at once
-//            (table entries, stage input, coefficients) and the per-point
-//            tables (R powers, Pbar, phases) go to LDS;
-//   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam, G_l' = c Pbar  -> LDS
+//            (table entries or cached F, stage input, coefficients) and the
+//            per-point tables (R powers, Pbar, phases) go to LDS;
+//   phase 1: x' = conj(ph) u, F_l'[rows][:] = A R^-(lam+1) + B R^lam (or the
+//            cached F), G_l' = c Pbar  -> LDS
 //   phase 2: W[r][g] = sum_n F_l'[r][e0(g) + n] x'_{l(g), q(g), n}
 //   phase 3: y[r][q'] = sum_g G_l'[q'][g] W[r][g];  K = -(i/v) Zp ph y; RK4 update.
-template <int KIND, int ROWS>
+//   phase 4 (FC with a.fc_next): F of the rows at point a.p_next from the
+//            moment-table entries loaded in phase 0 -> a.fc_next.
+// F32: the moment table is the scaled FP32 form.  FC: F at the stage's point
+// comes from the radial-integral cache a.fc_cur (KIND 0 only).
+template <int KIND, int ROWS, bool F32 = false, bool FC = false>
 __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* smem) {
+    // moment-table entries: FP64 (A_k, B_(k+1)) or the scaled FP32 form
+    using TabT = typename std::conditional<F32, float2, double2>::type;
     const Meta& m = *a.meta;
     const Tables& T = a.tb;
     const int N = m.n_states;
@@ -310,17 +371,29 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
     int2* gis = reinterpret_cast<int2*>(pbs + kMaxPb);                     // [gcols]
 
     // phase 0
-    const int k = a.pt.kidx[jp];
-    const double2* row = T.tab + (size_t)k * m.n_frow + t.frow_off + (size_t)row0 * nV;
+    // the moment-table rows are read at this stage's point (no cache) or at
+    // the cache's next point (FC with fc_next)
+    const bool tab_rows = !FC || a.fc_next != nullptr;
+    const size_t jt = FC ? (size_t)j * a.pt.n_pts + a.p_next : jp;
+    const int k = tab_rows ? a.pt.kidx[jt] : 0;
+    const TabT* tab = nullptr;
+    if constexpr (F32) tab = T.tab32;
+    else tab = T.tab;
+    const TabT* row = tab + (size_t)k * m.n_frow + t.frow_off + (size_t)row0 * nV;
+    // cached F: FP64, or FP32 for the scaled FP32 table
+    using FcT = typename std::conditional<F32, float, double>::type;
+    const FcT* frow = FC ? static_cast<const FcT*>(a.fc_cur) + (size_t)j * m.n_frow + t.frow_off + (size_t)row0 * nV
+                         : nullptr;
     const int* cl = T.col_lam + t.col_off;
     const int totF = nrows * nV;
     constexpr int FB = fbatch(ROWS);
-    double2 tv[FB];
+    TabT tv[FB];
     int lv[FB];
+    FcT fv[FC ? FB : 1];
     // Every lane loads (past the end: a clamped, in-bounds index whose value
-    // is not used), so that all loads of phase 0 are issued back to back
+    // is not used), so that all loads of a batch are issued back to back
     // before the first wait: one memory round trip instead of one per batch.
-    {
+    auto load_table_rows = [&]() {
         int q = tid % nV;
         const int dq = B % nV;
 #pragma unroll
@@ -330,6 +403,14 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
             q += dq;
             if (q >= nV) q -= nV;
         }
+    };
+    if (FC) {
+        // the next point's table rows are loaded after phase 1, so that they
+        // arrive during phases 2 and 3 instead of delaying the first wait
+#pragma unroll
+        for (int i = 0; i < (FC ? FB : 0); ++i) fv[i] = frow[min(tid + i * B, totF - 1)];
+    } else {
+        load_table_rows();
     }
     // stage input (KIND 1: v = cu1 u_in + cu2 u_in2)
     const double2* u = a.u_in + (size_t)j * a.n_pad;
@@ -408,7 +489,7 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
     // (larger tables: the rest is loaded below)
     const int n_rp = 2 * (m.lam_max + 1), n_pb = (m.lam_max + 1) * (m.lam_max + 2) / 2;
     const int2 gv = T.gcol_info[t.gcol_off + min(tid, gcols - 1)];
-    const double rpv = a.pt.rpow[jp * kRpow + min(tid, n_rp - 1)];
+    const double rpv = tab_rows ? a.pt.rpow[jt * kRpow + min(tid, n_rp - 1)] : 0.0;
     const double pbv = a.pt.pbar[jp * kMaxPb + min(tid, n_pb - 1)];
     const double2 phv = a.pt.ph[jp * m.n_f + min(tid, m.n_f - 1)];
     // every load above is issued before any of their values is used
@@ -449,15 +530,24 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
         const double2 ph = phs[T.st_rad[idx]], x = load_u(idx);
         xs[T.st_xs[idx]] = make_double2(ph.x * x.x + ph.y * x.y, ph.x * x.y - ph.y * x.x);
     }
+    if (FC) {
 #pragma unroll
-    for (int i = 0; i < FB; ++i) {
-        const int idx = tid + i * B;
-        if (idx < totF) Fs[idx] = tv[i].x * rps[2 * lv[i]] + tv[i].y * rps[2 * lv[i] + 1];
-    }
-    for (int idx = tid + FB * B; idx < totF; idx += B) {
-        const double2 t0 = row[idx];
-        const int l0 = cl[idx % nV];
-        Fs[idx] = t0.x * rps[2 * l0] + t0.y * rps[2 * l0 + 1];
+        for (int i = 0; i < (FC ? FB : 0); ++i) {
+            const int idx = tid + i * B;
+            if (idx < totF) Fs[idx] = (double)fv[i];
+        }
+        for (int idx = tid + FB * B; idx < totF; idx += B) Fs[idx] = (double)frow[idx];
+    } else {
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+            const int idx = tid + i * B;
+            if (idx < totF) Fs[idx] = (double)tv[i].x * rps[2 * lv[i]] + (double)tv[i].y * rps[2 * lv[i] + 1];
+        }
+        for (int idx = tid + FB * B; idx < totF; idx += B) {
+            const TabT t0 = row[idx];
+            const int l0 = cl[idx % nV];
+            Fs[idx] = (double)t0.x * rps[2 * l0] + (double)t0.y * rps[2 * l0 + 1];
+        }
     }
 #pragma unroll
     for (int i = 0; i < kGBatch; ++i) {
@@ -470,6 +560,7 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
     }
     __syncthreads();
 
+    if (FC && tab_rows) load_table_rows();
     stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
     __syncthreads();
     const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
@@ -511,6 +602,20 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
             // graph replays read the step length from device memory
             const double hh = a.hdev ? a.hdev[(size_t)(*a.chunk) * kChunkSteps + a.hidx] : h;
             rk4_update(a, oi, K, x0, xa, hh);
+        }
+    }
+    if (FC && a.fc_next) {
+        // phase 4: the cache's next point (rps holds its R factors)
+        FcT* fout = static_cast<FcT*>(a.fc_next) + (size_t)j * m.n_frow + t.frow_off + (size_t)row0 * nV;
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+            const int idx = tid + i * B;
+            if (idx < totF) fout[idx] = (FcT)((double)tv[i].x * rps[2 * lv[i]] + (double)tv[i].y * rps[2 * lv[i] + 1]);
+        }
+        for (int idx = tid + FB * B; idx < totF; idx += B) {
+            const TabT t0 = row[idx];
+            const int l0 = cl[idx % nV];
+            fout[idx] = (FcT)((double)t0.x * rps[2 * l0] + (double)t0.y * rps[2 * l0 + 1]);
         }
     }
     if (KIND == 1 && a.grad) {
@@ -588,7 +693,7 @@ __device__ inline bool xcd_item(const Meta& m, int n_paths, int bx, int* jl, int
 // One RK4 stage for a.n_paths paths from a.traj0 (grid of xcd_item).  Small
 // row tiles ask for registers that leave room for four workgroups per CU
 // (their LDS does), larger ones for three.
-template <int ROWS>
+template <int ROWS, bool F32, bool FC>
 __global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
     // work item W of the path-major list of a.n_paths x a.nwg row tiles, in
@@ -600,7 +705,33 @@ __global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(Stag
     if (W >= total) return;
     const int jl = W / a.nwg;
     const StageTile t = a.tiles[W - jl * a.nwg];
-    stage_body<0, ROWS>(a, a.traj0 + jl, t, reinterpret_cast<char*>(smem2));
+    stage_body<0, ROWS, F32, FC>(a, a.traj0 + jl, t, reinterpret_cast<char*>(smem2));
+}
+
+// F of Eq. D2 at point slot p for every entry of the row layout and every path
+// of the launch (grid: entries / 256 x paths), with the arithmetic of the
+// stage kernels' phase 1 / phase 4.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_fpoint(const Meta* __restrict__ mp_, Tables T, PointArrays pt, int p,
+                                                int traj0, void* __restrict__ fc_) {
+    const Meta& m = *mp_;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= m.n_frow) return;
+    const int j = traj0 + blockIdx.y;
+    const size_t jp = (size_t)j * pt.n_pts + p;
+    int lp = 0;
+    while (lp < m.l_max && d >= m.frow_off[lp + 1]) ++lp;
+    const int lam = T.col_lam[m.col_off[lp] + (d - m.frow_off[lp]) % m.nV[lp]];
+    const double* rp = pt.rpow + jp * kRpow;
+    const size_t i = (size_t)pt.kidx[jp] * m.n_frow + d;
+    if constexpr (F32) {
+        const float2 t0 = T.tab32[i];
+        static_cast<float*>(fc_)[(size_t)j * m.n_frow + d] =
+            (float)((double)t0.x * rp[2 * lam] + (double)t0.y * rp[2 * lam + 1]);
+    } else {
+        const double2 t0 = T.tab[i];
+        static_cast<double*>(fc_)[(size_t)j * m.n_frow + d] = t0.x * rp[2 * lam] + t0.y * rp[2 * lam + 1];
+    }
 }
 
 constexpr int kBarrierSpin = 1 << 22;  // polls (0.2 s or more) before a barrier gives up
@@ -917,7 +1048,15 @@ __global__ __launch_bounds__(256) void k_slot_setup(SetupArgs a) {
         while (lp < m.l_max && d >= m.frow_off[lp + 1]) ++lp;
         const int e = (d - m.frow_off[lp]) % m.nV[lp];
         const int k = grid_index(R, m.r_max, m.n_r);
-        a.Frow[d] = radial_at(T.tab[(size_t)k * m.n_frow + d], R, T.col_lam[m.col_off[lp] + e]);
+        const int lam = T.col_lam[m.col_off[lp] + e];
+        if (T.tab32) {
+            const float2 ab = T.tab32[(size_t)k * m.n_frow + d];
+            double fa, fb;
+            scaled_factors(R, k, lam, m.r_max, m.n_r, &fa, &fb);
+            a.Frow[d] = (double)ab.x * fa + (double)ab.y * fb;
+        } else {
+            a.Frow[d] = radial_at(T.tab[(size_t)k * m.n_frow + d], R, lam);
+        }
         return;
     }
     if (bx < a.nbF + a.nbP) {
@@ -1053,13 +1192,23 @@ int chunk_smem_bytes(const Meta& m, int rows) {
     return best;
 }
 
+// The dynamic-LDS attribute is per kernel and process-wide: it is only ever
+// raised (to the largest size any plan has asked for), so that a plan created
+// later with a smaller basis does not lower it under an earlier plan's launches.
 hipError_t stage_set_smem_limit(int, int bytes) {
-#define WPCCC_FN_PAIR(R) (const void*)k_stage<R>, (const void*)k_chunk<R>,
+    static std::mutex mu;
+    static int set_bytes = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (bytes <= set_bytes) return hipSuccess;
+#define WPCCC_FN_PAIR(R)                                                                        \
+    (const void*)k_stage<R, false, false>, (const void*)k_stage<R, false, true>,                 \
+        (const void*)k_stage<R, true, true>, (const void*)k_chunk<R>,
     const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR)(const void*)k_apply};
 #undef WPCCC_FN_PAIR
     hipError_t e = hipSuccess;
     for (const void* f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) set_bytes = bytes;
     return e;
 }
 
@@ -1113,6 +1262,13 @@ hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_
     return hipGetLastError();
 }
 
+hipError_t launch_table_f32(const double2* tab, const int* dl, int n_frow, int n_r, double r_max, float2* out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_table_f32, dim3((n_frow + 255) / 256, n_r + 1), dim3(256), 0, st, tab, dl, n_frow, n_r, r_max,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
                               hipStream_t st) {
     if (count <= 0) return hipSuccess;
@@ -1145,13 +1301,25 @@ hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, i
     StageArgs a1 = a;
     a1.n_paths = n_traj_launch;
     switch (rows) {
-#define WPCCC_CASE(R)                                               \
-    case R: WPCCC_LAUNCH(ev, k_stage<R>, grid, block, smem, st, a1); \
+#define WPCCC_CASE(R)                                                                    \
+    case R:                                                                              \
+        if (a.tb.tab32 && a.fc_cur) WPCCC_LAUNCH(ev, (k_stage<R, true, true>), grid, block, smem, st, a1); \
+        else if (a.tb.tab32) return hipErrorInvalidValue;                                \
+        else if (a.fc_cur) WPCCC_LAUNCH(ev, (k_stage<R, false, true>), grid, block, smem, st, a1);       \
+        else WPCCC_LAUNCH(ev, (k_stage<R, false, false>), grid, block, smem, st, a1);                    \
         break;
         WPCCC_STAGE_ROWS(WPCCC_CASE)
 #undef WPCCC_CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fpoint(const Meta* m, const Meta& hm, const Tables& tb, const PointArrays& pt, int p, int traj0,
+                         int n_paths, void* fc, hipStream_t st, const LaunchEv& ev) {
+    const dim3 grid((hm.n_frow + 255) / 256, n_paths);
+    if (tb.tab32) WPCCC_LAUNCH(ev, k_fpoint<true>, grid, dim3(256), 0, st, m, tb, pt, p, traj0, fc);
+    else WPCCC_LAUNCH(ev, k_fpoint<false>, grid, dim3(256), 0, st, m, tb, pt, p, traj0, fc);
     return hipGetLastError();
 }
 

@@ -63,7 +63,9 @@ __host__ __device__ inline int2 gcol_pack(int e0, int nl, int xoff) { return mak
 
 // Basis tables shared by every launch of a plan.
 struct Tables {
-    const double2* tab;     // [n_r+1][n_frow]: (A_k, B_(k+1)) per Frow entry
+    const double2* tab;     // [n_r+1][n_frow]: (A_k, B_(k+1)) per Frow entry (FP64 plans)
+    const float2* tab32;    // [n_r+1][n_frow]: the scaled FP32 form (reduced-precision plans, else NULL):
+                            //   (A_k / r_k^(lam+1), B_(k+1) r_(k+1)^lam)
     const int* col_lam;     // [n_cols] lambda of each Frow column, per l'
     const int2* gcol_info;  // [n_gcols] gcol_pack of each G column, per l'
     const double* gcoef;    // [n_g] c(l'm', lm, lambda), (-1)^mu folded in for mu < 0
@@ -79,7 +81,8 @@ struct Tables {
 // Per (path, z-point) quantities shared by every workgroup of a stage,
 // computed once by k_prologue for all points of a propagation chunk:
 //   kidx[j][p]                grid node of R (last r_k <= R)
-//   rpow[j][p][2 lam]         R^-(lam+1) at 2 lam, R^lam at 2 lam + 1
+//   rpow[j][p][2 lam]         R^-(lam+1) at 2 lam, R^lam at 2 lam + 1 (FP64 table);
+//                             (r_k/R)^(lam+1) and (R/r_(k+1))^lam (scaled FP32 table)
 //   pbar[j][p][n_pb]          Pbar_lam^mu(cos Theta)
 //   ph[j][p][n_f]             exp(i eps_f z / v) per radial function
 struct PointArrays {
@@ -126,6 +129,14 @@ struct StageArgs {
     const double* hdev;
     const int* chunk;
     int hidx;
+    // radial-integral cache of the stage kernels (kFcSlots): fc_cur holds F
+    // at this stage's point for every path ([n_traj][n_frow], double, or
+    // float with the scaled FP32 table; NULL: the stage forms F from the
+    // moment table itself); fc_next (may be NULL) receives F at point p_next,
+    // formed from the moment table after the stage's own work
+    const void* fc_cur;
+    void* fc_next;
+    int p_next;
     // operator application (k_apply): y = O v with O = M(z_p) (deriv 0),
     // (b/R) dM/dR (deriv 1) or (-z b/R^3) dM/dcos(Theta) (deriv 2) applied to
     // v = cu1 u_in + cu2 u_in2 (u_in2 may be NULL), then
@@ -155,6 +166,16 @@ struct StageArgs {
     const double* va;
     const double* vc;
 };
+
+// Radial-integral cache of a one-centre propagation: F_l'(R) of Eq. D2 in the
+// row layout for every path at two points, slot 0 holding the step's end
+// points and slot 1 its midpoints.  Of the four stages of a step (points z,
+// z_mid, z_mid, z_new), stage 1 reads slot 0 and fills slot 1 with F(z_mid),
+// stage 2 reads slot 1, stage 3 reads slot 1 and fills slot 0 with F(z_new),
+// stage 4 reads slot 0; k_fpoint fills slot 0 at the first point of a run of
+// steps.  So the moment table is read at the two new points of each step,
+// while the stage that consumes a point's couplings has them ready.
+constexpr int kFcSlots = 2;
 
 // gradient share slots of k_apply per path: b (deriv 1), b (deriv 2), a, c
 constexpr int kGradSlots = 4;
@@ -214,11 +235,13 @@ struct Centre {
     double *d_eps = nullptr, *d_gcoef = nullptr, *d_rad_eps = nullptr;
     int *d_col_lam = nullptr, *d_gpb = nullptr, *d_st_rad = nullptr, *d_st_xs = nullptr;
     int2* d_gcol = nullptr;
-    double2* d_tab = nullptr;
+    double2* d_tab = nullptr;     // FP64 moment table (NULL once a scaled FP32 table replaces it)
+    float2* d_tab32 = nullptr;    // scaled FP32 moment table (reduced-precision one-centre plans)
     long long bytes = 0;
     Tables tables(const double* bvec, const double* vvec) const {
         Tables t;
         t.tab = d_tab;
+        t.tab32 = d_tab32;
         t.col_lam = d_col_lam;
         t.gcol_info = d_gcol;
         t.gcoef = d_gcoef;
@@ -251,7 +274,7 @@ struct LaunchEv {
 enum KernelId {
     kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
     k2cNodes, k2cInterp, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
-    kChunk, k2cReduce, kNumKernels
+    kChunk, k2cReduce, kFpoint, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 
@@ -275,8 +298,9 @@ struct KernelTimer {
 // model_a != 0 adds DeltaV = -a e^{-c r}/r (block diagonal in l, m) to the
 // lambda = 0 moments of the equal-l blocks, so that every use of the tables
 // sees D_T + DeltaV (projectile charge Zp)
+// tab_f32: replace the FP64 moment table by its scaled FP32 form (Tables::tab32)
 int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a = 0.0, double model_c = 0.0,
-                 double Zp = 1.0);
+                 double Zp = 1.0, bool tab_f32 = false);
 // radial blocks va, vc of the model potential (layout of StageArgs::va, vc)
 void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& va, std::vector<double>& vc);
 void centre_free(Centre& c);
@@ -315,6 +339,11 @@ hipError_t launch_slot_setup(const SetupArgs& a, const Meta& host_meta, hipStrea
 // rows: output rows n' per workgroup (4, 8 or 16; chosen per plan by timing)
 hipError_t launch_stage(const StageArgs& a, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
                         const LaunchEv& ev = LaunchEv{}, int rows = kRowsPerBlock);
+// F of Eq. D2 at point slot p of the prologue arrays for paths [traj0, traj0 +
+// n_paths) into fc[j][n_frow] (the radial-integral cache; float elements with
+// the scaled FP32 table, else double)
+hipError_t launch_fpoint(const Meta* m, const Meta& host_meta, const Tables& tb, const PointArrays& pt, int p,
+                         int traj0, int n_paths, void* fc, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const double* Frow, const double* G,
                                   const double2* PH, double Zp, double2* H, hipStream_t st,
                                   const LaunchEv& ev = LaunchEv{});
@@ -329,6 +358,9 @@ hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_
 hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st);
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
                               hipStream_t st);
+// scaled FP32 copy of a moment table (Tables::tab32); dl: multipole order of each entry
+hipError_t launch_table_f32(const double2* tab, const int* dl, int n_frow, int n_r, double r_max, float2* out,
+                            hipStream_t st);
 hipError_t stage_set_smem_limit(int l_max, int bytes);
 // k_chunk with `rows` rows per workgroup as one cooperative launch; returns
 // hipErrorCooperativeLaunchTooLarge (and launches nothing) when the grid

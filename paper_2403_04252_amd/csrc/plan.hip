@@ -49,6 +49,8 @@ struct wpccc_plan_s {
     int* d_kidx = nullptr;
     double *d_rpow = nullptr, *d_pbar = nullptr;
     double2* d_ph = nullptr;
+    void* d_fc = nullptr;    // [kFcSlots][n_traj][n_frow] radial-integral cache of the stage kernels
+                             // (double; float for the scaled FP32 table)
     // model potential blocks and adjoint workspace (allocated on first use)
     double *d_va = nullptr, *d_vc = nullptr;
     int ckpt_every = 0;
@@ -73,6 +75,7 @@ struct wpccc_plan_s {
     // propagation chunks kernel by kernel (WPCCC_LAUNCH_STAGES) or as one
     // persistent k_chunk launch (WPCCC_LAUNCH_PERSISTENT)
     int launch = WPCCC_LAUNCH_STAGES;
+    bool mixed = false;       // scaled FP32 moment table (WPCCC_MIXED): per-stage launches only, no adjoint
     int chunk_smem = 0;       // k_chunk with stage_rows
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
     double* d_gpart = nullptr;  // [n_traj][kGradSlots][n_chunks] per-workgroup gradient shares (k_apply)
@@ -109,7 +112,7 @@ void free_plan(wpccc_plan_s* p) {
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Frow1, p->d_G1,   p->d_PH1,  p->d_Ua,
                     p->d_Ub,   p->d_Xacc, p->d_kidx, p->d_rpow,  p->d_pbar, p->d_ph,   p->d_va,
                     p->d_vc,   p->d_lam,  p->d_nu,   p->d_ckpt,  p->d_seg,  p->d_bar,  p->d_gpart,
-                    p->d_tiles};
+                    p->d_tiles, p->d_fc};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;
@@ -155,9 +158,28 @@ StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
     return a;
 }
 
+// Slot s of the radial-integral cache (FCache in plan.h).
+void* fc_slot(const wpccc_plan_s* p, int s) {
+    const size_t elem = p->mixed ? sizeof(float) : sizeof(double);
+    return static_cast<char*>(p->d_fc) + (size_t)s * p->n_traj * p->c.meta.n_frow * elem;
+}
+
+// F at point slot `point` into cache slot 0 for paths [j0, j0+nj): the start of
+// a run of cached steps.
+int enqueue_fpoint(wpccc_plan_s* p, int j0, int nj, int point, hipStream_t st) {
+    hipError_t e = launch_fpoint(p->c.d_meta, p->c.meta, p->tables(), p->points(), point, j0, nj, fc_slot(p, 0), st,
+                                 p->timer.open(kFpoint));
+    return launched(e, "k_fpoint");
+}
+
+// fc_cur / fc_next: cache slots (-1: none; fc_cur -1 forms F from the table)
 int enqueue_stage(wpccc_plan_s* p, int j0, int nj, int stage, int point, int step, double h, const double2* u_in,
-                  double2* X, double2* u_out, hipStream_t st, double2* Xout = nullptr) {
+                  double2* X, double2* u_out, hipStream_t st, double2* Xout = nullptr, int fc_cur = -1,
+                  int fc_next = -1, int p_next = 0) {
     StageArgs a = stage_args(p, j0, X);
+    a.fc_cur = fc_cur >= 0 ? fc_slot(p, fc_cur) : nullptr;
+    a.fc_next = fc_next >= 0 ? fc_slot(p, fc_next) : nullptr;
+    a.p_next = p_next;
     a.Xout = Xout;
     a.p = point;
     a.h = h;
@@ -189,15 +211,20 @@ int enqueue_chunk(wpccc_plan_s* p, double2* X, int j0, int nj, const double* h, 
 
 // One RK4 step of length h for paths [j0, j0+nj) with M at the points pz (z),
 // pz+1 (z_mid) and pz+2 (z_new).  Stage inputs alternate between two buffers
-// so that no stage reads what it writes.
-int enqueue_step(wpccc_plan_s* p, double2* X, int j0, int nj, int pz, double h, hipStream_t st) {
+// so that no stage reads what it writes.  cached: the stages take F from the
+// radial-integral cache, whose slot 0 must hold F(pz) (enqueue_fpoint, or the
+// previous cached step), and leave F(pz+2) in slot 0; otherwise every stage
+// forms F from the moment table.
+int enqueue_step(wpccc_plan_s* p, double2* X, int j0, int nj, int pz, double h, hipStream_t st, bool cached = true) {
     int rc;
     // the step's index within its chunk (graph replays read h at this index)
     const int step = pz / 2;
-    if ((rc = enqueue_stage(p, j0, nj, 1, pz, step, h, X, X, p->d_Ua, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, step, h, p->d_Ua, X, p->d_Ub, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, step, h, p->d_Ub, X, p->d_Ua, st))) return rc;
-    if ((rc = enqueue_stage(p, j0, nj, 4, pz + 2, step, h, p->d_Ua, X, nullptr, st))) return rc;
+    const int c0 = cached ? 0 : -1, c1 = cached ? 1 : -1;
+    if ((rc = enqueue_stage(p, j0, nj, 1, pz, step, h, X, X, p->d_Ua, st, nullptr, c0, c1, pz + 1))) return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, step, h, p->d_Ua, X, p->d_Ub, st, nullptr, c1))) return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, step, h, p->d_Ub, X, p->d_Ua, st, nullptr, c1, c0, pz + 2)))
+        return rc;
+    if ((rc = enqueue_stage(p, j0, nj, 4, pz + 2, step, h, p->d_Ua, X, nullptr, st, nullptr, c0))) return rc;
     return WPCCC_OK;
 }
 
@@ -331,6 +358,7 @@ int capture_chunk_graph(wpccc_plan_s* p, double2* X) {
     p->capturing = true;
     double dummy[kChunkPoints] = {0.0};
     int rc = enqueue_prologue(p, dummy, kChunkPoints, 0, p->n_traj, p->gstream);
+    if (rc == WPCCC_OK) rc = enqueue_fpoint(p, 0, p->n_traj, 0, p->gstream);
     for (int i = 0; i < kChunkSteps && rc == WPCCC_OK; ++i) rc = enqueue_step(p, X, 0, p->n_traj, 2 * i, 0.0, p->gstream);
     if (rc == WPCCC_OK) rc = launched(launch_chunk_counter(p->d_chunk, 0, p->gstream), "k_chunk_counter");
     p->capturing = false;
@@ -460,6 +488,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
             if (launch == WPCCC_LAUNCH_PERSISTENT) {
                 if (r == WPCCC_OK) r = enqueue_chunk(p, X, 0, nj, hs, kTuneSteps, rows, chunk_smem_bytes(m, rows), st);
             } else {
+                if (r == WPCCC_OK) r = enqueue_fpoint(p, 0, nj, 0, st);
                 for (int i = 0; i < kTuneSteps && r == WPCCC_OK; ++i) r = enqueue_step(p, X, 0, nj, 2 * i, hs[i], st);
             }
             float t = 0.f;
@@ -479,6 +508,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
         if (smem > kMaxDynLds || !stage_rows_fit(m, rows)) continue;
         for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
             if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
+            if (launch == WPCCC_LAUNCH_PERSISTENT && p->mixed) continue;
             if (launch == WPCCC_LAUNCH_PERSISTENT &&
                 (chunk_smem_bytes(m, rows) > kMaxDynLds || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
                 continue;
@@ -619,9 +649,13 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: use wpccc_plan_create_2c for the two-centre form");
         return WPCCC_EINVAL;
     }
-    if (o.precision != WPCCC_FP64) {
-        set_error("wpccc_plan_create: the one-centre path has no reduced-precision form (its radial "
-                  "integrals come from exact moment tables, not from a per-R contraction)");
+    if (o.precision != WPCCC_FP64 && o.precision != WPCCC_MIXED) {
+        set_error("wpccc_plan_create: precision must be WPCCC_FP64 or WPCCC_MIXED");
+        return WPCCC_EINVAL;
+    }
+    const bool mixed = o.precision == WPCCC_MIXED;
+    if (mixed && o.stage_launch == WPCCC_LAUNCH_PERSISTENT) {
+        set_error("wpccc_plan_create: the persistent stage kernel has no reduced-precision form");
         return WPCCC_ENOTSUP;
     }
     for (int j = 0; j < n_traj; ++j)
@@ -649,7 +683,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->v.assign(v_host, v_host + n_traj);
     const int N = hb.n_states;
     plan->n_pad = (N + 7) & ~7;
-    TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp));
+    plan->mixed = mixed;
+    TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp, mixed));
     plan->ckpt_every = o.checkpoint_every;
     plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
@@ -717,6 +752,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     TRY(dev_alloc(&plan->d_rpow, (size_t)n_traj * kChunkPoints * kRpow, tot));
     TRY(dev_alloc(&plan->d_pbar, (size_t)n_traj * kChunkPoints * kMaxPb, tot));
     TRY(dev_alloc(&plan->d_ph, (size_t)n_traj * kChunkPoints * m.n_f, tot));
+    TRY(dev_alloc_bytes(&plan->d_fc, (size_t)kFcSlots * n_traj * m.n_frow * (mixed ? sizeof(float) : sizeof(double)),
+                        tot));
     std::vector<double> va, vc;
     model_blocks(hb, o.model_a, o.model_c, va, vc);
     TRY(dev_alloc(&plan->d_va, va.size(), tot));
@@ -1010,6 +1047,7 @@ int wpccc_step(wpccc_plan_t plan, void* X_dev, double z, double h, void* stream)
         const double pts[3] = {z, z + 0.5 * h, z + h};
         int rc = enqueue_prologue(plan, pts, 3, j0, nj, st);
         if (rc) return rc;
+        if ((rc = enqueue_fpoint(plan, j0, nj, 0, st))) return rc;
         if ((rc = enqueue_step(plan, X, j0, nj, 0, h, st))) return rc;
     }
     return WPCCC_OK;
@@ -1059,6 +1097,7 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points, v
                     return rc;
                 continue;
             }
+            if ((rc = enqueue_fpoint(plan, j0, nj, 0, st))) return rc;
             for (int i = 0; i < ns; ++i)
                 if ((rc = enqueue_step(plan, X, j0, nj, 2 * i, hs[i], st))) return rc;
         }
@@ -1080,6 +1119,10 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
     }
     if (plan->p2c) {
         set_error("wpccc_adjoint: one-centre plans only");
+        return WPCCC_ENOTSUP;
+    }
+    if (plan->mixed) {
+        set_error("wpccc_adjoint: FP64 plans only (the operator kernel reads the FP64 moment table)");
         return WPCCC_ENOTSUP;
     }
     if (!plan->apply_ok) {
@@ -1141,7 +1184,8 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
                 WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_ckpt + (size_t)(n / K) * V, xw, VB, hipMemcpyDeviceToDevice, st));
             const int pz = pts.slot(plan, n, st, &rc);
             if (rc) return rc;
-            if ((rc = enqueue_step(plan, xw, 0, plan->n_traj, pz, zgrid_host[n + 1] - zgrid_host[n], st))) return rc;
+            if ((rc = enqueue_step(plan, xw, 0, plan->n_traj, pz, zgrid_host[n + 1] - zgrid_host[n], st, false)))
+                return rc;
         }
         if (X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xw, VB, hipMemcpyDeviceToDevice, st));
     }
@@ -1230,7 +1274,7 @@ const char* const kKernelNames[kNumKernels] = {
     "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
     "k_2c_nodes",     "k_2c_interp",   "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
     "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish",  "k_chunk",
-    "k_2c_reduce"};
+    "k_2c_reduce",    "k_fpoint"};
 
 LaunchEv KernelTimer::open(int kernel) {
     LaunchEv ev;

@@ -206,7 +206,7 @@ def test_2c_propagation_multiblock(bases):
 
 
 def test_2c_mixed_precision(small_run, bases):
-    """Mixed form (FP32 products summed in FP32 per 32-node chunk, FP64
+    """Mixed form (FP32 products summed in FP32 per 64-node chunk, FP64
     across chunks): couplings within 1e-5 of max|S|, max|H| and probabilities
     within 1e-6 absolute or 1e-4 relative of the FP64 oracle."""
     wl, lt, lp, ref = small_run

@@ -6,9 +6,20 @@ written by tests/golden/make_golden.py from oracle/ only).
   at |dP| <= 1e-10 max(P, 1e-6); every path conserves sum_i P_i as the oracle's
   sampled paths do (RK4 is not exactly unitary: the drift is compared, not
   assumed zero).
+* seeded one-centre workload (the N = 580 basis, 64 impact parameters, all
+  800 steps) in FP64 and in the reduced-precision form: the FP64 run matches
+  the oracle's four stored paths at the FP64 bar; every probability of every
+  path of the mixed run is within 1e-6 absolute or 1e-4 relative of the FP64
+  run, and the four stored paths are within that bar of the oracle.
 * two-centre workload at 256 x 512 nodes, one position on a path with 101
   and one with 382 states per centre: 4096 sampled elements of S and H each,
   |d| <= 1e-11 max|S|, max|H|.
+* two-centre propagation: a whole path (800 steps) of the 101-states-per-
+  centre pair on 64 x 128 nodes, and 4 steps through closest approach of a
+  path with 382 states per centre on the full 256 x 512 nodes from a seeded
+  random state: FP64 at |dP| <= 1e-10 max(P, 1e-6) (and the amplitudes of
+  the 4-step run at 1e-11), the mixed form within 1e-6 absolute or 1e-4
+  relative of the oracle.
 """
 import os
 
@@ -55,6 +66,42 @@ def test_full_single_centre_batch_sampled():
     assert np.all(drift <= max(10 * ref, 1e-9)), (drift.max(), ref)
 
 
+def _mixed_ok(P, Pref):
+    d = np.abs(P - Pref)
+    return (d <= 1e-6) | (d <= 1e-4 * np.abs(Pref))
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "c4_paths.npz")), reason="golden file not generated")
+def test_full_seeded_fp64_and_mixed():
+    g = np.load(os.path.join(GOLDEN, "c4_paths.npz"))
+    w = WL.single_centre_seeded()
+    lb = lib_basis(w.basis)
+    out = {}
+    for mixed in (False, True):
+        print(f"full c4: 64 paths x 800 steps, mixed={mixed}", flush=True)
+        plan = W.wpccc_plan_create(lb, w.b, w.v, mixed=mixed)
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        P = torch.empty((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
+        W.wpccc_propagate(plan, w.zgrid, X, P)
+        torch.cuda.synchronize()
+        W.wpccc_plan_status(plan)
+        out[mixed] = P.cpu().numpy()[:, :plan.n_states]
+        del plan
+    P64, Pmx = out[False], out[True]
+    for k, j in enumerate(g["paths"]):
+        assert np.isclose(w.b[j], g["b"][k], rtol=0, atol=0)
+        Po = g["P"][k]
+        e64 = np.abs(P64[j] - Po)
+        emx = np.abs(Pmx[j] - Po)
+        print(f"  path {j}: FP64 max|dP| {e64.max():.2e}, mixed max|dP| {emx.max():.2e}", flush=True)
+        assert np.all(e64 <= 1e-10 * np.maximum(Po, 1e-6)), (j, e64.max())
+        assert _mixed_ok(Pmx[j], Po).all(), (j, emx.max())
+    d = np.abs(Pmx - P64)
+    print(f"  mixed vs FP64, all 64 paths: max|dP| {d.max():.2e}", flush=True)
+    assert _mixed_ok(Pmx, P64).all()
+
+
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "c3_couplings.npz")), reason="golden file not generated")
 def test_full_two_centre_couplings_sampled():
     g = np.load(os.path.join(GOLDEN, "c3_couplings.npz"))
@@ -79,3 +126,63 @@ def test_full_two_centre_couplings_sampled():
         assert eS <= 1e-11 and eH <= 1e-11
         k += 1
     assert k > 0
+
+
+def _run_2c(plan, zg, X0=None):
+    X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    if X0 is None:
+        X[:, 0] = 1.0
+    else:
+        X[0, :X0.size] = torch.from_numpy(X0).cuda()
+    W.wpccc_propagate(plan, zg, X)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    return X.cpu().numpy()[0]
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "c3_path101.npz")), reason="golden file not generated")
+def test_full_two_centre_path101():
+    g = np.load(os.path.join(GOLDEN, "c3_path101.npz"))
+    w = WL.two_centre_batched(1.0)
+    j = int(g["path"][0])
+    assert np.isclose(w.b[j], g["b"][0], rtol=0, atol=0) and w.set_of[j] == 0
+    lb = lib_basis(w.targets[0])
+    Po = g["P"]
+    N = Po.size
+    for mixed in (False, True):
+        print(f"full c3 path {j}: 101 + 101 states, 64 x 128 nodes, 800 steps, mixed={mixed}", flush=True)
+        plan = W.wpccc_plan_create_2c([lb], [lb], [0], w.b[[j]], w.v[[j]], q_lower=W.WPCCC_Q_PRIOR,
+                                      n_eta=int(g["n_eta"][0]), n_tau=int(g["n_tau"][0]), mixed=mixed)
+        X = _run_2c(plan, w.zgrid)[:N]
+        P = np.abs(X) ** 2
+        d = np.abs(P - Po)
+        print(f"  max|dP| {d.max():.2e} (sum P {P.sum():.6f})", flush=True)
+        if mixed:
+            assert _mixed_ok(P, Po).all(), d.max()
+        else:
+            assert np.all(d <= 1e-10 * np.maximum(Po, 1e-6)), d.max()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "c3_spot382.npz")), reason="golden file not generated")
+def test_full_two_centre_spot382():
+    g = np.load(os.path.join(GOLDEN, "c3_spot382.npz"))
+    w = WL.two_centre_batched(1.0)
+    j = int(g["path"][0])
+    assert np.isclose(w.b[j], g["b"][0], rtol=0, atol=0) and w.set_of[j] == 2
+    lb = lib_basis(w.targets[2])
+    Xo = g["X"]
+    Po = np.abs(Xo) ** 2
+    N = Xo.size
+    for mixed in (False, True):
+        print(f"full c3 spot path {j}: 382 + 382 states, 256 x 512 nodes, 4 steps, mixed={mixed}", flush=True)
+        plan = W.wpccc_plan_create_2c([lb], [lb], [0], w.b[[j]], w.v[[j]], q_lower=W.WPCCC_Q_PRIOR,
+                                      n_eta=w.n_eta, n_tau=w.n_tau, mixed=mixed)
+        X = _run_2c(plan, g["zgrid"], g["X0"])[:N]
+        P = np.abs(X) ** 2
+        d = np.abs(P - Po)
+        print(f"  max|dX| {np.abs(X - Xo).max():.2e} max|dP| {d.max():.2e}", flush=True)
+        if mixed:
+            assert _mixed_ok(P, Po).all(), d.max()
+        else:
+            assert np.abs(X - Xo).max() <= 1e-11
+            assert np.all(d <= 1e-10 * np.maximum(Po, 1e-6)), d.max()
