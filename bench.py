@@ -197,6 +197,17 @@ def main():
     value = n_traj * args.steps / wall
     # probability error of the timed run against the oracle's stored full paths
     golden_err = golden_prob_error(torch, X, n_states, w, args.steps, "c2_paths.npz")
+    # observables of the timed run (a whole grid: channel probabilities and
+    # cross sections of the batch of impact parameters)
+    obs = None
+    if args.steps == w.zgrid.size - 1:
+        Pobs = (X.abs() ** 2).contiguous()
+        chan = torch.empty((n_traj, W.WPCCC_N_CHANNELS), dtype=torch.float64, device="cuda")
+        sig = torch.empty((W.wpccc_plan_groups(plan)[0], W.WPCCC_N_CHANNELS), dtype=torch.float64, device="cuda")
+        W.wpccc_observables(plan, Pobs, chan, sig)
+        torch.cuda.synchronize()
+        obs = {"cross_sections_au": dict(zip(W.CHANNELS, sig[0].cpu().numpy().tolist())),
+               "note": "sigma = 2 pi int P b db (trapezoid over the 32 b, 0 at b = 0) at z = 40"}
 
     # the same K steps again with per-kernel HIP events on the library's stream
     X.zero_()
@@ -334,6 +345,7 @@ def main():
         "cpu_baseline": cpu,
         "prob_error": prob_err,
         "prob_error_cpu_sample": prob_err_sample,
+        "observables": obs,
         "plain_fp64_sequential": seq,
         "kernel_times": kernel_times,
     }

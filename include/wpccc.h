@@ -288,6 +288,42 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Observables at the end of the paths (Sec. II after Algorithm 1: the      */
+/* final amplitudes give the cross sections of the reaction processes, from */
+/* 30 to 50 paths per collision; Sec. III: the two-centre expansion         */
+/* separates capture from ionisation).                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Reaction channels, by the centre a state is expanded about and the sign
+ * of its energy (bound eigenstates below zero, wave-packet pseudostates
+ * above); index of each channel in the arrays below. */
+#define WPCCC_N_CHANNELS       6
+#define WPCCC_CH_ELASTIC       0   /* target state 0 (the initial state) */
+#define WPCCC_CH_EXCITATION    1   /* other target states with eps < 0 */
+#define WPCCC_CH_TARGET_CONT   2   /* target states with eps > 0 (ionisation, 1C: electron loss) */
+#define WPCCC_CH_CAPTURE       3   /* projectile states with eps < 0 (2C) */
+#define WPCCC_CH_PROJ_CONT     4   /* projectile states with eps > 0 (2C; ionisation with TARGET_CONT) */
+#define WPCCC_CH_TOTAL         5   /* every state */
+
+/* Groups of paths whose probabilities form one cross section: paths with the
+ * same basis pair (set) and the same speed, numbered in order of first
+ * appearance.  n_groups and group_of_traj_host[n_traj] may be NULL. */
+int wpccc_plan_groups(wpccc_plan_t plan, int* n_groups, int* group_of_traj_host);
+
+/* From the probabilities P_dev (double [n_traj][n_pad], as written by
+ * wpccc_propagate):
+ *   chan_dev   double [n_traj][WPCCC_N_CHANNELS]: the sum of P_i over the
+ *              states of each channel (and over all states), per path
+ *   sigma_dev  double [n_groups][WPCCC_N_CHANNELS] (may be NULL): the cross
+ *              section of each channel per group, 2 pi int_0^inf P(b) b db by
+ *              the trapezoidal rule over the group's impact parameters in
+ *              increasing order (integrand 0 at b = 0, nothing added beyond
+ *              the largest b), in a.u. (bohr^2)
+ * Both are written on `stream`; sums are taken in a fixed order (the result
+ * does not depend on scheduling).  Errors: WPCCC_EINVAL (NULL pointers). */
+int wpccc_observables(wpccc_plan_t plan, const void* P_dev, void* chan_dev, void* sigma_dev, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics: per-kernel device time with HIP events; device ceilings.    */
 /* ------------------------------------------------------------------------ */
 

@@ -20,7 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_couplings_noalloc", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
-    "wpccc_plan_stage_launch", "wpccc_measure_mfma", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
+    "wpccc_plan_stage_launch", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,8 @@ WPCCC_MIXED = 1
 WPCCC_LAUNCH_AUTO = 0
 WPCCC_LAUNCH_STAGES = 1
 WPCCC_LAUNCH_PERSISTENT = 2
+WPCCC_N_CHANNELS = 6
+CHANNELS = ("elastic", "excitation", "target_continuum", "capture", "projectile_continuum", "total")
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
 
 
@@ -109,6 +111,8 @@ def load_library():
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
         "wpccc_measure_mfma": ([pd, pd, vp], i),
+        "wpccc_plan_groups": ([vp, pi, pi], i),
+        "wpccc_observables": ([vp, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -365,3 +369,22 @@ def wpccc_measure_mfma(stream=None):
     f64, f32 = ctypes.c_double(), ctypes.c_double()
     _check(load_library().wpccc_measure_mfma(ctypes.byref(f64), ctypes.byref(f32), _stream_ptr(stream)))
     return f64.value, f32.value
+
+
+def wpccc_plan_groups(plan: Plan):
+    """(n_groups, group of every path): paths sharing the basis pair and the speed."""
+    n = ctypes.c_int()
+    g = np.zeros(plan.n_traj, dtype=np.int32)
+    _check(load_library().wpccc_plan_groups(plan.handle, ctypes.byref(n),
+                                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return n.value, g
+
+
+def wpccc_observables(plan: Plan, P, chan, sigma=None, stream=None):
+    """chan (float64 CUDA [n_traj, 6]) <- channel probabilities per path from P
+    ([n_traj, n_pad]); sigma (float64 CUDA [n_groups, 6] or None) <- cross sections."""
+    n_groups, _ = wpccc_plan_groups(plan)
+    _check(load_library().wpccc_observables(
+        plan.handle, _dev_ptr(P, "float64", (plan.n_traj, plan.n_pad), "P"),
+        _dev_ptr(chan, "float64", (plan.n_traj, WPCCC_N_CHANNELS), "chan"),
+        _dev_ptr(sigma, "float64", (n_groups, WPCCC_N_CHANNELS), "sigma"), _stream_ptr(stream)))

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libwpccc.so")
 
-SOURCES = ["plan.hip", "plan2c.hip", "centre.hip", "kernels_1c.hip", "kernels_2c.hip", "kernels_lu.hip", "basis.cpp"]
+SOURCES = ["plan.hip", "plan2c.hip", "centre.hip", "kernels_1c.hip", "kernels_2c.hip", "kernels_lu.hip",
+           "observables.hip", "basis.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

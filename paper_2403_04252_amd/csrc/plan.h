@@ -274,7 +274,7 @@ struct LaunchEv {
 enum KernelId {
     kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
     k2cNodes, k2cInterp, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
-    kChunk, k2cReduce, kFpoint, kNumKernels
+    kChunk, k2cReduce, kFpoint, kChannels, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 
@@ -293,6 +293,31 @@ struct KernelTimer {
     int take(int kernel, double* total_ms, long long* launches);
     ~KernelTimer();
 };
+
+// Reaction channels of the states (observables.hip): elastic, target
+// excitation, target continuum, capture, projectile continuum, total.
+constexpr int kNumChannels = 6;
+constexpr unsigned char kChElastic = 0, kChExcitation = 1, kChTargetCont = 2, kChCapture = 3, kChProjCont = 4,
+                        kChPadding = 255;
+
+// Per-plan tables of the observables: a channel code per state of every path
+// ([n_traj][n_pad], kChPadding beyond N_j), the group of every path (paths
+// sharing the basis pair and the speed) and each group's paths by increasing b.
+struct Observables {
+    int n_traj = 0, n_pad = 0, n_groups = 0;
+    std::vector<int> group_of;
+    unsigned char* d_code = nullptr;
+    int* d_order = nullptr;
+    int* d_gstart = nullptr;
+    double* d_b = nullptr;
+    long long bytes = 0;
+};
+int obs_build(Observables& o, int n_traj, int n_pad, const std::vector<unsigned char>& codes,
+              const std::vector<int>& group_of, const std::vector<double>& b);
+void obs_free(Observables& o);
+// chan [n_traj][kNumChannels] from P [n_traj][n_pad]; sigma [n_groups][kNumChannels] (may be NULL)
+hipError_t launch_observables(const Observables& o, const double* P, double* chan, double* sigma, hipStream_t st,
+                              const LaunchEv& ev = LaunchEv{});
 
 // centre.hip
 // model_a != 0 adds DeltaV = -a e^{-c r}/r (block diagonal in l, m) to the

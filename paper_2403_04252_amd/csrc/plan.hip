@@ -80,6 +80,7 @@ struct wpccc_plan_s {
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
     double* d_gpart = nullptr;  // [n_traj][kGradSlots][n_chunks] per-workgroup gradient shares (k_apply)
     StageTile* d_tiles = nullptr;  // the row tiles of every tiling in kStageRowsList, one after another
+    Observables obs;               // channel codes and path groups (wpccc_observables)
     int tile_off[kNumStageRows] = {}, tile_n[kNumStageRows] = {};
     KernelTimer timer;
 
@@ -100,6 +101,7 @@ namespace {
 void free_plan(wpccc_plan_s* p) {
     if (!p) return;
     if (p->p2c) plan2c_destroy(p->p2c);
+    obs_free(p->obs);
     centre_free(p->c);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -542,6 +544,38 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     return WPCCC_OK;
 }
 
+// Channel code of state i of a basis with energies eps (kChElastic .. kChProjCont).
+unsigned char channel_code(const std::vector<double>& eps, int i, bool projectile) {
+    if (projectile) return eps[i] < 0.0 ? kChCapture : kChProjCont;
+    if (i == 0) return kChElastic;
+    return eps[i] < 0.0 ? kChExcitation : kChTargetCont;
+}
+
+// Observable tables of a plan: the states of path j are the target basis of
+// its set (and the projectile basis after it, two-centre); group = (set, v).
+int build_observables(wpccc_plan_s* p, int n_traj, int n_pad, const std::vector<const HostBasis*>& tb,
+                      const std::vector<const HostBasis*>& pb, const int* set_of, const double* b, const double* v) {
+    std::vector<unsigned char> codes((size_t)n_traj * n_pad, kChPadding);
+    std::vector<int> group_of(n_traj);
+    std::vector<std::pair<int, double>> keys;
+    for (int j = 0; j < n_traj; ++j) {
+        const int s = set_of ? set_of[j] : 0;
+        unsigned char* c = codes.data() + (size_t)j * n_pad;
+        const HostBasis& t = *tb[s];
+        for (int i = 0; i < t.n_states; ++i) c[i] = channel_code(t.eps, i, false);
+        if (!pb.empty())
+            for (int i = 0; i < pb[s]->n_states; ++i) c[t.n_states + i] = channel_code(pb[s]->eps, i, true);
+        const std::pair<int, double> key(s, v[j]);
+        int g = 0;
+        while (g < (int)keys.size() && keys[g] != key) ++g;
+        if (g == (int)keys.size()) keys.push_back(key);
+        group_of[j] = g;
+    }
+    const int rc = obs_build(p->obs, n_traj, n_pad, codes, group_of, std::vector<double>(b, b + n_traj));
+    if (rc == WPCCC_OK) p->bytes += p->obs.bytes;
+    return rc;
+}
+
 }  // namespace
 
 #define TRY(x)                 \
@@ -791,6 +825,7 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         }
         plan->launch = WPCCC_LAUNCH_PERSISTENT;
     }
+    TRY(build_observables(plan, n_traj, plan->n_pad, {&hb}, {}, nullptr, b_host, v_host));
     *out = plan;
     return WPCCC_OK;
 }
@@ -822,6 +857,14 @@ int wpccc_plan_create_2c(const wpccc_basis_t* targets, const wpccc_basis_t* proj
         free_plan(plan);
         return rc;
     }
+    std::vector<const HostBasis*> tb, pb;
+    for (int s = 0; s < n_sets; ++s) {
+        tb.push_back(&targets[s]->hb);
+        pb.push_back(&projectiles[s]->hb);
+    }
+    int n_pad = 0;
+    plan2c_info(plan->p2c, nullptr, nullptr, &n_pad, nullptr);
+    TRY(build_observables(plan, n_traj, n_pad, tb, pb, set_of_traj, b_host, v_host));
     *out = plan;
     return WPCCC_OK;
 }
@@ -1266,6 +1309,28 @@ int wpccc_plan_kernel_time(wpccc_plan_t plan, const char* kernel, double* total_
     return plan->timer.take(id, total_ms, launches);
 }
 
+int wpccc_plan_groups(wpccc_plan_t plan, int* n_groups, int* group_of_traj_host) {
+    if (!plan) {
+        set_error("wpccc_plan_groups: NULL plan");
+        return WPCCC_EINVAL;
+    }
+    if (n_groups) *n_groups = plan->obs.n_groups;
+    if (group_of_traj_host)
+        std::memcpy(group_of_traj_host, plan->obs.group_of.data(), plan->obs.group_of.size() * sizeof(int));
+    return WPCCC_OK;
+}
+
+int wpccc_observables(wpccc_plan_t plan, const void* P_dev, void* chan_dev, void* sigma_dev, void* stream) {
+    clear_error();
+    if (!plan || !P_dev || !chan_dev) {
+        set_error("wpccc_observables: NULL plan, P_dev or chan_dev");
+        return WPCCC_EINVAL;
+    }
+    const hipError_t e = launch_observables(plan->obs, (const double*)P_dev, (double*)chan_dev, (double*)sigma_dev,
+                                            (hipStream_t)stream, plan->timer.open(kChannels));
+    return launched(e, "k_channels");
+}
+
 }  // extern "C"
 
 namespace wpccc {
@@ -1274,7 +1339,7 @@ const char* const kKernelNames[kNumKernels] = {
     "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
     "k_2c_nodes",     "k_2c_interp",   "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
     "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish",  "k_chunk",
-    "k_2c_reduce",    "k_fpoint"};
+    "k_2c_reduce",    "k_fpoint",      "k_channels"};
 
 LaunchEv KernelTimer::open(int kernel) {
     LaunchEv ev;

@@ -19,8 +19,8 @@ Every value here comes from ``oracle/`` only (FP64, numpy):
   over all 800 RK4 steps of z from -40 to 40 on 64 x 128 spheroidal nodes:
   final probabilities.
 * ``c3_spot382.npz``: a path with 382 states per centre (b = 0.2 * 50^(3/7),
-  v = 1) on the full 256 x 512 nodes, 4 RK4 steps from z = -0.2 starting
-  from a seeded random normalised state: final amplitudes.
+  v = 1) on the full 256 x 512 nodes, 4 RK4 steps from z = -0.2 through
+  closest approach starting from the target ground state: final amplitudes.
 
 Usage: python tests/golden/make_golden.py [c2] [c4] [c3] [c3p] [c3s]   (minutes of CPU each)
 """
@@ -120,13 +120,12 @@ def make_c3_path():
 
 
 def make_c3_spot():
-    from oracle.propagate import rk4_propagate
+    from oracle.propagate import initial_state, rk4_propagate
     from oracle.twocentre import m_two_centre
     w = WL.two_centre_batched(1.0)
     j = 16 + C3_PATH      # basis set 2: 382 states per centre
     ob = _c3_basis(3)
-    N = 2 * ob.n_states
-    X0 = WL.random_state(1, N, seed=17)[0]
+    X0 = initial_state(2 * ob.n_states)
     zg = np.linspace(C3_SPOT_Z[0], C3_SPOT_Z[1], C3_SPOT_Z[2] + 1)
     t0 = time.time()
     X = rk4_propagate(m_two_centre(ob, ob, float(w.b[j]), float(w.v[j]), w.n_eta, w.n_tau, w.q_lower), X0, zg)
