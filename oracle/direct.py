@@ -48,6 +48,44 @@ def radial_integrals(basis: Basis, R: float, lam: int) -> np.ndarray:
     return (phi * g) @ phi.T
 
 
+def lagrange5(nodes: np.ndarray, x: float) -> np.ndarray:
+    """Weights of the Lagrange polynomial through five nodes evaluated at x:
+    L_i(x) = prod_{k != i} (x - x_k) / (x_i - x_k)."""
+    w = np.ones(5)
+    for i in range(5):
+        for k in range(5):
+            if k != i:
+                w[i] *= (x - nodes[k]) / (nodes[i] - nodes[k])
+    return w
+
+
+def stencil_start(basis: Basis, R: float) -> int:
+    """First node of the five-point stencil at R < r_max: the node j nearest
+    to R in x = sqrt(r / r_max) (the grid is uniform in x), nodes j-2..j+2,
+    clamped to the grid."""
+    n_r = basis.spec.n_r
+    j = int(round(n_r * math.sqrt(R / basis.spec.r_max)))
+    return min(max(j, 2), n_r - 2) - 2
+
+
+def radial_integrals_interp(basis: Basis, R: float, lam: int) -> np.ndarray:
+    """F_{a b lambda}(R) as the paper's production code evaluates it (Sec. II):
+    F tabulated on the r-grid (R = r_k, the quadrature of Eq. D2 at each node)
+    and interpolated at R by the five-point Lagrange polynomial in r.  For R at
+    or beyond the grid's end the quadrature is the multipole form
+    R^-(lam+1) sum_i w_i r_i^(2+lam) f_a f_b, evaluated directly (reading: the
+    table ends at r_max).  Returns [N_f, N_f]."""
+    if R >= basis.spec.r_max:
+        return radial_integrals(basis, R, lam)
+    j0 = stencil_start(basis, R)
+    nodes = basis.r[j0:j0 + 5]
+    w = lagrange5(nodes, R)
+    out = np.zeros((basis.n_radial, basis.n_radial))
+    for i in range(5):
+        out += w[i] * radial_integrals(basis, float(nodes[i]), lam)
+    return out
+
+
 @lru_cache(maxsize=None)
 def d1_coefficient(lp: int, mp: int, l: int, m: int, lam: int) -> float:
     """The lambda-term of Eq. D1 without P and F:
@@ -74,13 +112,16 @@ def d1_angular(lp: int, mp: int, l: int, m: int, lam: int, cos_theta: float) -> 
 
 
 def direct_spatial(basis: Basis, R: float, cos_theta: float, Zp: float = 1.0,
-                   parity: int = 1) -> np.ndarray:
+                   parity: int = 1, radial: str = "exact") -> np.ndarray:
     """Real spatial part of D (Eq. D1) at (R, Theta): [N, N] float64.
 
     ``parity`` = -1 gives the projectile-centred form (factor (-1)^lambda).
+    ``radial``: "exact" (Eq. D2's quadrature at R) or "interp" (the tabulated
+    F interpolated at R, ``radial_integrals_interp``).
     """
     lmax = basis.spec.l_max
-    F = [radial_integrals(basis, R, lam) for lam in range(2 * lmax + 1)]
+    rad = radial_integrals_interp if radial == "interp" else radial_integrals
+    F = [rad(basis, R, lam) for lam in range(2 * lmax + 1)]
     P = {(lam, mu): float(assoc_legendre(lam, mu, cos_theta))
          for lam in range(2 * lmax + 1) for mu in range(-lam, lam + 1)}
     N = basis.n_states
@@ -117,7 +158,7 @@ def interaction_phases(eps_row: np.ndarray, eps_col: np.ndarray, z: float, v: fl
 
 
 def direct_matrix(basis: Basis, b: float, z: float, v: float, Zp: float = 1.0,
-                  parity: int = 1, z_phase: float = 0.0) -> np.ndarray:
+                  parity: int = 1, z_phase: float = 0.0, radial: str = "exact") -> np.ndarray:
     """D_T(b, z) of Eq. D1 with interaction-picture phases: complex [N, N].
 
     R = sqrt(b^2 + z^2), cos Theta = z / R (the straight-line path R = (b, 0, z)).
@@ -127,5 +168,5 @@ def direct_matrix(basis: Basis, b: float, z: float, v: float, Zp: float = 1.0,
     R = math.hypot(b, z)
     if R <= 0.0:
         raise ValueError("R must be positive")
-    Dsp = direct_spatial(basis, R, z / R, Zp=Zp, parity=parity)
+    Dsp = direct_spatial(basis, R, z / R, Zp=Zp, parity=parity, radial=radial)
     return Dsp * interaction_phases(basis.eps, basis.eps, z + z_phase, v)

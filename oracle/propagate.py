@@ -68,20 +68,21 @@ def initial_state(n: int) -> np.ndarray:
     return X
 
 
-def m_one_centre(basis: Basis, b: float, v: float, Zp: float = 1.0, z_phase: float = 0.0):
-    """z -> M(z) = -(i/v) D_T(b, z)."""
+def m_one_centre(basis: Basis, b: float, v: float, Zp: float = 1.0, z_phase: float = 0.0,
+                 radial: str = "exact"):
+    """z -> M(z) = -(i/v) D_T(b, z); ``radial`` as in ``direct_spatial``."""
     def M(z: float) -> np.ndarray:
-        return (-1j / v) * direct_matrix(basis, b, z, v, Zp=Zp, z_phase=z_phase)
+        return (-1j / v) * direct_matrix(basis, b, z, v, Zp=Zp, z_phase=z_phase, radial=radial)
     return M
 
 
 def propagate_one_centre(basis: Basis, b: float, v: float, zgrid: np.ndarray,
                          Zp: float = 1.0, X0: np.ndarray | None = None,
-                         z_phase: float = 0.0) -> np.ndarray:
+                         z_phase: float = 0.0, radial: str = "exact") -> np.ndarray:
     """X at the end of the z-grid for one straight-line path (1C)."""
     if X0 is None:
         X0 = initial_state(basis.n_states)
-    return rk4_propagate(m_one_centre(basis, b, v, Zp, z_phase), X0, zgrid)
+    return rk4_propagate(m_one_centre(basis, b, v, Zp, z_phase, radial), X0, zgrid)
 
 
 def probabilities(X: np.ndarray) -> np.ndarray:

@@ -256,18 +256,21 @@ def test_large_l_basis_parity():
     assert e.value.code == -6
 
 
-def test_paper_shape_l6_smaller_tiles():
-    """The paper's basis shape at l_max = 6 (N_l = 42 - l radial functions per
-    l, N = 1855): a stage tile of 8 rows (and the adjoint's operator kernel)
-    no longer fits the LDS, so the plan times the smaller tilings that do.
-    One path, 6 steps, against the oracle; 8 rows explicitly and the adjoint
-    are refused with WPCCC_ENOTSUP."""
-    rec = WL.Recipe(10, 6, 32, 3.0, 300, 100.0)
+@pytest.mark.parametrize("l_max,n_states,n_steps", [(6, 1855, 6), (7, 2380, 3)])
+def test_paper_shape_smaller_tiles(l_max, n_states, n_steps):
+    """The paper's basis shape at l_max = 6 and 7 (N_l = 42 - l radial
+    functions per l, N = 1855 and 2380, the largest the stage kernel takes):
+    a stage tile of 8 rows (and the adjoint's operator kernel) no longer fits
+    the LDS, so the plan times the smaller tilings that do.  One path against
+    the oracle; 8 rows explicitly and the adjoint are refused with
+    WPCCC_ENOTSUP; every admissible smaller tiling agrees with the timed one
+    to rounding (the order of the final reductions differs)."""
+    rec = WL.Recipe(10, l_max, 32, 3.0, 300, 100.0)
     lb, ob = lib_basis(rec), oracle_basis(rec)
-    zg = np.linspace(-3.0, -2.4, 7)
-    print("paper shape l_max = 6 (N = 1855), 1 path x 6 steps", flush=True)
+    zg = np.linspace(-3.0, -3.0 + 0.1 * n_steps, n_steps + 1)
+    print(f"paper shape l_max = {l_max} (N = {n_states}), 1 path x {n_steps} steps", flush=True)
     plan = W.wpccc_plan_create(lb, [1.5], [2.0])
-    assert plan.n_states == 1855
+    assert plan.n_states == n_states
     rows = W.wpccc_plan_stage_rows(plan)
     print(f"  timed tiling: {rows} rows", flush=True)
     assert rows < 8
@@ -284,6 +287,48 @@ def test_paper_shape_l6_smaller_tiles():
     with pytest.raises(W.WpcccError) as e:
         W.wpccc_adjoint(plan, zg, X0, X0.clone(), grad)
     assert e.value.code == -6
+    for r in (4, 5, 6, 7):
+        if r == rows:
+            continue
+        try:
+            Xr, _, _ = _propagate_gpu(lb, [1.5], [2.0], zg, stage_rows=r)
+        except W.WpcccError as err:
+            assert err.code in (-1, -6), str(err)   # does not fit this basis
+            continue
+        print(f"  tiling {r} rows vs timed: {np.abs(Xr - X).max():.1e}", flush=True)
+        assert np.abs(Xr - X).max() <= 1e-13
+
+
+def test_nonfinite_amplitude_latched(small):
+    """A non-finite input amplitude propagates to the RK4 update, whose
+    watchdog latches WPCCC_ENUMERIC for wpccc_plan_status (no device fault,
+    every kernel ends normally); the latch clears after it is read."""
+    rec, lb, _ = small
+    plan = W.wpccc_plan_create(lb, [1.0, 2.0], [1.0, 1.0])
+    X = torch.zeros((2, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    X[1, 3] = float("nan")
+    W.wpccc_propagate(plan, WL.z_uniform(-2.0, 2.0, 0.1), X)
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_status(plan)
+    assert e.value.code == -5
+    W.wpccc_plan_status(plan)   # cleared
+    assert torch.isfinite(X[0]).all()
+
+
+def test_smem_limit_only_raised():
+    """The dynamic-LDS limit of the stage kernels is process-wide: a plan with
+    a smaller basis created after a larger one must not lower it under the
+    larger plan, which propagates correctly afterwards."""
+    big = WL.Recipe(10, 6, 32, 3.0, 300, 100.0)
+    lbig = lib_basis(big)
+    zg = np.linspace(-3.0, -2.8, 3)
+    ref, _, _ = _propagate_gpu(lbig, [1.5], [2.0], zg, stage_rows=4)
+    mid = lib_basis(WL.Recipe(6, 4, 20, 3.0, 300, 100.0))
+    pmid = W.wpccc_plan_create(mid, [1.0], [1.0], stage_rows=4)
+    assert pmid.n_states == 580
+    again, _, _ = _propagate_gpu(lbig, [1.5], [2.0], zg, stage_rows=4)
+    assert np.array_equal(again, ref)
 
 
 def test_stage_rows_limit():

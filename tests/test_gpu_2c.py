@@ -269,3 +269,21 @@ def test_2c_step_at_large_n():
     err = np.abs(X.cpu().numpy()[0, :N] - x1).max()
     print(f"  max |dX| {err:.2e}", flush=True)
     assert err <= 1e-10
+
+
+def test_2c_nonfinite_amplitude_latched(small_run):
+    """Two-centre watchdog: a non-finite input amplitude reaches the RK4 update
+    of the solve kernel, which latches WPCCC_ENUMERIC for wpccc_plan_status
+    (every kernel ends normally); the other paths stay finite."""
+    wl, lt, lp, _ = small_run
+    plan = W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, n_eta=wl.n_eta, n_tau=wl.n_tau,
+                                  q_lower=_q_lower(wl.q_lower))
+    X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[:, 0] = 1.0
+    X[2, 1] = complex(float("inf"), 0.0)
+    W.wpccc_propagate(plan, wl.zgrid[:3], X)
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_status(plan)
+    assert e.value.code == -5
+    W.wpccc_plan_status(plan)
+    assert torch.isfinite(X[0]).all() and torch.isfinite(X[1]).all()
