@@ -123,9 +123,12 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed RK4 steps, each over all paths (default 800; 20 for c3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 40; 2 for c3)")
-    ap.add_argument("--workload", choices=["c2", "c3", "sweep"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "sweep", "paper"], default="c2",
                     help="c2: batched one-centre N=580 (the headline); c3: batched two-centre; "
-                         "sweep: one-centre throughput against basis size (paper shape N_l = 42 - l)")
+                         "sweep: one-centre throughput against basis size (paper shape N_l = 42 - l); "
+                         "paper: the paper's trajectory (v = 2, z -300..300 on 6001 points, 8 paths) "
+                         "with exact-R and interpolated radial integrals")
+    ap.add_argument("--lmax", type=int, default=6, help="paper: l_max of the paper-shape basis (<= 7)")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
     ap.add_argument("--no-2c", action="store_true",
@@ -155,6 +158,9 @@ def main():
         args.steps = 20 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         return bench_two_centre(args)
+    if args.workload == "paper":
+        args.warmup = 20 if args.warmup is None else args.warmup
+        return bench_paper(args)
     if args.workload == "sweep":
         args.steps = 200 if args.steps is None else args.steps
         args.warmup = 20 if args.warmup is None else args.warmup
@@ -490,6 +496,76 @@ def bench_sweep(args):
                                              "2000-pt grid, 8 b log-spaced 0.2-10, v=2, dz=0.1",
                                  "parallelism": "1 GPU, paths batched"},
                       "sweep": rows}), flush=True)
+
+
+def bench_paper(args):
+    """The paper's trajectory (Sec. III): p + H at 100 keV (v = 2 a.u.), z from
+    -300 to 300 a.u. on the paper's geometric grid (z_min = 1e-3, n_z = 3000:
+    6001 points, 6000 RK4 steps), 8 paths per batch (b log-spaced 0.2..10);
+    one-centre basis of the paper's shape, N_l = 42 - l radial functions per l
+    (bound n <= 10 plus 32 Coulomb bins per l) up to l_max, on a 10,000-point
+    r-grid to 100 a.u.  Both radial forms: the exact-R quadrature (moment
+    tables) and the paper's tabulated F with five-point interpolation.  Prints
+    one JSON line: rates, setup times, and the difference of the two forms'
+    final probabilities and cross sections."""
+    import torch
+    import paper_2403_04252_amd as W
+    from paper_2403_04252_amd import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    b = 0.2 * 50.0 ** (np.arange(8) / 7.0)
+    v = np.full(8, 2.0)
+    zg = WL.z_geometric(1e-3, 300.0, 3000)
+    rec = WL.Recipe(10, args.lmax, 32, 3.0, 10000)
+    t0 = time.perf_counter()
+    lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+    basis_s = time.perf_counter() - t0
+    n_states = W.wpccc_basis_info(lb)[0]
+    res, Pf, sig = {}, {}, {}
+    for form in ("exact", "interp"):
+        print(f"paper trajectory: N = {n_states}, radial form {form}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        plan = W.wpccc_plan_create(lb, b, v, interp=(form == "interp"))
+        setup = time.perf_counter() - t0
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        W.wpccc_propagate(plan, zg[: args.warmup + 1], X)
+        X.zero_()
+        X[:, 0] = 1.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W.wpccc_propagate(plan, zg, X)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        W.wpccc_plan_status(plan)
+        steps = zg.size - 1
+        P = (X.abs() ** 2).contiguous()
+        chan = torch.empty((plan.n_traj, W.WPCCC_N_CHANNELS), dtype=torch.float64, device="cuda")
+        sg = torch.empty((1, W.WPCCC_N_CHANNELS), dtype=torch.float64, device="cuda")
+        W.wpccc_observables(plan, P, chan, sg)
+        torch.cuda.synchronize()
+        Pf[form] = P.cpu().numpy()[:, :n_states]
+        sig[form] = sg.cpu().numpy()[0]
+        res[form] = {"value": plan.n_traj * steps / wall, "unit": "trajectory-steps/s",
+                     "ms_per_step": wall / steps * 1e3, "plan_setup_s": setup,
+                     "stage_rows": W.wpccc_plan_stage_rows(plan), "device_bytes": plan.device_bytes,
+                     "cross_sections_au": dict(zip(W.CHANNELS, sig[form].tolist()))}
+        del plan, X, P
+        torch.cuda.empty_cache()
+    d = np.abs(Pf["interp"] - Pf["exact"])
+    print(json.dumps({"metric": "RK4 steps/s over batched b on the paper's trajectory", "n_gpus": 1,
+                      "steps": int(zg.size - 1), "warmup": args.warmup, "higher_is_better": True, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": f"p+H 1C paper shape N_l = 42 - l, l_max {args.lmax} (N = {n_states}), "
+                                             "10000-pt r-grid to 100 a.u., 8 b log-spaced 0.2-10, v = 2 (100 keV), "
+                                             "geometric z-grid -300..300 (6001 points, z_min 1e-3)",
+                                 "parallelism": "1 GPU, paths batched", "basis_setup_s": basis_s},
+                      "exact": res["exact"], "interp": res["interp"],
+                      "interp_vs_exact": {"max_abs_dP": float(d.max()),
+                                          "max_rel_sigma": float(np.max(np.abs(sig["interp"] - sig["exact"])
+                                                                        / np.maximum(np.abs(sig["exact"]), 1e-300)))}}),
+          flush=True)
 
 
 def adjoint_measure(torch, W, WL):

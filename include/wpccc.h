@@ -161,7 +161,20 @@ typedef struct {
                        per-path barrier between stages (WPCCC_ENOTSUP at plan
                        creation when its grid cannot be resident at once).
                        Both forms give bitwise the same amplitudes. */
+    int radial;     /* 1C: how the radial integrals F of Eq. D2 are evaluated at R:
+                       WPCCC_RADIAL_EXACT (default): the r-grid quadrature at the
+                       exact R, from prefix/suffix moment tables;
+                       WPCCC_RADIAL_INTERP: the paper's production form (Sec. II),
+                       F tabulated on the r-grid nodes and interpolated at R by
+                       the five-point Lagrange polynomial in r on the stencil of
+                       the node nearest in sqrt(r / r_max), the multipole form
+                       F(r_max) (r_max / R)^(lam+1) beyond the grid.  FP64, one
+                       launch per stage (WPCCC_ENOTSUP with WPCCC_MIXED or
+                       WPCCC_LAUNCH_PERSISTENT), no adjoint. */
 } wpccc_plan_opts;
+
+#define WPCCC_RADIAL_EXACT  0
+#define WPCCC_RADIAL_INTERP 1
 
 #define WPCCC_LAUNCH_AUTO       0
 #define WPCCC_LAUNCH_STAGES     1
@@ -282,7 +295,7 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
  *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
  * Device memory for the checkpoints is allocated by the first call.  Errors:
  * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, a
- * WPCCC_MIXED plan, or a basis whose operator kernel does not fit the LDS at 8
+ * WPCCC_MIXED or WPCCC_RADIAL_INTERP plan, or a basis whose operator kernel does not fit the LDS at 8
  * rows per workgroup). */
 int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);

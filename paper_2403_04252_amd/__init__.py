@@ -57,7 +57,8 @@ class _PlanOpts(ctypes.Structure):
                 ("q_lower", ctypes.c_int), ("n_eta", ctypes.c_int), ("n_tau", ctypes.c_int),
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
                 ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
-                ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int),
+                ("radial", ctypes.c_int)]
 
 
 @dataclass
@@ -217,17 +218,20 @@ def wpccc_basis_destroy(basis: Basis):
 def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
                       two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
                       checkpoint_every: int = 0, stage_rows: int = 0, graph: bool = False,
-                      stage_launch: int = WPCCC_LAUNCH_AUTO, mixed: bool = False, stream=None) -> Plan:
+                      stage_launch: int = WPCCC_LAUNCH_AUTO, mixed: bool = False, interp: bool = False,
+                      stream=None) -> Plan:
     """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
     model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis;
     stage_launch: WPCCC_LAUNCH_AUTO / _STAGES / _PERSISTENT; mixed: the scaled
-    FP32 moment tables (WPCCC_MIXED)."""
+    FP32 moment tables (WPCCC_MIXED); interp: F tabulated on the grid and
+    interpolated at R (WPCCC_RADIAL_INTERP)."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
     opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
                      float(model_a), float(model_c), int(checkpoint_every), int(stage_rows),
-                     WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, int(stage_launch))
+                     WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, int(stage_launch),
+                     1 if interp else 0)
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),

@@ -60,7 +60,7 @@ void block_columns(const Meta& m, int lp, int l, int lam, int& e0, int& g0) {
 
 void centre_free(Centre& c) {
     void* bufs[] = {c.d_meta,   c.d_eps,  c.d_gcoef, c.d_rad_eps, c.d_col_lam,
-                    c.d_gpb,    c.d_st_rad, c.d_st_xs, c.d_gcol,  c.d_tab, c.d_tab32};
+                    c.d_gpb,    c.d_st_rad, c.d_st_xs, c.d_gcol,  c.d_tab, c.d_tab32, c.d_ftab};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     c = Centre{};
@@ -88,7 +88,7 @@ void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& 
 }
 
 int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a, double model_c, double Zp,
-                 bool tab_f32) {
+                 int form) {
     if (hb.spec.l_max > kMaxL) {
         set_error("basis l_max %d exceeds %d", hb.spec.l_max, kMaxL);
         return WPCCC_EINVAL;
@@ -270,11 +270,13 @@ int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a,
         if (rc == WPCCC_OK && e == hipSuccess)
             e = launch_table_shift(c.d_tab, m.n_frow, m.n_r, d_sidx, d_sval, (int)sh_idx.size(), st);
     }
-    if (tab_f32) {
-        // the scaled FP32 form replaces the FP64 table (after the model shift)
-        A(dev_alloc(&c.d_tab32, (size_t)(m.n_r + 1) * m.n_frow, tot));
+    if (form != kRadialMoments) {
+        // the scaled FP32 form or the node values replace the FP64 table (after the model shift)
+        if (form == kRadialMoments32) A(dev_alloc(&c.d_tab32, (size_t)(m.n_r + 1) * m.n_frow, tot));
+        else A(dev_alloc(&c.d_ftab, (size_t)(m.n_r + 1) * m.n_frow, tot));
         if (rc == WPCCC_OK && e == hipSuccess)
-            e = launch_table_f32(c.d_tab, d_dl, m.n_frow, m.n_r, m.r_max, c.d_tab32, st);
+            e = form == kRadialMoments32 ? launch_table_f32(c.d_tab, d_dl, m.n_frow, m.n_r, m.r_max, c.d_tab32, st)
+                                         : launch_table_nodes(c.d_tab, d_dl, m.n_frow, m.n_r, m.r_max, c.d_ftab, st);
         if (rc == WPCCC_OK && e == hipSuccess) e = hipStreamSynchronize(st);
         if (rc == WPCCC_OK && e == hipSuccess) {
             (void)hipFree(c.d_tab);

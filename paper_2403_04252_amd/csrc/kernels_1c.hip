@@ -180,6 +180,57 @@ __global__ void k_table_f32(const double2* __restrict__ tab, const int* __restri
     out[i] = make_float2((float)x, (float)y);
 }
 
+// F on the grid nodes, one thread per (entry d, node k): the quadrature of
+// Eq. D2 at R = r_k, r_k^-(lam+1) A_k + r_k^lam B_(k+1) (at r_0 = 0 only the
+// lam = 0 term B_1 survives).  The paper's production table (Sec. II).
+__global__ void k_table_nodes(const double2* __restrict__ tab, const int* __restrict__ dl, int n_frow, int n_r,
+                              double r_max, double* __restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (d >= n_frow) return;
+    const int lam = dl[d];
+    const size_t i = (size_t)k * n_frow + d;
+    const double2 ab = tab[i];
+    double f;
+    if (k == 0) {
+        f = lam == 0 ? ab.y : 0.0;
+    } else {
+        const double rk = node_r(k, r_max, n_r);
+        double p = 1.0;
+        for (int q = 0; q < lam; ++q) p *= rk;
+        f = ab.x / (p * rk) + ab.y * p;
+    }
+    out[i] = f;
+}
+
+// Five-point interpolation of the node table at R (R < r_max): the stencil of
+// the node j nearest to R in x = sqrt(r/r_max) (uniform in x), nodes j-2..j+2
+// clamped to the grid, with the Lagrange weights in r.  Returns the first node.
+__device__ inline int interp_stencil(double R, double r_max, int n_r, double* w) {
+    int j = (int)rint(n_r * sqrt(R / r_max));
+    j = min(max(j, 2), n_r - 2) - 2;
+    double x[5];
+    for (int i = 0; i < 5; ++i) x[i] = node_r(j + i, r_max, n_r);
+    for (int i = 0; i < 5; ++i) {
+        double p = 1.0;
+        for (int k = 0; k < 5; ++k)
+            if (k != i) p *= (R - x[k]) / (x[i] - x[k]);
+        w[i] = p;
+    }
+    return j;
+}
+
+// F of entry d (multipole lam) from the node table: the stencil sum (kidx >= 0,
+// weights rp[0..4]) or the multipole form beyond the grid, F(r_max) (r_max/R)^(lam+1)
+// (kidx = -1, rp[lam] = (r_max/R)^(lam+1)).
+__device__ inline double interp_value(const double* ftab, int n_frow, int n_r, int kidx, const double* rp, size_t d,
+                                      int lam) {
+    if (kidx < 0) return ftab[(size_t)n_r * n_frow + d] * rp[lam];
+    double f = 0.0;
+    for (int i = 0; i < 5; ++i) f += rp[i] * ftab[(size_t)(kidx + i) * n_frow + d];
+    return f;
+}
+
 __device__ inline double2 phase(double eps, double z, double v) {
     double sn, cs;
     sincos(eps * z / v, &sn, &cs);
@@ -198,9 +249,30 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     const size_t jp = (size_t)j * a.pt.n_pts + p;
     const int t = threadIdx.x;
     const int k = grid_index(R, m.r_max, m.n_r);
-    if (t == 0) a.pt.kidx[jp] = k;
+    if (a.tb.ftab) {
+        // interpolated F: stencil and weights, or the multipole factors beyond the grid
+        if (R < m.r_max) {
+            if (t == 0) {
+                double w[5];
+                a.pt.kidx[jp] = interp_stencil(R, m.r_max, m.n_r, w);
+                for (int i = 0; i < 5; ++i) a.pt.rpow[jp * kRpow + i] = w[i];
+            }
+        } else {
+            if (t == 0) a.pt.kidx[jp] = -1;
+            if (t <= m.lam_max) {
+                const double q = m.r_max / R;
+                double f = q;
+                for (int i = 0; i < t; ++i) f *= q;
+                a.pt.rpow[jp * kRpow + t] = f;
+            }
+        }
+    } else if (t == 0) {
+        a.pt.kidx[jp] = k;
+    }
     if (t <= m.lam_max) {
-        if (a.tb.tab32) {
+        if (a.tb.ftab) {
+            // factors written above
+        } else if (a.tb.tab32) {
             scaled_factors(R, k, t, m.r_max, m.n_r, &a.pt.rpow[jp * kRpow + 2 * t], &a.pt.rpow[jp * kRpow + 2 * t + 1]);
         } else {
             double Rl = 1.0;
@@ -723,6 +795,11 @@ __global__ __launch_bounds__(256) void k_fpoint(const Meta* __restrict__ mp_, Ta
     while (lp < m.l_max && d >= m.frow_off[lp + 1]) ++lp;
     const int lam = T.col_lam[m.col_off[lp] + (d - m.frow_off[lp]) % m.nV[lp]];
     const double* rp = pt.rpow + jp * kRpow;
+    if (T.ftab) {
+        static_cast<double*>(fc_)[(size_t)j * m.n_frow + d] =
+            interp_value(T.ftab, m.n_frow, m.n_r, pt.kidx[jp], rp, d, lam);
+        return;
+    }
     const size_t i = (size_t)pt.kidx[jp] * m.n_frow + d;
     if constexpr (F32) {
         const float2 t0 = T.tab32[i];
@@ -1049,7 +1126,20 @@ __global__ __launch_bounds__(256) void k_slot_setup(SetupArgs a) {
         const int e = (d - m.frow_off[lp]) % m.nV[lp];
         const int k = grid_index(R, m.r_max, m.n_r);
         const int lam = T.col_lam[m.col_off[lp] + e];
-        if (T.tab32) {
+        if (T.ftab) {
+            double rp[kRpow];
+            int kk = -1;
+            if (R < m.r_max) {
+                kk = interp_stencil(R, m.r_max, m.n_r, rp);
+            } else {
+                double f = m.r_max / R;
+                for (int q = 0; q <= lam; ++q) {
+                    rp[q] = f;
+                    f *= m.r_max / R;
+                }
+            }
+            a.Frow[d] = interp_value(T.ftab, m.n_frow, m.n_r, kk, rp, d, lam);
+        } else if (T.tab32) {
             const float2 ab = T.tab32[(size_t)k * m.n_frow + d];
             double fa, fb;
             scaled_factors(R, k, lam, m.r_max, m.n_r, &fa, &fb);
@@ -1259,6 +1349,13 @@ hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st) {
 
 hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_traj, hipStream_t st) {
     hipLaunchKernelGGL(k_grad_sum, dim3(n_traj), dim3(64), 0, st, gpart, n_part, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_nodes(const double2* tab, const int* dl, int n_frow, int n_r, double r_max, double* out,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_table_nodes, dim3((n_frow + 255) / 256, n_r + 1), dim3(256), 0, st, tab, dl, n_frow, n_r,
+                       r_max, out);
     return hipGetLastError();
 }
 

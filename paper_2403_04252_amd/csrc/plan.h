@@ -66,6 +66,7 @@ struct Tables {
     const double2* tab;     // [n_r+1][n_frow]: (A_k, B_(k+1)) per Frow entry (FP64 plans)
     const float2* tab32;    // [n_r+1][n_frow]: the scaled FP32 form (reduced-precision plans, else NULL):
                             //   (A_k / r_k^(lam+1), B_(k+1) r_(k+1)^lam)
+    const double* ftab;     // [n_r+1][n_frow]: F(r_k) on the grid nodes (interpolated-F plans, else NULL)
     const int* col_lam;     // [n_cols] lambda of each Frow column, per l'
     const int2* gcol_info;  // [n_gcols] gcol_pack of each G column, per l'
     const double* gcoef;    // [n_g] c(l'm', lm, lambda), (-1)^mu folded in for mu < 0
@@ -82,7 +83,10 @@ struct Tables {
 // computed once by k_prologue for all points of a propagation chunk:
 //   kidx[j][p]                grid node of R (last r_k <= R)
 //   rpow[j][p][2 lam]         R^-(lam+1) at 2 lam, R^lam at 2 lam + 1 (FP64 table);
-//                             (r_k/R)^(lam+1) and (R/r_(k+1))^lam (scaled FP32 table)
+//                             (r_k/R)^(lam+1) and (R/r_(k+1))^lam (scaled FP32 table);
+//                             interpolated F: the five Lagrange weights of the
+//                             stencil starting at node kidx (R < r_max), or
+//                             kidx = -1 and (r_max/R)^(lam+1) at lam (R >= r_max)
 //   pbar[j][p][n_pb]          Pbar_lam^mu(cos Theta)
 //   ph[j][p][n_f]             exp(i eps_f z / v) per radial function
 struct PointArrays {
@@ -237,11 +241,13 @@ struct Centre {
     int2* d_gcol = nullptr;
     double2* d_tab = nullptr;     // FP64 moment table (NULL once a scaled FP32 table replaces it)
     float2* d_tab32 = nullptr;    // scaled FP32 moment table (reduced-precision one-centre plans)
+    double* d_ftab = nullptr;     // F on the grid nodes (interpolated-F one-centre plans)
     long long bytes = 0;
     Tables tables(const double* bvec, const double* vvec) const {
         Tables t;
         t.tab = d_tab;
         t.tab32 = d_tab32;
+        t.ftab = d_ftab;
         t.col_lam = d_col_lam;
         t.gcol_info = d_gcol;
         t.gcoef = d_gcoef;
@@ -323,9 +329,14 @@ hipError_t launch_observables(const Observables& o, const double* P, double* cha
 // model_a != 0 adds DeltaV = -a e^{-c r}/r (block diagonal in l, m) to the
 // lambda = 0 moments of the equal-l blocks, so that every use of the tables
 // sees D_T + DeltaV (projectile charge Zp)
-// tab_f32: replace the FP64 moment table by its scaled FP32 form (Tables::tab32)
+// Radial-integral forms a centre's tables can take (centre_build):
+enum RadialForm {
+    kRadialMoments = 0,   // FP64 moment table: Eq. D2's quadrature at the exact R
+    kRadialMoments32 = 1, // its scaled FP32 form (Tables::tab32)
+    kRadialInterp = 2,    // F on the grid nodes, five-point interpolation at R (Tables::ftab)
+};
 int centre_build(const HostBasis& hb, hipStream_t st, Centre& c, double model_a = 0.0, double model_c = 0.0,
-                 double Zp = 1.0, bool tab_f32 = false);
+                 double Zp = 1.0, int form = kRadialMoments);
 // radial blocks va, vc of the model potential (layout of StageArgs::va, vc)
 void model_blocks(const HostBasis& hb, double a, double c, std::vector<double>& va, std::vector<double>& vc);
 void centre_free(Centre& c);
@@ -382,6 +393,9 @@ hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_
 // *chunk = value (reset) or *chunk += 1 (advance), one thread
 hipError_t launch_chunk_counter(int* chunk, int reset, hipStream_t st);
 hipError_t launch_table_shift(double2* tab, int n_frow, int n_r, const int* idx, const double* val, int count,
+                              hipStream_t st);
+// F on the grid nodes from a moment table (Tables::ftab)
+hipError_t launch_table_nodes(const double2* tab, const int* dl, int n_frow, int n_r, double r_max, double* out,
                               hipStream_t st);
 // scaled FP32 copy of a moment table (Tables::tab32); dl: multipole order of each entry
 hipError_t launch_table_f32(const double2* tab, const int* dl, int n_frow, int n_r, double r_max, float2* out,

@@ -76,6 +76,7 @@ struct wpccc_plan_s {
     // persistent k_chunk launch (WPCCC_LAUNCH_PERSISTENT)
     int launch = WPCCC_LAUNCH_STAGES;
     bool mixed = false;       // scaled FP32 moment table (WPCCC_MIXED): per-stage launches only, no adjoint
+    bool interp = false;      // F on the grid nodes, five-point interpolation (WPCCC_RADIAL_INTERP)
     int chunk_smem = 0;       // k_chunk with stage_rows
     int* d_bar = nullptr;     // [n_traj][kBarStride] path barrier counters of k_chunk
     double* d_gpart = nullptr;  // [n_traj][kGradSlots][n_chunks] per-workgroup gradient shares (k_apply)
@@ -166,10 +167,10 @@ void* fc_slot(const wpccc_plan_s* p, int s) {
     return static_cast<char*>(p->d_fc) + (size_t)s * p->n_traj * p->c.meta.n_frow * elem;
 }
 
-// F at point slot `point` into cache slot 0 for paths [j0, j0+nj): the start of
-// a run of cached steps.
-int enqueue_fpoint(wpccc_plan_s* p, int j0, int nj, int point, hipStream_t st) {
-    hipError_t e = launch_fpoint(p->c.d_meta, p->c.meta, p->tables(), p->points(), point, j0, nj, fc_slot(p, 0), st,
+// F at point slot `point` into cache slot `slot` (0: the start of a run of
+// cached steps) for paths [j0, j0+nj).
+int enqueue_fpoint(wpccc_plan_s* p, int j0, int nj, int point, hipStream_t st, int slot = 0) {
+    hipError_t e = launch_fpoint(p->c.d_meta, p->c.meta, p->tables(), p->points(), point, j0, nj, fc_slot(p, slot), st,
                                  p->timer.open(kFpoint));
     return launched(e, "k_fpoint");
 }
@@ -222,6 +223,15 @@ int enqueue_step(wpccc_plan_s* p, double2* X, int j0, int nj, int pz, double h, 
     // the step's index within its chunk (graph replays read h at this index)
     const int step = pz / 2;
     const int c0 = cached ? 0 : -1, c1 = cached ? 1 : -1;
+    if (p->interp) {
+        // interpolated F: the cache is filled by k_fpoint at each new point
+        if ((rc = enqueue_stage(p, j0, nj, 1, pz, step, h, X, X, p->d_Ua, st, nullptr, 0))) return rc;
+        if ((rc = enqueue_fpoint(p, j0, nj, pz + 1, st, 1))) return rc;
+        if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, step, h, p->d_Ua, X, p->d_Ub, st, nullptr, 1))) return rc;
+        if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, step, h, p->d_Ub, X, p->d_Ua, st, nullptr, 1))) return rc;
+        if ((rc = enqueue_fpoint(p, j0, nj, pz + 2, st, 0))) return rc;
+        return enqueue_stage(p, j0, nj, 4, pz + 2, step, h, p->d_Ua, X, nullptr, st, nullptr, 0);
+    }
     if ((rc = enqueue_stage(p, j0, nj, 1, pz, step, h, X, X, p->d_Ua, st, nullptr, c0, c1, pz + 1))) return rc;
     if ((rc = enqueue_stage(p, j0, nj, 2, pz + 1, step, h, p->d_Ua, X, p->d_Ub, st, nullptr, c1))) return rc;
     if ((rc = enqueue_stage(p, j0, nj, 3, pz + 1, step, h, p->d_Ub, X, p->d_Ua, st, nullptr, c1, c0, pz + 2)))
@@ -510,7 +520,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
         if (smem > kMaxDynLds || !stage_rows_fit(m, rows)) continue;
         for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
             if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
-            if (launch == WPCCC_LAUNCH_PERSISTENT && p->mixed) continue;
+            if (launch == WPCCC_LAUNCH_PERSISTENT && (p->mixed || p->interp)) continue;
             if (launch == WPCCC_LAUNCH_PERSISTENT &&
                 (chunk_smem_bytes(m, rows) > kMaxDynLds || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
                 continue;
@@ -692,6 +702,15 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: the persistent stage kernel has no reduced-precision form");
         return WPCCC_ENOTSUP;
     }
+    if (o.radial != WPCCC_RADIAL_EXACT && o.radial != WPCCC_RADIAL_INTERP) {
+        set_error("wpccc_plan_create: radial must be WPCCC_RADIAL_EXACT or WPCCC_RADIAL_INTERP");
+        return WPCCC_EINVAL;
+    }
+    const bool interp = o.radial == WPCCC_RADIAL_INTERP;
+    if (interp && (mixed || o.stage_launch == WPCCC_LAUNCH_PERSISTENT)) {
+        set_error("wpccc_plan_create: the interpolated radial integrals are an FP64, one-launch-per-stage form");
+        return WPCCC_ENOTSUP;
+    }
     for (int j = 0; j < n_traj; ++j)
         if (!(b_host[j] > 0.0) || !(v_host[j] > 0.0) || !std::isfinite(b_host[j]) || !std::isfinite(v_host[j])) {
             set_error("wpccc_plan_create: path %d needs finite b > 0 and v > 0", j);
@@ -718,7 +737,9 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     const int N = hb.n_states;
     plan->n_pad = (N + 7) & ~7;
     plan->mixed = mixed;
-    TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp, mixed));
+    plan->interp = interp;
+    TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp,
+                     interp ? kRadialInterp : (mixed ? kRadialMoments32 : kRadialMoments)));
     plan->ckpt_every = o.checkpoint_every;
     plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
@@ -1164,8 +1185,8 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
         set_error("wpccc_adjoint: one-centre plans only");
         return WPCCC_ENOTSUP;
     }
-    if (plan->mixed) {
-        set_error("wpccc_adjoint: FP64 plans only (the operator kernel reads the FP64 moment table)");
+    if (plan->mixed || plan->interp) {
+        set_error("wpccc_adjoint: plans with the FP64 moment table only (the operator kernel reads it)");
         return WPCCC_ENOTSUP;
     }
     if (!plan->apply_ok) {
