@@ -701,7 +701,7 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
     W.wpccc_plan_timing(plan, True)
     W.wpccc_propagate(plan, zs, X)
     names = ["k_2c_contract", "k_2c_reduce", "k_2c_interp", "k_2c_nodes", "k_2c_assemble", "k_setup_batch",
-             "k_2c_direct", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve"]
+             "k_2c_direct", "k_lu_check", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve"]
     kt = {}
     for nm in names:
         ms, n = W.wpccc_plan_kernel_time(plan, nm)
@@ -739,7 +739,7 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
     for j in range(n_traj):
         N = 2 * sum((2 * l + 1) * n for l, n in enumerate(n_per_l(w.targets[w.set_of[j]])))
         lu_fl += (steps * 2 + 1) * 8.0 / 3.0 * N ** 3
-    lu_ms = sum(kt[k]["total_ms"] for k in ("k_lu_panel", "k_lu_swap_trsm", "k_lu_update"))
+    lu_ms = sum(kt[k]["total_ms"] for k in ("k_lu_check", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update"))
     out = {
         "metric": METRIC,
         "value": value,

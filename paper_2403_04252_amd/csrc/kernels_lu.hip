@@ -27,6 +27,13 @@ __device__ inline void job_of(const Jobs& J, int y, int& pl, int& slot) {
     slot = J.slot[y % J.n_sub];
 }
 
+// Whether a launch's kernel has nothing to do for this matrix (LUStepArgs::skip_mode).
+__device__ inline bool skipped(const LUStepArgs& a, size_t ms) {
+    if (a.skip_mode == 0) return false;
+    const bool s = a.skip[ms] != 0;
+    return a.skip_mode == 1 ? s : !s;
+}
+
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -40,6 +47,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(LUStepArgs a) {
     job_of(a.jobs, blockIdx.x, pl, slot);
     const int N = a.N, k0 = a.k0, nb = a.nb;
     const size_t ms = (size_t)pl * kSlots2C + slot;
+    if (skipped(a, ms)) return;
     double2* A = a.LU + ms * (size_t)N * N;
     int* piv = a.piv + ms * N;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -163,6 +171,7 @@ __global__ __launch_bounds__(256) void k_lu_swap_trsm(LUStepArgs a) {
     job_of(a.jobs, blockIdx.y, pl, slot);
     const int N = a.N, k0 = a.k0, nb = a.nb;
     const size_t ms = (size_t)pl * kSlots2C + slot;
+    if (skipped(a, ms)) return;
     double2* A = a.LU + ms * (size_t)N * N;
     const int* piv = a.piv + ms * N;
     const int t = threadIdx.x;
@@ -228,23 +237,9 @@ __global__ __launch_bounds__(256) void k_lu_update(LUStepArgs a) {
     const int bi = blockIdx.x % T, bj = blockIdx.x / T;
     const int r0 = k1 + 64 * bi, c0 = k1 + 64 * bj;
     const size_t ms = (size_t)pl * kSlots2C + slot;
+    if (skipped(a, ms)) return;
     double2* A = a.LU + ms * (size_t)N * N;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < 64 * NB; e += blockDim.x) {
-        const int ii = e % 64, k = e / 64;
-        const int row = r0 + ii;
-        const double2 x = (row < N && k < nb) ? A[row + (size_t)(k0 + k) * N] : make_double2(0.0, 0.0);
-        Lr[k][ii] = x.x;
-        Li[k][ii] = x.y;
-    }
-    for (int e = t; e < 64 * NB; e += blockDim.x) {
-        const int k = e % NB, jj = e / NB;
-        const int col = c0 + jj;
-        const double2 x = (col < N && k < nb) ? A[(k0 + k) + (size_t)col * N] : make_double2(0.0, 0.0);
-        Ur[k][jj] = x.x;
-        Ui[k][jj] = x.y;
-    }
-    __syncthreads();
     const int jsub = (wave >> 1) * 32, isub = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
     dbl4 re[2][2], im[2][2];
@@ -255,6 +250,24 @@ __global__ __launch_bounds__(256) void k_lu_update(LUStepArgs a) {
             re[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
             im[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
+    // the k range k0 .. k0 + nb - 1 in chunks of NB (one chunk for a panel)
+    for (int kc = 0; kc < nb; kc += NB) {
+    if (kc) __syncthreads();
+    for (int e = t; e < 64 * NB; e += blockDim.x) {
+        const int ii = e % 64, k = e / 64;
+        const int row = r0 + ii;
+        const double2 x = (row < N && kc + k < nb) ? A[row + (size_t)(k0 + kc + k) * N] : make_double2(0.0, 0.0);
+        Lr[k][ii] = x.x;
+        Li[k][ii] = x.y;
+    }
+    for (int e = t; e < 64 * NB; e += blockDim.x) {
+        const int k = e % NB, jj = e / NB;
+        const int col = c0 + jj;
+        const double2 x = (col < N && kc + k < nb) ? A[(k0 + kc + k) + (size_t)col * N] : make_double2(0.0, 0.0);
+        Ur[k][jj] = x.x;
+        Ui[k][jj] = x.y;
+    }
+    __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < NB / 4; ++ks) {
         const int kr = ks * 4 + lk;
@@ -270,6 +283,7 @@ __global__ __launch_bounds__(256) void k_lu_update(LUStepArgs a) {
                 im[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ui, lr, im[x][y], 0, 0, 0);
             }
         }
+    }
     }
     // D'[row][col] of a 16 x 16 tile: lane l, register r -> row 4 r + l / 16, col l % 16
 #pragma unroll
@@ -290,7 +304,44 @@ __global__ __launch_bounds__(256) void k_lu_update(LUStepArgs a) {
             }
 }
 
+// One workgroup per matrix: skip = (every |A[i][j]| <= 1 for rows i >= nt,
+// columns j < nt, i.e. |K^dagger| <= 1); where set, the identity permutation
+// and the diagonal pivots of the first nt columns are written here (the panel
+// steps that would write them return at once).
+__global__ __launch_bounds__(256) void k_lu_check(LUStepArgs a) {
+    __shared__ int bad;
+    int pl, slot;
+    job_of(a.jobs, blockIdx.x, pl, slot);
+    const int N = a.N, nt = a.nt;
+    const size_t ms = (size_t)pl * kSlots2C + slot;
+    const double2* A = a.LU + ms * (size_t)N * N;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    int b = 0;
+    for (int j = 0; j < nt && !b; ++j)
+        for (int i = nt + t; i < N; i += blockDim.x) {
+            const double2 x = A[i + (size_t)j * N];
+            if (!(x.x * x.x + x.y * x.y <= 1.0)) b = 1;
+        }
+    if (b) atomicOr(&bad, 1);
+    __syncthreads();
+    const int ok = bad ? 0 : 1;
+    if (t == 0) a.skip[ms] = ok;
+    if (ok) {
+        int* perm = a.perm + ms * N;
+        int* piv = a.piv + ms * N;
+        for (int i = t; i < N; i += blockDim.x) perm[i] = i;
+        for (int j = t; j < nt; j += blockDim.x) piv[j] = j;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_lu_check, dim3(n_jobs), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_lu_panel(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     WPCCC_LAUNCH(ev, k_lu_panel, dim3(n_jobs), dim3(kPanelThreads), 0, st, a);

@@ -1360,7 +1360,7 @@ const char* const kKernelNames[kNumKernels] = {
     "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
     "k_2c_nodes",     "k_2c_interp",   "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
     "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish",  "k_chunk",
-    "k_2c_reduce",    "k_fpoint",      "k_channels"};
+    "k_2c_reduce",    "k_fpoint",      "k_channels",    "k_lu_check"};
 
 LaunchEv KernelTimer::open(int kernel) {
     LaunchEv ev;

@@ -172,14 +172,26 @@ struct DirectArgs {         // D_T and D_P blocks of H from the per-job Frow / G
 constexpr int kLUPanel = 16;
 constexpr int kLUMaxN = 1024;       // two rows per thread in the 512-thread panel kernel
 
+// Overlap matrices S = [[I, K], [K^dagger, I]]: while every |K_ij| <= 1,
+// partial pivoting keeps the diagonal 1 as the pivot of each of the first
+// N_T columns (ties go to the lowest row), so those columns factor with
+// L21 = K^dagger, U12 = K, L11 = U11 = I, and the rest is the LU of the
+// Schur complement I - K^dagger K.  k_lu_check decides this per matrix
+// (skip = 1) on the device; the Schur update then is one GEMM (k_lu_update
+// with nb = N_T) and the panel steps of the first N_T columns return at once,
+// while a matrix that fails the test takes those panel steps instead: the
+// pivots are those of the general algorithm either way.
 struct LUStepArgs {
-    int N, k0, nb;          // panel columns k0 .. k0 + nb - 1
+    int N, k0, nb;          // panel columns k0 .. k0 + nb - 1 (k_lu_update: any nb)
     Jobs jobs;
     double2* LU;            // [path][slot][N*N] column-major, factorised in place
     int* piv;               // [path][slot][N] LAPACK-style pivot rows (0-based)
     int* perm;              // [path][slot][N]
     const int* paths;
     int* flag;              // [1] first singular path + 1, [2] its pivot column
+    int* skip;              // [path][slot] 1: the first nt columns factor without pivoting (k_lu_check)
+    int nt;                 // N_T (k_lu_check)
+    int skip_mode;          // 0: run; 1: return where skip is set; 2: return where it is not
 };
 
 struct Stage2CArgs {
@@ -210,6 +222,9 @@ hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, h
 hipError_t launch_lu_panel(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_lu_swap_trsm(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_lu_update(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+// skip[matrix] = (max |L21| <= 1 over the first nt columns); where set, also
+// perm = identity and piv[j] = j for j < nt
+hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,

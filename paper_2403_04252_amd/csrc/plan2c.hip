@@ -138,6 +138,7 @@ struct Group2C {
     double2 *d_S = nullptr, *d_LU = nullptr, *d_H = nullptr;  // [path][slot][N*N]
     int* d_piv = nullptr;                                      // [path][slot][N]
     int* d_perm = nullptr;                                     // [path][slot][N]
+    int* d_skip = nullptr;                                     // [path][slot] no-pivot block form (k_lu_check)
     int max_jobs = 0;
     double* d_nodes = nullptr;
     int* d_jst = nullptr;
@@ -182,7 +183,7 @@ void free_group(Group2C& g) {
     centre_free(g.cT);
     centre_free(g.cP);
     void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
-                    g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_nodes,  g.d_jst,    g.d_nact,
+                    g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_skip,   g.d_nodes,  g.d_jst,    g.d_nact,
                     g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP,
                     g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT};
     for (void* q : bufs)
@@ -324,6 +325,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_H, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_piv, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_perm, np * kSlots2C * m.N, tot))) return rc;
+    if ((rc = dev_alloc(&g.d_skip, np * kSlots2C, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nodes, J * m.n_fields * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_jst, J * 2 * m.n_nodes, tot))) return rc;
     if ((rc = dev_alloc(&g.d_nact, J, tot))) return rc;
@@ -457,7 +459,9 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.H = g.d_H;
         if ((rc = timed(p, k2cAssemble, [&](const LaunchEv& ev) { return launch_2c_assemble(a, g.m, nj, st, ev); }))) return rc;
     }
-    LUStepArgs a;
+    // LU of S with partial pivoting: the first N_T columns by the no-pivot
+    // block form where k_lu_check allows it (see LUStepArgs), else by panels
+    LUStepArgs a{};
     a.N = g.m.N;
     a.jobs = J;
     a.LU = g.d_LU;
@@ -465,14 +469,28 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
     a.perm = g.d_perm;
     a.paths = g.d_paths;
     a.flag = p->d_flag;
-    for (int k0 = 0; k0 < a.N; k0 += kLUPanel) {
-        a.k0 = k0;
-        a.nb = std::min(kLUPanel, a.N - k0);
-        if ((rc = timed(p, kLuPanel, [&](const LaunchEv& ev) { return launch_lu_panel(a, nj, st, ev); }))) return rc;
-        if ((rc = timed(p, kLuSwap, [&](const LaunchEv& ev) { return launch_lu_swap_trsm(a, nj, st, ev); }))) return rc;
-        if ((rc = timed(p, kLuUpdate, [&](const LaunchEv& ev) { return launch_lu_update(a, nj, st, ev); }))) return rc;
-    }
-    return WPCCC_OK;
+    a.skip = g.d_skip;
+    a.nt = g.m.NT;
+    if ((rc = timed(p, kLuCheck, [&](const LaunchEv& ev) { return launch_lu_check(a, nj, st, ev); }))) return rc;
+    a.k0 = 0;
+    a.nb = g.m.NT;
+    a.skip_mode = 2;
+    if ((rc = timed(p, kLuUpdate, [&](const LaunchEv& ev) { return launch_lu_update(a, nj, st, ev); }))) return rc;
+    auto panels = [&](int from, int to) -> int {
+        for (int k0 = from; k0 < to; k0 += kLUPanel) {
+            a.k0 = k0;
+            a.nb = std::min(kLUPanel, to - k0);
+            int r;
+            if ((r = timed(p, kLuPanel, [&](const LaunchEv& ev) { return launch_lu_panel(a, nj, st, ev); }))) return r;
+            if ((r = timed(p, kLuSwap, [&](const LaunchEv& ev) { return launch_lu_swap_trsm(a, nj, st, ev); }))) return r;
+            if ((r = timed(p, kLuUpdate, [&](const LaunchEv& ev) { return launch_lu_update(a, nj, st, ev); }))) return r;
+        }
+        return WPCCC_OK;
+    };
+    a.skip_mode = 1;
+    if ((rc = panels(0, g.m.NT))) return rc;
+    a.skip_mode = 0;
+    return panels(g.m.NT, g.m.N);
 }
 
 int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,

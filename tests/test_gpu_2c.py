@@ -287,3 +287,39 @@ def test_2c_nonfinite_amplitude_latched(small_run):
     assert e.value.code == -5
     W.wpccc_plan_status(plan)
     assert torch.isfinite(X[0]).all() and torch.isfinite(X[1]).all()
+
+
+def test_2c_lu_block_form_and_pivoting_fallback():
+    """The LU of S takes the no-pivot block form for its first N_T columns only
+    where every |K_ij| <= 1 (then partial pivoting would keep the diagonal
+    pivots); with identical coarse-grid bases at b = 0.01 the interpolated
+    overlaps exceed 1 (max |K| about 1.002 on a 40-interval grid), so the
+    general panels run, pivoting into the lower rows.  One RK4 step from a
+    seeded random state at z = 0 (h/v = 0.1) matches the oracle (LAPACK's
+    ZGESV for S^{-1} H) in both regimes: the well-separated case b = 1.5 takes the block
+    form.  Tolerance 1e-11 on amplitudes of size ~0.5, or 20 cond(S) eps
+    max|X| where S is ill-conditioned (nearly coincident identical bases)."""
+    rec = WL.Recipe(2, 1, 1, 1.5, 40, 20.0)
+    lb, ob = lib_basis(rec), oracle_basis(rec)
+    for b, v, h in ((0.01, 1e-3, 1e-4), (1.5, 1.0, 0.1)):
+        S, _ = two_centre_matrices(ob, ob, b, 0.0, v, 24, 32, Q_PRIOR)
+        NT = ob.n_states
+        kmax = np.abs(S[:NT, NT:]).max()
+        print(f"b={b}: max|K| {kmax:.3f}", flush=True)
+        assert (kmax > 1.0) == (b < 0.1)
+        plan = W.wpccc_plan_create_2c([lb], [lb], [0], [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=32)
+        N = plan.n_states
+        X0 = WL.random_state(1, N, seed=21)[0]
+        X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[0, :N] = torch.from_numpy(X0).cuda()
+        W.wpccc_step(plan, X, 0.0, h)
+        torch.cuda.synchronize()
+        W.wpccc_plan_status(plan)
+        Xo = rk4_propagate(m_two_centre(ob, ob, b, v, 24, 32, Q_PRIOR), X0, np.array([0.0, h]))
+        err = np.abs(X.cpu().numpy()[0, :N] - Xo).max()
+        cond = np.linalg.cond(S)
+        # a backward-stable solve moves the solution by ~ cond(S) eps relative
+        bar = max(1e-11, 20.0 * cond * np.finfo(float).eps * np.abs(Xo).max())
+        print(f"  one step (h/v = {h / v:g}): max|dX| {err:.2e}, max|X| {np.abs(Xo).max():.2f}, "
+              f"cond(S) {cond:.1e}, bar {bar:.1e}", flush=True)
+        assert err <= bar
