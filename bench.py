@@ -228,12 +228,16 @@ def main():
     torch.cuda.synchronize()
 
     stage_flops = stage_work(n_l, rec.l_max) * n_traj
-    # algorithmic bytes of one stage pass over the batch: every path reads its
-    # rows of the moment table (one (A_k, B_k+1) pair of 16 B per
-    # radial-integral entry) and five amplitude vectors (u_in, X, Xacc in and
-    # out, u_out)
+    # algorithmic bytes of one stage pass over the batch, the average of the
+    # four stages of a step: stages 1 and 3 read the moment-table rows of the
+    # step's next new point (one (A_k, B_k+1) pair of 16 B per radial-integral
+    # entry), read the cached F of their own point (8 B) and write the new
+    # point's F (8 B); stages 2 and 4 read the cached F (8 B): 20 B per entry;
+    # plus five amplitude vectors (u_in, X, Xacc in and out, u_out)
     n_entries = n_frow_entries(n_l, rec.l_max)
-    stage_bytes = n_traj * (n_entries * 16 + 5 * n_states * 16)
+    stage_bytes = n_traj * (n_entries * 20 + 5 * n_states * 16)
+    # the method's minimum per step: the table rows at the two new points
+    step_min_bytes = n_traj * (2 * n_entries * 16 + 4 * 5 * n_states * 16)
     passes = 4 * args.steps   # stage passes in the timed run
     if persistent:
         # k_chunk runs the four stages of up to 64 steps per launch
@@ -253,7 +257,9 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "flops_per_stage_pass": stage_flops,
             "fp64_alu_frac": stage_flops / stage_pass_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
-            "stage_rows": W.wpccc_plan_stage_rows(plan)}
+            "stage_rows": W.wpccc_plan_stage_rows(plan),
+            "method_min_bytes_per_step": step_min_bytes,
+            "method_min_frac": step_min_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS}
     if persistent:
         t = profiled_traffic("k_chunk_1c_N580x32.md", "kernels_1c.hip", "traffic_bytes_per_stage_pass")
         roof["traffic"] = None if t is None else t * passes / max(k_n, 1)
