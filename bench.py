@@ -123,11 +123,12 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed RK4 steps, each over all paths (default 800; 20 for c3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 40; 2 for c3)")
-    ap.add_argument("--workload", choices=["c2", "c3", "sweep", "paper"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "sweep", "sweep2c", "paper"], default="c2",
                     help="c2: batched one-centre N=580 (the headline); c3: batched two-centre; "
                          "sweep: one-centre throughput against basis size (paper shape N_l = 42 - l); "
                          "paper: the paper's trajectory (v = 2, z -300..300 on 6001 points, 8 paths) "
-                         "with exact-R and interpolated radial integrals")
+                         "with exact-R and interpolated radial integrals; sweep2c: two-centre throughput "
+                         "against basis size (paper shape N_l = 30 - l per centre, N = 60..1910)")
     ap.add_argument("--lmax", type=int, default=6, help="paper: l_max of the paper-shape basis (<= 7)")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
@@ -158,6 +159,10 @@ def main():
         args.steps = 20 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         return bench_two_centre(args)
+    if args.workload == "sweep2c":
+        args.steps = 10 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        return bench_sweep_2c(args)
     if args.workload == "paper":
         args.warmup = 20 if args.warmup is None else args.warmup
         return bench_paper(args)
@@ -500,6 +505,59 @@ def bench_sweep(args):
                       "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..8, "
                                              "2000-pt grid, 8 b log-spaced 0.2-10, v=2, dz=0.1",
+                                 "parallelism": "1 GPU, paths batched"},
+                      "sweep": rows}), flush=True)
+
+
+def bench_sweep_2c(args):
+    """Two-centre batched throughput against basis size with the paper's
+    two-centre basis shape, N_l = 30 - l radial functions per l on each centre
+    (bound n <= 6 plus 24 Coulomb bins per l), l_max = 0..5 (N = 60..1910),
+    4000-point grids, 256 x 512 spheroidal nodes, prior lower-left block;
+    8 paths (b log-spaced 0.2..10) at v = 2, `steps` steps of 0.1 from
+    z = -0.5 (through closest approach, where the most nodes are active).
+    Prints one JSON line with one entry per l_max."""
+    import torch
+    import paper_2403_04252_amd as W
+    from paper_2403_04252_amd import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    b = 0.2 * 50.0 ** (np.arange(8) / 7.0)
+    v = np.full(8, 2.0)
+    zs = -0.5 + 0.1 * np.arange(args.steps + 1)
+    rows = []
+    for l_max in range(6):
+        rec = WL.Recipe(6, l_max, 24, 3.0, 4000)
+        lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
+        t0 = time.perf_counter()
+        plan = W.wpccc_plan_create_2c([lb], [lb], np.zeros(8, dtype=np.int32), b, v, q_lower=W.WPCCC_Q_PRIOR,
+                                      n_eta=256, n_tau=512)
+        setup = time.perf_counter() - t0
+        N = plan.n_states
+        print(f"sweep2c l_max {l_max}: N = {N}", file=sys.stderr, flush=True)
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        W.wpccc_propagate(plan, zs[: args.warmup + 1], X)
+        X.zero_()
+        X[:, 0] = 1.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W.wpccc_propagate(plan, zs, X)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        W.wpccc_plan_status(plan)
+        rows.append({"l_max": l_max, "n_states": N, "value": plan.n_traj * args.steps / wall,
+                     "unit": "trajectory-steps/s", "ms_per_batched_step": wall / args.steps * 1e3,
+                     "plan_setup_s": setup, "device_bytes": plan.device_bytes})
+        del plan, X
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "two-centre RK4 steps/s over batched b against basis size", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": "p+H 2C paper shape N_l = 30 - l per centre (n <= 6 + 24 bins/l), "
+                                             "l_max 0..5, 4000-pt grids, 256x512 nodes, prior lower block, "
+                                             "8 b log-spaced 0.2-10, v = 2, z -0.5..0.5",
                                  "parallelism": "1 GPU, paths batched"},
                       "sweep": rows}), flush=True)
 

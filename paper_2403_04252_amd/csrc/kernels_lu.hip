@@ -18,7 +18,6 @@ namespace wpccc {
 namespace {
 
 constexpr int kPanelThreads = 512;
-constexpr int kPanelRows = kLUMaxN / kPanelThreads;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -38,8 +37,11 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// ROWS rows per thread (N <= ROWS x 512), panels of up to NB columns: the
+// panel's N - k0 rows live in registers (ROWS x NB complex values per thread).
+template <int ROWS, int NB>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(LUStepArgs a) {
-    constexpr int NB = kLUPanel;
+    constexpr int kPanelRows = ROWS;
     __shared__ double2 prow[NB], xrow[NB];
     __shared__ double redv[kPanelThreads / 64];
     __shared__ int redi[kPanelThreads / 64];
@@ -343,8 +345,14 @@ hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, cons
     return hipGetLastError();
 }
 
+int lu_panel_width(int N) { return N <= 2 * kPanelThreads ? kLUPanel : kLUPanel / 2; }
+
 hipError_t launch_lu_panel(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_lu_panel, dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    if (a.N > kLUMaxN || a.nb > lu_panel_width(a.N)) return hipErrorInvalidValue;
+    if (a.N <= 2 * kPanelThreads)
+        WPCCC_LAUNCH(ev, (k_lu_panel<2, kLUPanel>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    else
+        WPCCC_LAUNCH(ev, (k_lu_panel<4, kLUPanel / 2>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -170,7 +170,10 @@ struct DirectArgs {         // D_T and D_P blocks of H from the per-job Frow / G
 // U12 block row, k_lu_update subtracts L21 U12 from the trailing matrix on
 // MFMA.  perm accumulates the swaps as a row gather (y_perm[i] = y[perm[i]]).
 constexpr int kLUPanel = 16;
-constexpr int kLUMaxN = 1024;       // two rows per thread in the 512-thread panel kernel
+constexpr int kLUMaxN = 2048;       // up to four rows per thread in the 512-thread panel kernel
+// panel width of the factorisation of an N x N matrix: kLUPanel up to 1024
+// rows (two rows per thread), half of it up to kLUMaxN (four rows per thread)
+int lu_panel_width(int N);
 
 // Overlap matrices S = [[I, K], [K^dagger, I]]: while every |K_ij| <= 1,
 // partial pivoting keeps the diagonal 1 as the pivot of each of the first

@@ -476,10 +476,11 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
     a.nb = g.m.NT;
     a.skip_mode = 2;
     if ((rc = timed(p, kLuUpdate, [&](const LaunchEv& ev) { return launch_lu_update(a, nj, st, ev); }))) return rc;
+    const int pw = lu_panel_width(g.m.N);
     auto panels = [&](int from, int to) -> int {
-        for (int k0 = from; k0 < to; k0 += kLUPanel) {
+        for (int k0 = from; k0 < to; k0 += pw) {
             a.k0 = k0;
-            a.nb = std::min(kLUPanel, to - k0);
+            a.nb = std::min(pw, to - k0);
             int r;
             if ((r = timed(p, kLuPanel, [&](const LaunchEv& ev) { return launch_lu_panel(a, nj, st, ev); }))) return r;
             if ((r = timed(p, kLuSwap, [&](const LaunchEv& ev) { return launch_lu_swap_trsm(a, nj, st, ev); }))) return r;

@@ -323,3 +323,31 @@ def test_2c_lu_block_form_and_pivoting_fallback():
         print(f"  one step (h/v = {h / v:g}): max|dX| {err:.2e}, max|X| {np.abs(Xo).max():.2f}, "
               f"cond(S) {cond:.1e}, bar {bar:.1e}", flush=True)
         assert err <= bar
+
+
+@pytest.mark.parametrize("l_max,N", [(4, 1360), (5, 1910)])
+def test_2c_paper_shape_step(l_max, N):
+    """The paper's two-centre basis shape, N_l = 30 - l radial functions per l
+    on each centre (bound n <= 6 plus 24 bins per l), at l_max = 4 and 5
+    (N = 1360 and 1910, the largest two-centre systems of the paper's
+    scaling runs; beyond 1024 states the LU panels are 8 columns wide with
+    four rows per thread): one RK4 step from a seeded random state against
+    the oracle's full Eq. 1 blocks and ZGESV, on a 300-point grid and
+    16 x 24 spheroidal nodes.  |dX| <= 1e-10 (S is well conditioned at b = 3)."""
+    rec = WL.Recipe(6, l_max, 24, 3.0, 300, 60.0)
+    lb, ob = lib_basis(rec), oracle_basis(rec)
+    b, v, z, h = 3.0, 1.0, -0.4, 0.1
+    plan = W.wpccc_plan_create_2c([lb], [lb], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=16, n_tau=24)
+    n, nt = W.wpccc_plan_path_info(plan, 0)
+    print(f"2C paper shape l_max = {l_max}: N = {n}", flush=True)
+    assert n == N and nt == N // 2
+    x0 = WL.random_state(1, N, seed=31)[0]
+    X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[0, :N] = torch.as_tensor(x0, device="cuda")
+    W.wpccc_step(plan, X, z, h)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    xo = rk4_propagate(m_two_centre(ob, ob, b, v, 16, 24, Q_PRIOR), x0, np.array([z, z + h]))
+    err = np.abs(X.cpu().numpy()[0, :N] - xo).max()
+    print(f"  max |dX| {err:.2e}", flush=True)
+    assert err <= 1e-10
