@@ -143,6 +143,8 @@ def main():
                     help="c2: rows per workgroup of the RK4 stage kernels (0: chosen by timing at plan creation)")
     ap.add_argument("--stage-launch", choices=["auto", "stages", "persistent"], default="auto",
                     help="c2: kernel per stage, persistent chunk kernel, or the faster (timed at plan creation)")
+    ap.add_argument("--stage-cache", choices=["auto", "on", "off"], default="auto",
+                    help="c2: stage kernels with the radial-integral cache, without, or timed at plan creation")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-path-per-launch comparison (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -186,7 +188,8 @@ def main():
     n_l = [rec.n_max - l + rec.n_bins for l in range(rec.l_max + 1)]
     launch = {"auto": W.WPCCC_LAUNCH_AUTO, "stages": W.WPCCC_LAUNCH_STAGES,
               "persistent": W.WPCCC_LAUNCH_PERSISTENT}[args.stage_launch]
-    plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=args.stage_rows, stage_launch=launch)
+    cache = {"auto": W.WPCCC_CACHE_AUTO, "on": W.WPCCC_CACHE_ON, "off": W.WPCCC_CACHE_OFF}[args.stage_cache]
+    plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=args.stage_rows, stage_launch=launch, stage_cache=cache)
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0
@@ -240,7 +243,9 @@ def main():
     # point's F (8 B); stages 2 and 4 read the cached F (8 B): 20 B per entry;
     # plus five amplitude vectors (u_in, X, Xacc in and out, u_out)
     n_entries = n_frow_entries(n_l, rec.l_max)
-    stage_bytes = n_traj * (n_entries * 20 + 5 * n_states * 16)
+    cached = W.wpccc_plan_stage_cache(plan)
+    # without the cache every stage reads its point's table rows (16 B per entry)
+    stage_bytes = n_traj * (n_entries * (20 if cached else 16) + 5 * n_states * 16)
     # the method's minimum per step: the table rows at the two new points
     step_min_bytes = n_traj * (2 * n_entries * 16 + 4 * 5 * n_states * 16)
     passes = 4 * args.steps   # stage passes in the timed run
@@ -255,7 +260,9 @@ def main():
     stage_pass_s = k_ms * 1e-3 / passes
     roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if persistent else profiled_traffic("k_stage_1c_N580x32.md", "kernels_1c.hip"),
+            "traffic": None if persistent else profiled_traffic(
+                "k_stage_1c_N580x32.md" if cached else "k_stage_direct_1c_N580x32.md", "kernels_1c.hip"),
+            "radial_cache": cached,
             "avg_launch_us": launch_s * 1e6, "launches": k_n,
             "stage_passes_per_launch": passes / max(k_n, 1),
             "algorithmic_bytes_per_stage_pass": stage_bytes,
@@ -456,7 +463,7 @@ def seeded_measure(torch, W, WL, repeats=3):
 def bench_sweep(args):
     """One-centre batched throughput against basis size with the paper's basis
     shape, N_l = 42 - l radial functions per l (bound n <= 10 plus 32 Coulomb
-    wave-packet bins per l), l_max = 0..8, on a 2000-point grid; 8 paths with b
+    wave-packet bins per l), l_max = 0..10, on a 2000-point grid; 8 paths with b
     log-spaced 0.2..10, v = 2, dz = 0.1 from z = -40.  Prints one JSON line with
     one entry per l_max (sizes the stage kernel's LDS cannot hold are listed as
     unsupported)."""
@@ -470,7 +477,7 @@ def bench_sweep(args):
     v = np.full(8, 2.0)
     zg = WL.z_uniform(-40.0, -40.0 + 0.1 * (args.warmup + args.steps), 0.1)
     rows = []
-    for l_max in range(9):
+    for l_max in range(11):
         rec = WL.Recipe(10, l_max, 32, 3.0, 2000)
         lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
         n_states = W.wpccc_basis_info(lb)[0]
@@ -503,7 +510,7 @@ def bench_sweep(args):
     print(json.dumps({"metric": "RK4 steps/s over batched b against basis size", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
                       "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..8, "
+                      "config": {"workload": "p+H 1C, N_l = 42 - l (n <= 10 + 32 bins/l), l_max 0..10, "
                                              "2000-pt grid, 8 b log-spaced 0.2-10, v=2, dz=0.1",
                                  "parallelism": "1 GPU, paths batched"},
                       "sweep": rows}), flush=True)

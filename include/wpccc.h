@@ -171,7 +171,15 @@ typedef struct {
                        F(r_max) (r_max / R)^(lam+1) beyond the grid.  FP64, one
                        launch per stage (WPCCC_ENOTSUP with WPCCC_MIXED or
                        WPCCC_LAUNCH_PERSISTENT), no adjoint. */
+    int stage_cache; /* 1C: WPCCC_CACHE_AUTO (default: timed at plan creation
+                       where both forms apply), WPCCC_CACHE_ON or WPCCC_CACHE_OFF
+                       (see wpccc_plan_stage_cache; WPCCC_ENOTSUP where the
+                       form needs the cache) */
 } wpccc_plan_opts;
+
+#define WPCCC_CACHE_AUTO 0
+#define WPCCC_CACHE_ON   1
+#define WPCCC_CACHE_OFF  2
 
 #define WPCCC_RADIAL_EXACT  0
 #define WPCCC_RADIAL_INTERP 1
@@ -223,6 +231,14 @@ int wpccc_plan_destroy(wpccc_plan_t plan);
 /* Rows per workgroup of a one-centre plan's RK4 stage kernel (stage_rows as
  * given, or as chosen by timing at plan creation). */
 int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows);
+
+/* Whether a one-centre plan's stage kernels take the radial integrals F from
+ * a cache filled at the two new points of each step (1) or form them from the
+ * moment table in every stage (0); chosen by timing at plan creation for the
+ * FP64 exact-R form, always 1 for the WPCCC_MIXED and WPCCC_RADIAL_INTERP
+ * forms and for bases whose angular factors do not fit the LDS; 0 for a
+ * two-centre plan.  Both give bitwise the same amplitudes. */
+int wpccc_plan_stage_cache(wpccc_plan_t plan, int* cached);
 
 /* Launch form a one-centre plan's wpccc_propagate uses for its RK4 stages
  * (WPCCC_LAUNCH_STAGES or WPCCC_LAUNCH_PERSISTENT, as requested or as chosen

@@ -20,7 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_couplings_noalloc", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
-    "wpccc_plan_stage_launch", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
+    "wpccc_plan_stage_launch", "wpccc_plan_stage_cache", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,9 @@ WPCCC_MIXED = 1
 WPCCC_LAUNCH_AUTO = 0
 WPCCC_LAUNCH_STAGES = 1
 WPCCC_LAUNCH_PERSISTENT = 2
+WPCCC_CACHE_AUTO = 0
+WPCCC_CACHE_ON = 1
+WPCCC_CACHE_OFF = 2
 WPCCC_N_CHANNELS = 6
 CHANNELS = ("elastic", "excitation", "target_continuum", "capture", "projectile_continuum", "total")
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
@@ -58,7 +61,7 @@ class _PlanOpts(ctypes.Structure):
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
                 ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int),
-                ("radial", ctypes.c_int)]
+                ("radial", ctypes.c_int), ("stage_cache", ctypes.c_int)]
 
 
 @dataclass
@@ -109,6 +112,7 @@ def load_library():
         "wpccc_adjoint": ([vp, pd, i, vp, vp, vp, vp, vp], i),
         "wpccc_plan_stage_rows": ([vp, pi], i),
         "wpccc_plan_stage_launch": ([vp, pi], i),
+        "wpccc_plan_stage_cache": ([vp, pi], i),
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
         "wpccc_measure_mfma": ([pd, pd, vp], i),
@@ -219,7 +223,7 @@ def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
                       two_centre: bool = False, model_a: float = 0.0, model_c: float = 0.0,
                       checkpoint_every: int = 0, stage_rows: int = 0, graph: bool = False,
                       stage_launch: int = WPCCC_LAUNCH_AUTO, mixed: bool = False, interp: bool = False,
-                      stream=None) -> Plan:
+                      stage_cache: int = 0, stream=None) -> Plan:
     """Plan for len(b) straight-line paths in one basis; b, v in a.u.  model_a,
     model_c: screened target potential -(1 + a e^{-c r})/r on the fixed basis;
     stage_launch: WPCCC_LAUNCH_AUTO / _STAGES / _PERSISTENT; mixed: the scaled
@@ -231,7 +235,7 @@ def wpccc_plan_create(basis: Basis, b, v, Zp: float = 1.0, batched: bool = True,
     opts = _PlanOpts(float(Zp), 1 if batched else 0, 1 if two_centre else 0, 0, 0, 0,
                      float(model_a), float(model_c), int(checkpoint_every), int(stage_rows),
                      WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, int(stage_launch),
-                     1 if interp else 0)
+                     1 if interp else 0, int(stage_cache))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create(basis.handle, int(b.size), dp(b), dp(v), ctypes.byref(opts),
@@ -255,6 +259,13 @@ def wpccc_plan_stage_launch(plan: Plan) -> int:
     r = ctypes.c_int()
     _check(load_library().wpccc_plan_stage_launch(plan.handle, ctypes.byref(r)))
     return r.value
+
+
+def wpccc_plan_stage_cache(plan: Plan) -> bool:
+    """True when the plan's stage kernels read F from the radial-integral cache."""
+    r = ctypes.c_int()
+    _check(load_library().wpccc_plan_stage_cache(plan.handle, ctypes.byref(r)))
+    return bool(r.value)
 
 
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,

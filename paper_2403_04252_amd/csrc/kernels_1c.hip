@@ -390,6 +390,33 @@ __device__ inline double2 stage_phase3(const double* Gs, const double2* Ws, int 
     return make_double2(re, im);
 }
 
+// phase 3 of the large-basis form: as stage_phase3, with the angular factor
+// G_l'[q'][g] = c(g) Pbar[p(g)] formed from the coefficient tables (global
+// memory, shared by every path and point: L2 hits) instead of staged in LDS.
+__device__ inline double2 stage_phase3_global(const double* gc, const int* gp, const double* pbs, const double2* Ws,
+                                              int o, int s, int S, int n_out, int nmp, int gcols) {
+    double re = 0.0, im = 0.0;
+    if (o < n_out) {
+        const int r = o / nmp, qp = o - r * nmp;
+        const double* c = gc + qp * gcols;
+        const int* pp = gp + qp * gcols;
+        const double2* w = Ws + r * gcols;
+        for (int k = s; k < gcols; k += S) {
+            const int p = pp[k];
+            if (p >= 0) {
+                const double g = c[k] * pbs[p];
+                re += g * w[k].x;
+                im += g * w[k].y;
+            }
+        }
+    }
+    for (int off = S >> 1; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+    }
+    return make_double2(re, im);
+}
+
 // Lanes per output of phase 3: the largest power of two S <= 64 with
 // 2 n_out S <= B (so that every output keeps at least half the lanes busy).
 // Every output has a lane group when n_out <= B (phase3_fits).
@@ -416,8 +443,10 @@ __host__ __device__ inline bool phase3_fits(int rows, int nmp_max) { return rows
 //   phase 4 (FC with a.fc_next): F of the rows at point a.p_next from the
 //            moment-table entries loaded in phase 0 -> a.fc_next.
 // F32: the moment table is the scaled FP32 form.  FC: F at the stage's point
-// comes from the radial-integral cache a.fc_cur (KIND 0 only).
-template <int KIND, int ROWS, bool F32 = false, bool FC = false>
+// comes from the radial-integral cache a.fc_cur (KIND 0 only).  GG (large
+// bases, FC only): G_l' is not staged in LDS; phase 3 forms it from the
+// coefficient tables.
+template <int KIND, int ROWS, bool F32 = false, bool FC = false, bool GG = false>
 __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* smem) {
     // moment-table entries: FP64 (A_k, B_(k+1)) or the scaled FP32 form
     using TabT = typename std::conditional<F32, float2, double2>::type;
@@ -437,8 +466,8 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
     double2* Ws = xs + m.n_xs;                                             // [rows][gcols]
     double2* phs = Ws + ROWS * gcols;                                      // [n_f]
     double* Fs = reinterpret_cast<double*>(phs + m.n_f);                  // [rows][nV]
-    double* Gs = Fs + ROWS * nV;                                           // [nmp][gcols]
-    double* rps = Gs + nmp * gcols;                                        // [kRpow]
+    double* Gs = Fs + ROWS * nV;                                           // [nmp][gcols] (not with GG)
+    double* rps = GG ? Gs : Gs + nmp * gcols;                              // [kRpow]
     double* pbs = rps + kRpow;                                             // [kMaxPb]
     int2* gis = reinterpret_cast<int2*>(pbs + kMaxPb);                     // [gcols]
 
@@ -515,8 +544,8 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
 #pragma unroll
     for (int i = 0; i < kGBatch; ++i) {
         const int idx = min(tid + i * B, totG - 1);
-        gcv[i] = gc[idx];
-        gpv[i] = gp[idx];
+        gcv[i] = GG ? 0.0 : gc[idx];
+        gpv[i] = GG ? -1 : gp[idx];
     }
     // output-side values, prefetched by the thread that writes output o
     const int n_out = nrows * nmp;
@@ -621,21 +650,24 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
             Fs[idx] = (double)t0.x * rps[2 * l0] + (double)t0.y * rps[2 * l0 + 1];
         }
     }
+    if (!GG) {
 #pragma unroll
-    for (int i = 0; i < kGBatch; ++i) {
-        const int idx = tid + i * B;
-        if (idx < totG) Gs[idx] = gpv[i] >= 0 ? gcv[i] * pbs[gpv[i]] : 0.0;
-    }
-    for (int idx = tid + kGBatch * B; idx < totG; idx += B) {
-        const int p = gp[idx];
-        Gs[idx] = p >= 0 ? gc[idx] * pbs[p] : 0.0;
+        for (int i = 0; i < kGBatch; ++i) {
+            const int idx = tid + i * B;
+            if (idx < totG) Gs[idx] = gpv[i] >= 0 ? gcv[i] * pbs[gpv[i]] : 0.0;
+        }
+        for (int idx = tid + kGBatch * B; idx < totG; idx += B) {
+            const int p = gp[idx];
+            Gs[idx] = p >= 0 ? gc[idx] * pbs[p] : 0.0;
+        }
     }
     __syncthreads();
 
     if (FC && tab_rows) load_table_rows();
     stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
     __syncthreads();
-    const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
+    const double2 y = GG ? stage_phase3_global(gc, gp, pbs, Ws, o, s, S, n_out, nmp, gcols)
+                         : stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
     double gval = 0.0, gma = 0.0, gmc = 0.0;
     if (writer) {
         const double2 py = cmul(phs[rad_o], y);
@@ -765,7 +797,7 @@ __device__ inline bool xcd_item(const Meta& m, int n_paths, int bx, int* jl, int
 // One RK4 stage for a.n_paths paths from a.traj0 (grid of xcd_item).  Small
 // row tiles ask for registers that leave room for four workgroups per CU
 // (their LDS does), larger ones for three.
-template <int ROWS, bool F32, bool FC>
+template <int ROWS, bool F32, bool FC, bool GG = false>
 __global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(StageArgs a) {
     extern __shared__ double2 smem2[];
     // work item W of the path-major list of a.n_paths x a.nwg row tiles, in
@@ -777,7 +809,7 @@ __global__ __launch_bounds__(kStageThreads, ROWS <= 4 ? 4 : 3) void k_stage(Stag
     if (W >= total) return;
     const int jl = W / a.nwg;
     const StageTile t = a.tiles[W - jl * a.nwg];
-    stage_body<0, ROWS, F32, FC>(a, a.traj0 + jl, t, reinterpret_cast<char*>(smem2));
+    stage_body<0, ROWS, F32, FC, GG>(a, a.traj0 + jl, t, reinterpret_cast<char*>(smem2));
 }
 
 // F of Eq. D2 at point slot p for every entry of the row layout and every path
@@ -1254,10 +1286,10 @@ void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out) {
     }
 }
 
-int stage_smem_bytes(const Meta& m, int rows) {
+int stage_smem_bytes(const Meta& m, int rows, bool gg) {
     int best = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
-        const size_t nmp = 2 * lp + 1;
+        const size_t nmp = gg ? 0 : 2 * lp + 1;
         const size_t bytes = m.n_xs * sizeof(double2) + (size_t)rows * m.gcols[lp] * sizeof(double2) +
                              (size_t)m.n_f * sizeof(double2) + (size_t)rows * m.nV[lp] * sizeof(double) +
                              nmp * m.gcols[lp] * sizeof(double) + (kRpow + kMaxPb) * sizeof(double) +
@@ -1293,8 +1325,10 @@ hipError_t stage_set_smem_limit(int, int bytes) {
 #define WPCCC_FN_PAIR(R)                                                                        \
     (const void*)k_stage<R, false, false>, (const void*)k_stage<R, false, true>,                 \
         (const void*)k_stage<R, true, true>, (const void*)k_chunk<R>,
-    const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR)(const void*)k_apply};
+#define WPCCC_FN_GG(R) (const void*)k_stage<R, false, true, true>, (const void*)k_stage<R, true, true, true>,
+    const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR) WPCCC_STAGE_ROWS_GG(WPCCC_FN_GG)(const void*)k_apply};
 #undef WPCCC_FN_PAIR
+#undef WPCCC_FN_GG
     hipError_t e = hipSuccess;
     for (const void* f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1397,6 +1431,21 @@ hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, i
     const dim3 grid(8 * ((n_traj_launch * a.nwg + 7) / 8)), block(kStageThreads);
     StageArgs a1 = a;
     a1.n_paths = n_traj_launch;
+    if (a.gg) {
+        // large bases: cached F, angular factors from global memory
+        if (!a.fc_cur) return hipErrorInvalidValue;
+        switch (rows) {
+#define WPCCC_CASE(R)                                                                                        \
+    case R:                                                                                                  \
+        if (a.tb.tab32) WPCCC_LAUNCH(ev, (k_stage<R, true, true, true>), grid, block, smem, st, a1);       \
+        else WPCCC_LAUNCH(ev, (k_stage<R, false, true, true>), grid, block, smem, st, a1);                  \
+        break;
+            WPCCC_STAGE_ROWS_GG(WPCCC_CASE)
+#undef WPCCC_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (rows) {
 #define WPCCC_CASE(R)                                                                    \
     case R:                                                                              \

@@ -22,6 +22,9 @@ constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply 
 // row tilings the stage kernels are built for (X-macro over the values)
 #define WPCCC_STAGE_ROWS(X) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
 constexpr int kStageRowsList[] = {4, 5, 6, 7, 8, 10, 12, 16};
+// row tilings of the large-basis form (angular factors from global memory)
+#define WPCCC_STAGE_ROWS_GG(X) X(1) X(2) X(4)
+constexpr int kStageRowsGG[] = {1, 2, 4};
 constexpr int kNumStageRows = sizeof(kStageRowsList) / sizeof(kStageRowsList[0]);
 constexpr int kChunkSteps = 64;                 // RK4 steps per prologue launch
 constexpr int kChunkPoints = 2 * kChunkSteps + 1;  // z_0, z_mid_0, z_1, ..., z_n
@@ -121,6 +124,7 @@ struct StageArgs {
     double h;
     int n_pad;
     int stage;            // 1..4
+    int gg;               // large-basis form: angular factors read from global memory (k_stage only)
     int traj0;
     int n_paths;          // paths of a k_stage launch (set by launch_stage)
     const double2* u_in;  // stage input   [n_traj][n_pad]
@@ -409,7 +413,8 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& host_meta, int smem, int
 // workgroups k_chunk needs for n_traj paths (rows per workgroup), and whether they fit at once
 int chunk_grid(const Meta& host_meta, int n_traj, int rows);
 bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
-int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock);
+// gg: the large-basis form (no angular factors in LDS)
+int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock, bool gg = false);
 // the row tiles of one path for `rows` rows per workgroup, l' order
 void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out);
 // whether the stage kernels can use `rows` rows per workgroup for this basis

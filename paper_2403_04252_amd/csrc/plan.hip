@@ -83,6 +83,16 @@ struct wpccc_plan_s {
     StageTile* d_tiles = nullptr;  // the row tiles of every tiling in kStageRowsList, one after another
     Observables obs;               // channel codes and path groups (wpccc_observables)
     int tile_off[kNumStageRows] = {}, tile_n[kNumStageRows] = {};
+    // large-basis form (no regular tiling fits the LDS): angular factors read
+    // from global memory, tilings of kStageRowsGG rows after the regular ones
+    bool gg = false;
+    int tile_off_gg[3] = {}, tile_n_gg[3] = {};
+    // stage kernels take F from the radial-integral cache (else every stage
+    // forms F from the moment table); required by the FP32-table,
+    // interpolated-F and large-basis forms, timed against the direct form
+    // otherwise
+    bool fcache = true;
+    int cache_req = WPCCC_CACHE_AUTO;
     KernelTimer timer;
 
     Tables tables() const { return c.tables(d_b, d_v); }
@@ -136,8 +146,17 @@ int enqueue_prologue(wpccc_plan_s* p, const double* z, int n, int j0, int nj, hi
     return launched(e, "k_prologue");
 }
 
-// The row tiles of a tiling (`rows` from kStageRowsList).
+// The row tiles of a tiling (`rows` from kStageRowsList, or from
+// kStageRowsGG in the large-basis form).
 void set_tiles(const wpccc_plan_s* p, int rows, StageArgs& a) {
+    if (p->gg) {
+        for (int i = 0; i < 3; ++i)
+            if (kStageRowsGG[i] == rows) {
+                a.tiles = p->d_tiles + p->tile_off_gg[i];
+                a.nwg = p->tile_n_gg[i];
+            }
+        return;
+    }
     for (int i = 0; i < kNumStageRows; ++i)
         if (kStageRowsList[i] == rows) {
             a.tiles = p->d_tiles + p->tile_off[i];
@@ -150,6 +169,7 @@ StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
     StageArgs a{};
     a.meta = p->c.d_meta;
     set_tiles(p, p->stage_rows, a);
+    a.gg = p->gg ? 1 : 0;
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -220,6 +240,7 @@ int enqueue_chunk(wpccc_plan_s* p, double2* X, int j0, int nj, const double* h, 
 // forms F from the moment table.
 int enqueue_step(wpccc_plan_s* p, double2* X, int j0, int nj, int pz, double h, hipStream_t st, bool cached = true) {
     int rc;
+    cached = cached && p->fcache;
     // the step's index within its chunk (graph replays read h at this index)
     const int step = pz / 2;
     const int c0 = cached ? 0 : -1, c1 = cached ? 1 : -1;
@@ -488,10 +509,14 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     float best_ms = 1e30f;
     int best_rows = 0, best_launch = 0;
     const int saved_rows = p->stage_rows, saved_smem = p->stage_smem_rows;
-    auto time_it = [&](int rows, int launch, float* ms) -> int {
-        const int smem = stage_smem_bytes(m, rows);
+    const bool direct_ok = !p->mixed && !p->interp && !p->gg && p->cache_req != WPCCC_CACHE_ON;
+    const bool cache_ok = p->cache_req != WPCCC_CACHE_OFF;
+    bool best_cache = cache_ok;
+    auto time_it = [&](int rows, int launch, bool cache, float* ms) -> int {
+        const int smem = stage_smem_bytes(m, rows, p->gg);
         p->stage_rows = rows;
         p->stage_smem_rows = smem;
+        p->fcache = cache;
         // a warm-up pass, then the fastest of kTunePasses timed passes
         int r = WPCCC_OK;
         *ms = 1e30f;
@@ -516,23 +541,30 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     };
     for (int ci = 0; ci < n_cand && rc == WPCCC_OK; ++ci) {
         const int rows = cand[ci];
-        const int smem = stage_smem_bytes(m, rows);
+        const int smem = stage_smem_bytes(m, rows, p->gg);
         if (smem > kMaxDynLds || !stage_rows_fit(m, rows)) continue;
         for (int launch : {WPCCC_LAUNCH_STAGES, WPCCC_LAUNCH_PERSISTENT}) {
             if (launch_req != WPCCC_LAUNCH_AUTO && launch != launch_req) continue;
-            if (launch == WPCCC_LAUNCH_PERSISTENT && (p->mixed || p->interp)) continue;
+            if (launch == WPCCC_LAUNCH_PERSISTENT && (p->mixed || p->interp || p->gg)) continue;
             if (launch == WPCCC_LAUNCH_PERSISTENT &&
                 (chunk_smem_bytes(m, rows) > kMaxDynLds || !chunk_fits(m, nj, rows, chunk_smem_bytes(m, rows))))
                 continue;
-            float ms = 0.f;
-            if ((rc = time_it(rows, launch, &ms))) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_rows = rows;
-                best_launch = launch;
+            for (int cache = 1; cache >= 0; --cache) {
+                if (!cache && (launch == WPCCC_LAUNCH_PERSISTENT || !direct_ok)) continue;
+                if (cache && !cache_ok && launch != WPCCC_LAUNCH_PERSISTENT) continue;
+                float ms = 0.f;
+                if ((rc = time_it(rows, launch, cache != 0, &ms))) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_rows = rows;
+                    best_launch = launch;
+                    best_cache = cache != 0;
+                }
             }
+            if (rc) break;
         }
     }
+    p->fcache = best_cache;
     p->timer.on = timing;
     const hipError_t es = hipStreamSynchronize(st);
     (void)hipFree(X);
@@ -548,7 +580,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
         return WPCCC_ENOTSUP;
     }
     p->stage_rows = best_rows;
-    p->stage_smem_rows = stage_smem_bytes(m, best_rows);
+    p->stage_smem_rows = stage_smem_bytes(m, best_rows, p->gg);
     p->chunk_smem = chunk_smem_bytes(m, best_rows);
     p->launch = best_launch;
     return WPCCC_OK;
@@ -707,6 +739,14 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_EINVAL;
     }
     const bool interp = o.radial == WPCCC_RADIAL_INTERP;
+    if (o.stage_cache < WPCCC_CACHE_AUTO || o.stage_cache > WPCCC_CACHE_OFF) {
+        set_error("wpccc_plan_create: stage_cache must be WPCCC_CACHE_AUTO, _ON or _OFF");
+        return WPCCC_EINVAL;
+    }
+    if (o.stage_cache == WPCCC_CACHE_OFF && (mixed || interp)) {
+        set_error("wpccc_plan_create: the reduced-precision and interpolated forms need the radial-integral cache");
+        return WPCCC_ENOTSUP;
+    }
     if (interp && (mixed || o.stage_launch == WPCCC_LAUNCH_PERSISTENT)) {
         set_error("wpccc_plan_create: the interpolated radial integrals are an FP64, one-launch-per-stage form");
         return WPCCC_ENOTSUP;
@@ -738,18 +778,37 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     plan->n_pad = (N + 7) & ~7;
     plan->mixed = mixed;
     plan->interp = interp;
+    plan->cache_req = o.stage_cache;
+    plan->fcache = o.stage_cache != WPCCC_CACHE_OFF;
     TRY(centre_build(hb, st, plan->c, o.model_a, o.model_c, o.Zp,
                      interp ? kRadialInterp : (mixed ? kRadialMoments32 : kRadialMoments)));
     plan->ckpt_every = o.checkpoint_every;
     plan->use_graph = o.graph != 0;
     const Meta& m = plan->c.meta;
     plan->stage_smem = stage_smem_bytes(m);
-    bool rows_ok = o.stage_rows == 0;
-    for (int r : kStageRowsList) rows_ok = rows_ok || o.stage_rows == r;
-    if (!rows_ok) {
-        set_error("wpccc_plan_create: stage_rows must be 0, 4, 5, 6, 7, 8, 10, 12 or 16");
+    // the large-basis form when no regular tiling fits the LDS
+    bool regular_fits = false;
+    for (int r : kStageRowsList)
+        regular_fits = regular_fits || (stage_smem_bytes(m, r) <= kMaxDynLds && stage_rows_fit(m, r));
+    plan->gg = !regular_fits;
+    if (plan->gg && o.stage_cache == WPCCC_CACHE_OFF) {
+        set_error("wpccc_plan_create: a basis this large needs the radial-integral cache");
         free_plan(plan);
-        return WPCCC_EINVAL;
+        return WPCCC_ENOTSUP;
+    }
+    if (plan->gg && o.stage_launch == WPCCC_LAUNCH_PERSISTENT) {
+        set_error("wpccc_plan_create: the persistent stage kernel does not take a basis this large");
+        free_plan(plan);
+        return WPCCC_ENOTSUP;
+    }
+    bool rows_ok = o.stage_rows == 0;
+    for (int r : kStageRowsList) rows_ok = rows_ok || (!plan->gg && o.stage_rows == r);
+    for (int r : kStageRowsGG) rows_ok = rows_ok || (plan->gg && o.stage_rows == r);
+    if (!rows_ok) {
+        set_error(plan->gg ? "wpccc_plan_create: stage_rows must be 0, 1, 2 or 4 for a basis this large"
+                           : "wpccc_plan_create: stage_rows must be 0, 4, 5, 6, 7, 8, 10, 12 or 16");
+        free_plan(plan);
+        return plan->gg && o.stage_rows > 0 ? WPCCC_ENOTSUP : WPCCC_EINVAL;
     }
     if (o.stage_launch < WPCCC_LAUNCH_AUTO || o.stage_launch > WPCCC_LAUNCH_PERSISTENT) {
         set_error("wpccc_plan_create: stage_launch must be WPCCC_LAUNCH_AUTO, _STAGES or _PERSISTENT");
@@ -759,14 +818,18 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
     // untimed default tiling: kRowsPerBlock rows, or the largest admissible
     // smaller tiling whose LDS fits (large bases)
     int rows0 = o.stage_rows;
-    if (!rows0) {
+    if (!rows0 && plan->gg) {
+        rows0 = kStageRowsGG[0];
+        for (int r : kStageRowsGG)
+            if (stage_smem_bytes(m, r, true) <= kMaxDynLds && stage_rows_fit(m, r)) rows0 = r;
+    } else if (!rows0) {
         rows0 = kRowsPerBlock;
         if (stage_smem_bytes(m, rows0) > kMaxDynLds)
             for (int r : kStageRowsList)
                 if (r < kRowsPerBlock && stage_smem_bytes(m, r) <= kMaxDynLds) rows0 = r;
     }
     plan->stage_rows = rows0;
-    plan->stage_smem_rows = stage_smem_bytes(m, plan->stage_rows);
+    plan->stage_smem_rows = stage_smem_bytes(m, plan->stage_rows, plan->gg);
     if (!stage_rows_fit(m, plan->stage_rows)) {
         set_error("wpccc_plan_create: stage_rows %d is too many for l_max = %d (rows x (2 l_max + 1) must not "
                   "exceed %d)", plan->stage_rows, m.l_max, kStageThreads);
@@ -774,8 +837,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_EINVAL;
     }
     if (plan->stage_smem_rows > kMaxDynLds) {
-        set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes at %d rows)",
-                  plan->stage_smem_rows, plan->stage_rows);
+        set_error("wpccc_plan_create: basis too large for the stage kernel's LDS (%d bytes at %d rows%s)",
+                  plan->stage_smem_rows, plan->stage_rows, plan->gg ? ", angular factors in global memory" : "");
         free_plan(plan);
         return WPCCC_ENOTSUP;
     }
@@ -794,6 +857,13 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         stage_tiles(m, kStageRowsList[i], t);
         plan->tile_off[i] = (int)tiles.size();
         plan->tile_n[i] = (int)t.size();
+        tiles.insert(tiles.end(), t.begin(), t.end());
+    }
+    for (int i = 0; i < 3; ++i) {
+        std::vector<StageTile> t;
+        stage_tiles(m, kStageRowsGG[i], t);
+        plan->tile_off_gg[i] = (int)tiles.size();
+        plan->tile_n_gg[i] = (int)t.size();
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
     TRY(dev_alloc(&plan->d_tiles, tiles.size(), tot));
@@ -833,8 +903,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_EHIP;
     }
     if (o.stage_rows == 0 || o.stage_launch == WPCCC_LAUNCH_AUTO) {
-        const int* cand = o.stage_rows ? &o.stage_rows : kStageRowsList;
-        TRY(tune_stage(plan, cand, o.stage_rows ? 1 : kNumStageRows, o.stage_launch, st));
+        const int* cand = o.stage_rows ? &o.stage_rows : (plan->gg ? kStageRowsGG : kStageRowsList);
+        TRY(tune_stage(plan, cand, o.stage_rows ? 1 : (plan->gg ? 3 : kNumStageRows), o.stage_launch, st));
     } else if (o.stage_launch == WPCCC_LAUNCH_PERSISTENT) {
         // nothing to choose: check that the grid can be resident at once
         const int nj = plan->batched ? n_traj : 1;
@@ -924,6 +994,15 @@ int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows) {
         return WPCCC_EINVAL;
     }
     *rows = plan->p2c ? 0 : plan->stage_rows;
+    return WPCCC_OK;
+}
+
+int wpccc_plan_stage_cache(wpccc_plan_t plan, int* cached) {
+    if (!plan || !cached) {
+        set_error("wpccc_plan_stage_cache: NULL argument");
+        return WPCCC_EINVAL;
+    }
+    *cached = (!plan->p2c && plan->fcache) ? 1 : 0;
     return WPCCC_OK;
 }
 

@@ -250,9 +250,12 @@ def test_large_l_basis_parity():
         Xo = propagate_one_centre(ob, w.b[j], w.v[j], w.zgrid)
         assert np.abs(X[j] - Xo).max() <= 1e-12, (j, np.abs(X[j] - Xo).max())
         assert prob_ok(P[j], probabilities(Xo)).all()
+    # l_max = 10: no regular tiling fits the LDS, the large-basis form is
+    # used (tilings of 1, 2 or 4 rows only)
     big = lib_basis(WL.Recipe(2, 10, 1, 2.0, 300, 60.0))
+    assert W.wpccc_plan_stage_rows(W.wpccc_plan_create(big, [1.0], [1.0])) in (1, 2, 4)
     with pytest.raises(W.WpcccError) as e:
-        W.wpccc_plan_create(big, [1.0], [1.0])
+        W.wpccc_plan_create(big, [1.0], [1.0], stage_rows=8)
     assert e.value.code == -6
 
 
@@ -471,4 +474,51 @@ def test_interpolated_radial_form(small):
     assert 0.0 < d < 1e-3
     with pytest.raises(W.WpcccError) as e:
         W.wpccc_plan_create(lb, [1.0], [1.0], interp=True, mixed=True)
+    assert e.value.code == -6
+
+
+@pytest.mark.parametrize("l_max,n_states", [(8, 2958), (10, 4257)])
+def test_paper_shape_large_basis_form(l_max, n_states):
+    """The paper's one-centre basis shape beyond l_max = 7 (N_l = 42 - l; at
+    l_max = 10, N = 4257, the largest one-centre system of the paper's
+    scaling runs): no tiling of the stage kernel fits the LDS with the
+    angular factors staged there, so the plan reads them from global memory
+    (1, 2 or 4 rows per workgroup).  Two paths, 2 steps, against the oracle
+    on a 300-point grid."""
+    rec = WL.Recipe(10, l_max, 32, 3.0, 300, 100.0)
+    lb, ob = lib_basis(rec), oracle_basis(rec)
+    zg = np.array([-3.0, -2.9, -2.8])
+    bs, vs = [1.5, 4.0], [2.0, 2.0]
+    print(f"paper shape l_max = {l_max} (N = {n_states}), large-basis form", flush=True)
+    X, P, _ = _propagate_gpu(lb, bs, vs, zg)
+    assert X.shape[1] == n_states
+    for j in range(2):
+        Xo = propagate_one_centre(ob, bs[j], vs[j], zg)
+        err = np.abs(X[j] - Xo).max()
+        print(f"  path {j}: max|dX| {err:.2e}", flush=True)
+        assert err <= 1e-12
+        assert prob_ok(P[j], probabilities(Xo)).all()
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create(lb, [1.0], [1.0], stage_launch=W.WPCCC_LAUNCH_PERSISTENT)
+    assert e.value.code == -6
+
+
+def test_stage_cache_forms_bitwise(large):
+    """Stage kernels with the radial-integral cache (F formed at the two new
+    points of a step and read back) and without it (F formed from the moment
+    table in every stage) run the same arithmetic: bitwise the same
+    amplitudes over two chunks and a ragged one; the timed choice is one of
+    the two; the forms that need the cache refuse WPCCC_CACHE_OFF."""
+    rec, lb, _ = large
+    w = WL.reduced(WL.single_centre_batched(), n_paths=6, n_steps=150)
+    outs = {}
+    for c in (W.WPCCC_CACHE_ON, W.WPCCC_CACHE_OFF):
+        plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=6, stage_launch=W.WPCCC_LAUNCH_STAGES, stage_cache=c)
+        assert W.wpccc_plan_stage_cache(plan) == (c == W.WPCCC_CACHE_ON)
+        outs[c] = _run_plan(plan, w.zgrid)
+    assert np.array_equal(outs[W.WPCCC_CACHE_ON], outs[W.WPCCC_CACHE_OFF])
+    auto = W.wpccc_plan_create(lb, w.b, w.v)
+    print("timed choice: rows", W.wpccc_plan_stage_rows(auto), "cache", W.wpccc_plan_stage_cache(auto), flush=True)
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create(lb, w.b, w.v, mixed=True, stage_cache=W.WPCCC_CACHE_OFF)
     assert e.value.code == -6
