@@ -235,9 +235,10 @@ int wpccc_plan_stage_rows(wpccc_plan_t plan, int* rows);
 /* Whether a one-centre plan's stage kernels take the radial integrals F from
  * a cache filled at the two new points of each step (1) or form them from the
  * moment table in every stage (0); chosen by timing at plan creation for the
- * FP64 exact-R form, always 1 for the WPCCC_MIXED and WPCCC_RADIAL_INTERP
- * forms and for bases whose angular factors do not fit the LDS; 0 for a
- * two-centre plan.  Both give bitwise the same amplitudes. */
+ * exact-R forms (FP64 and WPCCC_MIXED), always 1 for the
+ * WPCCC_RADIAL_INTERP form and for bases whose angular factors do not fit the
+ * LDS; 0 for a two-centre plan.  In FP64 both give bitwise the same
+ * amplitudes (in WPCCC_MIXED the cache holds F in FP32, one more rounding). */
 int wpccc_plan_stage_cache(wpccc_plan_t plan, int* cached);
 
 /* Launch form a one-centre plan's wpccc_propagate uses for its RK4 stages

@@ -1324,7 +1324,7 @@ hipError_t stage_set_smem_limit(int, int bytes) {
     if (bytes <= set_bytes) return hipSuccess;
 #define WPCCC_FN_PAIR(R)                                                                        \
     (const void*)k_stage<R, false, false>, (const void*)k_stage<R, false, true>,                 \
-        (const void*)k_stage<R, true, true>, (const void*)k_chunk<R>,
+        (const void*)k_stage<R, true, true>, (const void*)k_stage<R, true, false>, (const void*)k_chunk<R>,
 #define WPCCC_FN_GG(R) (const void*)k_stage<R, false, true, true>, (const void*)k_stage<R, true, true, true>,
     const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR) WPCCC_STAGE_ROWS_GG(WPCCC_FN_GG)(const void*)k_apply};
 #undef WPCCC_FN_PAIR
@@ -1450,7 +1450,7 @@ hipError_t launch_stage(const StageArgs& a, const Meta& hm, int n_traj_launch, i
 #define WPCCC_CASE(R)                                                                    \
     case R:                                                                              \
         if (a.tb.tab32 && a.fc_cur) WPCCC_LAUNCH(ev, (k_stage<R, true, true>), grid, block, smem, st, a1); \
-        else if (a.tb.tab32) return hipErrorInvalidValue;                                \
+        else if (a.tb.tab32) WPCCC_LAUNCH(ev, (k_stage<R, true, false>), grid, block, smem, st, a1);       \
         else if (a.fc_cur) WPCCC_LAUNCH(ev, (k_stage<R, false, true>), grid, block, smem, st, a1);       \
         else WPCCC_LAUNCH(ev, (k_stage<R, false, false>), grid, block, smem, st, a1);                    \
         break;

@@ -509,7 +509,7 @@ int tune_stage(wpccc_plan_s* p, const int* cand, int n_cand, int launch_req, hip
     float best_ms = 1e30f;
     int best_rows = 0, best_launch = 0;
     const int saved_rows = p->stage_rows, saved_smem = p->stage_smem_rows;
-    const bool direct_ok = !p->mixed && !p->interp && !p->gg && p->cache_req != WPCCC_CACHE_ON;
+    const bool direct_ok = !p->interp && !p->gg && p->cache_req != WPCCC_CACHE_ON;
     const bool cache_ok = p->cache_req != WPCCC_CACHE_OFF;
     bool best_cache = cache_ok;
     auto time_it = [&](int rows, int launch, bool cache, float* ms) -> int {
@@ -743,8 +743,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: stage_cache must be WPCCC_CACHE_AUTO, _ON or _OFF");
         return WPCCC_EINVAL;
     }
-    if (o.stage_cache == WPCCC_CACHE_OFF && (mixed || interp)) {
-        set_error("wpccc_plan_create: the reduced-precision and interpolated forms need the radial-integral cache");
+    if (o.stage_cache == WPCCC_CACHE_OFF && interp) {
+        set_error("wpccc_plan_create: the interpolated form needs the radial-integral cache");
         return WPCCC_ENOTSUP;
     }
     if (interp && (mixed || o.stage_launch == WPCCC_LAUNCH_PERSISTENT)) {

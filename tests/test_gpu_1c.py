@@ -520,5 +520,5 @@ def test_stage_cache_forms_bitwise(large):
     auto = W.wpccc_plan_create(lb, w.b, w.v)
     print("timed choice: rows", W.wpccc_plan_stage_rows(auto), "cache", W.wpccc_plan_stage_cache(auto), flush=True)
     with pytest.raises(W.WpcccError) as e:
-        W.wpccc_plan_create(lb, w.b, w.v, mixed=True, stage_cache=W.WPCCC_CACHE_OFF)
+        W.wpccc_plan_create(lb, w.b, w.v, interp=True, stage_cache=W.WPCCC_CACHE_OFF)
     assert e.value.code == -6

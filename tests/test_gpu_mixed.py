@@ -110,9 +110,24 @@ def test_mixed_tilings_and_graph(large):
         outs[rows] = run(plan, w.zgrid)[0]
     for rows in (4, 6):
         assert np.abs(outs[rows] - outs[8]).max() <= 1e-13
-    gp = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=8, graph=True, mixed=True)
+    gp = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=8, stage_launch=W.WPCCC_LAUNCH_STAGES, graph=True, mixed=True)
     for rep in range(2):
         assert np.array_equal(run(gp, w.zgrid)[0], outs[8]), rep
+
+
+def test_mixed_cache_forms(large):
+    """The reduced-precision form with and without the radial-integral cache
+    (FP32 F in the cache: one more rounding): both within the reduced-
+    precision bar of the FP64 run over 150 steps of six paths."""
+    rec, lb, _ = large
+    w = WL.reduced(WL.single_centre_batched(), n_paths=6, n_steps=150)
+    ref = run(W.wpccc_plan_create(lb, w.b, w.v, stage_rows=6, stage_launch=W.WPCCC_LAUNCH_STAGES), w.zgrid)[1]
+    for c in (W.WPCCC_CACHE_ON, W.WPCCC_CACHE_OFF):
+        plan = W.wpccc_plan_create(lb, w.b, w.v, stage_rows=6, stage_launch=W.WPCCC_LAUNCH_STAGES, mixed=True,
+                                   stage_cache=c)
+        P = run(plan, w.zgrid)[1]
+        print(f"mixed cache {c}: max|dP| vs FP64 {np.abs(P - ref).max():.2e}", flush=True)
+        assert mixed_ok(P, ref).all()
 
 
 def test_mixed_refusals(small):
