@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--lmax", type=int, default=6, help="paper: l_max of the paper-shape basis (<= 7)")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
+    ap.add_argument("--explicit-m", action="store_true",
+                    help="c3: form M = S^-1 H per coupling point (the paper's form) instead of solving per stage")
     ap.add_argument("--no-2c", action="store_true",
                     help="c2: skip the short two-centre measurement added to the output line")
     ap.add_argument("--no-seeded", action="store_true",
@@ -698,7 +700,7 @@ def contract_flops(recT, recP, n_w, n_act):
 
 def bench_two_centre(args):
     """Batched two-centre propagation (Eq. 1 with capture) on one GPU: prints its own JSON line."""
-    out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed)
+    out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed, explicit=args.explicit_m)
     print(json.dumps(out), flush=True)
 
 
@@ -708,10 +710,14 @@ def two_centre_pair(args, steps, warmup, z0=-1.0):
     the mixed probabilities against the FP64 ones at the end of the stretch."""
     r64 = two_centre_measure(args, steps, warmup, mixed=False, z0=z0)
     rmx = two_centre_measure(args, steps, warmup, mixed=True, z0=z0)
-    P64, Pmx = r64.pop("P_final"), rmx.pop("P_final")
+    rex = two_centre_measure(args, steps, warmup, mixed=False, z0=z0, explicit=True)
+    P64, Pmx, Pex = r64.pop("P_final"), rmx.pop("P_final"), rex.pop("P_final")
     d = np.abs(Pmx - P64)
     keep = ("value", "unit", "ms_per_step", "roofline", "lu", "config", "kernel_times")
-    out = {"fp64": {k: r64[k] for k in keep}, "mixed": {k: rmx[k] for k in keep}}
+    out = {"fp64": {k: r64[k] for k in keep}, "mixed": {k: rmx[k] for k in keep},
+           "fp64_explicit_m": {k: rex[k] for k in keep + ("rhs",)}}
+    out["fp64_explicit_m"]["dtype"] = "f64"
+    out["fp64_explicit_m"]["max_abs_dP_vs_factored"] = float(np.abs(Pex - P64).max())
     out["fp64"]["dtype"] = "f64"
     out["mixed"]["dtype"] = "f64 (contraction products f32)"
     out["mixed"]["prob_error_vs_fp64_gpu"] = {
@@ -722,7 +728,7 @@ def two_centre_pair(args, steps, warmup, z0=-1.0):
     return out
 
 
-def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
+def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False):
     """Time `steps` RK4 steps of the batched two-centre workload; returns the
     result dict.  z0 None: the workload's grid from its start, amplitudes from
     e_0; else `steps` steps of 0.1 from z0 from a seeded random state (the
@@ -740,7 +746,7 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
     ql = W.WPCCC_Q_PRIOR if w.q_lower == "prior" else W.WPCCC_Q_DAGGER
     t0 = time.perf_counter()
     plan = W.wpccc_plan_create_2c(bases, bases, w.set_of, w.b, w.v, q_lower=ql, n_eta=w.n_eta, n_tau=w.n_tau,
-                                  mixed=mixed)
+                                  mixed=mixed, solve=W.WPCCC_SOLVE_EXPLICIT if explicit else W.WPCCC_SOLVE_FACTORED)
     setup_s = time.perf_counter() - t0
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
@@ -772,7 +778,8 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
     W.wpccc_plan_timing(plan, True)
     W.wpccc_propagate(plan, zs, X)
     names = ["k_2c_contract", "k_2c_reduce", "k_2c_interp", "k_2c_nodes", "k_2c_assemble", "k_setup_batch",
-             "k_2c_direct", "k_lu_check", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve"]
+             "k_2c_direct", "k_lu_check", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update", "k_2c_hu", "k_2c_solve",
+             "k_lu_rhs"]
     kt = {}
     for nm in names:
         ms, n = W.wpccc_plan_kernel_time(plan, nm)
@@ -806,10 +813,11 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
             "traffic": None, "avg_launch_us": c_ms / max(kt["k_2c_contract"]["launches"], 1) * 1e3,
             "launches": kt["k_2c_contract"]["launches"], "algorithmic_flops_total": fl,
             "measured_mfma_ceiling": ceiling, "frac_of_measured_ceiling": achieved / ceiling}
-    lu_fl = 0
+    lu_fl = rhs_fl = 0
     for j in range(n_traj):
         N = 2 * sum((2 * l + 1) * n for l, n in enumerate(n_per_l(w.targets[w.set_of[j]])))
         lu_fl += (steps * 2 + 1) * 8.0 / 3.0 * N ** 3
+        rhs_fl += (steps * 2 + 1) * 8.0 * N ** 3   # two triangular solves with N right-hand sides
     lu_ms = sum(kt[k]["total_ms"] for k in ("k_lu_check", "k_lu_panel", "k_lu_swap_trsm", "k_lu_update"))
     out = {
         "metric": METRIC,
@@ -827,7 +835,8 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
         "config": {"workload": w.name + ": same recipe on both centres (n<=6 + 20 bins/l, l<=1/2/3), "
                                "4000-pt grid, 8 b log-spaced 0.2-10 per size, 256x512 nodes, "
                                f"z {zs[0]:.1f}..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
-                   "form": "batched mixed (FP32 contraction products)" if mixed else "batched FP64",
+                   "form": ("batched mixed (FP32 contraction products)" if mixed else "batched FP64")
+                           + (", explicit M = S^-1 H" if explicit else ", per-stage triangular solves"),
                    "n_paths": n_traj, "plan_setup_s": setup_s,
                    "parallelism": "1 GPU, paths batched per basis size"},
         "roofline": roof,
@@ -836,6 +845,10 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None):
         "kernel_times": kt,
         "cpu_baseline": None,
     }
+    if explicit:
+        rhs_ms = kt["k_lu_rhs"]["total_ms"]
+        out["rhs"] = {"algorithmic_flops": rhs_fl, "device_ms": rhs_ms,
+                      "achieved_tflops": rhs_fl / max(rhs_ms * 1e-3, 1e-12) / 1e12}
     if z0 is not None:
         out["P_final"] = P_final
     return out

@@ -175,7 +175,20 @@ typedef struct {
                        where both forms apply), WPCCC_CACHE_ON or WPCCC_CACHE_OFF
                        (see wpccc_plan_stage_cache; WPCCC_ENOTSUP where the
                        form needs the cache) */
+    int solve;      /* 2C: how each RK4 stage applies S^{-1} (Eq. INV):
+                       WPCCC_SOLVE_FACTORED (default): S is factored once per
+                       coupling point (LU with partial pivoting) and each
+                       stage solves S y = H u with the two triangular factors;
+                       WPCCC_SOLVE_EXPLICIT: the paper's form (Sec. II),
+                       M = S^{-1} H formed once per coupling point from the
+                       same factors with N right-hand sides, each stage the
+                       product M u.  The same FP64 arithmetic up to the order
+                       of the sums; the explicit form holds one more N x N
+                       matrix per path and slot.  1C: must be 0. */
 } wpccc_plan_opts;
+
+#define WPCCC_SOLVE_FACTORED 0
+#define WPCCC_SOLVE_EXPLICIT 1
 
 #define WPCCC_CACHE_AUTO 0
 #define WPCCC_CACHE_ON   1

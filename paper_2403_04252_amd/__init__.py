@@ -20,7 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_couplings_noalloc", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
-    "wpccc_plan_stage_launch", "wpccc_plan_stage_cache", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
+    "wpccc_plan_stage_launch", "wpccc_plan_stage_cache", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_SOLVE_FACTORED", "WPCCC_SOLVE_EXPLICIT", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +38,8 @@ WPCCC_LAUNCH_PERSISTENT = 2
 WPCCC_CACHE_AUTO = 0
 WPCCC_CACHE_ON = 1
 WPCCC_CACHE_OFF = 2
+WPCCC_SOLVE_FACTORED = 0
+WPCCC_SOLVE_EXPLICIT = 1
 WPCCC_N_CHANNELS = 6
 CHANNELS = ("elastic", "excitation", "target_continuum", "capture", "projectile_continuum", "total")
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENUMERIC", -6: "ENOTSUP"}
@@ -61,7 +63,7 @@ class _PlanOpts(ctypes.Structure):
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
                 ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int),
-                ("radial", ctypes.c_int), ("stage_cache", ctypes.c_int)]
+                ("radial", ctypes.c_int), ("stage_cache", ctypes.c_int), ("solve", ctypes.c_int)]
 
 
 @dataclass
@@ -270,8 +272,10 @@ def wpccc_plan_stage_cache(plan: Plan) -> bool:
 
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
                          n_eta: int = 0, n_tau: int = 0, batched: bool = True, mixed: bool = False,
-                         stream=None) -> Plan:
-    """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j]."""
+                         solve: int = WPCCC_SOLVE_FACTORED, stream=None) -> Plan:
+    """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j].
+    solve: WPCCC_SOLVE_FACTORED (triangular solves per stage) or WPCCC_SOLVE_EXPLICIT
+    (M = S^-1 H per coupling point, the paper's form)."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
@@ -282,7 +286,7 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
     opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
-                     WPCCC_MIXED if mixed else WPCCC_FP64, 0, 0)
+                     WPCCC_MIXED if mixed else WPCCC_FP64, 0, 0, 0, 0, int(solve))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

@@ -15,7 +15,9 @@
 //                  frame, interaction phases -> K, Q blocks of S and H
 //   k_setup_batch, k_2c_direct   D_T and D_P blocks (Eq. D1 on each centre)
 // Per RK4 stage: k_2c_hu  y = P (H u) over many workgroups per path, then
-// k_2c_solve  y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update.
+// k_2c_solve  y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update (in the
+// explicit form y = M u with M = S^{-1} H formed per coupling point, and
+// k_2c_solve only updates).
 // The LU factorisation of S is in kernels_lu.hip.
 #include <hip/hip_runtime.h>
 
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(256) void k_2c_direct(DirectArgs a) {
     a.H[ps + (size_t)(off + row) * N + off + col] = make_double2(Zc * acc * wr, Zc * acc * wi);
 }
 
-// y = P (H u) for every path of the launch: grid x = blocks of 16 rows,
+// y = P (H u) (or y = M u) for every path of the launch: grid x = blocks of 16 rows,
 // y = path; each wave accumulates four rows at once (four 1 KB row segments
 // in flight per iteration).
 __global__ __launch_bounds__(256) void k_2c_hu(Stage2CArgs a) {
@@ -747,12 +749,15 @@ __global__ __launch_bounds__(256) void k_2c_hu(Stage2CArgs a) {
     const int N = a.N, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const size_t ps = ((size_t)pl * kSlots2C + a.slot) * (size_t)N * N;
     const double2* H = a.H + ps;
-    const int* perm = a.perm + ((size_t)pl * kSlots2C + a.slot) * N;
+    const int* perm = a.perm ? a.perm + ((size_t)pl * kSlots2C + a.slot) * N : nullptr;
     const double2* u = a.u_in + (size_t)j * a.n_pad;
     const int r0 = blockIdx.x * 16 + wave * 4;
     const double2* hr[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) hr[q] = H + (size_t)perm[min(r0 + q, N - 1)] * N;
+    for (int q = 0; q < 4; ++q) {
+        const int row = min(r0 + q, N - 1);
+        hr[q] = H + (size_t)(perm ? perm[row] : row) * N;
+    }
     double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = lane; c < N; c += 64) {
         const double2 x = u[c];
@@ -781,8 +786,8 @@ constexpr int kSolveBlock = 32;
 // loads in flight on the path's CU
 constexpr int kSolveThreads = 1024;
 
-// y <- U^{-1} L^{-1} y, K = -(i/v) y and the RK4 update; one workgroup per
-// path.  The triangular solves go by blocks of 32 rows: the diagonal block is
+// y <- U^{-1} L^{-1} y (where the stage solves), K = -(i/v) y and the RK4
+// update; one workgroup per path.  The triangular solves go by blocks of 32 rows: the diagonal block is
 // staged in LDS and solved by one wave with lane shuffles, then all waves
 // update the rows below (above) it from the column-major factors.
 __global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
@@ -796,7 +801,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
     for (int i = tid; i < N; i += blockDim.x) ys[i] = a.Y[(size_t)j * a.n_pad + i];
     __syncthreads();
     // L (unit diagonal): forward
-    for (int kb = 0; kb < N; kb += kSolveBlock) {
+    for (int kb = 0; a.solve && kb < N; kb += kSolveBlock) {
         const int nbk = min(kSolveBlock, N - kb);
         for (int e = tid; e < nbk * nbk; e += blockDim.x) {
             const int r = e % nbk, c = e / nbk;
@@ -830,7 +835,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
         __syncthreads();
     }
     // U: backward
-    for (int kb = ((N - 1) / kSolveBlock) * kSolveBlock; kb >= 0; kb -= kSolveBlock) {
+    for (int kb = ((N - 1) / kSolveBlock) * kSolveBlock; a.solve && kb >= 0; kb -= kSolveBlock) {
         const int nbk = min(kSolveBlock, N - kb);
         for (int e = tid; e < nbk * nbk; e += blockDim.x) {
             const int r = e % nbk, c = e / nbk;

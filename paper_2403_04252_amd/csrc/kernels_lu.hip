@@ -9,6 +9,8 @@
 //                   order) and U12 = L11^-1 A12, one thread per column
 //   k_lu_update     A22 -= L21 U12 on MFMA (v_mfma_f64_16x16x4f64), 64 x 64
 //                   output tiles, complex product as four real products
+// and, for the explicit form of the derivative matrix, k_lu_rhs: M = S^-1 H
+// from the finished factors.
 #include <hip/hip_runtime.h>
 
 #include "plan2c.h"
@@ -338,6 +340,145 @@ __global__ __launch_bounds__(256) void k_lu_check(LUStepArgs a) {
     }
 }
 
+
+// M = S^{-1} H = U^{-1} L^{-1} (P H) for every matrix of the launch from the
+// factors above: the explicit form of Eq. INV, N right-hand sides.  One
+// workgroup per (matrix, block of 32 columns of H).  Column blocks are
+// independent, so a block's forward and backward substitutions run back to
+// back in one workgroup, left-looking by blocks of 32 rows: a row block
+// first subtracts its products with the finished blocks (32 x 32 tiles of
+// the factor and of the solution staged in LDS; each thread holds one row
+// and four columns), then solves its triangular diagonal block with
+// shuffles across the 32 lanes that hold the block's rows.  The solution is
+// written to M and read back by the later row blocks of the same workgroup.
+constexpr int kRhsB = 32;
+
+__global__ __launch_bounds__(256) void k_lu_rhs(RhsArgs a) {
+    __shared__ double2 ft[kRhsB][kRhsB + 1];  // factor tile [row][k]
+    __shared__ double2 yt[kRhsB][kRhsB + 1];  // right-hand-side / solution tile [row][column]
+    const int N = a.N, t = threadIdx.x, r = t & 31, cq = (t >> 5) * 4;
+    int pl, slot;
+    job_of(a.jobs, blockIdx.y, pl, slot);
+    const size_t ms = (size_t)pl * kSlots2C + slot, NN = (size_t)N * N;
+    const double2* LU = a.LU + ms * NN;
+    const int* perm = a.perm + ms * N;
+    double2* M = a.M + ms * NN;
+    const int c0 = blockIdx.x * kRhsB, nc = min(kRhsB, N - c0), nb = (N + kRhsB - 1) / kRhsB;
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 acc[4];
+    // rows [rb0, rb0 + 32) x columns [c0, c0 + 32) of a row-major matrix (row
+    // i of the tile taken from row rows[rb0 + i] when rows is given), zero-padded
+    auto load_rows = [&](const double2* src, const int* rows, int rb0) {
+        for (int e = t; e < kRhsB * kRhsB; e += 256) {
+            const int i = e >> 5, c = e & 31, row = rb0 + i;
+            double2 v = zero;
+            if (row < N && c < nc) v = src[(size_t)(rows ? rows[row] : row) * N + c0 + c];
+            yt[i][c] = v;
+        }
+    };
+    // rows [rb0, rb0 + 32) x columns [kb0, kb0 + 32) of the column-major factors, zero-padded
+    auto load_factor = [&](int rb0, int kb0) {
+        for (int e = t; e < kRhsB * kRhsB; e += 256) {
+            const int i = e & 31, k = e >> 5, row = rb0 + i, col = kb0 + k;
+            ft[i][k] = (row < N && col < N) ? LU[row + (size_t)col * N] : zero;
+        }
+    };
+    auto subtract_products = [&]() {
+#pragma unroll 8
+        for (int k = 0; k < kRhsB; ++k) {
+            const double2 f = ft[r][k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 y = yt[k][cq + q];
+                acc[q].x -= f.x * y.x - f.y * y.y;
+                acc[q].y -= f.x * y.y + f.y * y.x;
+            }
+        }
+    };
+    auto take_rows = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = yt[r][cq + q];
+    };
+    auto store_rows = [&](int rb0) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yt[r][cq + q] = acc[q];
+        __syncthreads();
+        for (int e = t; e < kRhsB * kRhsB; e += 256) {
+            const int i = e >> 5, c = e & 31, row = rb0 + i;
+            if (row < N && c < nc) M[(size_t)row * N + c0 + c] = yt[i][c];
+        }
+    };
+    // forward: L (unit diagonal) Y = P H
+    for (int rb = 0; rb < nb; ++rb) {
+        const int rb0 = rb * kRhsB;
+        __syncthreads();
+        load_rows(a.H + ms * NN, perm, rb0);
+        __syncthreads();
+        take_rows();
+        for (int cb = 0; cb < rb; ++cb) {
+            __syncthreads();
+            load_factor(rb0, cb * kRhsB);
+            load_rows(M, nullptr, cb * kRhsB);
+            __syncthreads();
+            subtract_products();
+        }
+        __syncthreads();
+        load_factor(rb0, rb0);
+        __syncthreads();
+        for (int k = 0; k + 1 < kRhsB; ++k) {
+            const double2 f = ft[r][k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double yr = __shfl(acc[q].x, k, 32), yi = __shfl(acc[q].y, k, 32);
+                if (r > k) {
+                    acc[q].x -= f.x * yr - f.y * yi;
+                    acc[q].y -= f.x * yi + f.y * yr;
+                }
+            }
+        }
+        store_rows(rb0);
+    }
+    // backward: U M = Y
+    for (int rb = nb - 1; rb >= 0; --rb) {
+        const int rb0 = rb * kRhsB;
+        __syncthreads();
+        load_rows(M, nullptr, rb0);
+        __syncthreads();
+        take_rows();
+        for (int cb = rb + 1; cb < nb; ++cb) {
+            __syncthreads();
+            load_factor(rb0, cb * kRhsB);
+            load_rows(M, nullptr, cb * kRhsB);
+            __syncthreads();
+            subtract_products();
+        }
+        __syncthreads();
+        load_factor(rb0, rb0);
+        __syncthreads();
+        for (int k = kRhsB - 1; k >= 0; --k) {
+            if (r == k && rb0 + k < N) {
+                const double2 d = ft[k][k];
+                const double dn = d.x * d.x + d.y * d.y;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[q] = make_double2((acc[q].x * d.x + acc[q].y * d.y) / dn,
+                                          (acc[q].y * d.x - acc[q].x * d.y) / dn);
+            }
+            const double2 f = ft[r][k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double yr = __shfl(acc[q].x, k, 32), yi = __shfl(acc[q].y, k, 32);
+                if (r < k) {
+                    acc[q].x -= f.x * yr - f.y * yi;
+                    acc[q].y -= f.x * yi + f.y * yr;
+                }
+            }
+        }
+        store_rows(rb0);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
@@ -365,6 +506,11 @@ hipError_t launch_lu_update(const LUStepArgs& a, int n_jobs, hipStream_t st, con
     const int T = (a.N - a.k0 - a.nb + 63) / 64;
     if (T <= 0) return hipSuccess;
     WPCCC_LAUNCH(ev, k_lu_update, dim3(T * T, n_jobs), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lu_rhs(const RhsArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_lu_rhs, dim3((a.N + kRhsB - 1) / kRhsB, n_jobs), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

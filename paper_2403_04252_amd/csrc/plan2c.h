@@ -197,15 +197,26 @@ struct LUStepArgs {
     int skip_mode;          // 0: run; 1: return where skip is set; 2: return where it is not
 };
 
+// M = S^{-1} H from the LU of S: the explicit form of Eq. INV, N right-hand sides
+struct RhsArgs {
+    int N;
+    Jobs jobs;
+    const double2* LU;      // [path][slot][N*N] column-major, P S = L U
+    const int* perm;        // [path][slot][N] row i of P S is row perm[i] of S
+    const double2* H;       // [path][slot][N*N] row-major
+    double2* M;             // [path][slot][N*N] row-major
+};
+
 struct Stage2CArgs {
     int N, n_pad, stage;
     double h;
     int slot;               // coupling slot used by this stage
     const int* paths;       // global index of each local path
     const double* vvec;
-    const double2* H;
+    const double2* H;       // H, or M = S^{-1} H when solve is 0
     const double2* LU;
-    const int* perm;
+    const int* perm;        // row order of the product (nullptr: identity)
+    int solve;              // 1: y = U^{-1} L^{-1} P (H u); 0: y = M u
     const double2* u_in;
     double2* Y;             // [n_traj][n_pad] P (H u) between the two kernels of a stage
     double2* X;
@@ -228,6 +239,7 @@ hipError_t launch_lu_update(const LUStepArgs& a, int n_jobs, hipStream_t st, con
 // skip[matrix] = (max |L21| <= 1 over the first nt columns); where set, also
 // perm = identity and piv[j] = j for j < nt
 hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_lu_rhs(const RhsArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,

@@ -136,6 +136,7 @@ struct Group2C {
     double *d_phiT_T = nullptr, *d_phiT_P = nullptr;
     int *d_radl_T = nullptr, *d_radl_P = nullptr;
     double2 *d_S = nullptr, *d_LU = nullptr, *d_H = nullptr;  // [path][slot][N*N]
+    double2* d_M = nullptr;  // [path][slot][N*N] S^{-1} H (explicit form only)
     int* d_piv = nullptr;                                      // [path][slot][N]
     int* d_perm = nullptr;                                     // [path][slot][N]
     int* d_skip = nullptr;                                     // [path][slot] no-pivot block form (k_lu_check)
@@ -154,6 +155,7 @@ struct Plan2C {
     std::vector<Group2C> groups;
     std::vector<int> group_of, local_of;
     int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0, mixed = 0;
+    int explicit_m = 0;  // M = S^{-1} H formed per coupling point (WPCCC_SOLVE_EXPLICIT)
     std::vector<double> b, v;
     double *d_b = nullptr, *d_v = nullptr;
     int* d_flag = nullptr;  // [0] non-finite amplitude, [1] singular path + 1, [2] its pivot row
@@ -185,7 +187,7 @@ void free_group(Group2C& g) {
     void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
                     g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_skip,   g.d_nodes,  g.d_jst,    g.d_nact,
                     g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP,
-                    g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT};
+                    g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT, g.d_M};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
 }
@@ -323,6 +325,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_S, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_LU, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_H, np * kSlots2C * NN, tot))) return rc;
+    if (p->explicit_m && (rc = dev_alloc(&g.d_M, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_piv, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_perm, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_skip, np * kSlots2C, tot))) return rc;
@@ -491,7 +494,16 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
     a.skip_mode = 1;
     if ((rc = panels(0, g.m.NT))) return rc;
     a.skip_mode = 0;
-    return panels(g.m.NT, g.m.N);
+    if ((rc = panels(g.m.NT, g.m.N))) return rc;
+    if (!p->explicit_m) return WPCCC_OK;
+    RhsArgs ra;
+    ra.N = g.m.N;
+    ra.jobs = J;
+    ra.LU = g.d_LU;
+    ra.perm = g.d_perm;
+    ra.H = g.d_H;
+    ra.M = g.d_M;
+    return timed(p, kLuRhs, [&](const LaunchEv& ev) { return launch_lu_rhs(ra, nj, st, ev); });
 }
 
 int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,
@@ -505,9 +517,10 @@ int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, do
     a.slot = slot;
     a.paths = g.d_paths + l0;
     a.vvec = p->d_v;
-    a.H = g.d_H + (size_t)l0 * kSlots2C * NN;
+    a.solve = !p->explicit_m;
+    a.H = (a.solve ? g.d_H : g.d_M) + (size_t)l0 * kSlots2C * NN;
     a.LU = g.d_LU + (size_t)l0 * kSlots2C * NN;
-    a.perm = g.d_perm + (size_t)l0 * kSlots2C * g.m.N;
+    a.perm = a.solve ? g.d_perm + (size_t)l0 * kSlots2C * g.m.N : nullptr;
     a.u_in = u_in;
     a.Y = p->d_Y;
     a.X = X;
@@ -598,6 +611,10 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
         set_error("wpccc_plan_create_2c: precision must be WPCCC_FP64 or WPCCC_MIXED");
         return WPCCC_EINVAL;
     }
+    if (o.solve != WPCCC_SOLVE_FACTORED && o.solve != WPCCC_SOLVE_EXPLICIT) {
+        set_error("wpccc_plan_create_2c: solve must be WPCCC_SOLVE_FACTORED or WPCCC_SOLVE_EXPLICIT");
+        return WPCCC_EINVAL;
+    }
     if (o.n_eta < 4 || o.n_eta > 1024 || o.n_tau < 4 || o.n_tau > 4096) {
         set_error("wpccc_plan_create_2c: n_eta must be in [4, 1024] and n_tau in [4, 4096]");
         return WPCCC_EINVAL;
@@ -643,6 +660,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     p->batched = o.batched ? 1 : 0;
     p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
     p->mixed = o.precision == WPCCC_MIXED;
+    p->explicit_m = o.solve == WPCCC_SOLVE_EXPLICIT;
     p->n_eta = o.n_eta;
     p->n_tau = o.n_tau;
     p->b.assign(b, b + n_traj);

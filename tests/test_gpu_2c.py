@@ -117,9 +117,9 @@ def _q_lower(name):
     return W.WPCCC_Q_PRIOR if name == Q_PRIOR else W.WPCCC_Q_DAGGER
 
 
-def _run_gpu(wl, lt, lp, batched=True, stepwise=False):
+def _run_gpu(wl, lt, lp, batched=True, stepwise=False, solve=W.WPCCC_SOLVE_FACTORED):
     plan = W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, n_eta=wl.n_eta, n_tau=wl.n_tau,
-                                  q_lower=_q_lower(wl.q_lower), batched=batched)
+                                  q_lower=_q_lower(wl.q_lower), batched=batched, solve=solve)
     X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
     X[:, 0] = 1.0
     P = torch.empty((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
@@ -137,10 +137,11 @@ def _run_gpu(wl, lt, lp, batched=True, stepwise=False):
     return X.cpu().numpy(), P.cpu().numpy(), nrm.cpu().numpy(), plan
 
 
-def test_2c_propagation_parity(small_run):
+@pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
+def test_2c_propagation_parity(small_run, solve):
     wl, lt, lp, ref = small_run
-    print(f"2C propagation: 3 paths, two basis pairs, 16 steps, {wl.q_lower} form", flush=True)
-    X, P, nrm, plan = _run_gpu(wl, lt, lp)
+    print(f"2C propagation: 3 paths, two basis pairs, 16 steps, {wl.q_lower} form, solve {solve}", flush=True)
+    X, P, nrm, plan = _run_gpu(wl, lt, lp, solve=solve)
     for j, (Xo, no) in enumerate(ref):
         N, NT = W.wpccc_plan_path_info(plan, j)
         assert N == Xo.size
@@ -177,14 +178,17 @@ def test_2c_couplings_errors(bases):
         W.wpccc_plan_path_info(plan, 1)
 
 
-def test_2c_propagation_multiblock(bases):
+@pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
+def test_2c_propagation_multiblock(bases, solve):
     """N = 146 (133 target + 13 projectile states): ten LU panels with a ragged
-    last one, three blocks of the triangular solves, several update tiles."""
+    last one, five blocks of the triangular solves (a ragged fifth: rows and
+    right-hand-side columns of the explicit form), several update tiles."""
     (lt, ot), (lp, op) = bases["wide"], bases["p0"]
     b, v, ne, nt = 1.3, 1.0, 32, 40
     zg = np.linspace(-2.0, 0.0, 5)
-    print("2C propagation: N=146, 4 steps", flush=True)
-    plan = W.wpccc_plan_create_2c([lt], [lp], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=ne, n_tau=nt)
+    print(f"2C propagation: N=146, 4 steps, solve {solve}", flush=True)
+    plan = W.wpccc_plan_create_2c([lt], [lp], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=ne, n_tau=nt,
+                                  solve=solve)
     N, NT = W.wpccc_plan_path_info(plan, 0)
     assert (N, NT) == (146, 133)
     X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
@@ -289,7 +293,8 @@ def test_2c_nonfinite_amplitude_latched(small_run):
     assert torch.isfinite(X[0]).all() and torch.isfinite(X[1]).all()
 
 
-def test_2c_lu_block_form_and_pivoting_fallback():
+@pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
+def test_2c_lu_block_form_and_pivoting_fallback(solve):
     """The LU of S takes the no-pivot block form for its first N_T columns only
     where every |K_ij| <= 1 (then partial pivoting would keep the diagonal
     pivots); with identical coarse-grid bases at b = 0.01 the interpolated
@@ -307,7 +312,8 @@ def test_2c_lu_block_form_and_pivoting_fallback():
         kmax = np.abs(S[:NT, NT:]).max()
         print(f"b={b}: max|K| {kmax:.3f}", flush=True)
         assert (kmax > 1.0) == (b < 0.1)
-        plan = W.wpccc_plan_create_2c([lb], [lb], [0], [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=32)
+        plan = W.wpccc_plan_create_2c([lb], [lb], [0], [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=32,
+                                      solve=solve)
         N = plan.n_states
         X0 = WL.random_state(1, N, seed=21)[0]
         X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
@@ -325,8 +331,9 @@ def test_2c_lu_block_form_and_pivoting_fallback():
         assert err <= bar
 
 
+@pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
 @pytest.mark.parametrize("l_max,N", [(4, 1360), (5, 1910)])
-def test_2c_paper_shape_step(l_max, N):
+def test_2c_paper_shape_step(l_max, N, solve):
     """The paper's two-centre basis shape, N_l = 30 - l radial functions per l
     on each centre (bound n <= 6 plus 24 bins per l), at l_max = 4 and 5
     (N = 1360 and 1910, the largest two-centre systems of the paper's
@@ -337,9 +344,10 @@ def test_2c_paper_shape_step(l_max, N):
     rec = WL.Recipe(6, l_max, 24, 3.0, 300, 60.0)
     lb, ob = lib_basis(rec), oracle_basis(rec)
     b, v, z, h = 3.0, 1.0, -0.4, 0.1
-    plan = W.wpccc_plan_create_2c([lb], [lb], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=16, n_tau=24)
+    plan = W.wpccc_plan_create_2c([lb], [lb], 0, [b], [v], q_lower=W.WPCCC_Q_PRIOR, n_eta=16, n_tau=24,
+                                  solve=solve)
     n, nt = W.wpccc_plan_path_info(plan, 0)
-    print(f"2C paper shape l_max = {l_max}: N = {n}", flush=True)
+    print(f"2C paper shape l_max = {l_max}: N = {n}, solve {solve}", flush=True)
     assert n == N and nt == N // 2
     x0 = WL.random_state(1, N, seed=31)[0]
     X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
@@ -351,3 +359,19 @@ def test_2c_paper_shape_step(l_max, N):
     err = np.abs(X.cpu().numpy()[0, :N] - xo).max()
     print(f"  max |dX| {err:.2e}", flush=True)
     assert err <= 1e-10
+
+
+def test_2c_explicit_matches_factored(small_run):
+    """The explicit form (M = S^-1 H per coupling point, products per stage)
+    against the factored form (triangular solves per stage) on the same
+    plan shape: the same arithmetic up to the order of the sums, so the
+    amplitudes agree to rounding; an unknown solve form is refused."""
+    wl, lt, lp, _ = small_run
+    Xf = _run_gpu(wl, lt, lp)[0]
+    Xe = _run_gpu(wl, lt, lp, solve=W.WPCCC_SOLVE_EXPLICIT)[0]
+    d = np.abs(Xe - Xf).max()
+    print(f"explicit vs factored: max|dX| {d:.2e}", flush=True)
+    assert d <= 1e-13 and not np.array_equal(Xe, Xf)
+    with pytest.raises(W.WpcccError) as e:
+        W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, solve=2)
+    assert e.value.code == -1
