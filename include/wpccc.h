@@ -150,7 +150,13 @@ typedef struct {
                        and has no adjoint. */
     int graph;      /* 1C, batched: replay each 64-step chunk of wpccc_propagate
                        from a captured HIP graph (step lengths and positions
-                       read from device memory); 0: launch kernel by kernel */
+                       read from device memory); 2C: replay each step of
+                       wpccc_propagate whose start point the plan already
+                       holds (every step after a run's first) from a graph
+                       captured per coupling slot, every group's launches in
+                       one graph.  Both capture again when X moves; results
+                       are bitwise those of launching kernel by kernel.
+                       0: launch kernel by kernel */
     int stage_launch; /* 1C: how wpccc_propagate runs the RK4 stages of each
                        64-step chunk outside graph replays:
                        WPCCC_LAUNCH_AUTO (default): the faster of the two

@@ -35,7 +35,7 @@ __device__ inline void job_of(const Jobs& J, int y, int& pl, int& slot, double& 
     pl = J.path0 + y / J.n_sub;
     const int sub = y % J.n_sub;
     slot = J.slot[sub];
-    z = J.z[sub];
+    z = J.zdev ? J.zdev[3 * (size_t)(*J.step) + sub] : J.z[sub];
 }
 
 // Lagrange weights at r for the nodes j0..j0+4 of r_i = rmax (i/nr)^2, j0 + 2
@@ -874,7 +874,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
         __syncthreads();
     }
     const double sc = 1.0 / a.vvec[j];
-    const double h = a.h;
+    const double h = a.hdev ? a.hdev[3 * (size_t)(*a.step) + 2] : a.h;
     for (int i = tid; i < N; i += blockDim.x) {
         const double2 yy = ys[i];
         const double2 K = make_double2(sc * yy.y, -sc * yy.x);  // -(i/v) y

@@ -78,6 +78,9 @@ struct Jobs {
     int n_sub;       // 1 or 2 coupling positions per path
     int slot[2];
     double z[2];
+    // graph replays: z[sub] = zdev[3 * *step + sub] instead (nullptr: z[])
+    const double* zdev;
+    const int* step;
 };
 
 struct NodeArgs {
@@ -217,6 +220,9 @@ struct Stage2CArgs {
     const double2* LU;
     const int* perm;        // row order of the product (nullptr: identity)
     int solve;              // 1: y = U^{-1} L^{-1} P (H u); 0: y = M u
+    // graph replays: h = hdev[3 * *step + 2] instead of h (nullptr: h)
+    const double* hdev;
+    const int* step;
     const double2* u_in;
     double2* Y;             // [n_traj][n_pad] P (H u) between the two kernels of a stage
     double2* X;

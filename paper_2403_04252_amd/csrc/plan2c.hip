@@ -171,6 +171,20 @@ struct Plan2C {
     std::vector<hipEvent_t> join_ev;
     double slot_z[kSlots2C];
     bool slot_ok[kSlots2C] = {false, false, false};
+    // graph replay of wpccc_propagate's steps (opts.graph): a step whose start
+    // point is already held replays the graph captured for that slot (the
+    // slots of z_mid and z_new follow from it); the step's z_mid, z_new and h
+    // come from d_zh[3 * *d_step + k], and the graph's last node advances
+    // *d_step.  A graph bakes in X and d_zh: either changing captures again.
+    bool use_graph = false, capturing = false;
+    hipGraphExec_t gexec[kSlots2C] = {nullptr, nullptr, nullptr};
+    double2* gX = nullptr;
+    hipStream_t gcap = nullptr;
+    double* d_zh = nullptr;
+    double* h_zh = nullptr;   // pinned staging of d_zh
+    int zh_cap = 0;           // steps d_zh holds
+    int* d_step = nullptr;
+    hipEvent_t zh_copied = nullptr;
 };
 
 namespace {
@@ -368,6 +382,10 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         J.slot[k] = slot[k];
         J.z[k] = z[k];
     }
+    if (p->capturing && n_sub == 2) {
+        J.zdev = p->d_zh;
+        J.step = p->d_step;
+    }
     const int nj = np * n_sub;
     int rc;
     for (int side = 0; side < 2; ++side) {
@@ -509,7 +527,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
 int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,
                   double2* X, double2* u_out, hipStream_t st) {
     const size_t NN = (size_t)g.m.N * g.m.N;
-    Stage2CArgs a;
+    Stage2CArgs a{};
     a.N = g.m.N;
     a.n_pad = p->n_pad;
     a.stage = stage;
@@ -527,6 +545,10 @@ int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, do
     a.Xacc = p->d_Xacc;
     a.u_out = u_out;
     a.flag = p->d_flag;
+    if (p->capturing) {
+        a.hdev = p->d_zh;
+        a.step = p->d_step;
+    }
     int rc = timed(p, k2cHu, [&](const LaunchEv& ev) { return launch_2c_hu(a, np, st, ev); });
     if (rc) return rc;
     return timed(p, k2cSolve, [&](const LaunchEv& ev) { return launch_2c_solve(a, np, st, ev); });
@@ -544,19 +566,40 @@ bool hits_origin(const Plan2C* p, double z) {
     return false;
 }
 
-// One RK4 step z -> z + h of every path.
-int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
-    const double zm = z + 0.5 * h, zn = z + h;
-    int s0 = find_slot(p, z);
-    const bool have0 = s0 >= 0;
-    if (!have0) s0 = 0;
-    int sm = -1, sn = -1;
-    for (int s = 0; s < kSlots2C; ++s) {
-        if (s == s0) continue;
-        if (sm < 0) sm = s;
-        else sn = s;
+// Coupling slots of one step z -> z + h: s0 holds z (have0: the couplings
+// there are already computed), sm and sn receive z + h/2 and z + h.
+struct StepSlots {
+    bool have0;
+    int s0, sm, sn;
+};
+
+StepSlots slots_with_start(int s0, bool have0) {
+    StepSlots s{have0, s0, -1, -1};
+    for (int k = 0; k < kSlots2C; ++k) {
+        if (k == s0) continue;
+        if (s.sm < 0) s.sm = k;
+        else s.sn = k;
     }
-    for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+    return s;
+}
+
+StepSlots step_slots(const Plan2C* p, double z) {
+    const int s0 = find_slot(p, z);
+    return s0 >= 0 ? slots_with_start(s0, true) : slots_with_start(0, false);
+}
+
+// every path keeps its own slots, so they hold these positions for all paths
+void commit_slots(Plan2C* p, const StepSlots& s, double z, double h) {
+    for (int k = 0; k < kSlots2C; ++k) p->slot_ok[k] = false;
+    p->slot_ok[s.s0] = p->slot_ok[s.sm] = p->slot_ok[s.sn] = true;
+    p->slot_z[s.s0] = z;
+    p->slot_z[s.sm] = z + 0.5 * h;
+    p->slot_z[s.sn] = z + h;
+}
+
+// The launches of one RK4 step of every path in the given slots.
+int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlots& ss, hipStream_t st) {
+    const double zm = z + 0.5 * h, zn = z + h;
     int rc;
     const bool fork = !p->gstreams.empty();
     if (fork) WPCCC_HIP_CHECK(hipEventRecord(p->fork_ev, st));
@@ -571,29 +614,163 @@ int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
         const int chunk = p->batched ? npath : 1;
         for (int l0 = 0; l0 < npath; l0 += chunk) {
             const int np = std::min(chunk, npath - l0);
-            if (!have0) {
-                const int sl[1] = {s0};
+            if (!ss.have0) {
+                const int sl[1] = {ss.s0};
                 const double zz[1] = {z};
                 if ((rc = enqueue_couplings(p, g, l0, np, 1, sl, zz, gs))) return rc;
             }
-            const int sl[2] = {sm, sn};
+            const int sl[2] = {ss.sm, ss.sn};
             const double zz[2] = {zm, zn};
             if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 1, s0, h, X, X, p->d_Ua, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 2, sm, h, p->d_Ua, X, p->d_Ub, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 3, sm, h, p->d_Ub, X, p->d_Ua, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 4, sn, h, p->d_Ua, X, nullptr, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 1, ss.s0, h, X, X, p->d_Ua, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 2, ss.sm, h, p->d_Ua, X, p->d_Ub, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 3, ss.sm, h, p->d_Ub, X, p->d_Ua, gs))) return rc;
+            if ((rc = enqueue_stage(p, g, l0, np, 4, ss.sn, h, p->d_Ua, X, nullptr, gs))) return rc;
         }
         if (fork) {
             WPCCC_HIP_CHECK(hipEventRecord(p->join_ev[gi], gs));
             WPCCC_HIP_CHECK(hipStreamWaitEvent(st, p->join_ev[gi], 0));
         }
     }
-    // every path keeps its own slots, so they hold these positions for all paths
-    p->slot_ok[s0] = p->slot_ok[sm] = p->slot_ok[sn] = true;
-    p->slot_z[s0] = z;
-    p->slot_z[sm] = zm;
-    p->slot_z[sn] = zn;
+    return WPCCC_OK;
+}
+
+// One RK4 step z -> z + h of every path.
+int enqueue_step(Plan2C* p, double2* X, double z, double h, hipStream_t st) {
+    const StepSlots ss = step_slots(p, z);
+    for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+    int rc;
+    if ((rc = enqueue_step_slots(p, X, z, h, ss, st))) return rc;
+    commit_slots(p, ss, z, h);
+    return WPCCC_OK;
+}
+
+void drop_graphs(Plan2C* p) {
+    for (int s = 0; s < kSlots2C; ++s) {
+        if (p->gexec[s]) (void)hipGraphExecDestroy(p->gexec[s]);
+        p->gexec[s] = nullptr;
+    }
+    p->gX = nullptr;
+}
+
+// Capture the step that starts in slot s0 (its couplings there held) into
+// gexec[s0]: positions and step length from d_zh at *d_step, which the
+// last node advances.  Nothing runs during the capture.
+int capture_step_graph(Plan2C* p, double2* X, int s0) {
+    if (!p->gcap) WPCCC_HIP_CHECK(hipStreamCreate(&p->gcap));
+    WPCCC_HIP_CHECK(hipStreamBeginCapture(p->gcap, hipStreamCaptureModeRelaxed));
+    const bool timing = p->timer->on;
+    p->timer->on = false;
+    p->capturing = true;
+    int rc = enqueue_step_slots(p, X, 0.0, 0.0, slots_with_start(s0, true), p->gcap);
+    if (rc == WPCCC_OK) rc = launched(launch_chunk_counter(p->d_step, 0, p->gcap), "k_chunk_counter");
+    p->capturing = false;
+    p->timer->on = timing;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gcap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return WPCCC_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&p->gexec[s0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        p->gexec[s0] = nullptr;
+        set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+        return WPCCC_EHIP;
+    }
+    return WPCCC_OK;
+}
+
+// Steps of zgrid by graph replays wherever the step's start point is held,
+// launch by launch elsewhere (the first step of a run): the same slots, the
+// same kernels on the same data as enqueue_step, hence the same amplitudes.
+int propagate_graph(Plan2C* p, const double* zgrid, int n_points, double2* X, hipStream_t st) {
+    const int n_steps = n_points - 1;
+    // which steps replay: the slot bookkeeping of the whole run, simulated
+    double sz[kSlots2C];
+    bool sok[kSlots2C];
+    std::copy(p->slot_z, p->slot_z + kSlots2C, sz);
+    std::copy(p->slot_ok, p->slot_ok + kSlots2C, sok);
+    std::vector<int> start(n_steps);
+    bool need[kSlots2C] = {false, false, false};
+    int n_rep = 0;
+    for (int i = 0; i < n_steps; ++i) {
+        const double z = zgrid[i], h = zgrid[i + 1] - zgrid[i];
+        const StepSlots ss = step_slots(p, z);
+        start[i] = ss.have0 ? ss.s0 : -1;
+        if (ss.have0) {
+            need[ss.s0] = true;
+            ++n_rep;
+        }
+        commit_slots(p, ss, z, h);
+    }
+    std::copy(sz, sz + kSlots2C, p->slot_z);
+    std::copy(sok, sok + kSlots2C, p->slot_ok);
+    if (n_rep > p->zh_cap) {
+        if (p->zh_copied) WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
+        WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+        drop_graphs(p);
+        if (p->h_zh) (void)hipHostFree(p->h_zh);
+        if (p->d_zh) (void)hipFree(p->d_zh);
+        p->h_zh = nullptr;
+        p->d_zh = nullptr;
+        p->zh_cap = 0;
+        WPCCC_HIP_CHECK(hipHostMalloc((void**)&p->h_zh, (size_t)3 * n_rep * sizeof(double), 0));
+        WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_zh, (size_t)3 * n_rep * sizeof(double)));
+        p->bytes += (long long)3 * n_rep * sizeof(double);
+        if (!p->d_step) {
+            WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_step, sizeof(int)));
+            p->bytes += sizeof(int);
+        }
+        if (!p->zh_copied) WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->zh_copied, hipEventDisableTiming));
+        p->zh_cap = n_rep;
+    }
+    int rc;
+    if (n_rep > 0) {
+        // the staging buffer may still feed the previous call's copy
+        WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
+        int r = 0;
+        for (int i = 0; i < n_steps; ++i) {
+            if (start[i] < 0) continue;
+            const double z = zgrid[i], h = zgrid[i + 1] - zgrid[i];
+            p->h_zh[3 * r] = z + 0.5 * h;
+            p->h_zh[3 * r + 1] = z + h;
+            p->h_zh[3 * r + 2] = h;
+            ++r;
+        }
+        WPCCC_HIP_CHECK(hipMemcpyAsync(p->d_zh, p->h_zh, (size_t)3 * n_rep * sizeof(double),
+                                       hipMemcpyHostToDevice, st));
+        WPCCC_HIP_CHECK(hipEventRecord(p->zh_copied, st));
+        if ((rc = launched(launch_chunk_counter(p->d_step, 1, st), "k_chunk_counter"))) return rc;
+        if (p->gX != X) drop_graphs(p);
+        bool fresh = false;
+        for (int s = 0; s < kSlots2C; ++s)
+            if (need[s] && !p->gexec[s]) {
+                if (!fresh) {
+                    // the group streams take part in the capture: let them drain first
+                    WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+                    fresh = true;
+                }
+                if ((rc = capture_step_graph(p, X, s))) return rc;
+            }
+        p->gX = X;
+    }
+    for (int i = 0; i < n_steps; ++i) {
+        const double z = zgrid[i], h = zgrid[i + 1] - zgrid[i];
+        if (start[i] < 0) {
+            if ((rc = enqueue_step(p, X, z, h, st))) return rc;
+            continue;
+        }
+        const StepSlots ss = slots_with_start(start[i], true);
+        for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
+        WPCCC_HIP_CHECK(hipGraphLaunch(p->gexec[start[i]], st));
+        commit_slots(p, ss, z, h);
+    }
     return WPCCC_OK;
 }
 
@@ -661,6 +838,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
     p->mixed = o.precision == WPCCC_MIXED;
     p->explicit_m = o.solve == WPCCC_SOLVE_EXPLICIT;
+    p->use_graph = o.graph != 0;
     p->n_eta = o.n_eta;
     p->n_tau = o.n_tau;
     p->b.assign(b, b + n_traj);
@@ -744,6 +922,15 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
 
 void plan2c_destroy(Plan2C* p) {
     if (!p) return;
+    if (p->zh_copied) {
+        (void)hipEventSynchronize(p->zh_copied);
+        (void)hipEventDestroy(p->zh_copied);
+    }
+    drop_graphs(p);
+    if (p->gcap) (void)hipStreamDestroy(p->gcap);
+    if (p->h_zh) (void)hipHostFree(p->h_zh);
+    if (p->d_zh) (void)hipFree(p->d_zh);
+    if (p->d_step) (void)hipFree(p->d_step);
     for (hipStream_t gs : p->gstreams) {
         (void)hipStreamSynchronize(gs);
         (void)hipStreamDestroy(gs);
@@ -838,8 +1025,12 @@ int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* Xv, voi
         }
     double2* X = (double2*)Xv;
     int rc;
-    for (int i = 0; i + 1 < n_points; ++i)
-        if ((rc = enqueue_step(p, X, zgrid[i], zgrid[i + 1] - zgrid[i], st))) return rc;
+    if (p->use_graph && !p->timer->on) {
+        if ((rc = propagate_graph(p, zgrid, n_points, X, st))) return rc;
+    } else {
+        for (int i = 0; i + 1 < n_points; ++i)
+            if ((rc = enqueue_step(p, X, zgrid[i], zgrid[i + 1] - zgrid[i], st))) return rc;
+    }
     if (!P && !norm) return WPCCC_OK;
     const double zl = zgrid[n_points - 1];
     for (Group2C& g : p->groups) {

@@ -375,3 +375,51 @@ def test_2c_explicit_matches_factored(small_run):
     with pytest.raises(W.WpcccError) as e:
         W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, solve=2)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
+def test_2c_graph_replay_bitwise(small_run, solve):
+    """Graph replay of the two-centre steps (one graph per slot of the step's
+    start point, both basis-pair groups with their forked streams inside it)
+    against launching kernel by kernel: bitwise equal amplitudes, norms and
+    probabilities over three calls on one plan with eager work in between
+    (a couplings evaluation, which moves the plan's slots, and a torch
+    reduction), on a grid whose steps are not all exactly representable
+    (some steps then start without a held point and run launch by launch),
+    and after X moves to another tensor (captured again)."""
+    wl, lt, lp, _ = small_run
+    ql = _q_lower(wl.q_lower)
+    # -1.9357... + (4.6346... - -1.9357...) rounds away from 4.6346...: the
+    # step from there starts without a held point
+    za, zb = -1.9357256578084852, 4.634624498830813
+    assert za + (zb - za) != zb
+    zg = np.concatenate([np.arange(-4.0, -2.0, 0.5), [za, zb], zb + np.cumsum(np.full(6, 0.5))])
+    mk = lambda g: W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, n_eta=wl.n_eta, n_tau=wl.n_tau,
+                                          q_lower=ql, solve=solve, graph=g)
+    eager, gp = mk(False), mk(True)
+
+    def run(plan, X):
+        X.zero_()
+        X[:, 0] = 1.0
+        P = torch.empty((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
+        nrm = torch.empty((plan.n_traj,), dtype=torch.float64, device="cuda")
+        W.wpccc_propagate(plan, zg, X, P, nrm)
+        W.wpccc_plan_status(plan)
+        torch.cuda.synchronize()
+        return X.cpu().numpy(), P.cpu().numpy(), nrm.cpu().numpy()
+
+    shape = (eager.n_traj, eager.n_pad)
+    ref = run(eager, torch.empty(shape, dtype=torch.complex128, device="cuda"))
+    Xg = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    for rep in range(3):
+        print(f"2C graph replay, solve {solve}, call {rep}", flush=True)
+        out = run(gp, Xg)
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), rep
+        N = W.wpccc_plan_path_info(gp, 0)[0]
+        H = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+        W.wpccc_couplings(gp, 0, 0.3, H, torch.empty_like(H))
+        assert float(torch.linalg.vector_norm(H).cpu()) > 0.0
+    out = run(gp, torch.empty(shape, dtype=torch.complex128, device="cuda"))
+    for a, b in zip(out, ref):
+        assert np.array_equal(a, b)
