@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--lmax", type=int, default=6, help="paper: l_max of the paper-shape basis (<= 7)")
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
+    ap.add_argument("--graph", action="store_true", help="c3: replay the steps from captured HIP graphs")
     ap.add_argument("--explicit-m", action="store_true",
                     help="c3: form M = S^-1 H per coupling point (the paper's form) instead of solving per stage")
     ap.add_argument("--no-2c", action="store_true",
@@ -700,24 +701,30 @@ def contract_flops(recT, recP, n_w, n_act):
 
 def bench_two_centre(args):
     """Batched two-centre propagation (Eq. 1 with capture) on one GPU: prints its own JSON line."""
-    out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed, explicit=args.explicit_m)
+    out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed, explicit=args.explicit_m,
+                             graph=args.graph)
     print(json.dumps(out), flush=True)
 
 
 def two_centre_pair(args, steps, warmup, z0=-1.0):
     """FP64 and mixed two-centre rates over `steps` steps of 0.1 from z0 (through
     closest approach by default), both from the same seeded random state, and
-    the mixed probabilities against the FP64 ones at the end of the stretch."""
-    r64 = two_centre_measure(args, steps, warmup, mixed=False, z0=z0)
-    rmx = two_centre_measure(args, steps, warmup, mixed=True, z0=z0)
-    rex = two_centre_measure(args, steps, warmup, mixed=False, z0=z0, explicit=True)
-    P64, Pmx, Pex = r64.pop("P_final"), rmx.pop("P_final"), rex.pop("P_final")
+    the mixed probabilities against the FP64 ones at the end of the stretch;
+    steps replayed from HIP graphs, beside the explicit-M form and FP64
+    launched kernel by kernel."""
+    r64 = two_centre_measure(args, steps, warmup, mixed=False, z0=z0, graph=True)
+    rmx = two_centre_measure(args, steps, warmup, mixed=True, z0=z0, graph=True)
+    rex = two_centre_measure(args, steps, warmup, mixed=False, z0=z0, explicit=True, graph=True)
+    rgr = two_centre_measure(args, steps, warmup, mixed=False, z0=z0, graph=False)
+    P64, Pmx, Pex, Pgr = r64.pop("P_final"), rmx.pop("P_final"), rex.pop("P_final"), rgr.pop("P_final")
     d = np.abs(Pmx - P64)
     keep = ("value", "unit", "ms_per_step", "roofline", "lu", "config", "kernel_times")
     out = {"fp64": {k: r64[k] for k in keep}, "mixed": {k: rmx[k] for k in keep},
            "fp64_explicit_m": {k: rex[k] for k in keep + ("rhs",)}}
     out["fp64_explicit_m"]["dtype"] = "f64"
     out["fp64_explicit_m"]["max_abs_dP_vs_factored"] = float(np.abs(Pex - P64).max())
+    out["fp64_no_graph"] = {k: rgr[k] for k in ("value", "unit", "ms_per_step")}
+    out["fp64_no_graph"]["bitwise_equal_to_graph"] = bool(np.array_equal(Pgr, P64))
     out["fp64"]["dtype"] = "f64"
     out["mixed"]["dtype"] = "f64 (contraction products f32)"
     out["mixed"]["prob_error_vs_fp64_gpu"] = {
@@ -728,7 +735,7 @@ def two_centre_pair(args, steps, warmup, z0=-1.0):
     return out
 
 
-def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False):
+def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False, graph=False):
     """Time `steps` RK4 steps of the batched two-centre workload; returns the
     result dict.  z0 None: the workload's grid from its start, amplitudes from
     e_0; else `steps` steps of 0.1 from z0 from a seeded random state (the
@@ -746,7 +753,8 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
     ql = W.WPCCC_Q_PRIOR if w.q_lower == "prior" else W.WPCCC_Q_DAGGER
     t0 = time.perf_counter()
     plan = W.wpccc_plan_create_2c(bases, bases, w.set_of, w.b, w.v, q_lower=ql, n_eta=w.n_eta, n_tau=w.n_tau,
-                                  mixed=mixed, solve=W.WPCCC_SOLVE_EXPLICIT if explicit else W.WPCCC_SOLVE_FACTORED)
+                                  mixed=mixed, solve=W.WPCCC_SOLVE_EXPLICIT if explicit else W.WPCCC_SOLVE_FACTORED,
+                                  graph=graph)
     setup_s = time.perf_counter() - t0
     n_traj = plan.n_traj
     X = torch.zeros((n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
@@ -761,7 +769,8 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
             N = W.wpccc_plan_path_info(plan, j)[0]
             X0[j, :N] = torch.from_numpy(WL.random_state(1, N, seed=100 + j)[0]).cuda()
     X.copy_(X0)
-    run_propagation(W, plan, X, zs, warmup)
+    # graph replay: three warm-up steps capture both graphs of the slot rotation
+    run_propagation(W, plan, X, zs, max(warmup, 3) if graph else warmup)
     torch.cuda.synchronize()
     X.copy_(X0)
     torch.cuda.synchronize()
@@ -836,7 +845,8 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
                                "4000-pt grid, 8 b log-spaced 0.2-10 per size, 256x512 nodes, "
                                f"z {zs[0]:.1f}..{zs[-1]:.1f} dz=0.1, lower-left block {w.q_lower}",
                    "form": ("batched mixed (FP32 contraction products)" if mixed else "batched FP64")
-                           + (", explicit M = S^-1 H" if explicit else ", per-stage triangular solves"),
+                           + (", explicit M = S^-1 H" if explicit else ", per-stage triangular solves")
+                           + (", graph replay" if graph else ""),
                    "n_paths": n_traj, "plan_setup_s": setup_s,
                    "parallelism": "1 GPU, paths batched per basis size"},
         "roofline": roof,
