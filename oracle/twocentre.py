@@ -251,3 +251,30 @@ def m_two_centre(tb: Basis, pb: Basis, b: float, v: float, n_eta: int, n_tau: in
         S, H = two_centre_matrices(tb, pb, b, z, v, n_eta, n_tau, q_lower)
         return (-1j / v) * np.linalg.solve(S, H)
     return M
+
+
+def symmetric_matrices(tb: Basis, pb: Basis, b: float, z: float, v: float, n_eta: int, n_tau: int,
+                       q_lower: str = Q_DAGGER, dz: float = 1e-4):
+    """S and the S-norm-conserving form of H at (b, z) (not in the paper; a
+    variant of Eq. 1): H~ = (H + H^dag)/2 - (i v / 2) dS/dz.
+
+    For i v S X' = H X the rate d(X^dag S X)/dz is X^dag [(i/v)(H^dag - H) +
+    dS/dz] X, so X^dag S X is constant exactly when H - H^dag = -i v dS/dz, a
+    relation the complete-basis matrices satisfy and the truncated ones do
+    not.  H~ keeps the Hermitian part of H and takes the anti-Hermitian part
+    the relation prescribes.  dS/dz is the central difference of the phased S
+    at z +- dz (only its K blocks vary)."""
+    S, H = two_centre_matrices(tb, pb, b, z, v, n_eta, n_tau, q_lower)
+    Sp, _ = two_centre_matrices(tb, pb, b, z + dz, v, n_eta, n_tau, q_lower)
+    Sm, _ = two_centre_matrices(tb, pb, b, z - dz, v, n_eta, n_tau, q_lower)
+    dS = (Sp - Sm) / (2.0 * dz)
+    return S, 0.5 * (H + H.conj().T) - 0.5j * v * dS
+
+
+def m_two_centre_symmetric(tb: Basis, pb: Basis, b: float, v: float, n_eta: int, n_tau: int,
+                           q_lower: str = Q_DAGGER, dz: float = 1e-4):
+    """z -> M(z) = -(i/v) S^{-1} H~ of the S-norm-conserving form (ZGESV)."""
+    def M(z: float) -> np.ndarray:
+        S, Hs = symmetric_matrices(tb, pb, b, z, v, n_eta, n_tau, q_lower, dz)
+        return (-1j / v) * np.linalg.solve(S, Hs)
+    return M

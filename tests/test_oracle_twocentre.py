@@ -19,8 +19,8 @@ from scipy.special import roots_laguerre, sph_harm_y
 from oracle.propagate import initial_state, rk4_propagate
 from oracle.radial import BasisSpec, build_basis
 from oracle.twocentre import (Q_DAGGER, Q_PRIOR, gauss_legendre, interpolate_radial, lab_matrix,
-                              laguerre_scaled_weights, m_two_centre, spheroidal_quadrature,
-                              two_centre_matrices)
+                              laguerre_scaled_weights, m_two_centre, m_two_centre_symmetric,
+                              spheroidal_quadrature, symmetric_matrices, two_centre_matrices)
 
 
 @pytest.fixture(scope="module")
@@ -223,3 +223,50 @@ def test_dagger_form_balance_law(bound2):
         gaps.append(abs(change - integral))
         assert abs(change) > 1e-3
     assert gaps[1] < 2e-7 and gaps[0] > 10 * gaps[1], gaps
+
+
+def test_symmetric_form_conserves_norm(bound2):
+    """The S-norm-conserving form built from the printed Q^dagger block (which
+    itself changes X^dag S X by ~1e-3 over this path, above): X^dag S X stays
+    at 1 up to RK4's error, which falls by more than 10x when h halves, and
+    the central difference of S.  A sign or factor slip in the -(i v/2) dS/dz
+    term, or dS/dz transposed, leaves a drift of the dagger form's size."""
+    b = bound2
+    n2 = 2 * b.n_states
+    M = m_two_centre_symmetric(b, b, 1.5, 1.0, 24, 32, q_lower=Q_DAGGER)
+    drift = []
+    for h in (0.1, 0.05):
+        zg = np.linspace(-3.0, 3.0, int(round(6.0 / h)) + 1)
+        S0, _ = two_centre_matrices(b, b, 1.5, zg[0], 1.0, 24, 32)
+        X0 = initial_state(n2) / math.sqrt((S0[0, 0]).real)
+        X = rk4_propagate(M, X0, zg)
+        S1, _ = two_centre_matrices(b, b, 1.5, zg[-1], 1.0, 24, 32)
+        drift.append(abs((X.conj() @ S1 @ X).real - (X0.conj() @ S0 @ X0).real))
+    assert drift[1] < 1e-8 and drift[0] > 10 * drift[1], drift
+
+
+@pytest.mark.parametrize("z", [-1.1, 0.4])
+def test_symmetric_form_reproduces_prior_form_on_eigenstates(bound2, z):
+    """On exact eigenstates the prior and post transfer blocks differ by the
+    overlap's derivative, Q - L^dag = -i v dK/dz, so the prior form already
+    has the anti-Hermitian part the symmetric form imposes: H~ built from the
+    prior form is the prior H itself, while H~ built from the dagger form
+    differs from that H by (v/2)|dK/dz|.  The bound states on the fine grid
+    are eigenstates to ~1e-6 (hence the bar)."""
+    b = bound2
+    v = 1.0
+    S, Hp = two_centre_matrices(b, b, 1.5, z, v, 24, 32, q_lower=Q_PRIOR)
+    _, Hs_prior = symmetric_matrices(b, b, 1.5, z, v, 24, 32, q_lower=Q_PRIOR)
+    _, Hs_dag = symmetric_matrices(b, b, 1.5, z, v, 24, 32, q_lower=Q_DAGGER)
+    _, Hd = two_centre_matrices(b, b, 1.5, z, v, 24, 32, q_lower=Q_DAGGER)
+    scale = np.abs(Hp).max()
+    assert np.abs(Hs_prior - Hp).max() <= 1e-5 * scale
+    # the dagger form's H~ has the same anti-Hermitian part ...
+    assert np.abs((Hs_dag - Hs_dag.conj().T) - (Hp - Hp.conj().T)).max() <= 1e-5 * scale
+    # ... and is not the dagger H: their difference is the K-block term
+    n = b.n_states
+    Sp, _ = two_centre_matrices(b, b, 1.5, z + 1e-3, v, 24, 32)
+    Sm, _ = two_centre_matrices(b, b, 1.5, z - 1e-3, v, 24, 32)
+    dK = (Sp - Sm)[:n, n:] / 2e-3
+    assert np.abs((Hs_dag - Hd)[:n, n:] + 0.5j * v * dK).max() <= 1e-6 * scale
+    assert np.abs(dK).max() > 1e-2
