@@ -191,6 +191,17 @@ typedef struct {
                        product M u.  The same FP64 arithmetic up to the order
                        of the sums; the explicit form holds one more N x N
                        matrix per path and slot.  1C: must be 0. */
+    int symmetric;  /* 2C: 1 replaces H by its S-norm-conserving form (not in the
+                       paper; a variant of Eq. 1): H~ = (H + H^dag)/2 -
+                       (i v / 2) dS/dz, which satisfies H~ - H~^dag = -i v dS/dz
+                       so that X^dag S X is constant along the path.  dS/dz is
+                       the central difference of S at z +- dz_sym, i.e. S at two
+                       more positions per coupling point (three times the
+                       coupling work).  FP64 and kernel-by-kernel only
+                       (WPCCC_ENOTSUP with WPCCC_MIXED or graph).
+                       wpccc_couplings returns H~.  1C: must be 0. */
+    double dz_sym;  /* 2C symmetric: difference step in z (a.u.), 0 means 1e-4;
+                       at most 0.01 */
 } wpccc_plan_opts;
 
 #define WPCCC_SOLVE_FACTORED 0

@@ -63,7 +63,8 @@ class _PlanOpts(ctypes.Structure):
                 ("model_a", ctypes.c_double), ("model_c", ctypes.c_double),
                 ("checkpoint_every", ctypes.c_int), ("stage_rows", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph", ctypes.c_int), ("stage_launch", ctypes.c_int),
-                ("radial", ctypes.c_int), ("stage_cache", ctypes.c_int), ("solve", ctypes.c_int)]
+                ("radial", ctypes.c_int), ("stage_cache", ctypes.c_int), ("solve", ctypes.c_int),
+                ("symmetric", ctypes.c_int), ("dz_sym", ctypes.c_double)]
 
 
 @dataclass
@@ -272,11 +273,13 @@ def wpccc_plan_stage_cache(plan: Plan) -> bool:
 
 def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int = WPCCC_Q_DAGGER,
                          n_eta: int = 0, n_tau: int = 0, batched: bool = True, mixed: bool = False,
-                         solve: int = WPCCC_SOLVE_FACTORED, graph: bool = False, stream=None) -> Plan:
+                         solve: int = WPCCC_SOLVE_FACTORED, graph: bool = False, symmetric: bool = False,
+                         dz_sym: float = 0.0, stream=None) -> Plan:
     """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j].
     solve: WPCCC_SOLVE_FACTORED (triangular solves per stage) or WPCCC_SOLVE_EXPLICIT
     (M = S^-1 H per coupling point, the paper's form); graph: replay wpccc_propagate's
-    steps from captured HIP graphs."""
+    steps from captured HIP graphs; symmetric: the S-norm-conserving form of H with dS/dz
+    by central differences of step dz_sym (0: 1e-4)."""
     lib = load_library()
     b = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float64)
     v = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(v), b.shape), dtype=np.float64)
@@ -287,7 +290,8 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
     opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
-                     WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, 0, 0, 0, int(solve))
+                     WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, 0, 0, 0, int(solve),
+                     1 if symmetric else 0, float(dz_sym))
     h = ctypes.c_void_p()
     dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     _check(lib.wpccc_plan_create_2c(T, P, ns, int(b.size), sets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

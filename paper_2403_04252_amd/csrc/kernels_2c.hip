@@ -929,6 +929,45 @@ __global__ __launch_bounds__(256) void k_2c_finish(const double2* __restrict__ X
     if (threadIdx.x == 0 && norm) norm[j] = red[0];
 }
 
+// dK[r][c] = (S_+[r][N_T + c] - S_-[r][N_T + c]) / (2 dz): the K block of the
+// central difference of S (its identity blocks do not vary)
+__global__ __launch_bounds__(256) void k_2c_dk(SymArgs a) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.NT * a.NP) return;
+    const int pl = a.path0 + blockIdx.y, r = e / a.NP, c = e % a.NP;
+    const size_t NN = (size_t)a.N * a.N, at = r + (size_t)(a.NT + c) * a.N;
+    const double2 sp = a.S[((size_t)pl * kSlots2C + a.slot_p) * NN + at];
+    const double2 sm = a.S[((size_t)pl * kSlots2C + a.slot_m) * NN + at];
+    a.dK[((size_t)pl * 2 + a.which) * a.NT * a.NP + e] =
+        make_double2((sp.x - sm.x) * a.inv_2dz, (sp.y - sm.y) * a.inv_2dz);
+}
+
+// H <- (H + H^dag)/2 - (i v / 2) dS/dz in place, dS/dz = [[0, dK], [dK^dag, 0]]:
+// each thread owns one unordered pair (r, c), r <= c, and writes both
+// elements.  Grid x: 16 x 16 blocks of the upper triangle (lower blocks
+// exit), y: paths.
+__global__ __launch_bounds__(256) void k_2c_symm(SymArgs a) {
+    const int nb = (a.N + 15) / 16;
+    const int br = blockIdx.x / nb, bc = blockIdx.x % nb;
+    if (br > bc) return;
+    const int r = br * 16 + (threadIdx.x >> 4), c = bc * 16 + (threadIdx.x & 15);
+    if (r > c || c >= a.N) return;
+    const int pl = a.path0 + blockIdx.y;
+    const double hv = 0.5 * a.vvec[a.paths[pl]];
+    double2* H = a.H + ((size_t)pl * kSlots2C + a.slot) * (size_t)a.N * a.N;
+    const double2 hrc = H[(size_t)r * a.N + c], hcr = H[(size_t)c * a.N + r];
+    double2 d = make_double2(0.0, 0.0);  // dS/dz at (r, c)
+    if (r < a.NT && c >= a.NT) d = a.dK[((size_t)pl * 2 + a.which) * a.NT * a.NP + (size_t)r * a.NP + (c - a.NT)];
+    // (H + H^dag)/2 at (r, c) and (c, r); -(i v/2) d = (v/2) (d.y, -d.x); at (c, r) d -> conj(d)
+    const double2 m = make_double2(0.5 * (hrc.x + hcr.x), 0.5 * (hrc.y - hcr.y));
+    if (r == c) {
+        H[(size_t)r * a.N + c] = make_double2(m.x, 0.0);
+        return;
+    }
+    H[(size_t)r * a.N + c] = make_double2(m.x + hv * d.y, m.y - hv * d.x);
+    H[(size_t)c * a.N + r] = make_double2(m.x - hv * d.y, -m.y - hv * d.x);
+}
+
 __global__ void k_transpose_copy(const double2* __restrict__ src, double2* __restrict__ dst, int N) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -1078,6 +1117,17 @@ hipError_t measure_mfma(double* tf64, double* tf32, hipStream_t st) {
     if (e1) (void)hipEventDestroy(e1);
     if (out) (void)hipFree(out);
     return e;
+}
+
+hipError_t launch_2c_dk(const SymArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
+    WPCCC_LAUNCH(ev, k_2c_dk, dim3((a.NT * a.NP + 255) / 256, n_paths), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_2c_symm(const SymArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
+    const int nb = (a.N + 15) / 16;
+    WPCCC_LAUNCH(ev, k_2c_symm, dim3(nb * nb, n_paths), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace wpccc

@@ -284,7 +284,7 @@ struct LaunchEv {
 enum KernelId {
     kStage = 0, kSetup, kDense, kProb, kMoments, kPrologue,
     k2cNodes, k2cInterp, k2cContract, k2cAssemble, k2cSetup, k2cDirect, kLuPanel, kLuSwap, kLuUpdate, k2cHu, k2cSolve, k2cFinish,
-    kChunk, k2cReduce, kFpoint, kChannels, kLuCheck, kLuRhs, kNumKernels
+    kChunk, k2cReduce, kFpoint, kChannels, kLuCheck, kLuRhs, k2cDk, k2cSymm, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 

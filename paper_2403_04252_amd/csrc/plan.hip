@@ -734,8 +734,8 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: the persistent stage kernel has no reduced-precision form");
         return WPCCC_ENOTSUP;
     }
-    if (o.solve != 0) {
-        set_error("wpccc_plan_create: solve is a two-centre option (the one-centre form has S = I)");
+    if (o.solve != 0 || o.symmetric != 0) {
+        set_error("wpccc_plan_create: solve and symmetric are two-centre options (the one-centre form has S = I)");
         return WPCCC_EINVAL;
     }
     if (o.radial != WPCCC_RADIAL_EXACT && o.radial != WPCCC_RADIAL_INTERP) {
@@ -1443,7 +1443,8 @@ const char* const kKernelNames[kNumKernels] = {
     "k_stage",        "k_slot_setup",  "k_couplings_dense", "k_probabilities", "k_moments",    "k_prologue",
     "k_2c_nodes",     "k_2c_interp",   "k_2c_contract", "k_2c_assemble",     "k_setup_batch",   "k_2c_direct",  "k_lu_panel",
     "k_lu_swap_trsm", "k_lu_update",   "k_2c_hu",           "k_2c_solve",      "k_2c_finish",  "k_chunk",
-    "k_2c_reduce",    "k_fpoint",      "k_channels",    "k_lu_check",        "k_lu_rhs"};
+    "k_2c_reduce",    "k_fpoint",      "k_channels",    "k_lu_check",        "k_lu_rhs",
+    "k_2c_dk",        "k_2c_symm"};
 
 LaunchEv KernelTimer::open(int kernel) {
     LaunchEv ev;

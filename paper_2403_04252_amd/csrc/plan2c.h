@@ -140,6 +140,22 @@ struct AssembleArgs {
     double2* H;             // [path][slot][N*N] row-major
 };
 
+// S-norm-conserving form: dK = (K(z + dz) - K(z - dz)) / (2 dz) from two
+// slots of S, then H <- (H + H^dag)/2 - (i v / 2) dS/dz in place
+struct SymArgs {
+    int N, NT, NP;
+    int path0;              // first local path of the launch (grid y: paths)
+    const int* paths;
+    const double* vvec;
+    double2* S;             // [path][slot][N*N] column-major
+    double2* H;             // [path][slot][N*N] row-major
+    double2* dK;            // [path][2][NT*NP] row-major
+    int slot_p, slot_m;     // k_2c_dk: slots holding S at z + dz and z - dz
+    int slot;               // k_2c_symm: slot whose H is replaced
+    int which;              // dK buffer written / read
+    double inv_2dz;
+};
+
 struct SetupBatchArgs {     // Frow, G, phases of one centre for the jobs of a launch
     const Meta* meta;
     Tables tb;
@@ -251,5 +267,7 @@ hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, co
 hipError_t launch_2c_finish(const double2* X, const double2* S, int N, int n_pad, const int* paths, int n_paths,
                             int slot, double* P, double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 hipError_t launch_transpose_copy(const double2* src_colmajor, double2* dst_rowmajor, int N, hipStream_t st);
+hipError_t launch_2c_dk(const SymArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
+hipError_t launch_2c_symm(const SymArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 
 }  // namespace wpccc

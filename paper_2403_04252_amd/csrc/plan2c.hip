@@ -137,6 +137,7 @@ struct Group2C {
     int *d_radl_T = nullptr, *d_radl_P = nullptr;
     double2 *d_S = nullptr, *d_LU = nullptr, *d_H = nullptr;  // [path][slot][N*N]
     double2* d_M = nullptr;  // [path][slot][N*N] S^{-1} H (explicit form only)
+    double2* d_dK = nullptr; // [path][2][NT*NP] dK/dz (symmetric form only)
     int* d_piv = nullptr;                                      // [path][slot][N]
     int* d_perm = nullptr;                                     // [path][slot][N]
     int* d_skip = nullptr;                                     // [path][slot] no-pivot block form (k_lu_check)
@@ -156,6 +157,8 @@ struct Plan2C {
     std::vector<int> group_of, local_of;
     int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0, mixed = 0;
     int explicit_m = 0;  // M = S^{-1} H formed per coupling point (WPCCC_SOLVE_EXPLICIT)
+    int symmetric = 0;   // S-norm-conserving form of H (opts.symmetric)
+    double dz_sym = 1e-4;
     std::vector<double> b, v;
     double *d_b = nullptr, *d_v = nullptr;
     int* d_flag = nullptr;  // [0] non-finite amplitude, [1] singular path + 1, [2] its pivot row
@@ -201,7 +204,7 @@ void free_group(Group2C& g) {
     void* bufs[] = {g.d_m,    g.d_paths, g.d_tiles, g.d_phiT_T, g.d_phiT_P, g.d_radl_T, g.d_radl_P,
                     g.d_S,    g.d_LU,    g.d_H,     g.d_piv,    g.d_perm,   g.d_skip,   g.d_nodes,  g.d_jst,    g.d_nact,
                     g.d_tmol, g.d_FrowT, g.d_GT,    g.d_FrowP,  g.d_GP,     g.d_PHT,    g.d_PHP,
-                    g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT, g.d_M};
+                    g.d_rinfoT, g.d_rinfoP, g.d_AT, g.d_BT, g.d_M, g.d_dK};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
 }
@@ -340,6 +343,7 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     if ((rc = dev_alloc(&g.d_LU, np * kSlots2C * NN, tot))) return rc;
     if ((rc = dev_alloc(&g.d_H, np * kSlots2C * NN, tot))) return rc;
     if (p->explicit_m && (rc = dev_alloc(&g.d_M, np * kSlots2C * NN, tot))) return rc;
+    if (p->symmetric && (rc = dev_alloc(&g.d_dK, np * 2 * (size_t)m.NT * m.NP, tot))) return rc;
     if ((rc = dev_alloc(&g.d_piv, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_perm, np * kSlots2C * m.N, tot))) return rc;
     if ((rc = dev_alloc(&g.d_skip, np * kSlots2C, tot))) return rc;
@@ -373,8 +377,12 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
 
 // Couplings of local paths [l0, l0 + np) of group g at n_sub positions
 // (slot[k], z[k]): D_T and D_P, K and Q (and the prior block), then LU of S.
+int enqueue_rhs(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const int* slot, hipStream_t st);
+
+// factor: also the LU of S (and, in the explicit form outside the symmetric
+// one, M = S^{-1} H); false for the positions that only feed dS/dz
 int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const int* slot, const double* z,
-                      hipStream_t st) {
+                      hipStream_t st, bool factor = true) {
     Jobs J{};
     J.path0 = l0;
     J.n_sub = n_sub;
@@ -480,6 +488,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
         a.H = g.d_H;
         if ((rc = timed(p, k2cAssemble, [&](const LaunchEv& ev) { return launch_2c_assemble(a, g.m, nj, st, ev); }))) return rc;
     }
+    if (!factor) return WPCCC_OK;
     // LU of S with partial pivoting: the first N_T columns by the no-pivot
     // block form where k_lu_check allows it (see LUStepArgs), else by panels
     LUStepArgs a{};
@@ -513,15 +522,60 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
     if ((rc = panels(0, g.m.NT))) return rc;
     a.skip_mode = 0;
     if ((rc = panels(g.m.NT, g.m.N))) return rc;
+    // the symmetric form replaces H first (enqueue_symm) and forms M after it
+    return p->symmetric ? WPCCC_OK : enqueue_rhs(p, g, l0, np, n_sub, slot, st);
+}
+
+// M = S^{-1} H at the given slots (explicit form; nothing otherwise)
+int enqueue_rhs(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const int* slot, hipStream_t st) {
     if (!p->explicit_m) return WPCCC_OK;
-    RhsArgs ra;
+    RhsArgs ra{};
     ra.N = g.m.N;
-    ra.jobs = J;
+    ra.jobs.path0 = l0;
+    ra.jobs.n_sub = n_sub;
+    for (int k = 0; k < n_sub; ++k) ra.jobs.slot[k] = slot[k];
     ra.LU = g.d_LU;
     ra.perm = g.d_perm;
     ra.H = g.d_H;
     ra.M = g.d_M;
-    return timed(p, kLuRhs, [&](const LaunchEv& ev) { return launch_lu_rhs(ra, nj, st, ev); });
+    return timed(p, kLuRhs, [&](const LaunchEv& ev) { return launch_lu_rhs(ra, np * n_sub, st, ev); });
+}
+
+SymArgs sym_args(const Plan2C* p, Group2C& g, int l0) {
+    SymArgs a{};
+    a.N = g.m.N;
+    a.NT = g.m.NT;
+    a.NP = g.m.NP;
+    a.path0 = l0;
+    a.paths = g.d_paths;
+    a.vvec = p->d_v;
+    a.S = g.d_S;
+    a.H = g.d_H;
+    a.dK = g.d_dK;
+    a.inv_2dz = 0.5 / p->dz_sym;
+    return a;
+}
+
+// dK/dz at zp into dK buffer `which`: S at zp + dz and zp - dz computed into
+// slots sa and sb (whose contents are given up)
+int enqueue_dk(Plan2C* p, Group2C& g, int l0, int np, double zp, int sa, int sb, int which, hipStream_t st) {
+    const int sl[2] = {sa, sb};
+    const double zz[2] = {zp + p->dz_sym, zp - p->dz_sym};
+    int rc;
+    if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, st, false))) return rc;
+    SymArgs a = sym_args(p, g, l0);
+    a.slot_p = sa;
+    a.slot_m = sb;
+    a.which = which;
+    return timed(p, k2cDk, [&](const LaunchEv& ev) { return launch_2c_dk(a, np, st, ev); });
+}
+
+// H at slot <- its S-norm-conserving form with dK buffer `which`
+int enqueue_symm(Plan2C* p, Group2C& g, int l0, int np, int slot, int which, hipStream_t st) {
+    SymArgs a = sym_args(p, g, l0);
+    a.slot = slot;
+    a.which = which;
+    return timed(p, k2cSymm, [&](const LaunchEv& ev) { return launch_2c_symm(a, np, st, ev); });
 }
 
 int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,
@@ -617,11 +671,22 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
             if (!ss.have0) {
                 const int sl[1] = {ss.s0};
                 const double zz[1] = {z};
+                if (p->symmetric && (rc = enqueue_dk(p, g, l0, np, z, ss.sm, ss.sn, 0, gs))) return rc;
                 if ((rc = enqueue_couplings(p, g, l0, np, 1, sl, zz, gs))) return rc;
+                if (p->symmetric && ((rc = enqueue_symm(p, g, l0, np, ss.s0, 0, gs)) ||
+                                     (rc = enqueue_rhs(p, g, l0, np, 1, sl, gs))))
+                    return rc;
             }
             const int sl[2] = {ss.sm, ss.sn};
             const double zz[2] = {zm, zn};
+            if (p->symmetric && ((rc = enqueue_dk(p, g, l0, np, zm, ss.sm, ss.sn, 0, gs)) ||
+                                 (rc = enqueue_dk(p, g, l0, np, zn, ss.sm, ss.sn, 1, gs))))
+                return rc;
             if ((rc = enqueue_couplings(p, g, l0, np, 2, sl, zz, gs))) return rc;
+            if (p->symmetric && ((rc = enqueue_symm(p, g, l0, np, ss.sm, 0, gs)) ||
+                                 (rc = enqueue_symm(p, g, l0, np, ss.sn, 1, gs)) ||
+                                 (rc = enqueue_rhs(p, g, l0, np, 2, sl, gs))))
+                return rc;
             if ((rc = enqueue_stage(p, g, l0, np, 1, ss.s0, h, X, X, p->d_Ua, gs))) return rc;
             if ((rc = enqueue_stage(p, g, l0, np, 2, ss.sm, h, p->d_Ua, X, p->d_Ub, gs))) return rc;
             if ((rc = enqueue_stage(p, g, l0, np, 3, ss.sm, h, p->d_Ub, X, p->d_Ua, gs))) return rc;
@@ -788,6 +853,18 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
         set_error("wpccc_plan_create_2c: precision must be WPCCC_FP64 or WPCCC_MIXED");
         return WPCCC_EINVAL;
     }
+    if (o.symmetric != 0 && o.symmetric != 1) {
+        set_error("wpccc_plan_create_2c: symmetric must be 0 or 1");
+        return WPCCC_EINVAL;
+    }
+    if (o.symmetric && !(o.dz_sym == 0.0 || (o.dz_sym > 0.0 && o.dz_sym <= 0.01))) {
+        set_error("wpccc_plan_create_2c: dz_sym must be 0 (1e-4) or in (0, 0.01]");
+        return WPCCC_EINVAL;
+    }
+    if (o.symmetric && (o.precision == WPCCC_MIXED || o.graph)) {
+        set_error("wpccc_plan_create_2c: the symmetric form is FP64 and launched kernel by kernel");
+        return WPCCC_ENOTSUP;
+    }
     if (o.solve != WPCCC_SOLVE_FACTORED && o.solve != WPCCC_SOLVE_EXPLICIT) {
         set_error("wpccc_plan_create_2c: solve must be WPCCC_SOLVE_FACTORED or WPCCC_SOLVE_EXPLICIT");
         return WPCCC_EINVAL;
@@ -839,6 +916,8 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     p->mixed = o.precision == WPCCC_MIXED;
     p->explicit_m = o.solve == WPCCC_SOLVE_EXPLICIT;
     p->use_graph = o.graph != 0;
+    p->symmetric = o.symmetric != 0;
+    if (o.dz_sym != 0.0) p->dz_sym = o.dz_sym;
     p->n_eta = o.n_eta;
     p->n_tau = o.n_tau;
     p->b.assign(b, b + n_traj);
@@ -1001,8 +1080,10 @@ int plan2c_couplings(Plan2C* p, int j, double z, void* H, void* S, hipStream_t s
     for (int s = 0; s < kSlots2C; ++s) p->slot_ok[s] = false;
     const int sl[1] = {0};
     const double zz[1] = {z};
-    int rc = enqueue_couplings(p, g, l, 1, 1, sl, zz, st);
-    if (rc) return rc;
+    int rc;
+    if (p->symmetric && (rc = enqueue_dk(p, g, l, 1, z, 1, 2, 0, st))) return rc;
+    if ((rc = enqueue_couplings(p, g, l, 1, 1, sl, zz, st))) return rc;
+    if (p->symmetric && (rc = enqueue_symm(p, g, l, 1, 0, 0, st))) return rc;
     const size_t NN = (size_t)g.m.N * g.m.N;
     const size_t off = (size_t)l * kSlots2C * NN;
     WPCCC_HIP_CHECK(hipMemcpyAsync(H, g.d_H + off, NN * sizeof(double2), hipMemcpyDeviceToDevice, st));
@@ -1044,7 +1125,7 @@ int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* Xv, voi
             const double zz[1] = {zl};
             const int chunk = std::max(1, g.max_jobs);
             for (int l0 = 0; l0 < npath; l0 += chunk)
-                if ((rc = enqueue_couplings(p, g, l0, std::min(chunk, npath - l0), 1, sl, zz, st))) return rc;
+                if ((rc = enqueue_couplings(p, g, l0, std::min(chunk, npath - l0), 1, sl, zz, st, false))) return rc;
         }
         if ((rc = timed(p, k2cFinish, [&](const LaunchEv& ev) {
                  return launch_2c_finish(X, g.d_S, g.m.N, p->n_pad, g.d_paths, npath, slot, (double*)P,

@@ -21,7 +21,8 @@ import paper_2403_04252_amd as W
 from paper_2403_04252_amd import workloads as WL
 from oracle.propagate import initial_state, rk4_propagate
 from oracle.radial import BasisSpec as OSpec, build_basis
-from oracle.twocentre import Q_DAGGER, Q_PRIOR, m_two_centre, two_centre_matrices
+from oracle.twocentre import (Q_DAGGER, Q_PRIOR, m_two_centre, m_two_centre_symmetric, symmetric_matrices,
+                              two_centre_matrices)
 
 pytestmark = pytest.mark.gpu
 
@@ -423,3 +424,86 @@ def test_2c_graph_replay_bitwise(small_run, solve):
     out = run(gp, torch.empty(shape, dtype=torch.complex128, device="cuda"))
     for a, b in zip(out, ref):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", [0, 2, 3])
+def test_2c_symmetric_couplings_parity(case, bases):
+    """H~ = (H + H^dag)/2 - (i v/2) dS/dz of the S-norm-conserving form against
+    the oracle's, dS/dz by the central difference at z +- 1e-4 on both sides.
+    S agrees to ~1e-14 of max|S|; the difference quotient divides those
+    discrepancies by 2e-4, so H~ is held to 1e-8 max|H~| (S to 1e-11)."""
+    tk, pk, ql, ne, nt, pts = CASES[case]
+    (lt, ot), (lp, op) = bases[tk], bases[pk]
+    b = np.array([p[0] for p in pts])
+    v = np.array([p[2] for p in pts])
+    plan = W.wpccc_plan_create_2c([lt], [lp], 0, b, v, q_lower=_q_lower(ql), n_eta=ne, n_tau=nt,
+                                  symmetric=True)
+    for j, (bb, z, vv) in enumerate(pts):
+        print(f"2C symmetric couplings case {case} b={bb} z={z} v={vv}", flush=True)
+        Sg, Hg = gpu_matrices(plan, j, z)
+        So, Ho = symmetric_matrices(ot, op, bb, z, vv, ne, nt, q_lower=ql)
+        _, Hplain = two_centre_matrices(ot, op, bb, z, vv, ne, nt, q_lower=ql)
+        eS = np.abs(Sg - So).max() / np.abs(So).max()
+        eH = np.abs(Hg - Ho).max() / np.abs(Ho).max()
+        moved = np.abs(Ho - Hplain).max() / np.abs(Ho).max()
+        print(f"  rel err S {eS:.2e}  H~ {eH:.2e} (H~ - H: {moved:.2e})", flush=True)
+        assert eS <= 1e-11 and eH <= 1e-8, (eS, eH)
+        assert moved > 1e-4
+    W.wpccc_plan_status(plan)
+
+
+def test_2c_symmetric_propagation_parity(bases):
+    """Four steps of the N = 146 pair (dagger form, its H~) against the
+    oracle's symmetric form; probabilities to 1e-8 max(P, 1e-6) (the
+    coupling bar above carried through four steps)."""
+    (lt, ot), (lp, op) = bases["wide"], bases["p0"]
+    b, v, ne, nt = 1.3, 1.0, 32, 40
+    zg = np.linspace(-2.0, 0.0, 5)
+    plan = W.wpccc_plan_create_2c([lt], [lp], 0, [b], [v], n_eta=ne, n_tau=nt, symmetric=True)
+    N = plan.n_states
+    X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X[0, 0] = 1.0
+    P = torch.empty((1, plan.n_pad), dtype=torch.float64, device="cuda")
+    W.wpccc_propagate(plan, zg, X, P)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    Xo = rk4_propagate(m_two_centre_symmetric(ot, op, b, v, ne, nt, Q_DAGGER), initial_state(N), zg)
+    Po = np.abs(Xo) ** 2
+    Pg = P.cpu().numpy()[0, :N]
+    d = np.abs(Pg - Po)
+    print(f"2C symmetric N=146 4 steps: max|dP| {d.max():.2e}", flush=True)
+    assert np.all(d <= 1e-8 * np.maximum(Po, P_FLOOR)), d.max()
+
+
+def test_2c_symmetric_form_conserves_norm():
+    """Along a whole pass of the 2 + 2 bound-state pair (b = 1.5, v = 1,
+    z = -4..4, h = 0.05), X^dag S X of the symmetric form stays at 1 to
+    1e-8 while the printed Q^dagger form's moves by more than 1e-4; equal
+    to the norm the same plan reports for X (X^dag S X from the plan's S)."""
+    rec = WL.Recipe(2, 1, 1, 1.5, 600, 40.0)
+    lb = lib_basis(rec)
+    zg = np.linspace(-4.0, 4.0, 161)
+    drift = {}
+    for sym in (False, True):
+        plan = W.wpccc_plan_create_2c([lb], [lb], 0, [1.5], [1.0], n_eta=24, n_tau=32, symmetric=sym)
+        X = torch.zeros((1, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[0, 0] = 1.0
+        nrm = torch.empty((1,), dtype=torch.float64, device="cuda")
+        W.wpccc_propagate(plan, zg, X, None, nrm)
+        torch.cuda.synchronize()
+        W.wpccc_plan_status(plan)
+        drift[sym] = abs(float(nrm.cpu()[0]) - 1.0)
+        print(f"symmetric={sym}: |X^dag S X - 1| = {drift[sym]:.2e}", flush=True)
+    assert drift[True] <= 1e-8 and drift[False] > 1e-4, drift
+
+
+def test_2c_symmetric_refusals(bases):
+    (lt, _), (lp, _) = bases["t0"], bases["p0"]
+    for kw in ({"mixed": True}, {"graph": True}):
+        with pytest.raises(W.WpcccError) as e:
+            W.wpccc_plan_create_2c([lt], [lp], 0, [1.0], [1.0], n_eta=24, n_tau=32, symmetric=True, **kw)
+        assert e.value.code == -6
+    for dz in (-1e-3, 0.5):
+        with pytest.raises(W.WpcccError) as e:
+            W.wpccc_plan_create_2c([lt], [lp], 0, [1.0], [1.0], n_eta=24, n_tau=32, symmetric=True, dz_sym=dz)
+        assert e.value.code == -1
