@@ -408,6 +408,20 @@ int wpccc_plan_kernel_time(wpccc_plan_t plan, const char* kernel, double* total_
  * published peaks.  Either pointer may be NULL.  Errors: WPCCC_EHIP. */
 int wpccc_measure_mfma(double* tflops_f64, double* tflops_f32, void* stream);
 
+/* The linear solve of Sec. II (ZGESV with N right-hand sides, Eq. INV) for
+ * caller matrices: X_b = A_b^{-1} B_b for b < batch, every A_b complex n x n
+ * and B_b n x n (n right-hand sides), by the kernels the two-centre plans
+ * use: LU with partial pivoting (largest |a|^2, ties to the lowest row),
+ * then forward and backward substitution by 32 x 32 blocks.
+ *  A_dev  complex128 [batch][n][n] column-major (A_b(i, j) at j*n + i), read only
+ *  B_dev  complex128 [batch][n][n] row-major (B_b(i, k) at i*n + k), read only
+ *  X_dev  complex128 [batch][n][n] row-major, written (may not alias A or B)
+ * 1 <= n <= 2048.  Allocates its staging buffers and synchronises `stream`.
+ * Errors: WPCCC_EINVAL (sizes, NULL), WPCCC_ENOMEM, WPCCC_EHIP,
+ * WPCCC_ESINGULAR (an exactly zero pivot; the message names the first
+ * such matrix and column; X then holds non-finite values). */
+int wpccc_zgesv_batched(int n, int batch, const void* A_dev, const void* B_dev, void* X_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ __all__ = [
     "wpccc_plan_path_info", "wpccc_plan_destroy", "WPCCC_Q_DAGGER", "WPCCC_Q_PRIOR",
     "wpccc_plan_status", "wpccc_couplings", "wpccc_couplings_noalloc", "wpccc_step", "wpccc_propagate",
     "wpccc_plan_timing", "wpccc_plan_kernel_time", "wpccc_adjoint", "wpccc_plan_stage_rows",
-    "wpccc_plan_stage_launch", "wpccc_plan_stage_cache", "wpccc_measure_mfma", "wpccc_plan_groups", "wpccc_observables", "WPCCC_SOLVE_FACTORED", "WPCCC_SOLVE_EXPLICIT", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
+    "wpccc_plan_stage_launch", "wpccc_plan_stage_cache", "wpccc_measure_mfma", "wpccc_zgesv_batched", "wpccc_plan_groups", "wpccc_observables", "WPCCC_SOLVE_FACTORED", "WPCCC_SOLVE_EXPLICIT", "WPCCC_LAUNCH_AUTO", "WPCCC_LAUNCH_STAGES", "WPCCC_LAUNCH_PERSISTENT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -119,6 +119,7 @@ def load_library():
         "wpccc_plan_timing": ([vp, i], i),
         "wpccc_plan_kernel_time": ([vp, ctypes.c_char_p, pd, ctypes.POINTER(ctypes.c_longlong)], i),
         "wpccc_measure_mfma": ([pd, pd, vp], i),
+        "wpccc_zgesv_batched": ([i, i, vp, vp, vp, vp], i),
         "wpccc_plan_groups": ([vp, pi, pi], i),
         "wpccc_observables": ([vp, vp, vp, vp, vp], i),
     }
@@ -393,6 +394,19 @@ def wpccc_measure_mfma(stream=None):
     f64, f32 = ctypes.c_double(), ctypes.c_double()
     _check(load_library().wpccc_measure_mfma(ctypes.byref(f64), ctypes.byref(f32), _stream_ptr(stream)))
     return f64.value, f32.value
+
+
+def wpccc_zgesv_batched(A, B, X, stream=None):
+    """X[b] = A[b]^-1 B[b] on the GPU for complex128 CUDA tensors of shape
+    [batch, n, n]: A[b] is read as stored column-major (pass the transpose of a
+    row-major matrix, e.g. A.transpose(1, 2).contiguous()), B and X row-major."""
+    if A.dim() != 3 or A.shape[1] != A.shape[2] or B.shape != A.shape or X.shape != A.shape:
+        raise ValueError("A, B and X must be [batch, n, n] of one shape")
+    batch, n = int(A.shape[0]), int(A.shape[1])
+    shp = (batch, n, n)
+    _check(load_library().wpccc_zgesv_batched(n, batch, _dev_ptr(A, "complex128", shp, "A"),
+                                              _dev_ptr(B, "complex128", shp, "B"),
+                                              _dev_ptr(X, "complex128", shp, "X"), _stream_ptr(stream)))
 
 
 def wpccc_plan_groups(plan: Plan):

@@ -366,6 +366,8 @@ void plan2c_destroy(Plan2C* p);
 int plan2c_info(Plan2C* p, int* n_traj, int* n_states, int* n_pad, long long* bytes);
 int plan2c_path_info(Plan2C* p, int j, int* n_states, int* n_target);
 int plan2c_status(Plan2C* p, hipStream_t st);
+// A X = B for batch column-major A with n row-major right-hand sides (plan2c.hip)
+int lu_solve_batched(int n, int batch, const void* A, const void* B, void* X, hipStream_t st);
 int plan2c_couplings(Plan2C* p, int j, double z, void* H, void* S, hipStream_t st);
 int plan2c_step(Plan2C* p, void* X, double z, double h, hipStream_t st);
 int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* X, void* P, void* norm, hipStream_t st);

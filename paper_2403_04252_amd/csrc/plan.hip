@@ -643,6 +643,11 @@ int wpccc_measure_mfma(double* tflops_f64, double* tflops_f32, void* stream) {
     return WPCCC_OK;
 }
 
+int wpccc_zgesv_batched(int n, int batch, const void* A_dev, const void* B_dev, void* X_dev, void* stream) {
+    clear_error();
+    return lu_solve_batched(n, batch, A_dev, B_dev, X_dev, (hipStream_t)stream);
+}
+
 const char* wpccc_version(void) { return "0.3.0"; }
 
 int wpccc_basis(const wpccc_basis_spec* spec, wpccc_basis_t* out) {

@@ -1136,4 +1136,80 @@ int plan2c_propagate(Plan2C* p, const double* zgrid, int n_points, void* Xv, voi
     return WPCCC_OK;
 }
 
+// A X = B for `batch` complex n x n systems with n right-hand sides: the LU
+// panels with partial pivoting over every column, then k_lu_rhs.  The
+// kernels address their matrices with the plan's slot stride, so A and B
+// are staged at that stride in buffers of this call.
+int lu_solve_batched(int n, int batch, const void* A, const void* B, void* X, hipStream_t st) {
+    if (n < 1 || n > kLUMaxN || batch < 1 || !A || !B || !X) {
+        set_error("wpccc_zgesv_batched: need 1 <= n <= %d, batch >= 1 and non-NULL matrices", kLUMaxN);
+        return WPCCC_EINVAL;
+    }
+    const size_t NN = (size_t)n * n, per = (size_t)kSlots2C * NN;
+    double2 *lu = nullptr, *hb = nullptr, *mb = nullptr;
+    int *piv = nullptr, *perm = nullptr, *paths = nullptr, *flag = nullptr;
+    int rc = WPCCC_OK;
+    long long tot = 0;
+    std::vector<int> ids(batch);
+    for (int i = 0; i < batch; ++i) ids[i] = i;
+    int hflag[4] = {0, 0, 0, 0};
+    auto run = [&]() -> int {
+        int r;
+        if ((r = dev_alloc(&lu, per * batch, tot)) || (r = dev_alloc(&hb, per * batch, tot)) ||
+            (r = dev_alloc(&mb, per * batch, tot)) || (r = dev_alloc(&piv, (size_t)kSlots2C * n * batch, tot)) ||
+            (r = dev_alloc(&perm, (size_t)kSlots2C * n * batch, tot)) || (r = dev_alloc(&paths, batch, tot)) ||
+            (r = dev_alloc(&flag, 4, tot)))
+            return r;
+        if ((r = upload(paths, ids.data(), batch * sizeof(int), st))) return r;
+        WPCCC_HIP_CHECK(hipMemsetAsync(flag, 0, 4 * sizeof(int), st));
+        WPCCC_HIP_CHECK(hipMemcpy2DAsync(lu, per * sizeof(double2), A, NN * sizeof(double2), NN * sizeof(double2),
+                                         batch, hipMemcpyDeviceToDevice, st));
+        WPCCC_HIP_CHECK(hipMemcpy2DAsync(hb, per * sizeof(double2), B, NN * sizeof(double2), NN * sizeof(double2),
+                                         batch, hipMemcpyDeviceToDevice, st));
+        LUStepArgs a{};
+        a.N = n;
+        a.jobs.path0 = 0;
+        a.jobs.n_sub = 1;
+        a.LU = lu;
+        a.piv = piv;
+        a.perm = perm;
+        a.paths = paths;
+        a.flag = flag;
+        a.skip_mode = 0;
+        const int pw = lu_panel_width(n);
+        for (int k0 = 0; k0 < n; k0 += pw) {
+            a.k0 = k0;
+            a.nb = std::min(pw, n - k0);
+            if ((r = launched(launch_lu_panel(a, batch, st), "k_lu_panel")) ||
+                (r = launched(launch_lu_swap_trsm(a, batch, st), "k_lu_swap_trsm")) ||
+                (r = launched(launch_lu_update(a, batch, st), "k_lu_update")))
+                return r;
+        }
+        RhsArgs ra{};
+        ra.N = n;
+        ra.jobs = a.jobs;
+        ra.LU = lu;
+        ra.perm = perm;
+        ra.H = hb;
+        ra.M = mb;
+        if ((r = launched(launch_lu_rhs(ra, batch, st), "k_lu_rhs"))) return r;
+        WPCCC_HIP_CHECK(hipMemcpy2DAsync(X, NN * sizeof(double2), mb, per * sizeof(double2), NN * sizeof(double2),
+                                         batch, hipMemcpyDeviceToDevice, st));
+        WPCCC_HIP_CHECK(hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st));
+        WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+        return WPCCC_OK;
+    };
+    rc = run();
+    if (rc != WPCCC_OK) (void)hipStreamSynchronize(st);
+    void* bufs[] = {lu, hb, mb, piv, perm, paths, flag};
+    for (void* q : bufs)
+        if (q) (void)hipFree(q);
+    if (rc != WPCCC_OK) return rc;
+    if (hflag[1]) {
+        set_error("wpccc_zgesv_batched: matrix %d is singular (zero pivot in column %d)", hflag[1] - 1, hflag[2]);
+        return WPCCC_ESINGULAR;
+    }
+    return WPCCC_OK;
+}
+
 }  // namespace wpccc
