@@ -123,8 +123,12 @@ typedef struct {
                        (Eq. D1 is written for Zp = 1; Zp = -1 is the negatively
                        charged projectile of Eq. NOINV).  0 means 1.  In 2C the
                        charges are the Z of the two bases. */
-    int batched;    /* 1: all paths in each launch (default); 0: one path per
-                       launch sequence, paths one after another */
+    int batched;    /* 1: all paths in each launch (default; 2C: the coupling
+                       launches cover one basis-size group each, on a stream
+                       per group, and each RK4 stage is one launch over the
+                       paths of every group); 2 (2C): the stage launches per
+                       group too; 0: one path per launch sequence, paths one
+                       after another */
     int two_centre; /* set by wpccc_plan_create_2c; must be 0 for wpccc_plan_create */
     int q_lower;    /* 2C: WPCCC_Q_DAGGER (default) or WPCCC_Q_PRIOR */
     int n_eta;      /* 2C: Gauss-Laguerre nodes in eta (0 means 256) */

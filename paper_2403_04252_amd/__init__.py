@@ -277,6 +277,8 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
                          solve: int = WPCCC_SOLVE_FACTORED, graph: bool = False, symmetric: bool = False,
                          dz_sym: float = 0.0, stream=None) -> Plan:
     """Two-centre plan: path j uses the basis pair (targets[s], projectiles[s]), s = set_of_traj[j].
+    batched: True/1 all paths of a basis-size group per coupling launch and every path in one
+    launch per RK4 stage; 2 the stages per group too; False/0 one path at a time.
     solve: WPCCC_SOLVE_FACTORED (triangular solves per stage) or WPCCC_SOLVE_EXPLICIT
     (M = S^-1 H per coupling point, the paper's form); graph: replay wpccc_propagate's
     steps from captured HIP graphs; symmetric: the S-norm-conserving form of H with dS/dz
@@ -290,7 +292,8 @@ def wpccc_plan_create_2c(targets, projectiles, set_of_traj, b, v, q_lower: int =
         raise ValueError("targets and projectiles must pair up")
     T = (ctypes.c_void_p * ns)(*[t.handle for t in targets])
     P = (ctypes.c_void_p * ns)(*[q.handle for q in projectiles])
-    opts = _PlanOpts(0.0, 1 if batched else 0, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
+    nb = int(batched) if not isinstance(batched, bool) else (1 if batched else 0)
+    opts = _PlanOpts(0.0, nb, 1, int(q_lower), int(n_eta), int(n_tau), 0.0, 0.0, 0, 0,
                      WPCCC_MIXED if mixed else WPCCC_FP64, 1 if graph else 0, 0, 0, 0, int(solve),
                      1 if symmetric else 0, float(dz_sym))
     h = ctypes.c_void_p()

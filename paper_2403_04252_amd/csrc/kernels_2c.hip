@@ -744,12 +744,12 @@ __global__ __launch_bounds__(256) void k_2c_direct(DirectArgs a) {
 // y = path; each wave accumulates four rows at once (four 1 KB row segments
 // in flight per iteration).
 __global__ __launch_bounds__(256) void k_2c_hu(Stage2CArgs a) {
-    const int pl = blockIdx.y;
-    const int j = a.paths[pl];
-    const int N = a.N, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t ps = ((size_t)pl * kSlots2C + a.slot) * (size_t)N * N;
-    const double2* H = a.H + ps;
-    const int* perm = a.perm ? a.perm + ((size_t)pl * kSlots2C + a.slot) * N : nullptr;
+    const PathMats pm = a.pm[blockIdx.y];
+    const int j = pm.path, N = pm.N;
+    if ((int)blockIdx.x * 16 >= N) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double2* H = pm.H + (size_t)a.slot * N * N;
+    const int* perm = pm.perm ? pm.perm + (size_t)a.slot * N : nullptr;
     const double2* u = a.u_in + (size_t)j * a.n_pad;
     const int r0 = blockIdx.x * 16 + wave * 4;
     const double2* hr[4];
@@ -793,11 +793,9 @@ constexpr int kSolveThreads = 1024;
 __global__ __launch_bounds__(kSolveThreads) void k_2c_solve(Stage2CArgs a) {
     extern __shared__ double2 ys[];      // [N]
     __shared__ double2 blk[kSolveBlock][kSolveBlock + 1];
-    const int pl = blockIdx.x;
-    const int j = a.paths[pl];
-    const int N = a.N, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const size_t ps = ((size_t)pl * kSlots2C + a.slot) * (size_t)N * N;
-    const double2* LU = a.LU + ps;
+    const PathMats pm = a.pm[blockIdx.x];
+    const int j = pm.path, N = pm.N, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const double2* LU = pm.LU + (size_t)a.slot * N * N;
     for (int i = tid; i < N; i += blockDim.x) ys[i] = a.Y[(size_t)j * a.n_pad + i];
     __syncthreads();
     // L (unit diagonal): forward
@@ -1024,12 +1022,12 @@ hipError_t launch_2c_direct(const DirectArgs& a, const Meta2C& hm, int n_jobs, h
 }
 
 hipError_t launch_2c_hu(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_2c_hu, dim3((a.N + 15) / 16, n_paths), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_2c_hu, dim3((a.N_max + 15) / 16, n_paths), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_2c_solve(const Stage2CArgs& a, int n_paths, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_2c_solve, dim3(n_paths), dim3(kSolveThreads), a.N * sizeof(double2), st, a);
+    WPCCC_LAUNCH(ev, k_2c_solve, dim3(n_paths), dim3(kSolveThreads), a.N_max * sizeof(double2), st, a);
     return hipGetLastError();
 }
 

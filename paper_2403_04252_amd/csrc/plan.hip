@@ -739,6 +739,10 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         set_error("wpccc_plan_create: the persistent stage kernel has no reduced-precision form");
         return WPCCC_ENOTSUP;
     }
+    if (o.batched != 0 && o.batched != 1) {
+        set_error("wpccc_plan_create: batched must be 0 or 1");
+        return WPCCC_EINVAL;
+    }
     if (o.solve != 0 || o.symmetric != 0) {
         set_error("wpccc_plan_create: solve and symmetric are two-centre options (the one-centre form has S = I)");
         return WPCCC_EINVAL;

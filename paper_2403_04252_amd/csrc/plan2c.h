@@ -226,15 +226,24 @@ struct RhsArgs {
     double2* M;             // [path][slot][N*N] row-major
 };
 
-struct Stage2CArgs {
-    int N, n_pad, stage;
-    double h;
-    int slot;               // coupling slot used by this stage
-    const int* paths;       // global index of each local path
-    const double* vvec;
-    const double2* H;       // H, or M = S^{-1} H when solve is 0
+// One path's matrices for the stage kernels: slot s of the path starts at
+// s * N * N (s * N for perm) from these bases.
+struct PathMats {
+    int N;
+    int path;               // global path index (row of X, u, Y)
+    const double2* H;       // H, or M = S^{-1} H when the stage does not solve
     const double2* LU;
     const int* perm;        // row order of the product (nullptr: identity)
+};
+
+// A stage for every path of pm[0 .. n_paths): the paths may differ in N (one
+// launch over every basis-size group), N_max bounds them all.
+struct Stage2CArgs {
+    int N_max, n_pad, stage;
+    double h;
+    int slot;               // coupling slot used by this stage
+    const PathMats* pm;
+    const double* vvec;
     int solve;              // 1: y = U^{-1} L^{-1} P (H u); 0: y = M u
     // graph replays: h = hdev[3 * *step + 2] instead of h (nullptr: h)
     const double* hdev;

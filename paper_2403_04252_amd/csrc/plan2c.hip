@@ -157,6 +157,11 @@ struct Plan2C {
     std::vector<int> group_of, local_of;
     int n_traj = 0, n_pad = 0, batched = 1, q_prior = 0, n_eta = 0, n_tau = 0, mixed = 0;
     int explicit_m = 0;  // M = S^{-1} H formed per coupling point (WPCCC_SOLVE_EXPLICIT)
+    // stage kernels: one launch over every group's paths (batched 1) or per group (batched 2)
+    bool stage_all = true;
+    PathMats* d_pm = nullptr;       // [n_traj] ordered by group, then local path
+    std::vector<int> pm_first;      // first entry of each group in d_pm
+    int N_max = 0;
     int symmetric = 0;   // S-norm-conserving form of H (opts.symmetric)
     double dz_sym = 1e-4;
     std::vector<double> b, v;
@@ -578,21 +583,18 @@ int enqueue_symm(Plan2C* p, Group2C& g, int l0, int np, int slot, int which, hip
     return timed(p, k2cSymm, [&](const LaunchEv& ev) { return launch_2c_symm(a, np, st, ev); });
 }
 
-int enqueue_stage(Plan2C* p, Group2C& g, int l0, int np, int stage, int slot, double h, const double2* u_in,
-                  double2* X, double2* u_out, hipStream_t st) {
-    const size_t NN = (size_t)g.m.N * g.m.N;
+// One RK4 stage for the np paths of pm (entries of d_pm), N <= N_max.
+int enqueue_stage(Plan2C* p, const PathMats* pm, int np, int N_max, int stage, int slot, double h,
+                  const double2* u_in, double2* X, double2* u_out, hipStream_t st) {
     Stage2CArgs a{};
-    a.N = g.m.N;
+    a.N_max = N_max;
     a.n_pad = p->n_pad;
     a.stage = stage;
     a.h = h;
     a.slot = slot;
-    a.paths = g.d_paths + l0;
+    a.pm = pm;
     a.vvec = p->d_v;
     a.solve = !p->explicit_m;
-    a.H = (a.solve ? g.d_H : g.d_M) + (size_t)l0 * kSlots2C * NN;
-    a.LU = g.d_LU + (size_t)l0 * kSlots2C * NN;
-    a.perm = a.solve ? g.d_perm + (size_t)l0 * kSlots2C * g.m.N : nullptr;
     a.u_in = u_in;
     a.Y = p->d_Y;
     a.X = X;
@@ -651,6 +653,16 @@ void commit_slots(Plan2C* p, const StepSlots& s, double z, double h) {
     p->slot_z[s.sn] = z + h;
 }
 
+// The four RK4 stages of a step for the np paths of pm.
+int enqueue_stages(Plan2C* p, const PathMats* pm, int np, int N_max, const StepSlots& ss, double h, double2* X,
+                   hipStream_t st) {
+    int rc;
+    if ((rc = enqueue_stage(p, pm, np, N_max, 1, ss.s0, h, X, X, p->d_Ua, st))) return rc;
+    if ((rc = enqueue_stage(p, pm, np, N_max, 2, ss.sm, h, p->d_Ua, X, p->d_Ub, st))) return rc;
+    if ((rc = enqueue_stage(p, pm, np, N_max, 3, ss.sm, h, p->d_Ub, X, p->d_Ua, st))) return rc;
+    return enqueue_stage(p, pm, np, N_max, 4, ss.sn, h, p->d_Ua, X, nullptr, st);
+}
+
 // The launches of one RK4 step of every path in the given slots.
 int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlots& ss, hipStream_t st) {
     const double zm = z + 0.5 * h, zn = z + h;
@@ -687,16 +699,17 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
                                  (rc = enqueue_symm(p, g, l0, np, ss.sn, 1, gs)) ||
                                  (rc = enqueue_rhs(p, g, l0, np, 2, sl, gs))))
                 return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 1, ss.s0, h, X, X, p->d_Ua, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 2, ss.sm, h, p->d_Ua, X, p->d_Ub, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 3, ss.sm, h, p->d_Ub, X, p->d_Ua, gs))) return rc;
-            if ((rc = enqueue_stage(p, g, l0, np, 4, ss.sn, h, p->d_Ua, X, nullptr, gs))) return rc;
+            if (!p->stage_all &&
+                (rc = enqueue_stages(p, p->d_pm + p->pm_first[gi] + l0, np, g.m.N, ss, h, X, gs)))
+                return rc;
         }
         if (fork) {
             WPCCC_HIP_CHECK(hipEventRecord(p->join_ev[gi], gs));
             WPCCC_HIP_CHECK(hipStreamWaitEvent(st, p->join_ev[gi], 0));
         }
     }
+    // the stages of every group's paths in one launch each, after all couplings
+    if (p->stage_all && (rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, h, X, st))) return rc;
     return WPCCC_OK;
 }
 
@@ -853,6 +866,10 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
         set_error("wpccc_plan_create_2c: precision must be WPCCC_FP64 or WPCCC_MIXED");
         return WPCCC_EINVAL;
     }
+    if (o.batched < 0 || o.batched > 2) {
+        set_error("wpccc_plan_create_2c: batched must be 0, 1 or 2");
+        return WPCCC_EINVAL;
+    }
     if (o.symmetric != 0 && o.symmetric != 1) {
         set_error("wpccc_plan_create_2c: symmetric must be 0 or 1");
         return WPCCC_EINVAL;
@@ -912,6 +929,7 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     p->timer = timer;
     p->n_traj = n_traj;
     p->batched = o.batched ? 1 : 0;
+    p->stage_all = o.batched == 1;
     p->q_prior = o.q_lower == WPCCC_Q_PRIOR;
     p->mixed = o.precision == WPCCC_MIXED;
     p->explicit_m = o.solve == WPCCC_SOLVE_EXPLICIT;
@@ -946,6 +964,26 @@ int plan2c_create(const wpccc_basis_t* targets, const wpccc_basis_t* projectiles
     };
     for (Group2C& g : p->groups)
         if ((rc = build_group(p, g, st))) return fail(rc);
+    // stage descriptors, group by group
+    {
+        std::vector<PathMats> pm;
+        for (Group2C& g : p->groups) {
+            p->pm_first.push_back((int)pm.size());
+            const size_t NN = (size_t)g.m.N * g.m.N;
+            for (size_t l = 0; l < g.paths.size(); ++l) {
+                PathMats e{};
+                e.N = g.m.N;
+                e.path = g.paths[l];
+                e.H = (p->explicit_m ? g.d_M : g.d_H) + l * kSlots2C * NN;
+                e.LU = g.d_LU + l * kSlots2C * NN;
+                e.perm = p->explicit_m ? nullptr : g.d_perm + l * kSlots2C * g.m.N;
+                pm.push_back(e);
+            }
+            p->N_max = std::max(p->N_max, g.m.N);
+        }
+        if ((rc = dev_alloc(&p->d_pm, pm.size(), p->bytes))) return fail(rc);
+        if ((rc = upload(p->d_pm, pm.data(), pm.size() * sizeof(PathMats), st))) return fail(rc);
+    }
     std::vector<double> xl, wl, tl, wt;
     gauss_laguerre_scaled(p->n_eta, xl, wl);
     gauss_legendre(p->n_tau, tl, wt);
@@ -1018,7 +1056,7 @@ void plan2c_destroy(Plan2C* p) {
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     for (Group2C& g : p->groups) free_group(g);
     void* bufs[] = {p->d_b,    p->d_v,    p->d_flag, p->d_Ua,   p->d_Ub,  p->d_Xacc,
-                    p->d_Y,    p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg};
+                    p->d_Y,    p->d_xlag, p->d_wlag, p->d_tleg, p->d_wleg, p->d_pm};
     for (void* q : bufs)
         if (q) (void)hipFree(q);
     delete p;

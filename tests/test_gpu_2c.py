@@ -162,8 +162,10 @@ def test_2c_stepwise_and_unbatched_bitwise(small_run):
     X0, P0, _, _ = _run_gpu(wl, lt, lp)
     X1, _, _, _ = _run_gpu(wl, lt, lp, stepwise=True)
     X2, P2, _, _ = _run_gpu(wl, lt, lp, batched=False)
+    X3, P3, _, _ = _run_gpu(wl, lt, lp, batched=2)   # stage launches per basis-size group
     assert np.array_equal(X0, X1)
     assert np.array_equal(X0, X2) and np.array_equal(P0, P2)
+    assert np.array_equal(X0, X3) and np.array_equal(P0, P3)
 
 
 def test_2c_couplings_errors(bases):
