@@ -346,8 +346,8 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
  *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
  * Device memory for the checkpoints is allocated by the first call.  Errors:
  * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, a
- * WPCCC_MIXED or WPCCC_RADIAL_INTERP plan, or a basis whose operator kernel does not fit the LDS at 8
- * rows per workgroup). */
+ * WPCCC_MIXED or WPCCC_RADIAL_INTERP plan, or a basis whose operator kernel does not fit the LDS at 4
+ * rows per workgroup, 8 where they fit: up to l_max = 7 of the paper's basis shape). */
 int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 

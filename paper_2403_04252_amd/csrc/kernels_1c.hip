@@ -1105,10 +1105,13 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
     }
 }
 
-// Operator application with the grid of k_stage (see StageArgs).
+// Operator application with the grid of k_stage (see StageArgs), ROWS rows
+// per workgroup (kRowsPerBlock, or kApplyRowsLarge where that does not fit
+// the LDS).
+template <int ROWS>
 __global__ __launch_bounds__(kStageThreads) void k_apply(ApplyArgs a) {
     extern __shared__ double2 smem2[];
-    stage_entry<1, kRowsPerBlock>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
+    stage_entry<1, ROWS>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
 }
 
 // grad[j] = (dL/da, dL/dc, dL/db): the k_apply shares of path j (slots 2, 3
@@ -1326,7 +1329,8 @@ hipError_t stage_set_smem_limit(int, int bytes) {
     (const void*)k_stage<R, false, false>, (const void*)k_stage<R, false, true>,                 \
         (const void*)k_stage<R, true, true>, (const void*)k_stage<R, true, false>, (const void*)k_chunk<R>,
 #define WPCCC_FN_GG(R) (const void*)k_stage<R, false, true, true>, (const void*)k_stage<R, true, true, true>,
-    const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR) WPCCC_STAGE_ROWS_GG(WPCCC_FN_GG)(const void*)k_apply};
+    const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR) WPCCC_STAGE_ROWS_GG(WPCCC_FN_GG)(const void*)k_apply<kRowsPerBlock>,
+                         (const void*)k_apply<kApplyRowsLarge>};
 #undef WPCCC_FN_PAIR
 #undef WPCCC_FN_GG
     hipError_t e = hipSuccess;
@@ -1370,9 +1374,15 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& hm, int smem, int rows, 
     return e;
 }
 
-hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& hm, int n_traj_launch, int smem, hipStream_t st,
-                        const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_apply, dim3(hm.n_chunks, n_traj_launch, n_ops), dim3(kStageThreads), smem, st, a);
+hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& hm, int n_traj_launch, int smem, int rows,
+                        hipStream_t st, const LaunchEv& ev) {
+    const dim3 grid(stage_chunks(hm, rows), n_traj_launch, n_ops);
+    if (rows == kRowsPerBlock)
+        WPCCC_LAUNCH(ev, k_apply<kRowsPerBlock>, grid, dim3(kStageThreads), smem, st, a);
+    else if (rows == kApplyRowsLarge)
+        WPCCC_LAUNCH(ev, k_apply<kApplyRowsLarge>, grid, dim3(kStageThreads), smem, st, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ constexpr int kStageThreads = 256;
 // the kernels' few static LDS words
 constexpr int kMaxDynLds = 160 * 1024 - 1024;
 constexpr int kRowsPerBlock = 8;     // output rows n' per workgroup of k_apply (and the untimed default of k_stage)
+constexpr int kApplyRowsLarge = 4;   // k_apply's rows where kRowsPerBlock does not fit the LDS
 // row tilings the stage kernels are built for (X-macro over the values)
 #define WPCCC_STAGE_ROWS(X) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
 constexpr int kStageRowsList[] = {4, 5, 6, 7, 8, 10, 12, 16};
@@ -391,8 +392,9 @@ hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const do
                                   const LaunchEv& ev = LaunchEv{});
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
                                 double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
-hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& host_meta, int n_traj_launch, int smem, hipStream_t st,
-                        const LaunchEv& ev = LaunchEv{});
+// rows: kRowsPerBlock or kApplyRowsLarge (a.tiles must be that tiling)
+hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& host_meta, int n_traj_launch, int smem, int rows,
+                        hipStream_t st, const LaunchEv& ev = LaunchEv{});
 // grad[j][0..2] = (a, c, b) sums of the k_apply shares gpart[j][kGradSlots][n_part]
 // in a fixed order; one workgroup per path
 hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_traj, hipStream_t st);

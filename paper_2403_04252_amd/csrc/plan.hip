@@ -68,7 +68,8 @@ struct wpccc_plan_s {
     int* d_chunk = nullptr;
     hipEvent_t g_copied = nullptr;
     long long bytes = 0;
-    int stage_smem = 0;       // k_apply (kRowsPerBlock rows)
+    int stage_smem = 0;       // k_apply (apply_rows rows)
+    int apply_rows = kRowsPerBlock;
     bool apply_ok = true;     // k_apply's LDS fits (wpccc_adjoint is available)
     int stage_rows = kRowsPerBlock;
     int stage_smem_rows = 0;  // k_stage with stage_rows
@@ -320,7 +321,7 @@ int stored_step(wpccc_plan_s* p, int pz, double h, double2* x, double2* xn, doub
 StageArgs apply_args(const wpccc_plan_s* p, int pt, double z, int deriv) {
     StageArgs a{};
     a.meta = p->c.d_meta;
-    set_tiles(p, kRowsPerBlock, a);
+    set_tiles(p, p->apply_rows, a);
     a.tb = p->tables();
     a.pt = p->points();
     a.Zp = p->Zp;
@@ -372,7 +373,7 @@ int enqueue_reverse_stage(wpccc_plan_s* p, int pt, double z, const double2* v1, 
             g.vc = p->d_vc;
         }
     }
-    return launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, st), "k_apply");
+    return launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, p->apply_rows, st), "k_apply");
 }
 
 // Capture one chunk of kChunkSteps steps for all paths on X into plan->gexec:
@@ -855,15 +856,22 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         free_plan(plan);
         return WPCCC_ENOTSUP;
     }
-    // the adjoint's operator kernel (k_apply, kRowsPerBlock rows)
-    plan->apply_ok = plan->stage_smem <= kMaxDynLds;
+    // the adjoint's operator kernel (k_apply): kRowsPerBlock rows, or
+    // kApplyRowsLarge where those do not fit the LDS (not with the large-basis form)
+    plan->apply_ok = false;
+    for (int r : {kRowsPerBlock, kApplyRowsLarge})
+        if (!plan->apply_ok && !plan->gg && stage_smem_bytes(m, r) <= kMaxDynLds && stage_rows_fit(m, r)) {
+            plan->apply_ok = true;
+            plan->apply_rows = r;
+            plan->stage_smem = stage_smem_bytes(m, r);
+        }
     long long& tot = plan->bytes;
     tot = plan->c.bytes;
     TRY(dev_alloc(&plan->d_b, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_v, (size_t)n_traj, tot));
     TRY(dev_alloc(&plan->d_flag, 1, tot));
     TRY(dev_alloc(&plan->d_bar, (size_t)n_traj * kBarStride, tot));
-    TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * kGradSlots * m.n_chunks, tot));
+    TRY(dev_alloc(&plan->d_gpart, (size_t)n_traj * kGradSlots * stage_chunks(m, plan->apply_rows), tot));
     std::vector<StageTile> tiles;
     for (int i = 0; i < kNumStageRows; ++i) {
         std::vector<StageTile> t;
@@ -1354,7 +1362,8 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
     double2* nu2 = plan->d_nu + 2 * V;
     WPCCC_HIP_CHECK(hipMemcpyAsync(lam, gX_dev, VB, hipMemcpyDeviceToDevice, st));
     WPCCC_HIP_CHECK(hipMemsetAsync(plan->d_gpart, 0,
-                                   (size_t)plan->n_traj * kGradSlots * plan->c.meta.n_chunks * sizeof(double), st));
+                                   (size_t)plan->n_traj * kGradSlots * stage_chunks(plan->c.meta, plan->apply_rows) *
+                                       sizeof(double), st));
     for (int s = n_ck - 1; s >= 0; --s) {
         const int n0 = s * K, n1 = std::min(n0 + K, n_steps);
         const void* x0 = n_ck > 1 ? (const void*)(plan->d_ckpt + (size_t)s * V) : X0_dev;
@@ -1390,7 +1399,8 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
             std::swap(lam, lam_next);
         }
     }
-    return launched(launch_grad_sum(plan->d_gpart, plan->c.meta.n_chunks, (double*)grad_dev, plan->n_traj, st),
+    return launched(launch_grad_sum(plan->d_gpart, stage_chunks(plan->c.meta, plan->apply_rows), (double*)grad_dev,
+                                    plan->n_traj, st),
                     "k_grad_sum");
 }
 

@@ -155,3 +155,50 @@ def test_autograd_function(small):
     assert np.allclose(b.grad.numpy(), g[:, 2], rtol=1e-12, atol=0)
     assert abs(a.grad.item() - g[:, 0].sum()) <= 1e-12 * abs(g[:, 0].sum())
     assert abs(c.grad.item() - g[:, 1].sum()) <= 1e-12 * abs(g[:, 1].sum())
+
+
+@pytest.mark.parametrize("l_max", [6, 7])
+def test_adjoint_paper_shape_vs_finite_differences(l_max):
+    """The paper's basis shape (N_l = 42 - l: N = 1855 at l_max = 6, 2380 at
+    7), where the operator kernel takes 4-row tiles (8 rows do not fit the
+    LDS): adjoint gradients in a, c and b of a weighted sum of probabilities
+    after 6 steps through closest approach, against central differences
+    (relative step 1e-5) of the GPU forward, to 1e-6 max(1, |FD|).  No R of
+    the grid falls on a radial grid node: there the grid quadrature F of
+    Eq. D2 has a kink in R (a node changes sides), and a central difference
+    averages the two one-sided derivatives (b = 0.8 with z = 0.6 gives R = 1
+    = r_30 of this grid)."""
+    lb = lib_basis(WL.Recipe(10, l_max, 32, 3.0, 300, 100.0))
+    b, v, a, c = np.array([0.83, 2.5]), 1.0, 0.4, 1.3
+    zg = np.linspace(-0.6, 0.6, 7)
+    plan = W.wpccc_plan_create(lb, b, v, model_a=a, model_c=c)
+    N = plan.n_states
+    print(f"adjoint paper shape l_max = {l_max}: N = {N}", flush=True)
+    wts = np.linspace(0.5, 1.5, N)
+    X0 = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+    X0[:, 0] = 1.0
+    Xf = X0.clone()
+    W.wpccc_propagate(plan, zg, Xf)
+    gX = torch.zeros_like(X0)
+    gX[:, :N] = torch.as_tensor(wts, device="cuda") * Xf[:, :N]
+    grad = torch.empty((plan.n_traj, 3), dtype=torch.float64, device="cuda")
+    W.wpccc_adjoint(plan, zg, X0, gX, grad)
+    torch.cuda.synchronize()
+    W.wpccc_plan_status(plan)
+    g = grad.cpu().numpy()
+
+    def loss(aa, cc, bb):
+        p = W.wpccc_plan_create(lb, bb, v, model_a=aa, model_c=cc, stage_rows=W.wpccc_plan_stage_rows(plan))
+        X = X0.clone()
+        W.wpccc_propagate(p, zg, X)
+        return (X.abs() ** 2).cpu().numpy()[:, :N] @ wts
+
+    d = 1e-5
+    fa = (loss(a * (1 + d), c, b) - loss(a * (1 - d), c, b)) / (2 * d * a)
+    fc = (loss(a, c * (1 + d), b) - loss(a, c * (1 - d), b)) / (2 * d * c)
+    fb = (loss(a, c, b * (1 + d)) - loss(a, c, b * (1 - d))) / (2 * d * b)
+    for k, fd in enumerate([fa, fc, fb]):
+        err = np.abs(g[:, k] - fd)
+        print(f"  parameter {k}: adjoint {g[:, k]}, FD {fd}, max err {err.max():.2e}", flush=True)
+        assert np.all(err <= 1e-6 * np.maximum(1.0, np.abs(fd))), (k, err.max())
+        assert np.abs(fd).max() > 1e-4
