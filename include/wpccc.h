@@ -346,8 +346,10 @@ int wpccc_propagate(wpccc_plan_t plan, const double* zgrid_host, int n_points,
  *   grad_dev  double  [n_traj][3], per path dL/da, dL/dc, dL/db (written)
  * Device memory for the checkpoints is allocated by the first call.  Errors:
  * WPCCC_EINVAL (grid as wpccc_propagate), WPCCC_ENOTSUP (two-centre plan, a
- * WPCCC_MIXED or WPCCC_RADIAL_INTERP plan, or a basis whose operator kernel does not fit the LDS at 4
- * rows per workgroup, 8 where they fit: up to l_max = 7 of the paper's basis shape). */
+ * WPCCC_MIXED or WPCCC_RADIAL_INTERP plan, or a basis whose operator kernel does not fit the LDS:
+ * it takes 8 rows per workgroup, 4 where 8 do not fit, and 4, 2 or 1 with the
+ * angular factors formed from the coefficient tables for the bases that need
+ * the large-basis stage form; the paper's basis shape fits to l_max = 10). */
 int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, const void* X0_dev,
                   void* X_dev, const void* gX_dev, void* grad_dev, void* stream);
 

@@ -755,11 +755,11 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
 }
 
 // k_apply's grid: x = row tile of a path (a.tiles, l' order), y = path.
-template <int KIND, int ROWS>
+template <int KIND, int ROWS, bool GG = false>
 __device__ void stage_entry(const StageArgs& a, char* smem) {
     const StageTile t = a.tiles[blockIdx.x];
     if (t.nrows <= 0) return;
-    stage_body<KIND, ROWS>(a, a.traj0 + blockIdx.y, t, smem);
+    stage_body<KIND, ROWS, false, false, GG>(a, a.traj0 + blockIdx.y, t, smem);
 }
 
 __device__ inline int chunks_of(const Meta& m, int rows) {
@@ -1107,11 +1107,12 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
 
 // Operator application with the grid of k_stage (see StageArgs), ROWS rows
 // per workgroup (kRowsPerBlock, or kApplyRowsLarge where that does not fit
-// the LDS).
-template <int ROWS>
+// the LDS); GG: the large-basis form (angular factors formed in phase 3 from
+// the coefficient tables, F from the moment table as in every k_apply).
+template <int ROWS, bool GG = false>
 __global__ __launch_bounds__(kStageThreads) void k_apply(ApplyArgs a) {
     extern __shared__ double2 smem2[];
-    stage_entry<1, ROWS>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
+    stage_entry<1, ROWS, GG>(a.s[blockIdx.z], reinterpret_cast<char*>(smem2));
 }
 
 // grad[j] = (dL/da, dL/dc, dL/db): the k_apply shares of path j (slots 2, 3
@@ -1330,7 +1331,8 @@ hipError_t stage_set_smem_limit(int, int bytes) {
         (const void*)k_stage<R, true, true>, (const void*)k_stage<R, true, false>, (const void*)k_chunk<R>,
 #define WPCCC_FN_GG(R) (const void*)k_stage<R, false, true, true>, (const void*)k_stage<R, true, true, true>,
     const void* fns[] = {WPCCC_STAGE_ROWS(WPCCC_FN_PAIR) WPCCC_STAGE_ROWS_GG(WPCCC_FN_GG)(const void*)k_apply<kRowsPerBlock>,
-                         (const void*)k_apply<kApplyRowsLarge>};
+                         (const void*)k_apply<kApplyRowsLarge>, (const void*)k_apply<4, true>,
+                         (const void*)k_apply<2, true>, (const void*)k_apply<1, true>};
 #undef WPCCC_FN_PAIR
 #undef WPCCC_FN_GG
     hipError_t e = hipSuccess;
@@ -1375,8 +1377,15 @@ hipError_t launch_chunk(const ChunkArgs& a, const Meta& hm, int smem, int rows, 
 }
 
 hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& hm, int n_traj_launch, int smem, int rows,
-                        hipStream_t st, const LaunchEv& ev) {
+                        bool gg, hipStream_t st, const LaunchEv& ev) {
     const dim3 grid(stage_chunks(hm, rows), n_traj_launch, n_ops);
+    if (gg) {
+        if (rows == 4) WPCCC_LAUNCH(ev, (k_apply<4, true>), grid, dim3(kStageThreads), smem, st, a);
+        else if (rows == 2) WPCCC_LAUNCH(ev, (k_apply<2, true>), grid, dim3(kStageThreads), smem, st, a);
+        else if (rows == 1) WPCCC_LAUNCH(ev, (k_apply<1, true>), grid, dim3(kStageThreads), smem, st, a);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (rows == kRowsPerBlock)
         WPCCC_LAUNCH(ev, k_apply<kRowsPerBlock>, grid, dim3(kStageThreads), smem, st, a);
     else if (rows == kApplyRowsLarge)

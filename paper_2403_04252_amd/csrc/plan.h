@@ -392,9 +392,10 @@ hipError_t launch_couplings_dense(const Meta* m, const Meta& host_meta, const do
                                   const LaunchEv& ev = LaunchEv{});
 hipError_t launch_probabilities(const double2* X, int n_traj, int n_states, int n_pad, double* P,
                                 double* norm, hipStream_t st, const LaunchEv& ev = LaunchEv{});
-// rows: kRowsPerBlock or kApplyRowsLarge (a.tiles must be that tiling)
+// rows: kRowsPerBlock or kApplyRowsLarge; gg: the large-basis form with rows
+// 4, 2 or 1 (a.tiles must be that tiling)
 hipError_t launch_apply(const ApplyArgs& a, int n_ops, const Meta& host_meta, int n_traj_launch, int smem, int rows,
-                        hipStream_t st, const LaunchEv& ev = LaunchEv{});
+                        bool gg, hipStream_t st, const LaunchEv& ev = LaunchEv{});
 // grad[j][0..2] = (a, c, b) sums of the k_apply shares gpart[j][kGradSlots][n_part]
 // in a fixed order; one workgroup per path
 hipError_t launch_grad_sum(const double* gpart, int n_part, double* grad, int n_traj, hipStream_t st);

@@ -311,10 +311,15 @@ int stored_step(wpccc_plan_s* p, int pz, double h, double2* x, double2* xn, doub
                 hipStream_t st) {
     int rc;
     const int nj = p->n_traj;
-    if ((rc = enqueue_stage(p, 0, nj, 1, pz, 0, h, x, x, u2, st))) return rc;
-    if ((rc = enqueue_stage(p, 0, nj, 2, pz + 1, 0, h, u2, x, u3, st))) return rc;
-    if ((rc = enqueue_stage(p, 0, nj, 3, pz + 1, 0, h, u3, x, u4, st))) return rc;
-    return enqueue_stage(p, 0, nj, 4, pz + 2, 0, h, u4, x, nullptr, st, xn);
+    // the large-basis stage form takes F from the radial-integral cache:
+    // F(pz) into slot 0 first, then the cached pattern of enqueue_step
+    const bool c = p->gg;
+    if (c && (rc = enqueue_fpoint(p, 0, nj, pz, st, 0))) return rc;
+    const int c0 = c ? 0 : -1, c1 = c ? 1 : -1;
+    if ((rc = enqueue_stage(p, 0, nj, 1, pz, 0, h, x, x, u2, st, nullptr, c0, c1, pz + 1))) return rc;
+    if ((rc = enqueue_stage(p, 0, nj, 2, pz + 1, 0, h, u2, x, u3, st, nullptr, c1))) return rc;
+    if ((rc = enqueue_stage(p, 0, nj, 3, pz + 1, 0, h, u3, x, u4, st, nullptr, c1, c0, pz + 2))) return rc;
+    return enqueue_stage(p, 0, nj, 4, pz + 2, 0, h, u4, x, nullptr, st, xn, c0);
 }
 
 // Fields of a k_apply operation at point slot pt (z of the point).
@@ -373,7 +378,7 @@ int enqueue_reverse_stage(wpccc_plan_s* p, int pt, double z, const double2* v1, 
             g.vc = p->d_vc;
         }
     }
-    return launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, p->apply_rows, st), "k_apply");
+    return launched(launch_apply(a, 3, p->c.meta, p->n_traj, p->stage_smem, p->apply_rows, p->gg, st), "k_apply");
 }
 
 // Capture one chunk of kChunkSteps steps for all paths on X into plan->gexec:
@@ -857,13 +862,15 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         return WPCCC_ENOTSUP;
     }
     // the adjoint's operator kernel (k_apply): kRowsPerBlock rows, or
-    // kApplyRowsLarge where those do not fit the LDS (not with the large-basis form)
+    // kApplyRowsLarge where those do not fit the LDS; with the large-basis
+    // form 4, 2 or 1 rows
     plan->apply_ok = false;
-    for (int r : {kRowsPerBlock, kApplyRowsLarge})
-        if (!plan->apply_ok && !plan->gg && stage_smem_bytes(m, r) <= kMaxDynLds && stage_rows_fit(m, r)) {
+    for (int r : plan->gg ? std::initializer_list<int>{4, 2, 1}
+                          : std::initializer_list<int>{kRowsPerBlock, kApplyRowsLarge})
+        if (!plan->apply_ok && stage_smem_bytes(m, r, plan->gg) <= kMaxDynLds && stage_rows_fit(m, r)) {
             plan->apply_ok = true;
             plan->apply_rows = r;
-            plan->stage_smem = stage_smem_bytes(m, r);
+            plan->stage_smem = stage_smem_bytes(m, r, plan->gg);
         }
     long long& tot = plan->bytes;
     tot = plan->c.bytes;
@@ -1348,7 +1355,9 @@ int wpccc_adjoint(wpccc_plan_t plan, const double* zgrid_host, int n_points, con
                 WPCCC_HIP_CHECK(hipMemcpyAsync(plan->d_ckpt + (size_t)(n / K) * V, xw, VB, hipMemcpyDeviceToDevice, st));
             const int pz = pts.slot(plan, n, st, &rc);
             if (rc) return rc;
-            if ((rc = enqueue_step(plan, xw, 0, plan->n_traj, pz, zgrid_host[n + 1] - zgrid_host[n], st, false)))
+            // large bases: the cached stage form, from F(pz) (the cache may hold another point)
+            if (plan->gg && (rc = enqueue_fpoint(plan, 0, plan->n_traj, pz, st, 0))) return rc;
+            if ((rc = enqueue_step(plan, xw, 0, plan->n_traj, pz, zgrid_host[n + 1] - zgrid_host[n], st, plan->gg)))
                 return rc;
         }
         if (X_dev) WPCCC_HIP_CHECK(hipMemcpyAsync(X_dev, xw, VB, hipMemcpyDeviceToDevice, st));

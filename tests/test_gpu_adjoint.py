@@ -157,11 +157,13 @@ def test_autograd_function(small):
     assert abs(c.grad.item() - g[:, 1].sum()) <= 1e-12 * abs(g[:, 1].sum())
 
 
-@pytest.mark.parametrize("l_max", [6, 7])
+@pytest.mark.parametrize("l_max", [6, 7, 8, 10])
 def test_adjoint_paper_shape_vs_finite_differences(l_max):
-    """The paper's basis shape (N_l = 42 - l: N = 1855 at l_max = 6, 2380 at
-    7), where the operator kernel takes 4-row tiles (8 rows do not fit the
-    LDS): adjoint gradients in a, c and b of a weighted sum of probabilities
+    """The paper's basis shape (N_l = 42 - l: N = 1855, 2380, 2958 and 4257 at
+    l_max = 6, 7, 8, 10), where the operator kernel takes 4-row tiles (8 rows
+    do not fit the LDS) and, from l_max = 8, the large-basis form (angular
+    factors formed in phase 3; the sweeps' stages read F from the cache):
+    adjoint gradients in a, c and b of a weighted sum of probabilities
     after 6 steps through closest approach, against central differences
     (relative step 1e-5) of the GPU forward, to 1e-6 max(1, |FD|).  No R of
     the grid falls on a radial grid node: there the grid quadrature F of
