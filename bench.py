@@ -133,6 +133,9 @@ def main():
     ap.add_argument("--v", type=float, default=1.0, help="c3: projectile speed of the batch (a.u.)")
     ap.add_argument("--mixed", action="store_true", help="c3: the reduced-precision contraction")
     ap.add_argument("--graph", action="store_true", help="c3: replay the steps from captured HIP graphs")
+    ap.add_argument("--z0", type=float, default=None,
+                    help="c3: steps of 0.1 from this z from a seeded random state (default: the workload's "
+                         "grid from its start, from the ground state)")
     ap.add_argument("--explicit-m", action="store_true",
                     help="c3: form M = S^-1 H per coupling point (the paper's form) instead of solving per stage")
     ap.add_argument("--no-2c", action="store_true",
@@ -702,7 +705,8 @@ def contract_flops(recT, recP, n_w, n_act):
 def bench_two_centre(args):
     """Batched two-centre propagation (Eq. 1 with capture) on one GPU: prints its own JSON line."""
     out = two_centre_measure(args, args.steps, args.warmup, mixed=args.mixed, explicit=args.explicit_m,
-                             graph=args.graph)
+                             graph=args.graph, z0=args.z0)
+    out.pop("P_final", None)
     print(json.dumps(out), flush=True)
 
 
