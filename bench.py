@@ -803,7 +803,9 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
 
     # algorithmic flops of the contraction over the timed steps: the first step
     # computes z, z_mid, z_new, later steps z_mid and z_new
-    n_w = 3 if w.q_lower == "prior" else 2
+    # the plan is given one basis object per size for both centres, so the
+    # prior block comes from Q by symmetry: two weights in the contraction
+    n_w = 2
     xl = roots_laguerre(w.n_eta)[0]
     fl = 0
     for i in range(steps):

@@ -116,7 +116,10 @@ int wpccc_basis_destroy(wpccc_basis_t basis);
 
 /* lower-left block of H in the two-centre form */
 #define WPCCC_Q_DAGGER 0   /* Q^dagger, as printed in Eq. 1 */
-#define WPCCC_Q_PRIOR  1   /* <phi_P | -Z_P/r_P | phi_T>, the other side's potential */
+#define WPCCC_Q_PRIOR  1   /* <phi_P | -Z_P/r_P | phi_T>, the other side's potential; for a
+                              set whose target and projectile are the same basis object it
+                              is (-1)^(l_i + l_j) Q_ij by the symmetry of the quadrature
+                              under exchange of the centres (not integrated again) */
 
 typedef struct {
     double Zp;      /* 1C: projectile charge, the target electron sees -Zp/|r-R|

@@ -616,8 +616,17 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
     LU[row + (size_t)col * N] = val[0];
     LU[col + (size_t)row * N] = make_double2(val[0].x, -val[0].y);
     H[(size_t)row * N + col] = val[1];                          // Q
-    const double2 low = (m.q_prior && n_w > 2) ? val[2] : val[1];
-    H[(size_t)col * N + row] = make_double2(low.x, -low.y);     // Q^dagger or the prior form
+    if (m.mirror) {
+        // one basis on both centres: tau -> -tau exchanges the centres, turns
+        // the target potential's weight into the projectile's and conjugates
+        // the translation phase, so the prior block's element at (projectile
+        // state al, target state be) is (-1)^(l_a + l_b) Q_(al, be)
+        const double sg = ((la + lb) & 1) ? -1.0 : 1.0;
+        H[(size_t)(NT + al) * N + be] = make_double2(sg * val[1].x, sg * val[1].y);
+    } else {
+        const double2 low = (m.q_prior && n_w > 2) ? val[2] : val[1];
+        H[(size_t)col * N + row] = make_double2(low.x, -low.y);     // Q^dagger or the prior form
+    }
 }
 
 // grid: x = [nbF Frow blocks | nbP phase blocks | G blocks], y = job.

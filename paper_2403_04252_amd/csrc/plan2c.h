@@ -53,6 +53,8 @@ struct Meta2C {
     int f_pa, f_pb;          // first Legendre field of each side
     int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
     int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
+    int mirror;              // prior form of one basis on both centres: lower-left
+                             // block (-1)^(l_i + l_j) Q_ij, no third weight (k_2c_assemble)
     int mixed;               // 1: contraction products in FP32 (chunk sums promoted to FP64)
     // contraction blocks: rows of block s are the radial functions a >= radT_off[s]
     int radT_off[kMaxL + 2], radP_off[kMaxL + 2];

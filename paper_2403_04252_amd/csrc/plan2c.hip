@@ -227,8 +227,8 @@ int check_basis(const HostBasis& hb, const char* who) {
 }
 
 // Meta2C of one basis pair.
-void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, int mixed, Meta2C& m,
-               std::vector<int2>& tiles) {
+void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, int mirror, int mixed,
+               Meta2C& m, std::vector<int2>& tiles) {
     std::memset(&m, 0, sizeof m);
     m.LT = tb.spec.l_max;
     m.LP = pb.spec.l_max;
@@ -250,7 +250,8 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     m.f_pa = kFJ + 2 * m.L + 1;
     m.f_pb = m.f_pa + (m.LT + 1) * (m.LT + 2) / 2;
     m.n_fields = m.f_pb + (m.LP + 1) * (m.LP + 2) / 2;
-    m.n_w = q_prior ? 3 : 2;
+    m.mirror = q_prior && mirror;
+    m.n_w = (q_prior && !m.mirror) ? 3 : 2;
     m.q_prior = q_prior;
     m.mixed = mixed;
     for (int l = 0; l <= kMaxL + 1; ++l) {
@@ -314,7 +315,9 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     int rc;
     if ((rc = centre_build(*g.tb, st, g.cT))) return rc;
     if ((rc = centre_build(*g.pb, st, g.cP))) return rc;
-    fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, p->mixed, g.m, g.tiles);
+    // one basis object on both centres: the prior block follows from Q by the
+    // tau -> -tau symmetry of the quadrature (k_2c_assemble)
+    fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, g.tb == g.pb, p->mixed, g.m, g.tiles);
     long long& tot = p->bytes;
     tot += g.cT.bytes + g.cP.bytes;
     const Meta2C& m = g.m;

@@ -509,3 +509,42 @@ def test_2c_symmetric_refusals(bases):
         with pytest.raises(W.WpcccError) as e:
             W.wpccc_plan_create_2c([lt], [lp], 0, [1.0], [1.0], n_eta=24, n_tau=32, symmetric=True, dz_sym=dz)
         assert e.value.code == -1
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_2c_mirrored_prior_block(mixed):
+    """A set whose target and projectile are the same basis object takes the
+    prior lower-left block from Q by the tau -> -tau symmetry (two weights in
+    the contraction instead of three); the same recipe as two basis objects
+    computes the third weight.  S and H at three positions agree to 1e-13 of
+    max|H| (FP64; 1e-6 for the FP32 products, whose chunk sums round
+    differently for the two weights), and a 20-step propagation's
+    probabilities to 1e-12 (FP64)."""
+    rec = WL.Recipe(3, 2, 4, 2.0, 600, 40.0)
+    b1, b2 = lib_basis(rec), lib_basis(rec)
+    bs, vs = np.array([0.7, 2.2]), np.array([1.0, 0.5])
+    mir = W.wpccc_plan_create_2c([b1], [b1], 0, bs, vs, q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=32, mixed=mixed)
+    ful = W.wpccc_plan_create_2c([b1], [b2], 0, bs, vs, q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=32, mixed=mixed)
+    bar = 1e-6 if mixed else 1e-13
+    for j in range(2):
+        for z in (-1.5, 0.0, 0.8):
+            Sm, Hm = gpu_matrices(mir, j, z)
+            Sf, Hf = gpu_matrices(ful, j, z)
+            dS = np.abs(Sm - Sf).max()
+            dH = np.abs(Hm - Hf).max() / np.abs(Hf).max()
+            print(f"mirrored prior block mixed={mixed} path {j} z={z}: |dS| {dS:.1e}, |dH|/max {dH:.1e}", flush=True)
+            assert dS <= (1e-6 if mixed else 1e-14) and dH <= bar
+    if mixed:
+        return
+    zg = WL.z_uniform(-1.0, 1.0, 0.1)
+    P = []
+    for plan in (mir, ful):
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        Pp = torch.empty((plan.n_traj, plan.n_pad), dtype=torch.float64, device="cuda")
+        W.wpccc_propagate(plan, zg, X, Pp)
+        W.wpccc_plan_status(plan)
+        P.append(Pp.cpu().numpy())
+    d = np.abs(P[0] - P[1]).max()
+    print(f"  20 steps: max|dP| {d:.1e}", flush=True)
+    assert d <= 1e-12

@@ -270,3 +270,20 @@ def test_symmetric_form_reproduces_prior_form_on_eigenstates(bound2, z):
     dK = (Sp - Sm)[:n, n:] / 2e-3
     assert np.abs((Hs_dag - Hd)[:n, n:] + 0.5j * v * dK).max() <= 1e-6 * scale
     assert np.abs(dK).max() > 1e-2
+
+
+def test_prior_block_mirrors_q_on_one_basis(mixed):
+    """With one basis on both centres the spheroidal quadrature is symmetric
+    under tau -> -tau, which exchanges the centres, turns the target
+    potential's weight into the projectile's and conjugates the translation
+    phase: the prior lower-left block is then (-1)^(l_i + l_j) Q_ij (the same
+    indices), to rounding.  With the dagger form the block is Q^dagger, which
+    differs."""
+    b = mixed
+    par = np.concatenate([np.full((2 * l + 1) * b.n_per_l[l], (-1.0) ** l) for l in range(b.spec.l_max + 1)])
+    n = b.n_states
+    for bb, z, v in ((1.3, -0.7, 1.0), (0.6, 2.1, 0.5)):
+        _, H = two_centre_matrices(b, b, bb, z, v, 24, 32, q_lower=Q_PRIOR)
+        Q, L = H[:n, n:], H[n:, :n]
+        assert np.abs(L - par[:, None] * Q * par[None, :]).max() <= 1e-14 * np.abs(Q).max()
+        assert np.abs(L - Q.conj().T).max() > 1e-3 * np.abs(Q).max()
