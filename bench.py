@@ -686,18 +686,21 @@ def n_per_l(rec):
     return [max(0, rec.n_max - l) + rec.n_bins for l in range(rec.l_max + 1)]
 
 
-def contract_flops(recT, recP, n_w, n_act):
+def contract_flops(recT, recP, n_w, n_act, mirror=False):
     """Algorithmic flops of the Eq. K2 contraction of one position: for molecular
     |q'| = s, |q| = t, 2 * nk(s, t) * nA[s] * nB[t] per active node, nA[s] = radial
     functions of the target with l >= s; nk = 2 n_w weights (cos, sin) per
-    Bessel order, one order when s t = 0 and two (|s-t|, s+t) otherwise."""
+    Bessel order, one order when s t = 0 and two (|s-t|, s+t) otherwise.
+    mirror (one basis on both centres): the blocks s > t take their overlap
+    from block (t, s), one weight fewer."""
     nlT, nlP = n_per_l(recT), n_per_l(recP)
     nA = [sum(nlT[s:]) for s in range(len(nlT))]
     nB = [sum(nlP[t:]) for t in range(len(nlP))]
     tot = 0
     for s in range(len(nA)):
         for t in range(len(nB)):
-            nk = (2 if s > 0 and t > 0 else 1) * 2 * n_w
+            nwb = n_w - (1 if mirror and s > t else 0)
+            nk = (2 if s > 0 and t > 0 else 1) * 2 * nwb
             tot += 2 * nk * nA[s] * nB[t]
     return tot * n_act
 
@@ -804,8 +807,9 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
     # algorithmic flops of the contraction over the timed steps: the first step
     # computes z, z_mid, z_new, later steps z_mid and z_new
     # the plan is given one basis object per size for both centres, so the
-    # prior block comes from Q by symmetry: two weights in the contraction
-    n_w = 2
+    # prior block comes from Q by symmetry (two weights in the contraction)
+    # and the overlap of the blocks s > t from block (t, s)
+    n_w, mirror = 2, w.q_lower == "prior"
     xl = roots_laguerre(w.n_eta)[0]
     fl = 0
     for i in range(steps):
@@ -816,7 +820,7 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
                 R = math.hypot(w.b[j], z)
                 lim = (2 * rec.r_max - R) * (1.0 + 1e-12) + 1e-12
                 n_act = int(np.sum(xl <= lim)) * w.n_tau
-                fl += contract_flops(rec, rec, n_w, n_act)
+                fl += contract_flops(rec, rec, n_w, n_act, mirror)
     c_ms = kt["k_2c_contract"]["total_ms"]
     achieved = fl / (c_ms * 1e-3) / 1e12
     peak = FP32_MFMA_PEAK_TFLOPS if mixed else FP64_VECTOR_PEAK_TFLOPS
