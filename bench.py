@@ -809,7 +809,7 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
     # the plan is given one basis object per size for both centres, so the
     # prior block comes from Q by symmetry (two weights in the contraction)
     # and the overlap of the blocks s > t from block (t, s)
-    n_w, mirror = 2, w.q_lower == "prior"
+    n_w, mirror = 2, True
     xl = roots_laguerre(w.n_eta)[0]
     fl = 0
     for i in range(steps):

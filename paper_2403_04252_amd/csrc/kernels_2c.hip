@@ -323,7 +323,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     auto& fl = L.fl;
     auto& wk = L.wk;
     const Meta2C& m = *a.m;
-    const int w0 = st_w0(m.mirror, s, t), n_w = m.n_w - w0;   // weights [w0, m.n_w) of this block
+    const int w0 = st_w0(m.same, s, t), n_w = m.n_w - w0;   // weights [w0, m.n_w) of this block
     const int nk = st_nk(s, t, n_w);
     const int o1 = abs(s - t), o2 = s + t;
     const int nA = m.nA[s], nB = m.nB[t];
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kStageThreads2C, MIXED ? 2 : 3) void k_2c_contract(
 #define WPCCC_TILE2(KPW)                                                                          \
     if (!MIXED || c2) contract_tile<MIXED, KPW, 2, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);         \
     else contract_tile<MIXED, KPW, 2, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
-    switch (st_nk(s, t, m.n_w - st_w0(m.mirror, s, t))) {
+    switch (st_nk(s, t, m.n_w - st_w0(m.same, s, t))) {
         case 2: WPCCC_TILE2(1) break;
         case 4: WPCCC_TILE4(1) break;
         case 6: WPCCC_TILE2(3) break;
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
             const int nBt = m.nB[t];
             const size_t blk = (size_t)m.nA[s] * nBt;
             const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
-            const int w0 = st_w0(m.mirror, s, t), nwb = n_w - w0;
+            const int w0 = st_w0(m.same, s, t), nwb = n_w - w0;
             for (int w = w0; w < n_w; ++w) {
                 const double tc = base[(size_t)((order * 2 + 0) * nwb + w - w0) * blk];
                 const double ts = base[(size_t)((order * 2 + 1) * nwb + w - w0) * blk];

@@ -53,9 +53,10 @@ struct Meta2C {
     int f_pa, f_pb;          // first Legendre field of each side
     int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
     int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
-    int mirror;              // prior form of one basis on both centres: lower-left
-                             // block (-1)^(l_i + l_j) Q_ij, no third weight, and the
-                             // overlap of blocks s > t from block (t, s) (k_2c_assemble)
+    int same;                // one basis object on both centres: the overlap of the
+                             // blocks s > t from block (t, s) (k_2c_assemble)
+    int mirror;              // same and the prior form: lower-left block
+                             // (-1)^(l_i + l_j) Q_ij, no third weight (k_2c_assemble)
     int mixed;               // 1: contraction products in FP32 (chunk sums promoted to FP64)
     // contraction blocks: rows of block s are the radial functions a >= radT_off[s]
     int radT_off[kMaxL + 2], radP_off[kMaxL + 2];
@@ -76,9 +77,9 @@ struct Meta2C {
 // index ((order * 2 + trig) * n_w + w)
 __host__ __device__ inline int st_nk(int s, int t, int n_w) { return ((s > 0 && t > 0) ? 2 : 1) * 2 * n_w; }
 // first weight the contraction forms for block (s, t): with one basis on both
-// centres (mirror) the overlap of the blocks s > t is block (t, s) transposed
+// centres (same) the overlap of the blocks s > t is block (t, s) transposed
 // (k_2c_assemble), so those blocks hold only the target-potential weight
-__host__ __device__ inline int st_w0(int mirror, int s, int t) { return (mirror && s > t) ? 1 : 0; }
+__host__ __device__ inline int st_w0(int same, int s, int t) { return (same && s > t) ? 1 : 0; }
 
 struct Jobs {
     int path0;       // first local path of the launch

@@ -227,7 +227,7 @@ int check_basis(const HostBasis& hb, const char* who) {
 }
 
 // Meta2C of one basis pair.
-void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, int mirror, int mixed,
+void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, int q_prior, int same, int mixed,
                Meta2C& m, std::vector<int2>& tiles) {
     std::memset(&m, 0, sizeof m);
     m.LT = tb.spec.l_max;
@@ -250,7 +250,8 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     m.f_pa = kFJ + 2 * m.L + 1;
     m.f_pb = m.f_pa + (m.LT + 1) * (m.LT + 2) / 2;
     m.n_fields = m.f_pb + (m.LP + 1) * (m.LP + 2) / 2;
-    m.mirror = q_prior && mirror;
+    m.same = same;
+    m.mirror = q_prior && same;
     m.n_w = (q_prior && !m.mirror) ? 3 : 2;
     m.q_prior = q_prior;
     m.mixed = mixed;
@@ -271,7 +272,7 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     for (int s = 0; s <= m.LT; ++s)
         for (int t = 0; t <= m.LP; ++t) {
             m.st_off[s][t] = off;
-            off += st_nk(s, t, m.n_w - st_w0(m.mirror, s, t)) * m.nA[s] * m.nB[t];
+            off += st_nk(s, t, m.n_w - st_w0(m.same, s, t)) * m.nA[s] * m.nB[t];
             for (int a0 = 0; a0 < m.nA[s]; a0 += kTile)
                 for (int b0 = 0; b0 < m.nB[t]; b0 += kTile) tiles.push_back(make_int2(s | (t << 8), a0 | (b0 << 16)));
         }
@@ -315,8 +316,9 @@ int build_group(Plan2C* p, Group2C& g, hipStream_t st) {
     int rc;
     if ((rc = centre_build(*g.tb, st, g.cT))) return rc;
     if ((rc = centre_build(*g.pb, st, g.cP))) return rc;
-    // one basis object on both centres: the prior block follows from Q by the
-    // tau -> -tau symmetry of the quadrature (k_2c_assemble)
+    // one basis object on both centres: the overlap of the blocks s > t and
+    // the prior block follow by the tau -> -tau symmetry of the quadrature
+    // (k_2c_assemble)
     fill_meta(*g.tb, *g.pb, p->n_eta, p->n_tau, p->q_prior, g.tb == g.pb, p->mixed, g.m, g.tiles);
     long long& tot = p->bytes;
     tot += g.cT.bytes + g.cP.bytes;
