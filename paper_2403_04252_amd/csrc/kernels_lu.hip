@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_lu_update(LUStepArgs a) {
 // columns j < nt, i.e. |K^dagger| <= 1); where set, the identity permutation
 // and the diagonal pivots of the first nt columns are written here (the panel
 // steps that would write them return at once).
-__global__ __launch_bounds__(256) void k_lu_check(LUStepArgs a) {
+__global__ __launch_bounds__(1024) void k_lu_check(LUStepArgs a) {
     __shared__ int bad;
     int pl, slot;
     job_of(a.jobs, blockIdx.x, pl, slot);
@@ -322,12 +322,16 @@ __global__ __launch_bounds__(256) void k_lu_check(LUStepArgs a) {
     const int t = threadIdx.x;
     if (t == 0) bad = 0;
     __syncthreads();
+    // every element of the block independent of the others (all loads in
+    // flight at once; consecutive threads read consecutive rows of a column)
     int b = 0;
-    for (int j = 0; j < nt && !b; ++j)
-        for (int i = nt + t; i < N; i += blockDim.x) {
-            const double2 x = A[i + (size_t)j * N];
-            if (!(x.x * x.x + x.y * x.y <= 1.0)) b = 1;
-        }
+    const int nr = N - nt;
+    const long long n_el = (long long)nt * nr;
+    for (long long e = t; e < n_el; e += blockDim.x) {
+        const int j = (int)(e / nr), i = nt + (int)(e - (long long)j * nr);
+        const double2 x = A[i + (size_t)j * N];
+        b |= !(x.x * x.x + x.y * x.y <= 1.0);
+    }
     if (b) atomicOr(&bad, 1);
     __syncthreads();
     const int ok = bad ? 0 : 1;
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(256) void k_lu_rhs(RhsArgs a) {
 }  // namespace
 
 hipError_t launch_lu_check(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    WPCCC_LAUNCH(ev, k_lu_check, dim3(n_jobs), dim3(256), 0, st, a);
+    WPCCC_LAUNCH(ev, k_lu_check, dim3(n_jobs), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 
