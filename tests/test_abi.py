@@ -79,16 +79,37 @@ def test_plan_without_gpu_fails_loudly(lib):
 
 
 @pytest.mark.parametrize("bad", [dict(q_lower=2), dict(n_eta=2), dict(n_tau=5000), dict(sets=[1]),
-                                 dict(b=[0.0]), dict(v=[-1.0])])
+                                 dict(b=[0.0]), dict(v=[-1.0]), dict(b=[], v=[], sets=[]), dict(solve=2),
+                                 dict(batched=3), dict(symmetric=True, dz_sym=0.5),
+                                 dict(symmetric=True, dz_sym=-1e-4)])
 def test_two_centre_plan_arguments_rejected(lib, bad):
     """Argument checks of wpccc_plan_create_2c run on the host, before any device call."""
     hb = W.wpccc_basis(W.BasisSpec(2, 1, 2, 1.0, 100, 50.0))
-    kw = dict(q_lower=0, n_eta=8, n_tau=8, sets=[0], b=[1.0], v=[1.0])
+    kw = dict(q_lower=0, n_eta=8, n_tau=8, sets=[0], b=[1.0], v=[1.0], solve=0, batched=True,
+              symmetric=False, dz_sym=0.0)
     kw.update(bad)
     with pytest.raises(W.WpcccError) as ei:
         W.wpccc_plan_create_2c([hb], [hb], kw["sets"], kw["b"], kw["v"], q_lower=kw["q_lower"],
-                               n_eta=kw["n_eta"], n_tau=kw["n_tau"], stream=0)
+                               n_eta=kw["n_eta"], n_tau=kw["n_tau"], solve=kw["solve"], batched=kw["batched"],
+                               symmetric=kw["symmetric"], dz_sym=kw["dz_sym"], stream=0)
     assert ei.value.code == -1
+
+
+def test_two_centre_symmetric_refusals_on_host(lib):
+    """The symmetric form with reduced precision or graph replay is refused on the host."""
+    hb = W.wpccc_basis(W.BasisSpec(2, 1, 2, 1.0, 100, 50.0))
+    for kw in (dict(mixed=True), dict(graph=True)):
+        with pytest.raises(W.WpcccError) as ei:
+            W.wpccc_plan_create_2c([hb], [hb], [0], [1.0], [1.0], n_eta=8, n_tau=8, symmetric=True, stream=0, **kw)
+        assert ei.value.code == -6
+
+
+def test_zgesv_arguments_rejected_on_host(lib):
+    """wpccc_zgesv_batched checks its sizes and pointers before any device call."""
+    assert lib.wpccc_zgesv_batched(0, 1, None, None, None, None) == -1
+    assert lib.wpccc_zgesv_batched(4, 0, None, None, None, None) == -1
+    assert lib.wpccc_zgesv_batched(4097, 1, 1, 1, 1, None) == -1
+    assert b"wpccc_zgesv_batched" in lib.wpccc_last_error()
 
 
 def test_two_centre_plan_without_gpu_fails_loudly(lib):
