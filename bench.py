@@ -691,15 +691,16 @@ def contract_flops(recT, recP, n_w, n_act, mirror=False):
     |q'| = s, |q| = t, 2 * nk(s, t) * nA[s] * nB[t] per active node, nA[s] = radial
     functions of the target with l >= s; nk = 2 n_w weights (cos, sin) per
     Bessel order, one order when s t = 0 and two (|s-t|, s+t) otherwise.
-    mirror (one basis on both centres): the blocks s > t take their overlap
-    from block (t, s), one weight fewer."""
+    mirror (one basis on both centres): the blocks s < t form three weights
+    (overlap, target and projectile potential), s = t two, and s > t none
+    (they follow from block (t, s))."""
     nlT, nlP = n_per_l(recT), n_per_l(recP)
     nA = [sum(nlT[s:]) for s in range(len(nlT))]
     nB = [sum(nlP[t:]) for t in range(len(nlP))]
     tot = 0
     for s in range(len(nA)):
         for t in range(len(nB)):
-            nwb = n_w - (1 if mirror and s > t else 0)
+            nwb = (3 if s < t else (2 if s == t else 0)) if mirror else n_w
             nk = (2 if s > 0 and t > 0 else 1) * 2 * nwb
             tot += 2 * nk * nA[s] * nB[t]
     return tot * n_act

@@ -323,7 +323,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     auto& fl = L.fl;
     auto& wk = L.wk;
     const Meta2C& m = *a.m;
-    const int w0 = st_w0(m.same, s, t), n_w = m.n_w - w0;   // weights [w0, m.n_w) of this block
+    const int n_w = st_nw(m.same, m.n_w, s, t);   // weights of this block (st_nw)
     const int nk = st_nk(s, t, n_w);
     const int o1 = abs(s - t), o2 = s + t;
     const int nA = m.nA[s], nB = m.nB[t];
@@ -358,7 +358,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 #pragma unroll
     for (int q = 0; q < kWIt; ++q) {
         const int kk = ffi + q * kFStep;
-        const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = w0 + kk % n_w;
+        const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
         wsel[q] = kk < nk ? (5 + order) | (trig << 4) | ((2 + w) << 8) : -1;
     }
     // this wave's weights and subtiles
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kStageThreads2C, MIXED ? 2 : 3) void k_2c_contract(
 #define WPCCC_TILE2(KPW)                                                                          \
     if (!MIXED || c2) contract_tile<MIXED, KPW, 2, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);         \
     else contract_tile<MIXED, KPW, 2, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
-    switch (st_nk(s, t, m.n_w - st_w0(m.same, s, t))) {
+    switch (st_nk(s, t, st_nw(m.same, m.n_w, s, t))) {
         case 2: WPCCC_TILE2(1) break;
         case 4: WPCCC_TILE4(1) break;
         case 6: WPCCC_TILE2(3) break;
@@ -592,25 +592,32 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
             const double pr = (n4 == 0) ? 1.0 : (n4 == 2 ? -1.0 : 0.0);
             const double pi = (n4 == 1) ? -1.0 : (n4 == 3 ? 1.0 : 0.0);
             const int nBt = m.nB[t];
-            const size_t blk = (size_t)m.nA[s] * nBt;
-            const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
-            const int w0 = st_w0(m.same, s, t), nwb = n_w - w0;
-            for (int w = w0; w < n_w; ++w) {
-                const double tc = base[(size_t)((order * 2 + 0) * nwb + w - w0) * blk];
-                const double ts = base[(size_t)((order * 2 + 1) * nwb + w - w0) * blk];
-                acc[w][0] += c * (pr * tc - pi * ts);
-                acc[w][1] += c * (pr * ts + pi * tc);
-            }
-            if (w0) {
-                // one basis on both centres: tau -> -tau gives the overlap sums
-                // T_(s,t)[a][b] = (-1)^(l_a+s+l_b+t) (+cos, -sin) T_(t,s)[b][a]
+            const int nwb = st_nw(m.same, n_w, s, t);
+            if (nwb) {
+                const size_t blk = (size_t)m.nA[s] * nBt;
+                const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
+                for (int w = 0; w < n_w; ++w) {
+                    const double tc = base[(size_t)((order * 2 + 0) * nwb + w) * blk];
+                    const double ts = base[(size_t)((order * 2 + 1) * nwb + w) * blk];
+                    acc[w][0] += c * (pr * tc - pi * ts);
+                    acc[w][1] += c * (pr * ts + pi * tc);
+                }
+            } else {
+                // one basis on both centres, s > t: tau -> -tau exchanges the
+                // centres, so T_(s,t),W[a][b] = (-1)^(l_a+s+l_b+t) (+cos, -sin)
+                // T_(t,s),W'[b][a] with W' = W for the overlap and the
+                // projectile potential for the target potential
+                const int nw2 = st_nw(m.same, n_w, t, s);
                 const size_t blk2 = (size_t)m.nA[t] * m.nB[s];
                 const double* base2 = tm + m.st_off[t][s] + (size_t)jt * m.nB[s] + is;
                 const double sg = ((la + s + lb + t) & 1) ? -1.0 : 1.0;
-                const double tc = sg * base2[(size_t)((order * 2 + 0) * n_w) * blk2];
-                const double ts = -sg * base2[(size_t)((order * 2 + 1) * n_w) * blk2];
-                acc[0][0] += c * (pr * tc - pi * ts);
-                acc[0][1] += c * (pr * ts + pi * tc);
+                for (int w = 0; w < n_w; ++w) {
+                    const int w2 = w == 0 ? 0 : 2;
+                    const double tc = sg * base2[(size_t)((order * 2 + 0) * nw2 + w2) * blk2];
+                    const double ts = -sg * base2[(size_t)((order * 2 + 1) * nw2 + w2) * blk2];
+                    acc[w][0] += c * (pr * tc - pi * ts);
+                    acc[w][1] += c * (pr * ts + pi * tc);
+                }
             }
         }
     }

@@ -53,8 +53,8 @@ struct Meta2C {
     int f_pa, f_pb;          // first Legendre field of each side
     int n_w;                 // 2 (overlap, target potential) or 3 (+ projectile potential)
     int q_prior;             // lower-left block: 0 Q^dagger, 1 prior form
-    int same;                // one basis object on both centres: the overlap of the
-                             // blocks s > t from block (t, s) (k_2c_assemble)
+    int same;                // one basis object on both centres: blocks s > t from
+                             // blocks (t, s) (st_nw, k_2c_assemble)
     int mirror;              // same and the prior form: lower-left block
                              // (-1)^(l_i + l_j) Q_ij, no third weight (k_2c_assemble)
     int mixed;               // 1: contraction products in FP32 (chunk sums promoted to FP64)
@@ -76,10 +76,15 @@ struct Meta2C {
 // each with cos and sin of (v z / 2) eta tau, each with the n_w weights;
 // index ((order * 2 + trig) * n_w + w)
 __host__ __device__ inline int st_nk(int s, int t, int n_w) { return ((s > 0 && t > 0) ? 2 : 1) * 2 * n_w; }
-// first weight the contraction forms for block (s, t): with one basis on both
-// centres (same) the overlap of the blocks s > t is block (t, s) transposed
-// (k_2c_assemble), so those blocks hold only the target-potential weight
-__host__ __device__ inline int st_w0(int same, int s, int t) { return (same && s > t) ? 1 : 0; }
+// weights the contraction forms and stores for block (s, t), in the order
+// overlap, target potential, projectile potential.  With one basis on both
+// centres (same) exchanging the centres maps block (s, t) to block (t, s)
+// transposed, the overlap to itself and the target potential to the
+// projectile's (k_2c_assemble): the blocks s < t form all three, the blocks
+// s = t the first two, the blocks s > t none.
+__host__ __device__ inline int st_nw(int same, int n_w, int s, int t) {
+    return same ? (s < t ? 3 : (s == t ? 2 : 0)) : n_w;
+}
 
 struct Jobs {
     int path0;       // first local path of the launch

@@ -272,7 +272,9 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
     for (int s = 0; s <= m.LT; ++s)
         for (int t = 0; t <= m.LP; ++t) {
             m.st_off[s][t] = off;
-            off += st_nk(s, t, m.n_w - st_w0(m.same, s, t)) * m.nA[s] * m.nB[t];
+            const int nw = st_nw(m.same, m.n_w, s, t);
+            if (!nw) continue;   // formed from block (t, s)
+            off += st_nk(s, t, nw) * m.nA[s] * m.nB[t];
             for (int a0 = 0; a0 < m.nA[s]; a0 += kTile)
                 for (int b0 = 0; b0 < m.nB[t]; b0 += kTile) tiles.push_back(make_int2(s | (t << 8), a0 | (b0 << 16)));
         }
