@@ -123,66 +123,96 @@ __global__ __launch_bounds__(256) void k_2c_nodes(NodeArgs a) {
 }
 
 // Interpolated operands of one position.  grid: x = blocks of 64 nodes,
-// y = blocks of 64 rows (side T, then side P), z = job.  Each wave takes 16
-// nodes; per node its 64 lanes are 64 rows, so the five stencil values of
-// consecutive radial functions are consecutive doubles of phiT (coalesced).
-// The Legendre factors are staged through LDS with lanes over nodes, and the
-// 64 x 64 result tile is written back row by row with lanes over nodes.
+// y = blocks of 64 radial functions (side T, then side P), z = job.  Each wave
+// takes 16 nodes; per node its 64 lanes are 64 radial functions, so the five
+// stencil values of consecutive functions are consecutive doubles of phiT
+// (coalesced).  The interpolated f_a(r) of the 64 x 64 tile is formed once in
+// LDS and written, times the Legendre factor, to the rows of every block s
+// whose radial functions (l_a >= s) it holds, row by row with lanes over
+// nodes; per s the factors Pbar_l^s of the tile's l range are staged in LDS
+// first (over the stencil weights).
 template <typename T>
 __global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
     __shared__ double tile[64][65];
-    __shared__ double sL[64][5];
-    __shared__ int sj[64];
+    // stencil weights (until f_a(r) is formed), then the Legendre factors
+    __shared__ union {
+        double L[64][5];
+        double P[kMaxL + 1][64];
+    } u;
+    auto& sL = u.L;
+    auto& sP = u.P;
+    __shared__ int sj[64], sl[64];
     const Meta2C& m = *a.m;
     const int y = blockIdx.z;
     const int nact = a.n_act[y];
     const int p0 = blockIdx.x * 64;
     if (p0 >= nact) return;
-    const int nbT = (m.rowsT + 63) / 64;
+    const int nbT = (m.nfT + 63) / 64;
     const bool sideP = (int)blockIdx.y >= nbT;
-    const int r0 = (sideP ? blockIdx.y - nbT : blockIdx.y) * 64;
-    const int rows = sideP ? m.rowsP : m.rowsT;
+    const int f0 = (sideP ? blockIdx.y - nbT : blockIdx.y) * 64;
     const int nf = sideP ? m.nfP : m.nfT;
+    const int ls = sideP ? m.LP : m.LT;
+    const int rows = sideP ? m.rowsP : m.rowsT;
+    const int fP = sideP ? m.f_pb : m.f_pa;
+    const int* rad_off = sideP ? m.radP_off : m.radT_off;
+    const int* row_off = sideP ? m.rowP_off : m.rowT_off;
     const double* phiT = sideP ? a.phiT_P : a.phiT_T;
-    const int2* rinfo = sideP ? a.rinfoP : a.rinfoT;
     const size_t nn = m.n_nodes;
     const double* nd = a.nodes + (size_t)y * m.n_fields * nn;
     const int* js = a.jst + (size_t)y * 2 * nn + (sideP ? nn : 0);
     const int fL = sideP ? kFLB : kFLA;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // stencils of the 64 nodes
+    const int fend = min(f0 + 64, nf);
+    // l of the tile's first and last function (functions are ordered by l)
+    int l_lo = 0, l_hi = 0;
+    while (l_lo < ls && rad_off[l_lo + 1] <= f0) ++l_lo;
+    while (l_hi < ls && rad_off[l_hi + 1] <= fend - 1) ++l_hi;
+    // stencils of the 64 nodes, l of the 64 functions
     for (int e = tid; e < 64 * 5; e += blockDim.x) {
         const int k = e % 64, q = e / 64, p = p0 + k;
         sL[k][q] = (p < nact) ? nd[(size_t)(fL + q) * nn + p] : 0.0;
     }
     if (tid < 64) sj[tid] = (p0 + tid < nact) ? js[p0 + tid] : -1;
-    // Legendre factor of each (row, node)
-    for (int e = tid; e < 64 * 64; e += blockDim.x) {
-        const int k = e % 64, r = e / 64, p = p0 + k;
-        double v = 0.0;
-        if (r0 + r < rows && p < nact) v = nd[(size_t)rinfo[r0 + r].y * nn + p];
-        tile[r][k] = v;
+    if (tid >= 64 && tid < 128) {
+        const int fa = f0 + tid - 64;
+        int l = l_lo;
+        while (l < l_hi && rad_off[l + 1] <= fa) ++l;
+        sl[tid - 64] = l;
     }
     __syncthreads();
-    const int r = lane;
-    const bool okr = r0 + r < rows;
-    const int arad = okr ? rinfo[r0 + r].x : 0;
+    // f_a(r) of function f0 + lane at the wave's 16 nodes
+    const int fa = f0 + lane;
     for (int kk = 0; kk < 16; ++kk) {
         const int k = wave * 16 + kk;
         const int j = sj[k];
         double v = 0.0;
-        if (okr && j >= 0) {
-            const double* f = phiT + (size_t)j * nf + arad;
-            v = (sL[k][0] * f[0] + sL[k][1] * f[nf] + sL[k][2] * f[2 * nf] + sL[k][3] * f[3 * nf] +
-                 sL[k][4] * f[4 * nf]) * tile[r][k];
+        if (fa < nf && j >= 0) {
+            const double* f = phiT + (size_t)j * nf + fa;
+            v = sL[k][0] * f[0] + sL[k][1] * f[nf] + sL[k][2] * f[2 * nf] + sL[k][3] * f[3 * nf] +
+                sL[k][4] * f[4 * nf];
         }
-        tile[r][k] = v;
+        tile[lane][k] = v;
     }
     __syncthreads();
+    // rows (s, a) for a in this tile and l_a >= s: functions [rad_off[s], nf)
     T* out = reinterpret_cast<T*>(sideP ? a.BT : a.AT) + (size_t)y * rows * nn;
-    for (int e = tid; e < 64 * 64; e += blockDim.x) {
-        const int k = e % 64, rr = e / 64, p = p0 + k;
-        if (r0 + rr < rows && p < nact) out[(size_t)(r0 + rr) * nn + p] = (T)tile[rr][k];
+    for (int s = 0; s <= l_hi; ++s) {
+        const int alo = max(f0, rad_off[s]);
+        const int cnt = fend - alo;
+        const int lb = max(l_lo, s), nl = l_hi - lb + 1;
+        // Pbar_l^s(cos theta) at the 64 nodes for l = lb .. l_hi
+        for (int e = tid; e < nl * 64; e += blockDim.x) {
+            const int k = e & 63, l = lb + (e >> 6), p = p0 + k;
+            sP[l - lb][k] = (p < nact) ? nd[(size_t)(fP + l * (l + 1) / 2 + s) * nn + p] : 0.0;
+        }
+        __syncthreads();
+        const int rbase = row_off[s] + alo - rad_off[s];
+        for (int e = tid; e < cnt * 64; e += blockDim.x) {
+            const int k = e & 63, i = e >> 6, p = p0 + k, ti = alo - f0 + i;
+            if (p < nact)
+                out[(size_t)(rbase + i) * nn + p] = sj[k] >= 0 ? (T)(tile[ti][k] * sP[sl[ti] - lb][k]) : (T)0;
+        }
+        __syncthreads();
     }
 }
 
@@ -1008,7 +1038,7 @@ hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipS
 }
 
 hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
-    const dim3 grid((hm.n_nodes + 63) / 64, (hm.rowsT + 63) / 64 + (hm.rowsP + 63) / 64, n_jobs), block(256);
+    const dim3 grid((hm.n_nodes + 63) / 64, (hm.nfT + 63) / 64 + (hm.nfP + 63) / 64, n_jobs), block(256);
     if (hm.mixed)
         WPCCC_LAUNCH(ev, k_2c_interp<float>, grid, block, 0, st, a);
     else

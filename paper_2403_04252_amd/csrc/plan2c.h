@@ -111,7 +111,9 @@ struct NodeArgs {
     int* n_act;           // [job] nodes in the active eta prefix
 };
 
-// k_2c_interp: the contraction operands of one position, once per job:
+// k_2c_interp: the contraction operands of one position, once per job (f_a
+// interpolated once per radial function and node, then scaled by the
+// Legendre factor of every block s it enters):
 //   AT[job][rowT_off[s] + i][p] = f_a(r_A(p)) Pbar_{l_a}^s(cos theta_A(p)),  a = radT_off[s] + i
 //   BT[job][rowP_off[t] + i][p] = f_b(r_B(p)) Pbar_{l_b}^t(cos theta_B(p)),  b = radP_off[t] + i
 // for active nodes p < n_act (node-contiguous rows, FP64, or FP32 in the mixed form).
