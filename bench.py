@@ -693,7 +693,9 @@ def contract_flops(recT, recP, n_w, n_act, mirror=False):
     Bessel order, one order when s t = 0 and two (|s-t|, s+t) otherwise.
     mirror (one basis on both centres): the blocks s < t form three weights
     (overlap, target and projectile potential), s = t two, and s > t none
-    (they follow from block (t, s))."""
+    (they follow from block (t, s)); in a block s = t the overlap is needed
+    only for a >= b (the element (a, b) follows from (b, a)), counted here
+    element by element although the kernel forms it in whole 32 x 32 tiles."""
     nlT, nlP = n_per_l(recT), n_per_l(recP)
     nA = [sum(nlT[s:]) for s in range(len(nlT))]
     nB = [sum(nlP[t:]) for t in range(len(nlP))]
@@ -701,8 +703,12 @@ def contract_flops(recT, recP, n_w, n_act, mirror=False):
     for s in range(len(nA)):
         for t in range(len(nB)):
             nwb = (3 if s < t else (2 if s == t else 0)) if mirror else n_w
-            nk = (2 if s > 0 and t > 0 else 1) * 2 * nwb
-            tot += 2 * nk * nA[s] * nB[t]
+            per = (2 if s > 0 and t > 0 else 1) * 2   # (order, trig) pairs
+            if mirror and s == t:
+                # target potential on the whole block, overlap on a >= b
+                tot += 2 * per * (nA[s] * nB[t] + nA[s] * (nA[s] + 1) // 2)
+            else:
+                tot += 2 * per * nwb * nA[s] * nB[t]
     return tot * n_act
 
 

@@ -343,8 +343,8 @@ __device__ __forceinline__ void chunk_mfma(const ContractLds<T, NC>& L, int mt0,
 // half lies outside the block skips its MFMAs (one branch per chunk).
 template <bool MIXED, int KPW, int SPW, int NA, int NV>
 __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, int t, int a0, int b0, bool r2, bool c2,
-                              ContractLds<typename std::conditional<MIXED, float, double>::type,
-                                          contract_chunk<MIXED>()>& L) {
+                              bool upper, ContractLds<typename std::conditional<MIXED, float, double>::type,
+                                                      contract_chunk<MIXED>()>& L) {
     typedef typename std::conditional<MIXED, float, double>::type T;
     constexpr int NC = contract_chunk<MIXED>();   // nodes per chunk
     constexpr int NPT = NC / 8;                   // nodes per loader thread and row
@@ -353,7 +353,10 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     auto& fl = L.fl;
     auto& wk = L.wk;
     const Meta2C& m = *a.m;
-    const int n_w = st_nw(m.same, m.n_w, s, t);   // weights of this block (st_nw)
+    // weights of this block (st_nw) and of this tile: all of them, or the
+    // target potential alone (weight 1) above the diagonal of a block (s, s)
+    // whose overlap follows from the transposed tile (overlap_mirrored)
+    const int n_w = upper ? 1 : st_nw(m.same, m.n_w, s, t), w0 = upper ? 1 : 0;
     const int nk = st_nk(s, t, n_w);
     const int o1 = abs(s - t), o2 = s + t;
     const int nA = m.nA[s], nB = m.nB[t];
@@ -389,7 +392,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
     for (int q = 0; q < kWIt; ++q) {
         const int kk = ffi + q * kFStep;
         const int order = kk / (2 * n_w), trig = (kk / n_w) & 1, w = kk % n_w;
-        wsel[q] = kk < nk ? (5 + order) | (trig << 4) | ((2 + w) << 8) : -1;
+        wsel[q] = kk < nk ? (5 + order) | (trig << 4) | ((2 + w0 + w) << 8) : -1;
     }
     // this wave's weights and subtiles
     const int kk0 = SPW == 4 ? wave * KPW : (wave & 1) * KPW;
@@ -446,6 +449,10 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 #pragma unroll
     for (int i = 0; i < KPW; ++i) {
         const int kk = kk0 + i;
+        // position of weight kk of the tile in the block's (order, trig, weight)
+        // layout: an upper tile's weight kk is the target potential (weight 1
+        // of the block's two) of (order, trig) = kk
+        const int ko = upper ? 2 * kk + 1 : kk;
 #pragma unroll
         for (int u = 0; u < NA; ++u)
 #pragma unroll
@@ -454,7 +461,7 @@ __device__ void contract_tile(const ContractArgs& a, int y, int piece, int s, in
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ii = a0 + (mt0 + u) * 16 + (MIXED ? mfma_row_f32(r, lane) : mfma_row_f64(r, lane));
-                    if (kk < nk && ii < nA && jj < nB) out[((size_t)kk * nA + ii) * nB + jj] = acc[i][u][v][r];
+                    if (kk < nk && ii < nA && jj < nB) out[((size_t)ko * nA + ii) * nB + jj] = acc[i][u][v][r];
                 }
             }
     }
@@ -486,21 +493,22 @@ __global__ __launch_bounds__(kStageThreads2C, MIXED ? 2 : 3) void k_2c_contract(
     const int rem = W - y * per_job;
     const int piece = rem / m.n_tiles;
     const int2 tl = a.tiles[rem - piece * m.n_tiles];
-    const int s = tl.x & 0xff, t = tl.x >> 8, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
+    const int s = tl.x & 0xff, t = (tl.x >> 8) & 0xff, a0 = tl.y & 0xffff, b0 = tl.y >> 16;
+    const bool upper = (tl.x & kTileUpper) != 0;
     __shared__ ContractLds<typename std::conditional<MIXED, float, double>::type, contract_chunk<MIXED>()> L;
     // second row / column half of the 32 x 32 tile inside the block
     const bool r2 = a0 + 16 < m.nA[s], c2 = b0 + 16 < m.nB[t];
     // FP32 products: one compiled variant per set of active subtiles; FP64:
     // one variant that tests r2 and c2 at run time
 #define WPCCC_TILE4(KPW)                                                                          \
-    if (!MIXED || (r2 && c2)) contract_tile<MIXED, KPW, 4, 2, 2>(a, y, piece, s, t, a0, b0, r2, c2, L); \
-    else if (r2) contract_tile<MIXED, KPW, 4, 2, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);              \
-    else if (c2) contract_tile<MIXED, KPW, 4, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);              \
-    else contract_tile<MIXED, KPW, 4, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
+    if (!MIXED || (r2 && c2)) contract_tile<MIXED, KPW, 4, 2, 2>(a, y, piece, s, t, a0, b0, r2, c2, upper, L); \
+    else if (r2) contract_tile<MIXED, KPW, 4, 2, 1>(a, y, piece, s, t, a0, b0, r2, c2, upper, L);              \
+    else if (c2) contract_tile<MIXED, KPW, 4, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, upper, L);              \
+    else contract_tile<MIXED, KPW, 4, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, upper, L);
 #define WPCCC_TILE2(KPW)                                                                          \
-    if (!MIXED || c2) contract_tile<MIXED, KPW, 2, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, L);         \
-    else contract_tile<MIXED, KPW, 2, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, L);
-    switch (st_nk(s, t, st_nw(m.same, m.n_w, s, t))) {
+    if (!MIXED || c2) contract_tile<MIXED, KPW, 2, 1, 2>(a, y, piece, s, t, a0, b0, r2, c2, upper, L);         \
+    else contract_tile<MIXED, KPW, 2, 1, 1>(a, y, piece, s, t, a0, b0, r2, c2, upper, L);
+    switch (st_nk(s, t, upper ? 1 : st_nw(m.same, m.n_w, s, t))) {
         case 2: WPCCC_TILE2(1) break;
         case 4: WPCCC_TILE4(1) break;
         case 6: WPCCC_TILE2(3) break;
@@ -626,9 +634,20 @@ __global__ __launch_bounds__(256) void k_2c_assemble(AssembleArgs a) {
             if (nwb) {
                 const size_t blk = (size_t)m.nA[s] * nBt;
                 const double* base = tm + m.st_off[s][t] + (size_t)is * nBt + jt;
+                // above the diagonal of a block (s, s) the overlap is that of
+                // (b, a) under the same exchange map (overlap_mirrored)
+                const bool ovl_t = overlap_mirrored(m.same, s, t, is, jt);
+                const double* bt = tm + m.st_off[s][t] + (size_t)jt * nBt + is;
+                const double sgt = ((la + lb) & 1) ? -1.0 : 1.0;
                 for (int w = 0; w < n_w; ++w) {
-                    const double tc = base[(size_t)((order * 2 + 0) * nwb + w) * blk];
-                    const double ts = base[(size_t)((order * 2 + 1) * nwb + w) * blk];
+                    double tc, ts;
+                    if (w == 0 && ovl_t) {
+                        tc = sgt * bt[(size_t)((order * 2 + 0) * nwb) * blk];
+                        ts = -sgt * bt[(size_t)((order * 2 + 1) * nwb) * blk];
+                    } else {
+                        tc = base[(size_t)((order * 2 + 0) * nwb + w) * blk];
+                        ts = base[(size_t)((order * 2 + 1) * nwb + w) * blk];
+                    }
                     acc[w][0] += c * (pr * tc - pi * ts);
                     acc[w][1] += c * (pr * ts + pi * tc);
                 }

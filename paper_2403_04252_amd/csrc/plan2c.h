@@ -85,6 +85,15 @@ __host__ __device__ inline int st_nk(int s, int t, int n_w) { return ((s > 0 && 
 __host__ __device__ inline int st_nw(int same, int n_w, int s, int t) {
     return same ? (s < t ? 3 : (s == t ? 2 : 0)) : n_w;
 }
+// The same map takes the overlap of a diagonal block (s, s) at (a, b) to the
+// overlap at (b, a), so a tile of such a block above its diagonal (a0 < b0)
+// forms the target potential only; k_2c_assemble reads the overlap there
+// from the transposed tile.  Contraction tiles: x = s | t << 8 | upper << 16,
+// y = a0 | b0 << 16.
+constexpr int kTileUpper = 1 << 16;
+__host__ __device__ inline bool overlap_mirrored(int same, int s, int t, int a, int b) {
+    return same && s == t && a / kTile < b / kTile;
+}
 
 struct Jobs {
     int path0;       // first local path of the launch

@@ -276,7 +276,9 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
             if (!nw) continue;   // formed from block (t, s)
             off += st_nk(s, t, nw) * m.nA[s] * m.nB[t];
             for (int a0 = 0; a0 < m.nA[s]; a0 += kTile)
-                for (int b0 = 0; b0 < m.nB[t]; b0 += kTile) tiles.push_back(make_int2(s | (t << 8), a0 | (b0 << 16)));
+                for (int b0 = 0; b0 < m.nB[t]; b0 += kTile)
+                    tiles.push_back(make_int2(s | (t << 8) | (overlap_mirrored(m.same, s, t, a0, b0) ? kTileUpper : 0),
+                                              a0 | (b0 << 16)));
         }
     m.n_tmol = off;
     m.n_tiles = (int)tiles.size();

@@ -511,18 +511,22 @@ def test_2c_symmetric_refusals(bases):
         assert e.value.code == -1
 
 
+@pytest.mark.parametrize("rec", [WL.Recipe(3, 2, 4, 2.0, 600, 40.0), WL.Recipe(4, 1, 36, 2.0, 600, 40.0)],
+                         ids=["one-tile", "multi-tile"])
 @pytest.mark.parametrize("n_tau", [40, 64])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_2c_mirrored_prior_block(mixed, n_tau):
+def test_2c_mirrored_prior_block(mixed, n_tau, rec):
     """A set whose target and projectile are the same basis object takes the
     prior lower-left block from Q by the tau -> -tau symmetry (two weights in
     the contraction instead of three); the same recipe as two basis objects
     computes the third weight; the overlap of the blocks s > t comes from
-    block (t, s) (two tau node counts).  S and H at three positions agree to 1e-13 of
+    block (t, s), and in the blocks s = t the overlap of the 32 x 32 tiles
+    above the diagonal from the transposed tile (the multi-tile recipe: 79
+    and 39 radial functions with l >= 0, 1, so three and two tiles per side;
+    two tau node counts).  S and H at three positions agree to 1e-13 of
     max|H| (FP64; 1e-6 for the FP32 products, whose chunk sums round
     differently for the two weights), and a 20-step propagation's
     probabilities to 1e-12 (FP64)."""
-    rec = WL.Recipe(3, 2, 4, 2.0, 600, 40.0)
     b1, b2 = lib_basis(rec), lib_basis(rec)
     bs, vs = np.array([0.7, 2.2]), np.array([1.0, 0.5])
     mir = W.wpccc_plan_create_2c([b1], [b1], 0, bs, vs, q_lower=W.WPCCC_Q_PRIOR, n_eta=24, n_tau=n_tau, mixed=mixed)
