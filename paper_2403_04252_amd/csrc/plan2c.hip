@@ -662,11 +662,12 @@ void commit_slots(Plan2C* p, const StepSlots& s, double z, double h) {
     p->slot_z[s.sn] = z + h;
 }
 
-// The four RK4 stages of a step for the np paths of pm.
+// The RK4 stages from `first` (1, or 2 when stage 1 ran already) of a step
+// for the np paths of pm.
 int enqueue_stages(Plan2C* p, const PathMats* pm, int np, int N_max, const StepSlots& ss, double h, double2* X,
-                   hipStream_t st) {
+                   hipStream_t st, int first = 1) {
     int rc;
-    if ((rc = enqueue_stage(p, pm, np, N_max, 1, ss.s0, h, X, X, p->d_Ua, st))) return rc;
+    if (first <= 1 && (rc = enqueue_stage(p, pm, np, N_max, 1, ss.s0, h, X, X, p->d_Ua, st))) return rc;
     if ((rc = enqueue_stage(p, pm, np, N_max, 2, ss.sm, h, p->d_Ua, X, p->d_Ub, st))) return rc;
     if ((rc = enqueue_stage(p, pm, np, N_max, 3, ss.sm, h, p->d_Ub, X, p->d_Ua, st))) return rc;
     return enqueue_stage(p, pm, np, N_max, 4, ss.sn, h, p->d_Ua, X, nullptr, st);
@@ -678,6 +679,11 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
     int rc;
     const bool fork = !p->gstreams.empty();
     if (fork) WPCCC_HIP_CHECK(hipEventRecord(p->fork_ev, st));
+    // stage 1 reads the couplings at z only: where they are held it runs on
+    // st while the group streams form those at z + h/2 and z + h (it touches
+    // none of their slots, and they none of its vectors)
+    const bool early1 = p->stage_all && ss.have0 && fork;
+    if (early1 && (rc = enqueue_stage(p, p->d_pm, p->n_traj, p->N_max, 1, ss.s0, h, X, X, p->d_Ua, st))) return rc;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         Group2C& g = p->groups[gi];
         hipStream_t gs = st;
@@ -718,7 +724,8 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
         }
     }
     // the stages of every group's paths in one launch each, after all couplings
-    if (p->stage_all && (rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, h, X, st))) return rc;
+    if (p->stage_all && (rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, h, X, st, early1 ? 2 : 1)))
+        return rc;
     return WPCCC_OK;
 }
 
