@@ -35,7 +35,7 @@ __device__ inline void job_of(const Jobs& J, int y, int& pl, int& slot, double& 
     pl = J.path0 + y / J.n_sub;
     const int sub = y % J.n_sub;
     slot = J.slot[sub];
-    z = J.zdev ? J.zdev[3 * (size_t)(*J.step) + sub] : J.z[sub];
+    z = J.zdev ? J.zdev[3 * (size_t)(*J.step + J.ahead) + sub] : J.z[sub];
 }
 
 // Lagrange weights at r for the nodes j0..j0+4 of r_i = rmax (i/nr)^2, j0 + 2

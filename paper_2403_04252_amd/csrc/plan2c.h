@@ -25,7 +25,9 @@ constexpr int kTile = 32;         // rows (target) and columns (projectile) per 
 // are added in a fixed order when the blocks are assembled)
 constexpr int kContractSplit = 8;
 constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
-constexpr int kSlots2C = 3;
+// coupling slots per path: a step reads three positions (z, z + h/2, z + h);
+// a pipelined graph step also forms the next step's last two
+constexpr int kSlots2C = 5;
 // lane layout of the FP32 16x16x4 MFMA result: 1 if register r of lane l holds
 // row 4 (l / 16) + r, 0 if it holds row 4 r + l / 16 (as the FP64 instruction)
 constexpr int kF32RowByLaneGroup = 1;
@@ -100,9 +102,11 @@ struct Jobs {
     int n_sub;       // 1 or 2 coupling positions per path
     int slot[2];
     double z[2];
-    // graph replays: z[sub] = zdev[3 * *step + sub] instead (nullptr: z[])
+    // graph replays: z[sub] = zdev[3 * (*step + ahead) + sub] instead
+    // (nullptr: z[]); ahead = 1 where a step forms the next step's couplings
     const double* zdev;
     const int* step;
+    int ahead;
 };
 
 struct NodeArgs {

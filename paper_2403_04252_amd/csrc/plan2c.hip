@@ -178,14 +178,23 @@ struct Plan2C {
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
     double slot_z[kSlots2C];
-    bool slot_ok[kSlots2C] = {false, false, false};
+    bool slot_ok[kSlots2C] = {};
     // graph replay of wpccc_propagate's steps (opts.graph): a step whose start
     // point is already held replays the graph captured for that slot (the
     // slots of z_mid and z_new follow from it); the step's z_mid, z_new and h
     // come from d_zh[3 * *d_step + k], and the graph's last node advances
     // *d_step.  A graph bakes in X and d_zh: either changing captures again.
     bool use_graph = false, capturing = false;
-    hipGraphExec_t gexec[kSlots2C] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[kSlots2C] = {};
+    // pipelined replays (one launch over every group's stages): graph step i
+    // runs the stages of step i and forms the couplings of step i + 1 on the
+    // group streams (zahead = 1 while such a graph is captured); one graph
+    // per slot assignment (pexec, keyed by pipe_key)
+    int zahead = 0;
+    std::vector<std::pair<int, hipGraphExec_t>> pexec;
+    hipStream_t pstream = nullptr;      // coupling stream of a one-group plan
+    hipEvent_t pfork = nullptr;
+    std::vector<hipEvent_t> pjoin;
     double2* gX = nullptr;
     hipStream_t gcap = nullptr;
     double* d_zh = nullptr;
@@ -407,6 +416,7 @@ int enqueue_couplings(Plan2C* p, Group2C& g, int l0, int np, int n_sub, const in
     if (p->capturing && n_sub == 2) {
         J.zdev = p->d_zh;
         J.step = p->d_step;
+        J.ahead = p->zahead;
     }
     const int nj = np * n_sub;
     int rc;
@@ -640,7 +650,7 @@ struct StepSlots {
 
 StepSlots slots_with_start(int s0, bool have0) {
     StepSlots s{have0, s0, -1, -1};
-    for (int k = 0; k < kSlots2C; ++k) {
+    for (int k = 0; k < kSlots2C && s.sn < 0; ++k) {
         if (k == s0) continue;
         if (s.sm < 0) s.sm = k;
         else s.sn = k;
@@ -674,7 +684,8 @@ int enqueue_stages(Plan2C* p, const PathMats* pm, int np, int N_max, const StepS
 }
 
 // The launches of one RK4 step of every path in the given slots.
-int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlots& ss, hipStream_t st) {
+int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlots& ss, hipStream_t st,
+                       bool with_stages = true) {
     const double zm = z + 0.5 * h, zn = z + h;
     int rc;
     const bool fork = !p->gstreams.empty();
@@ -682,7 +693,7 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
     // stage 1 reads the couplings at z only: where they are held it runs on
     // st while the group streams form those at z + h/2 and z + h (it touches
     // none of their slots, and they none of its vectors)
-    const bool early1 = p->stage_all && ss.have0 && fork;
+    const bool early1 = with_stages && p->stage_all && ss.have0 && fork;
     if (early1 && (rc = enqueue_stage(p, p->d_pm, p->n_traj, p->N_max, 1, ss.s0, h, X, X, p->d_Ua, st))) return rc;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         Group2C& g = p->groups[gi];
@@ -714,7 +725,7 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
                                  (rc = enqueue_symm(p, g, l0, np, ss.sn, 1, gs)) ||
                                  (rc = enqueue_rhs(p, g, l0, np, 2, sl, gs))))
                 return rc;
-            if (!p->stage_all &&
+            if (with_stages && !p->stage_all &&
                 (rc = enqueue_stages(p, p->d_pm + p->pm_first[gi] + l0, np, g.m.N, ss, h, X, gs)))
                 return rc;
         }
@@ -724,7 +735,8 @@ int enqueue_step_slots(Plan2C* p, double2* X, double z, double h, const StepSlot
         }
     }
     // the stages of every group's paths in one launch each, after all couplings
-    if (p->stage_all && (rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, h, X, st, early1 ? 2 : 1)))
+    if (with_stages && p->stage_all &&
+        (rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, h, X, st, early1 ? 2 : 1)))
         return rc;
     return WPCCC_OK;
 }
@@ -744,7 +756,73 @@ void drop_graphs(Plan2C* p) {
         if (p->gexec[s]) (void)hipGraphExecDestroy(p->gexec[s]);
         p->gexec[s] = nullptr;
     }
+    for (auto& e : p->pexec) (void)hipGraphExecDestroy(e.second);
+    p->pexec.clear();
     p->gX = nullptr;
+}
+
+// Slots of a pipelined step: it reads s0 (z), sm (z + h/2), sn (z + h) and
+// forms the next step's couplings at z' + h'/2 and z' + h' (z' = z + h) in
+// f1 and f2; the next step's slots are (sn, f1, f2, s0, sm).
+struct PipeSlots {
+    int s0, sm, sn, f1, f2;
+};
+int pipe_key(const PipeSlots& q) { return (((q.s0 * kSlots2C + q.sm) * kSlots2C + q.sn) * kSlots2C + q.f1) * kSlots2C + q.f2; }
+
+// Graph step of the pipelined replay: the couplings of the next step on the
+// group streams (one stream of its own for a one-group plan) beside this
+// step's four stages on st; positions and step lengths from d_zh.
+int enqueue_pipe_step(Plan2C* p, double2* X, const PipeSlots& q, hipStream_t st) {
+    int rc;
+    WPCCC_HIP_CHECK(hipEventRecord(p->pfork, st));
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        Group2C& g = p->groups[gi];
+        hipStream_t gs = p->gstreams.empty() ? p->pstream : p->gstreams[gi];
+        WPCCC_HIP_CHECK(hipStreamWaitEvent(gs, p->pfork, 0));
+        const int npath = (int)g.paths.size();
+        const int sl[2] = {q.f1, q.f2};
+        const double zz[2] = {0.0, 0.0};   // read from d_zh
+        if ((rc = enqueue_couplings(p, g, 0, npath, 2, sl, zz, gs)) || (rc = enqueue_rhs(p, g, 0, npath, 2, sl, gs)))
+            return rc;
+        WPCCC_HIP_CHECK(hipEventRecord(p->pjoin[gi], gs));
+    }
+    const StepSlots ss{true, q.s0, q.sm, q.sn};
+    if ((rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, ss, 0.0, X, st))) return rc;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) WPCCC_HIP_CHECK(hipStreamWaitEvent(st, p->pjoin[gi], 0));
+    return WPCCC_OK;
+}
+
+int capture_pipe_graph(Plan2C* p, double2* X, const PipeSlots& q, hipGraphExec_t* out) {
+    *out = nullptr;
+    if (!p->gcap) WPCCC_HIP_CHECK(hipStreamCreate(&p->gcap));
+    WPCCC_HIP_CHECK(hipStreamBeginCapture(p->gcap, hipStreamCaptureModeRelaxed));
+    const bool timing = p->timer->on;
+    p->timer->on = false;
+    p->capturing = true;
+    p->zahead = 1;
+    int rc = enqueue_pipe_step(p, X, q, p->gcap);
+    if (rc == WPCCC_OK) rc = launched(launch_chunk_counter(p->d_step, 0, p->gcap), "k_chunk_counter");
+    p->zahead = 0;
+    p->capturing = false;
+    p->timer->on = timing;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gcap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return WPCCC_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        *out = nullptr;
+        set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+        return WPCCC_EHIP;
+    }
+    return WPCCC_OK;
 }
 
 // Capture the step that starts in slot s0 (its couplings there held) into
@@ -780,18 +858,119 @@ int capture_step_graph(Plan2C* p, double2* X, int s0) {
     return WPCCC_OK;
 }
 
+// d_zh with room for n entries of (z + h/2, z + h, h) (graphs that read the
+// old array are dropped).
+int reserve_zh(Plan2C* p, int n, hipStream_t st) {
+    if (n <= p->zh_cap) return WPCCC_OK;
+    if (p->zh_copied) WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
+    WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+    drop_graphs(p);
+    if (p->h_zh) (void)hipHostFree(p->h_zh);
+    if (p->d_zh) (void)hipFree(p->d_zh);
+    p->h_zh = nullptr;
+    p->d_zh = nullptr;
+    p->zh_cap = 0;
+    WPCCC_HIP_CHECK(hipHostMalloc((void**)&p->h_zh, (size_t)3 * n * sizeof(double), 0));
+    WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_zh, (size_t)3 * n * sizeof(double)));
+    p->bytes += (long long)3 * n * sizeof(double);
+    if (!p->d_step) {
+        WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_step, sizeof(int)));
+        p->bytes += sizeof(int);
+    }
+    if (!p->zh_copied) WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->zh_copied, hipEventDisableTiming));
+    p->zh_cap = n;
+    return WPCCC_OK;
+}
+
+// Pipelined replay of n >= 2 steps (stages over every group in one launch),
+// per run of steps that each start where the previous one ended: the
+// couplings of its first step launch by launch (those at z where not held),
+// then graph steps, each the stages of step k beside the couplings of step
+// k + 1 (PipeSlots), then the stages of its last step launch by launch.  The
+// same kernels on the same data as enqueue_step, hence the same amplitudes;
+// the stages no longer wait for the next positions' LU.
+int propagate_pipe(Plan2C* p, const double* zgrid, int n_points, double2* X, hipStream_t st) {
+    const int n_steps = n_points - 1;
+    int rc;
+    if ((rc = reserve_zh(p, n_steps, st))) return rc;
+    // the staging buffer may still feed the previous call's copy
+    WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
+    for (int i = 0; i < n_steps; ++i) {
+        const double z = zgrid[i], h = zgrid[i + 1] - zgrid[i];
+        p->h_zh[3 * i] = z + 0.5 * h;
+        p->h_zh[3 * i + 1] = z + h;
+        p->h_zh[3 * i + 2] = h;
+    }
+    WPCCC_HIP_CHECK(hipMemcpyAsync(p->d_zh, p->h_zh, (size_t)3 * n_steps * sizeof(double), hipMemcpyHostToDevice, st));
+    WPCCC_HIP_CHECK(hipEventRecord(p->zh_copied, st));
+    if ((rc = launched(launch_chunk_counter(p->d_step, 1, st), "k_chunk_counter"))) return rc;
+    if (p->gX != X) drop_graphs(p);
+    if (!p->pfork) {
+        WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->pfork, hipEventDisableTiming));
+        for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+            hipEvent_t ev = nullptr;
+            WPCCC_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            p->pjoin.push_back(ev);
+        }
+        if (p->gstreams.empty()) WPCCC_HIP_CHECK(hipStreamCreate(&p->pstream));  // default priority
+    }
+    // segments of steps whose start point is the previous step's end point
+    // exactly (z_k + h_k == z_(k+1) in floating point): a step that starts
+    // elsewhere forms its couplings at z_(k+1), as enqueue_step does
+    for (int i = 0; i < n_steps;) {
+        int j = i;
+        while (j + 1 < n_steps && zgrid[j] + (zgrid[j + 1] - zgrid[j]) == zgrid[j + 1]) ++j;
+        // the couplings of step i (those at z_i where not held)
+        const StepSlots s0 = step_slots(p, zgrid[i]);
+        for (int k = 0; k < kSlots2C; ++k) p->slot_ok[k] = false;
+        if ((rc = enqueue_step_slots(p, X, zgrid[i], zgrid[i + 1] - zgrid[i], s0, st, false))) return rc;
+        PipeSlots q{s0.s0, s0.sm, s0.sn, -1, -1};
+        for (int k = 0; k < kSlots2C; ++k)
+            if (k != q.s0 && k != q.sm && k != q.sn) {
+                if (q.f1 < 0) q.f1 = k;
+                else if (q.f2 < 0) q.f2 = k;
+            }
+        // graph steps i .. j-1 (the device counter is the step index)
+        for (int k = i; k < j; ++k) {
+            const int key = pipe_key(q);
+            hipGraphExec_t ex = nullptr;
+            for (const auto& e : p->pexec)
+                if (e.first == key) ex = e.second;
+            if (!ex) {
+                // the group streams take part in the capture: let them drain first
+                WPCCC_HIP_CHECK(hipStreamSynchronize(st));
+                if ((rc = capture_pipe_graph(p, X, q, &ex))) return rc;
+                p->pexec.push_back({key, ex});
+            }
+            WPCCC_HIP_CHECK(hipGraphLaunch(ex, st));
+            q = PipeSlots{q.sn, q.f1, q.f2, q.s0, q.sm};
+        }
+        p->gX = X;
+        // the stages of step j; the slots then hold its three positions
+        const double zl = zgrid[j], hl = zgrid[j + 1] - zl;
+        const StepSlots sl{true, q.s0, q.sm, q.sn};
+        if ((rc = enqueue_stages(p, p->d_pm, p->n_traj, p->N_max, sl, hl, X, st))) return rc;
+        commit_slots(p, sl, zl, hl);
+        if ((rc = launched(launch_chunk_counter(p->d_step, 0, st), "k_chunk_counter"))) return rc;
+        i = j + 1;
+    }
+    return WPCCC_OK;
+}
+
 // Steps of zgrid by graph replays wherever the step's start point is held,
 // launch by launch elsewhere (the first step of a run): the same slots, the
 // same kernels on the same data as enqueue_step, hence the same amplitudes.
+// With one stage launch over every group, the pipelined form above.
 int propagate_graph(Plan2C* p, const double* zgrid, int n_points, double2* X, hipStream_t st) {
     const int n_steps = n_points - 1;
+    if (p->stage_all && n_steps >= 2) return propagate_pipe(p, zgrid, n_points, X, st);
     // which steps replay: the slot bookkeeping of the whole run, simulated
     double sz[kSlots2C];
     bool sok[kSlots2C];
     std::copy(p->slot_z, p->slot_z + kSlots2C, sz);
     std::copy(p->slot_ok, p->slot_ok + kSlots2C, sok);
     std::vector<int> start(n_steps);
-    bool need[kSlots2C] = {false, false, false};
+    bool need[kSlots2C] = {};
     int n_rep = 0;
     for (int i = 0; i < n_steps; ++i) {
         const double z = zgrid[i], h = zgrid[i + 1] - zgrid[i];
@@ -805,26 +984,8 @@ int propagate_graph(Plan2C* p, const double* zgrid, int n_points, double2* X, hi
     }
     std::copy(sz, sz + kSlots2C, p->slot_z);
     std::copy(sok, sok + kSlots2C, p->slot_ok);
-    if (n_rep > p->zh_cap) {
-        if (p->zh_copied) WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
-        WPCCC_HIP_CHECK(hipStreamSynchronize(st));
-        drop_graphs(p);
-        if (p->h_zh) (void)hipHostFree(p->h_zh);
-        if (p->d_zh) (void)hipFree(p->d_zh);
-        p->h_zh = nullptr;
-        p->d_zh = nullptr;
-        p->zh_cap = 0;
-        WPCCC_HIP_CHECK(hipHostMalloc((void**)&p->h_zh, (size_t)3 * n_rep * sizeof(double), 0));
-        WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_zh, (size_t)3 * n_rep * sizeof(double)));
-        p->bytes += (long long)3 * n_rep * sizeof(double);
-        if (!p->d_step) {
-            WPCCC_HIP_CHECK(hipMalloc((void**)&p->d_step, sizeof(int)));
-            p->bytes += sizeof(int);
-        }
-        if (!p->zh_copied) WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->zh_copied, hipEventDisableTiming));
-        p->zh_cap = n_rep;
-    }
     int rc;
+    if ((rc = reserve_zh(p, n_rep, st))) return rc;
     if (n_rep > 0) {
         // the staging buffer may still feed the previous call's copy
         WPCCC_HIP_CHECK(hipEventSynchronize(p->zh_copied));
@@ -1061,6 +1222,12 @@ void plan2c_destroy(Plan2C* p) {
     }
     drop_graphs(p);
     if (p->gcap) (void)hipStreamDestroy(p->gcap);
+    if (p->pstream) {
+        (void)hipStreamSynchronize(p->pstream);
+        (void)hipStreamDestroy(p->pstream);
+    }
+    if (p->pfork) (void)hipEventDestroy(p->pfork);
+    for (hipEvent_t ev : p->pjoin) (void)hipEventDestroy(ev);
     if (p->h_zh) (void)hipHostFree(p->h_zh);
     if (p->d_zh) (void)hipFree(p->d_zh);
     if (p->d_step) (void)hipFree(p->d_step);

@@ -380,16 +380,20 @@ def test_2c_explicit_matches_factored(small_run):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("batched", [1, 2], ids=["pipelined", "per-slot"])
 @pytest.mark.parametrize("solve", [W.WPCCC_SOLVE_FACTORED, W.WPCCC_SOLVE_EXPLICIT])
-def test_2c_graph_replay_bitwise(small_run, solve):
-    """Graph replay of the two-centre steps (one graph per slot of the step's
-    start point, both basis-pair groups with their forked streams inside it)
-    against launching kernel by kernel: bitwise equal amplitudes, norms and
-    probabilities over three calls on one plan with eager work in between
-    (a couplings evaluation, which moves the plan's slots, and a torch
-    reduction), on a grid whose steps are not all exactly representable
-    (some steps then start without a held point and run launch by launch),
-    and after X moves to another tensor (captured again)."""
+def test_2c_graph_replay_bitwise(small_run, solve, batched):
+    """Graph replay of the two-centre steps against launching kernel by
+    kernel: bitwise equal amplitudes, norms and probabilities over three calls
+    on one plan with eager work in between (a couplings evaluation, which
+    moves the plan's slots, and a torch reduction), on a grid whose steps are
+    not all exactly representable (a step that then starts without a held
+    point forms its couplings at its own z), and after X moves to another
+    tensor (captured again).  Both graph forms: pipelined (one stage launch
+    over every group; graph step k runs the stages of step k beside the
+    couplings of step k + 1) and per-slot (stages per group; one graph per
+    slot of the step's start point); both basis-pair groups with their forked
+    streams inside the graphs."""
     wl, lt, lp, _ = small_run
     ql = _q_lower(wl.q_lower)
     # -1.9357... + (4.6346... - -1.9357...) rounds away from 4.6346...: the
@@ -398,7 +402,7 @@ def test_2c_graph_replay_bitwise(small_run, solve):
     assert za + (zb - za) != zb
     zg = np.concatenate([np.arange(-4.0, -2.0, 0.5), [za, zb], zb + np.cumsum(np.full(6, 0.5))])
     mk = lambda g: W.wpccc_plan_create_2c(lt, lp, wl.set_of, wl.b, wl.v, n_eta=wl.n_eta, n_tau=wl.n_tau,
-                                          q_lower=ql, solve=solve, graph=g)
+                                          q_lower=ql, solve=solve, graph=g, batched=batched)
     eager, gp = mk(False), mk(True)
 
     def run(plan, X):
