@@ -21,6 +21,7 @@
 // The LU factorisation of S is in kernels_lu.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "plan2c.h"
@@ -129,19 +130,21 @@ __global__ __launch_bounds__(256) void k_2c_nodes(NodeArgs a) {
 // (coalesced).  The interpolated f_a(r) of the 64 x 64 tile is formed once in
 // LDS and written, times the Legendre factor, to the rows of every block s
 // whose radial functions (l_a >= s) it holds, row by row with lanes over
-// nodes; per s the factors Pbar_l^s of the tile's l range are staged in LDS
-// first (over the stencil weights).
+// nodes.  The factors Pbar_l^s of the tile's l range (one contiguous range
+// of node fields) are loaded into registers with the stencils, held while
+// f_a(r) is formed and then staged in LDS over the stencil weights (dynamic
+// LDS of interp_lds_bytes).
+constexpr int kInterpPReg = 4;   // Legendre factors per thread held in registers
+constexpr int kInterpMaxDynLds = 64 * 1024;   // at most 66 fields of 64 doubles (l <= 10)
 template <typename T>
 __global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
     __shared__ double tile[64][65];
-    // stencil weights (until f_a(r) is formed), then the Legendre factors
-    __shared__ union {
-        double L[64][5];
-        double P[kMaxL + 1][64];
-    } u;
-    auto& sL = u.L;
-    auto& sP = u.P;
     __shared__ int sj[64], sl[64];
+    // stencil weights [64][5] until f_a(r) is formed, then the Legendre
+    // factors [n_pf][64] (fields pb0 .. pb0 + n_pf - 1 of the side)
+    extern __shared__ double dyn[];
+    double (*sL)[5] = reinterpret_cast<double (*)[5]>(dyn);
+    double* sP = dyn;
     const Meta2C& m = *a.m;
     const int y = blockIdx.z;
     const int nact = a.n_act[y];
@@ -167,6 +170,14 @@ __global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
     int l_lo = 0, l_hi = 0;
     while (l_lo < ls && rad_off[l_lo + 1] <= f0) ++l_lo;
     while (l_hi < ls && rad_off[l_hi + 1] <= fend - 1) ++l_hi;
+    // Legendre fields l (l + 1) / 2 + s for l_lo <= l <= l_hi, s <= l
+    const int pb0 = l_lo * (l_lo + 1) / 2, n_pf = (l_hi + 1) * (l_hi + 2) / 2 - pb0;
+    double pv[kInterpPReg];
+#pragma unroll
+    for (int r = 0; r < kInterpPReg; ++r) {
+        const int e = tid + r * 256, k = e & 63, p = p0 + k;
+        pv[r] = (e < n_pf * 64 && p < nact) ? nd[(size_t)(fP + pb0 + (e >> 6)) * nn + p] : 0.0;
+    }
     // stencils of the 64 nodes, l of the 64 functions
     for (int e = tid; e < 64 * 5; e += blockDim.x) {
         const int k = e % 64, q = e / 64, p = p0 + k;
@@ -194,25 +205,27 @@ __global__ __launch_bounds__(256) void k_2c_interp(InterpArgs a) {
         tile[lane][k] = v;
     }
     __syncthreads();
+    // the Legendre factors over the stencil weights
+#pragma unroll
+    for (int r = 0; r < kInterpPReg; ++r)
+        if (tid + r * 256 < n_pf * 64) sP[tid + r * 256] = pv[r];
+    for (int e = tid + kInterpPReg * 256; e < n_pf * 64; e += blockDim.x) {
+        const int k = e & 63, p = p0 + k;
+        sP[e] = (p < nact) ? nd[(size_t)(fP + pb0 + (e >> 6)) * nn + p] : 0.0;
+    }
+    __syncthreads();
     // rows (s, a) for a in this tile and l_a >= s: functions [rad_off[s], nf)
     T* out = reinterpret_cast<T*>(sideP ? a.BT : a.AT) + (size_t)y * rows * nn;
     for (int s = 0; s <= l_hi; ++s) {
         const int alo = max(f0, rad_off[s]);
         const int cnt = fend - alo;
-        const int lb = max(l_lo, s), nl = l_hi - lb + 1;
-        // Pbar_l^s(cos theta) at the 64 nodes for l = lb .. l_hi
-        for (int e = tid; e < nl * 64; e += blockDim.x) {
-            const int k = e & 63, l = lb + (e >> 6), p = p0 + k;
-            sP[l - lb][k] = (p < nact) ? nd[(size_t)(fP + l * (l + 1) / 2 + s) * nn + p] : 0.0;
-        }
-        __syncthreads();
         const int rbase = row_off[s] + alo - rad_off[s];
         for (int e = tid; e < cnt * 64; e += blockDim.x) {
-            const int k = e & 63, i = e >> 6, p = p0 + k, ti = alo - f0 + i;
+            const int k = e & 63, i = e >> 6, p = p0 + k, ti = alo - f0 + i, l = sl[ti];
             if (p < nact)
-                out[(size_t)(rbase + i) * nn + p] = sj[k] >= 0 ? (T)(tile[ti][k] * sP[sl[ti] - lb][k]) : (T)0;
+                out[(size_t)(rbase + i) * nn + p] =
+                    sj[k] >= 0 ? (T)(tile[ti][k] * sP[(l * (l + 1) / 2 + s - pb0) * 64 + k]) : (T)0;
         }
-        __syncthreads();
     }
 }
 
@@ -1056,12 +1069,40 @@ hipError_t launch_2c_nodes(const NodeArgs& a, const Meta2C& hm, int n_jobs, hipS
     return hipGetLastError();
 }
 
+// Dynamic LDS of k_2c_interp: the larger of the stencil weights (64 x 5) and
+// the Legendre factors of the widest l range of a 64-function tile.
+size_t interp_lds_bytes(const Meta2C& hm) {
+    int npf = 5;
+    for (int side = 0; side < 2; ++side) {
+        const int nf = side ? hm.nfP : hm.nfT, ls = side ? hm.LP : hm.LT;
+        const int* rad_off = side ? hm.radP_off : hm.radT_off;
+        for (int f0 = 0; f0 < nf; f0 += 64) {
+            const int fend = std::min(f0 + 64, nf);
+            int l_lo = 0, l_hi = 0;
+            while (l_lo < ls && rad_off[l_lo + 1] <= f0) ++l_lo;
+            while (l_hi < ls && rad_off[l_hi + 1] <= fend - 1) ++l_hi;
+            npf = std::max(npf, (l_hi + 1) * (l_hi + 2) / 2 - l_lo * (l_lo + 1) / 2);
+        }
+    }
+    return (size_t)npf * 64 * sizeof(double);
+}
+
 hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     const dim3 grid((hm.n_nodes + 63) / 64, (hm.nfT + 63) / 64 + (hm.nfP + 63) / 64, n_jobs), block(256);
+    const size_t smem = interp_lds_bytes(hm);
+    // above 64 KiB per workgroup (the factors of a tile that spans many l)
+    // the kernels need the larger limit, set once to a fixed value
+    static bool raised = false;
+    if (!raised) {
+        for (const void* f : {(const void*)k_2c_interp<float>, (const void*)k_2c_interp<double>})
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kInterpMaxDynLds) != hipSuccess)
+                return hipGetLastError();
+        raised = true;
+    }
     if (hm.mixed)
-        WPCCC_LAUNCH(ev, k_2c_interp<float>, grid, block, 0, st, a);
+        WPCCC_LAUNCH(ev, k_2c_interp<float>, grid, block, smem, st, a);
     else
-        WPCCC_LAUNCH(ev, k_2c_interp<double>, grid, block, 0, st, a);
+        WPCCC_LAUNCH(ev, k_2c_interp<double>, grid, block, smem, st, a);
     return hipGetLastError();
 }
 
