@@ -159,13 +159,13 @@ typedef struct {
                        from a captured HIP graph (step lengths and positions
                        read from device memory); 2C: replay the steps of
                        wpccc_propagate from captured graphs, every group's
-                       launches in one graph: with batched = 1 each graph
-                       step runs the stages of one step beside the couplings
-                       of the next (a step whose start point z + h rounds
-                       away from the next grid point begins a new run of
-                       graph steps), with batched = 0 or 2 one graph per
-                       start slot replays each step whose start point the
-                       plan holds.  Both capture again when X moves; results
+                       launches in one graph: with batched = 1 and
+                       WPCCC_SOLVE_FACTORED each graph step runs the stages
+                       of one step beside the couplings of the next (a step
+                       whose start point z + h rounds away from the next
+                       grid point begins a new run of graph steps);
+                       otherwise one graph per start slot replays each step
+                       whose start point the plan holds.  Both capture again when X moves; results
                        are bitwise those of launching kernel by kernel.
                        0: launch kernel by kernel */
     int stage_launch; /* 1C: how wpccc_propagate runs the RK4 stages of each

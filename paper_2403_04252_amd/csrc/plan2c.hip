@@ -960,10 +960,12 @@ int propagate_pipe(Plan2C* p, const double* zgrid, int n_points, double2* X, hip
 // Steps of zgrid by graph replays wherever the step's start point is held,
 // launch by launch elsewhere (the first step of a run): the same slots, the
 // same kernels on the same data as enqueue_step, hence the same amplitudes.
-// With one stage launch over every group, the pipelined form above.
+// With one stage launch over every group and the factored solves, the
+// pipelined form above (with M = S^-1 H formed per point, its N^3 right-hand
+// sides beside the next step's contractions measured slower than this form).
 int propagate_graph(Plan2C* p, const double* zgrid, int n_points, double2* X, hipStream_t st) {
     const int n_steps = n_points - 1;
-    if (p->stage_all && n_steps >= 2) return propagate_pipe(p, zgrid, n_points, X, st);
+    if (p->stage_all && !p->explicit_m && n_steps >= 2) return propagate_pipe(p, zgrid, n_points, X, st);
     // which steps replay: the slot bookkeeping of the whole run, simulated
     double sz[kSlots2C];
     bool sok[kSlots2C];
