@@ -1091,14 +1091,15 @@ hipError_t launch_2c_interp(const InterpArgs& a, const Meta2C& hm, int n_jobs, h
     const dim3 grid((hm.n_nodes + 63) / 64, (hm.nfT + 63) / 64 + (hm.nfP + 63) / 64, n_jobs), block(256);
     const size_t smem = interp_lds_bytes(hm);
     // above 64 KiB per workgroup (the factors of a tile that spans many l)
-    // the kernels need the larger limit, set once to a fixed value
-    static bool raised = false;
-    if (!raised) {
+    // the kernels need the larger limit, set once (thread-safe static
+    // initialisation) to a fixed value that no later call lowers
+    static const hipError_t raised = [] {
+        hipError_t e = hipSuccess;
         for (const void* f : {(const void*)k_2c_interp<float>, (const void*)k_2c_interp<double>})
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kInterpMaxDynLds) != hipSuccess)
-                return hipGetLastError();
-        raised = true;
-    }
+            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kInterpMaxDynLds);
+        return e;
+    }();
+    if (raised != hipSuccess) return raised;
     if (hm.mixed)
         WPCCC_LAUNCH(ev, k_2c_interp<float>, grid, block, smem, st, a);
     else
