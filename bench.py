@@ -528,8 +528,9 @@ def bench_sweep_2c(args):
     (bound n <= 6 plus 24 Coulomb bins per l), l_max = 0..5 (N = 60..1910),
     4000-point grids, 256 x 512 spheroidal nodes, prior lower-left block;
     8 paths (b log-spaced 0.2..10) at v = 2, `steps` steps of 0.1 from
-    z = -0.5 (through closest approach, where the most nodes are active).
-    Prints one JSON line with one entry per l_max."""
+    z = -0.5 (through closest approach, where the most nodes are active),
+    replayed from HIP graphs (pipelined: the stages of a step beside the
+    couplings of the next).  Prints one JSON line with one entry per l_max."""
     import torch
     import paper_2403_04252_amd as W
     from paper_2403_04252_amd import workloads as WL
@@ -545,13 +546,14 @@ def bench_sweep_2c(args):
         lb = W.wpccc_basis(W.BasisSpec(rec.n_max, rec.l_max, rec.n_bins, rec.k_max, rec.n_r, rec.r_max, rec.Z))
         t0 = time.perf_counter()
         plan = W.wpccc_plan_create_2c([lb], [lb], np.zeros(8, dtype=np.int32), b, v, q_lower=W.WPCCC_Q_PRIOR,
-                                      n_eta=256, n_tau=512)
+                                      n_eta=256, n_tau=512, graph=True)
         setup = time.perf_counter() - t0
         N = plan.n_states
         print(f"sweep2c l_max {l_max}: N = {N}", file=sys.stderr, flush=True)
         X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
         X[:, 0] = 1.0
-        W.wpccc_propagate(plan, zs[: args.warmup + 1], X)
+        # at least six warm-up steps: they capture the five graphs of the slot rotation
+        W.wpccc_propagate(plan, zs[: max(args.warmup, 6) + 1], X)
         X.zero_()
         X[:, 0] = 1.0
         torch.cuda.synchronize()
@@ -571,6 +573,7 @@ def bench_sweep_2c(args):
                       "config": {"workload": "p+H 2C paper shape N_l = 30 - l per centre (n <= 6 + 24 bins/l), "
                                              "l_max 0..5, 4000-pt grids, 256x512 nodes, prior lower block, "
                                              "8 b log-spaced 0.2-10, v = 2, z -0.5..0.5",
+                                 "form": "steps replayed from pipelined HIP graphs",
                                  "parallelism": "1 GPU, paths batched"},
                       "sweep": rows}), flush=True)
 
@@ -783,8 +786,9 @@ def two_centre_measure(args, steps, warmup, mixed=False, z0=None, explicit=False
             N = W.wpccc_plan_path_info(plan, j)[0]
             X0[j, :N] = torch.from_numpy(WL.random_state(1, N, seed=100 + j)[0]).cuda()
     X.copy_(X0)
-    # graph replay: three warm-up steps capture both graphs of the slot rotation
-    run_propagation(W, plan, X, zs, max(warmup, 3) if graph else warmup)
+    # graph replay: six warm-up steps capture the five graphs of the pipelined
+    # slot rotation (three, both per-slot graphs of the explicit form)
+    run_propagation(W, plan, X, zs, max(warmup, 6) if graph else warmup)
     torch.cuda.synchronize()
     X.copy_(X0)
     torch.cuda.synchronize()
