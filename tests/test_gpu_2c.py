@@ -558,3 +558,35 @@ def test_2c_mirrored_prior_block(mixed, n_tau, rec):
     d = np.abs(P[0] - P[1]).max()
     print(f"  20 steps: max|dP| {d:.1e}", flush=True)
     assert d <= 1e-12
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_2c_pipelined_graph_one_group(mixed):
+    """Pipelined graph replay of a one-group plan (one basis object on both
+    centres; the next step's couplings on the plan's own coupling stream)
+    against launching kernel by kernel: bitwise equal amplitudes over two
+    calls of 9 steps (the second continues from the first's end point), in
+    FP64 and with the FP32 contraction products."""
+    rec = WL.Recipe(3, 2, 4, 2.0, 600, 40.0)
+    lb = lib_basis(rec)
+    bs, vs = np.array([0.7, 2.2, 5.0]), np.array([1.0, 0.5, 2.0])
+    mk = lambda g: W.wpccc_plan_create_2c([lb], [lb], [0, 0, 0], bs, vs, q_lower=W.WPCCC_Q_PRIOR, n_eta=24,
+                                          n_tau=40, mixed=mixed, graph=g)
+    zg1 = np.linspace(-2.0, 0.25, 10)
+    zg2 = np.concatenate([[zg1[-1]], zg1[-1] + 0.25 * np.arange(1, 10)])
+    out = []
+    for g in (False, True):
+        plan = mk(g)
+        X = torch.zeros((plan.n_traj, plan.n_pad), dtype=torch.complex128, device="cuda")
+        X[:, 0] = 1.0
+        res = []
+        for zg in (zg1, zg2):
+            print(f"pipelined one-group graph={g} mixed={mixed}: {zg.size - 1} steps from z = {zg[0]}", flush=True)
+            W.wpccc_propagate(plan, zg, X)
+            W.wpccc_plan_status(plan)
+            torch.cuda.synchronize()
+            res.append(X.cpu().numpy().copy())
+        out.append(res)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    assert np.abs(out[0][1]).max() > 0.0
