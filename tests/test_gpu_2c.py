@@ -390,10 +390,11 @@ def test_2c_graph_replay_bitwise(small_run, solve, batched):
     not all exactly representable (a step that then starts without a held
     point forms its couplings at its own z), and after X moves to another
     tensor (captured again).  Both graph forms: pipelined (one stage launch
-    over every group; graph step k runs the stages of step k beside the
-    couplings of step k + 1) and per-slot (stages per group; one graph per
-    slot of the step's start point); both basis-pair groups with their forked
-    streams inside the graphs."""
+    over every group with the factored solves; graph step k runs the stages
+    of step k beside the couplings of step k + 1) and per-slot (stages per
+    group, or the explicit M = S^-1 H; one graph per slot of the step's start
+    point); both basis-pair groups with their forked streams inside the
+    graphs."""
     wl, lt, lp, _ = small_run
     ql = _q_lower(wl.q_lower)
     # -1.9357... + (4.6346... - -1.9357...) rounds away from 4.6346...: the
