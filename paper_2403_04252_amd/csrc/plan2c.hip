@@ -906,13 +906,14 @@ int propagate_pipe(Plan2C* p, const double* zgrid, int n_points, double2* X, hip
     if ((rc = launched(launch_chunk_counter(p->d_step, 1, st), "k_chunk_counter"))) return rc;
     if (p->gX != X) drop_graphs(p);
     if (!p->pfork) {
-        WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->pfork, hipEventDisableTiming));
-        for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        // the join events and the coupling stream first: pfork set means all exist
+        while (p->pjoin.size() < p->groups.size()) {
             hipEvent_t ev = nullptr;
             WPCCC_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
             p->pjoin.push_back(ev);
         }
-        if (p->gstreams.empty()) WPCCC_HIP_CHECK(hipStreamCreate(&p->pstream));  // default priority
+        if (p->gstreams.empty() && !p->pstream) WPCCC_HIP_CHECK(hipStreamCreate(&p->pstream));  // default priority
+        WPCCC_HIP_CHECK(hipEventCreateWithFlags(&p->pfork, hipEventDisableTiming));
     }
     // segments of steps whose start point is the previous step's end point
     // exactly (z_k + h_k == z_(k+1) in floating point): a step that starts
