@@ -418,7 +418,8 @@ __device__ inline double2 stage_phase3_global(const double* gc, const int* gp, c
 }
 
 // Lanes per output of phase 3: the largest power of two S <= 64 with
-// 2 n_out S <= B (so that every output keeps at least half the lanes busy).
+// 2 n_out S <= B (so that every output keeps at least half the lanes busy),
+// for the n_out = ROWS x (2 l' + 1) outputs of a full tile of the block.
 // Every output has a lane group when n_out <= B (phase3_fits).
 __device__ inline int phase3_lanes(int n_out, int B) {
     int S = 1;
@@ -547,9 +548,12 @@ __device__ void stage_body(const StageArgs& a, int j, const StageTile& t, char* 
         gcv[i] = GG ? 0.0 : gc[idx];
         gpv[i] = GG ? -1 : gp[idx];
     }
-    // output-side values, prefetched by the thread that writes output o
+    // output-side values, prefetched by the thread that writes output o.
+    // The lanes per output follow from the tiling's ROWS, not from this
+    // tile's rows, so that an output sums its columns in the same order in
+    // every split of its block (even or greedy tiles, the persistent kernel)
     const int n_out = nrows * nmp;
-    const int S = phase3_lanes(n_out, B);
+    const int S = phase3_lanes(ROWS * nmp, B);
     const int o = tid / S, s = tid - o * S;
     const bool writer = (o < n_out) && (s == 0);
     const double v = T.vvec[j];
@@ -1008,7 +1012,7 @@ __device__ void chunk_stage(const StageArgs& a, int j, int lp, int row0, int nro
     stage_phase2<ROWS>(Fs, xs, gis, Ws, nrows, gcols, nV);
     __syncthreads();
     const int n_out = nrows * nmp;
-    const int S = phase3_lanes(n_out, B);
+    const int S = phase3_lanes(ROWS * nmp, B);   // as stage_body
     const int o = tid / S, s = tid - o * S;
     const double2 y = stage_phase3(Gs, Ws, o, s, S, n_out, nmp, gcols);
     if (o < n_out && s == 0) {
@@ -1072,7 +1076,7 @@ __global__ __launch_bounds__(kStageThreads, 2) void k_chunk(ChunkArgs c) {
         int* cls = reinterpret_cast<int*>(gis + gcols);
         for (int i = tid; i < nV; i += B) cls[i] = T.col_lam[m.col_off[lp] + i];
         const int n_out = nrows * nmp;
-        const int S = phase3_lanes(n_out, B);
+        const int S = phase3_lanes(ROWS * nmp, B);   // as stage_body
         const int o = tid / S;
         r.x0 = r.xa = make_double2(0.0, 0.0);
         if (o < n_out && tid - o * S == 0) {
@@ -1262,31 +1266,64 @@ int stage_chunks(const Meta& m, int rows) {
     return n;
 }
 
+namespace {
+// Rows [r0, r0 + nrows) of block l' of one path (vo: offset of the block's
+// model-potential rows).
+StageTile make_tile(const Meta& m, int lp, int r0, int nrows, int vo) {
+    StageTile t{};
+    t.lp = lp;
+    t.row0 = r0;
+    t.nrows = nrows;
+    t.nmp = 2 * lp + 1;
+    t.nV = m.nV[lp];
+    t.gcols = m.gcols[lp];
+    t.frow_off = m.frow_off[lp];
+    t.col_off = m.col_off[lp];
+    t.g_off = m.g_off[lp];
+    t.gcol_off = m.gcol_off[lp];
+    t.state_off = m.state_off[lp];
+    t.rad_off = m.rad_off[lp];
+    t.n_l = m.n_l[lp];
+    t.xs_off = m.xs_off[lp];
+    t.xs_stride = m.xs_stride[lp];
+    t.vo = vo;
+    return t;
+}
+}  // namespace
+
 void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out) {
     out.clear();
     int vo = 0;
     for (int lp = 0; lp <= m.l_max; ++lp) {
-        for (int r0 = 0; r0 < m.n_l[lp]; r0 += rows) {
-            StageTile t{};
-            t.lp = lp;
-            t.row0 = r0;
-            t.nrows = std::min(rows, m.n_l[lp] - r0);
-            t.nmp = 2 * lp + 1;
-            t.nV = m.nV[lp];
-            t.gcols = m.gcols[lp];
-            t.frow_off = m.frow_off[lp];
-            t.col_off = m.col_off[lp];
-            t.g_off = m.g_off[lp];
-            t.gcol_off = m.gcol_off[lp];
-            t.state_off = m.state_off[lp];
-            t.rad_off = m.rad_off[lp];
-            t.n_l = m.n_l[lp];
-            t.xs_off = m.xs_off[lp];
-            t.xs_stride = m.xs_stride[lp];
-            t.vo = vo;
-            out.push_back(t);
-        }
+        for (int r0 = 0; r0 < m.n_l[lp]; r0 += rows) out.push_back(make_tile(m, lp, r0, std::min(rows, m.n_l[lp] - r0), vo));
         vo += m.n_l[lp] * m.n_l[lp];
+    }
+}
+
+void stage_tiles_balanced(const Meta& m, int rows, int n_launch, long long wg_slots, std::vector<StageTile>& out) {
+    out.clear();
+    int cap[kMaxL + 1];
+    long long per_path = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) {
+        cap[lp] = rows;
+        per_path += (m.n_l[lp] + rows - 1) / rows;
+    }
+    for (int lp = m.l_max; lp >= 0 && rows > 1; --lp) {
+        const int extra = (m.n_l[lp] + rows - 2) / (rows - 1) - (m.n_l[lp] + rows - 1) / rows;
+        if ((long long)n_launch * (per_path + extra) <= wg_slots) {
+            cap[lp] = rows - 1;
+            per_path += extra;
+        }
+    }
+    int vo = 0;
+    for (int lp = 0; lp <= m.l_max; ++lp) {
+        const int n = m.n_l[lp], nt = (n + cap[lp] - 1) / cap[lp];
+        for (int ti = 0, r0 = 0; ti < nt; ++ti) {
+            const int nr = n / nt + (ti < n % nt ? 1 : 0);
+            out.push_back(make_tile(m, lp, r0, nr, vo));
+            r0 += nr;
+        }
+        vo += n * n;
     }
 }
 
@@ -1343,6 +1380,27 @@ hipError_t stage_set_smem_limit(int, int bytes) {
 }
 
 int chunk_grid(const Meta& hm, int n_traj, int rows) { return 8 * ((n_traj * stage_chunks(hm, rows) + 7) / 8); }
+
+int stage_wgs_per_cu(int rows, int smem) {
+    const void* f = nullptr;
+    switch (rows) {
+#define WPCCC_CASE(R) \
+    case R: f = (const void*)k_stage<R, false, false>; break;
+        WPCCC_STAGE_ROWS(WPCCC_CASE)
+#undef WPCCC_CASE
+        default: return 0;
+    }
+    int dev = 0, per_cu = 0, lds_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kStageThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    // the occupancy query without dynamic LDS (above 64 KiB it would need the
+    // kernel attribute first), then the LDS bound
+    return smem > 0 ? std::min(per_cu, lds_cu / smem) : per_cu;
+}
 
 static const void* chunk_fn(int rows) {
     switch (rows) {

@@ -422,6 +422,14 @@ bool chunk_fits(const Meta& host_meta, int n_traj, int rows, int smem);
 int stage_smem_bytes(const Meta& m, int rows = kRowsPerBlock, bool gg = false);
 // the row tiles of one path for `rows` rows per workgroup, l' order
 void stage_tiles(const Meta& m, int rows, std::vector<StageTile>& out);
+// k_stage's tiles: every l' block split into tiles of even size, of at most
+// `rows` rows, or rows - 1 for the largest l' (from l_max down) while
+// n_launch paths of such tiles still fit wg_slots resident workgroups (the
+// larger l' blocks take longer per row, and a launch ends with its slowest
+// workgroup)
+void stage_tiles_balanced(const Meta& m, int rows, int n_launch, long long wg_slots, std::vector<StageTile>& out);
+// resident k_stage workgroups per CU at `rows` rows and smem bytes of dynamic LDS (0: unknown)
+int stage_wgs_per_cu(int rows, int smem);
 // whether the stage kernels can use `rows` rows per workgroup for this basis
 // (every output of a workgroup needs a lane of the phase-3 reduction)
 bool stage_rows_fit(const Meta& m, int rows);

@@ -84,6 +84,8 @@ struct wpccc_plan_s {
     StageTile* d_tiles = nullptr;  // the row tiles of every tiling in kStageRowsList, one after another
     Observables obs;               // channel codes and path groups (wpccc_observables)
     int tile_off[kNumStageRows] = {}, tile_n[kNumStageRows] = {};
+    // k_stage's balanced tilings (stage_tiles_balanced); k_apply keeps the plain ones
+    int tile_off_bal[kNumStageRows] = {}, tile_n_bal[kNumStageRows] = {};
     // large-basis form (no regular tiling fits the LDS): angular factors read
     // from global memory, tilings of kStageRowsGG rows after the regular ones
     bool gg = false;
@@ -170,6 +172,12 @@ StageArgs stage_args(const wpccc_plan_s* p, int j0, double2* X) {
     StageArgs a{};
     a.meta = p->c.d_meta;
     set_tiles(p, p->stage_rows, a);
+    if (!p->gg)
+        for (int i = 0; i < kNumStageRows; ++i)
+            if (kStageRowsList[i] == p->stage_rows) {
+                a.tiles = p->d_tiles + p->tile_off_bal[i];
+                a.nwg = p->tile_n_bal[i];
+            }
     a.gg = p->gg ? 1 : 0;
     a.tb = p->tables();
     a.pt = p->points();
@@ -893,6 +901,26 @@ int wpccc_plan_create(wpccc_basis_t target, int n_traj, const double* b_host, co
         plan->tile_off_gg[i] = (int)tiles.size();
         plan->tile_n_gg[i] = (int)t.size();
         tiles.insert(tiles.end(), t.begin(), t.end());
+    }
+    {
+        // resident workgroups of the device for each tiling (0 if unknown:
+        // then the tiles are only balanced in size)
+        int dev = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            n_cu = 0;
+        }
+        const int n_launch = plan->batched ? n_traj : 1;
+        for (int i = 0; i < kNumStageRows; ++i) {
+            const int r = kStageRowsList[i];
+            const long long slots = (long long)n_cu * stage_wgs_per_cu(r, stage_smem_bytes(m, r));
+            std::vector<StageTile> t;
+            stage_tiles_balanced(m, r, n_launch, slots, t);
+            plan->tile_off_bal[i] = (int)tiles.size();
+            plan->tile_n_bal[i] = (int)t.size();
+            tiles.insert(tiles.end(), t.begin(), t.end());
+        }
     }
     TRY(dev_alloc(&plan->d_tiles, tiles.size(), tot));
     TRY(dev_alloc(&plan->d_Frow1, (size_t)m.n_frow, tot));
