@@ -23,7 +23,7 @@ constexpr int kTile = 32;         // rows (target) and columns (projectile) per 
 // their weight count (4 to 12) and node count, so several shorter items per
 // tile let the dispatcher balance them over the CUs (partial sums per range
 // are added in a fixed order when the blocks are assembled)
-constexpr int kContractSplit = 8;
+constexpr int kContractSplit = 24;
 constexpr int kMaxK = 4 * kMaxW;  // weights per (s, t): 2 Bessel orders x (cos, sin) x weights
 // coupling slots per path: a step reads three positions (z, z + h/2, z + h);
 // a pipelined graph step also forms the next step's last two
