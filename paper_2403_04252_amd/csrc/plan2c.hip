@@ -289,6 +289,16 @@ void fill_meta(const HostBasis& tb, const HostBasis& pb, int n_eta, int n_tau, i
                     tiles.push_back(make_int2(s | (t << 8) | (overlap_mirrored(m.same, s, t, a0, b0) ? kTileUpper : 0),
                                               a0 | (b0 << 16)));
         }
+    // heaviest tiles first (weights formed x active 16 x 16 subtiles): the
+    // dispatcher takes each XCD's work items in order, so the last ones it
+    // hands out are the short ones; the order changes no sum
+    auto tile_cost = [&](const int2& q) {
+        const int s = q.x & 0xff, t = (q.x >> 8) & 0xff, a0 = q.y & 0xffff, b0 = q.y >> 16;
+        const int nk = (q.x & kTileUpper) ? st_nk(s, t, 1) : st_nk(s, t, st_nw(m.same, m.n_w, s, t));
+        return nk * (a0 + 16 < m.nA[s] ? 2 : 1) * (b0 + 16 < m.nB[t] ? 2 : 1);
+    };
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [&](const int2& x, const int2& y) { return tile_cost(x) > tile_cost(y); });
     m.n_tmol = off;
     m.n_tiles = (int)tiles.size();
     m.n_split = kContractSplit;
