@@ -1,8 +1,8 @@
 // Batched complex LU with partial pivoting (the overlap matrices S of Eq. 1)
 // on gfx950.  Right-looking, one panel of kLUPanel columns per pass and one
 // launch of each kernel per pass for every matrix of the batch:
-//   k_lu_panel      the N - k0 rows of the panel in registers (two rows per
-//                   thread, 512 threads): per column an argmax (largest
+//   k_lu_panel      the N - k0 rows of the panel in registers (one to four
+//                   rows per thread, 512 threads): per column an argmax (largest
 //                   |a|^2, ties to the lowest row), the row swap, the scaling
 //                   of L and the rank-1 update of the remaining panel columns
 //   k_lu_swap_trsm  the panel's swaps on every other column (LAPACK getrf
@@ -39,7 +39,7 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// ROWS rows per thread (N <= ROWS x 512), panels of up to NB columns: the
+// ROWS rows per thread (N - k0 <= ROWS x 512), panels of up to NB columns: the
 // panel's N - k0 rows live in registers (ROWS x NB complex values per thread).
 template <int ROWS, int NB>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(LUStepArgs a) {
@@ -494,10 +494,21 @@ int lu_panel_width(int N) { return N <= 2 * kPanelThreads ? kLUPanel : kLUPanel 
 
 hipError_t launch_lu_panel(const LUStepArgs& a, int n_jobs, hipStream_t st, const LaunchEv& ev) {
     if (a.N > kLUMaxN || a.nb > lu_panel_width(a.N)) return hipErrorInvalidValue;
-    if (a.N <= 2 * kPanelThreads)
-        WPCCC_LAUNCH(ev, (k_lu_panel<2, kLUPanel>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
-    else
+    // rows per thread from the rows left below k0 (the pivot is the same
+    // whatever the split: largest |a|^2, lowest row on ties)
+    const int rows = (a.N - a.k0 + kPanelThreads - 1) / kPanelThreads;
+    if (lu_panel_width(a.N) == kLUPanel) {
+        if (rows <= 1)
+            WPCCC_LAUNCH(ev, (k_lu_panel<1, kLUPanel>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+        else
+            WPCCC_LAUNCH(ev, (k_lu_panel<2, kLUPanel>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    } else if (rows <= 1) {
+        WPCCC_LAUNCH(ev, (k_lu_panel<1, kLUPanel / 2>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    } else if (rows <= 2) {
+        WPCCC_LAUNCH(ev, (k_lu_panel<2, kLUPanel / 2>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    } else {
         WPCCC_LAUNCH(ev, (k_lu_panel<4, kLUPanel / 2>), dim3(n_jobs), dim3(kPanelThreads), 0, st, a);
+    }
     return hipGetLastError();
 }
 
